@@ -1,0 +1,384 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formula: each compares it with a hand-worked
+example, a closed form, an invariance, an exact rational computation done with Python
+integers, a textbook routine (dynamic programming on a chain, brute force over all
+labellings) or a second schedule that must agree exactly.
+"""
+import itertools
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")))
+
+
+# ---------------------------------------------------------------- luma
+def test_luma_grey_is_identity():
+    v = np.arange(256, dtype=np.uint8)
+    rgb = np.stack([v, v, v], -1).reshape(16, 16, 3)
+    assert np.array_equal(oracle.luma(rgb), v.reshape(16, 16))
+
+
+def test_luma_close_to_bt601():
+    rng = np.random.default_rng(0)
+    rgb = rng.integers(0, 256, (32, 32, 3), dtype=np.uint8)
+    y = oracle.luma(rgb).astype(np.float64)
+    ref = 0.299 * rgb[..., 0] + 0.587 * rgb[..., 1] + 0.114 * rgb[..., 2]
+    assert np.max(np.abs(y - ref)) <= 1.0
+    # pure primaries: (77*255 + 128) >> 8 = 77 etc.
+    prim = np.zeros((1, 3, 3), np.uint8)
+    prim[0, 0, 0] = prim[0, 1, 1] = prim[0, 2, 2] = 255
+    assert oracle.luma(prim).tolist() == [[77, 149, 29]]
+
+
+# ---------------------------------------------------------------- NCC and cost
+@pytest.mark.parametrize("case", GOLDEN["ncc"], ids=lambda c: c["name"])
+def test_ncc_hand_cases(case):
+    L = np.array(case["left"], np.uint8)
+    R = np.array(case["right"], np.uint8)
+    v = oracle.ncc_at(L, R, case["window"], case["x"], case["y"], case["d"])
+    assert abs(v - case["ncc"]) <= 1e-15
+    assert oracle.cost_at(L, R, case["window"], case["x"], case["y"], case["d"]) == case["cost"]
+
+
+def _exact_sums(L, R, win, x, y, d):
+    H, W = L.shape
+    r = win // 2
+    si = sj = sii = sjj = sij = 0
+    for j in range(-r, r + 1):
+        yy = min(max(y + j, 0), H - 1)
+        for i in range(-r, r + 1):
+            a = int(L[yy, min(max(x + i, 0), W - 1)])
+            b = int(R[yy, min(max(x - d + i, 0), W - 1)])
+            si += a; sj += b; sii += a * a; sjj += b * b; sij += a * b
+    n = win * win
+    return n * sij - si * sj, n * sii - si * si, n * sjj - sj * sj
+
+
+def _exact_cost(num, vi, vj, scale=256, trunc=1024):
+    """round-half-up(scale*(1 - num/sqrt(vi*vj))) decided with integers only."""
+    if vi == 0 or vj == 0:
+        return min(scale, trunc)
+    P = vi * vj
+
+    def ok(k):  # k <= scale*(1 - num/sqrt(P)) + 1/2  <=>  2*scale*num <= (2*scale - 2k + 1)*sqrt(P)
+        A, B = 2 * scale - 2 * k + 1, 2 * scale * num
+        if A >= 0:
+            return B <= 0 or B * B <= A * A * P
+        return B < 0 and B * B >= A * A * P
+
+    k = 0
+    while ok(k + 1):
+        k += 1
+    while not ok(k):
+        k -= 1
+    return max(0, min(k, trunc))
+
+
+def test_ncc_matches_integer_sum_form_and_cost_is_exact():
+    rng = np.random.default_rng(1)
+    for trial in range(6):
+        H, W = 7, 11
+        L = rng.integers(0, 256, (H, W), dtype=np.uint8)
+        R = np.clip(np.roll(L, -2, axis=1).astype(int) + rng.integers(-30, 31, (H, W)), 0, 255).astype(np.uint8)
+        for win in (1, 3, 5):
+            for (x, y, d) in [(0, 0, 0), (W - 1, H - 1, 3), (5, 3, 2), (2, 6, 1), (10, 2, 7), (3, 3, 3)]:
+                num, vi, vj = _exact_sums(L, R, win, x, y, d)
+                got = oracle.ncc_at(L, R, win, x, y, d)
+                ref = 0.0 if (vi == 0 or vj == 0) else num / math.sqrt(vi * vj)
+                assert abs(got - ref) <= 1e-12
+                assert oracle.cost_at(L, R, win, x, y, d) == _exact_cost(num, vi, vj)
+
+
+def test_cost_exact_at_rounding_ties():
+    """Windows whose cost sits exactly on a .5 boundary are rounded up, never by float luck."""
+    rng = np.random.default_rng(7)
+    found = 0
+    for _ in range(20000):
+        I = rng.integers(0, 12, 9)
+        J = rng.permutation(I)  # same variance, so sqrt(P) is an integer and ties can occur
+        num, vi, vj = _exact_sums(I.reshape(3, 3).astype(np.uint8), J.reshape(3, 3).astype(np.uint8), 3, 1, 1, 0)
+        if vi == 0:
+            continue
+        v = Fraction(256) * (1 - Fraction(num, vi))  # sqrt(vi*vj) = vi
+        if (v + Fraction(1, 2)).denominator != 1:
+            continue
+        L = I.reshape(3, 3).astype(np.uint8)
+        R = J.reshape(3, 3).astype(np.uint8)
+        assert oracle.cost_at(L, R, 3, 1, 1, 0) == int(v + Fraction(1, 2))
+        found += 1
+        if found >= 5:
+            break
+    assert found >= 1
+
+
+def test_ncc_identity_affine_and_flip():
+    rng = np.random.default_rng(2)
+    L = rng.integers(0, 120, (9, 13), dtype=np.uint8)
+    for (x, y) in [(6, 4), (0, 0), (12, 8)]:
+        assert abs(oracle.ncc_at(L, L, 5, x, y, 0) - 1.0) <= 1e-12
+    R = rng.integers(0, 120, (9, 13), dtype=np.uint8)
+    R2 = (2 * R.astype(int) + 7).astype(np.uint8)  # a > 0, no clipping
+    R3 = (255 - R.astype(int)).astype(np.uint8)  # a < 0
+    for (x, y, d) in [(6, 4, 2), (3, 3, 0), (12, 8, 5)]:
+        base = oracle.ncc_at(L, R, 5, x, y, d)
+        assert abs(oracle.ncc_at(L, R2, 5, x, y, d) - base) <= 1e-12
+        assert abs(oracle.ncc_at(L, R3, 5, x, y, d) + base) <= 1e-12
+        assert oracle.cost_at(L, R3, 5, x, y, d) == _exact_cost(*_exact_sums(L, R3, 5, x, y, d))
+
+
+def test_cost_volume_matches_pointwise_and_invalid_columns():
+    rng = np.random.default_rng(3)
+    L = rng.integers(0, 256, (6, 9), dtype=np.uint8)
+    R = rng.integers(0, 256, (6, 9), dtype=np.uint8)
+    cost, ncc = oracle.cost_volume(L, R, 5, 3, want_ncc=True)
+    for y in range(6):
+        for x in range(9):
+            for d in range(5):
+                if x - d < 0:
+                    assert cost[y, x, d] == 1024 and ncc[y, x, d] == -2.0
+                else:
+                    assert cost[y, x, d] == _exact_cost(*_exact_sums(L, R, 3, x, y, d))
+    assert cost.min() >= 0 and cost[:, 4:, :].max() <= 512
+
+
+# ---------------------------------------------------------------- pyramid
+def test_pyramid_hand_case():
+    case = GOLDEN["pyramid"][0]
+    got = oracle.pyramid_level(np.array(case["cost"], np.int16))
+    assert got.tolist() == case["coarse"]
+
+
+def test_pyramid_saturates_and_is_offset_invariant():
+    c = np.full((2, 2, 3), 30000, np.int16)
+    c[..., 0] = 0
+    out = oracle.pyramid_level(c)
+    assert out.tolist() == [[[0, 32767, 32767]]]
+    rng = np.random.default_rng(4)
+    c = rng.integers(0, 500, (7, 5, 6)).astype(np.int16)
+    off = rng.integers(-100, 100, (7, 5, 1)).astype(np.int16)
+    assert np.array_equal(oracle.pyramid_level(c), oracle.pyramid_level(c + off))
+
+
+# ---------------------------------------------------------------- one message
+def test_message_closed_forms():
+    D = 12
+    for lam, T in [(64, 4), (3, 100), (7, 1)]:
+        for d0 in (0, 5, 11):
+            h = np.full(D, 10**6, np.int32)
+            h[d0] = 3
+            m = oracle.message(h, lam, T)
+            ref = [lam * min(abs(d - d0), T) for d in range(D)]
+            assert m.tolist() == [min(v, 32767) for v in ref]
+    rng = np.random.default_rng(5)
+    h = rng.integers(0, 2000, D).astype(np.int32)
+    assert oracle.message(h, 0, 4).tolist() == [0] * D  # lambda = 0: no smoothness, flat message
+    assert oracle.message(h, 64, 0).tolist() == [0] * D  # T = 0: same
+    assert oracle.message(np.full(D, 77, np.int32), 64, 4).tolist() == [0] * D
+    # a V-shaped h keeps its shape under a shallower slope and saturates at lam*T
+    h = np.abs(np.arange(D) - 6).astype(np.int32) * 100
+    assert oracle.message(h, 30, 3).tolist() == [min(30 * abs(d - 6), 90) for d in range(D)]
+    # values never exceed lam*T and the minimum is 0
+    for _ in range(20):
+        h = rng.integers(-5000, 5000, D).astype(np.int32)
+        m = oracle.message(h, 64, 4)
+        assert m.min() == 0 and m.max() <= 256
+
+
+# ---------------------------------------------------------------- energy
+def test_energy_hand_case():
+    e = GOLDEN["energy"][0]
+    got = oracle.energy(np.array(e["cost"], np.int16), np.array(e["disparity"], np.int16), e["lambda"], e["trunc"])
+    assert got == e["energy"]
+    bad = np.array(e["disparity"], np.int16)
+    bad[0, 0] = 3
+    assert oracle.energy(np.array(e["cost"], np.int16), bad, e["lambda"], e["trunc"]) == -(2**63)
+
+
+# ---------------------------------------------------------------- BP on chains = dynamic programming
+def _chain_minmarginals(C, lam, T):
+    """Forward-backward min-sum DP on a chain (textbook), returns min-marginals [n, D]."""
+    n, D = C.shape
+    V = np.array([[lam * min(abs(a - b), T) for b in range(D)] for a in range(D)], np.int64)
+    a = np.zeros((n, D), np.int64)
+    b = np.zeros((n, D), np.int64)
+    a[0] = C[0]
+    for i in range(1, n):
+        a[i] = C[i] + np.min(a[i - 1][:, None] + V, axis=0)
+    b[n - 1] = 0
+    for i in range(n - 2, -1, -1):
+        b[i] = np.min(V + (C[i + 1] + b[i + 1])[None, :], axis=1)
+    return a + b
+
+
+@pytest.mark.parametrize("orient", ["row", "col"])
+@pytest.mark.parametrize("scales", [1, 3])
+def test_chain_bp_equals_dp(orient, scales):
+    rng = np.random.default_rng(10 + scales)
+    n, D, lam, T = 23, 9, 37, 3
+    C = rng.integers(0, 400, (n, D)).astype(np.int16)
+    cost = C[None] if orient == "row" else C[:, None]
+    iters = [2 * n + 4] + [5] * (scales - 1)
+    disp, msgs, _ = oracle.bp_solve(cost, scales, iters, lam, T)
+    belief = cost.astype(np.int64) + msgs.astype(np.int64).sum(0)
+    belief = belief.reshape(n, D)
+    mm = _chain_minmarginals(C.astype(np.int64), lam, T)
+    assert np.array_equal(belief - belief.min(1, keepdims=True), mm - mm.min(1, keepdims=True))
+    # labels: argmin of the min-marginals (smallest d on ties); energy = DP optimum
+    assert np.array_equal(disp.reshape(n), np.argmin(mm, 1))
+    if all(np.sum(mm[i] == mm[i].min()) == 1 for i in range(n)):
+        assert oracle.energy(cost, disp, lam, T) == mm[0].min()
+
+
+def test_tiny_chain_brute_force():
+    rng = np.random.default_rng(12)
+    n, D, lam, T = 6, 4, 23, 2
+    C = rng.integers(0, 100, (1, n, D)).astype(np.int16)
+    best = min(oracle.energy(C, np.array(lab, np.int16).reshape(1, n), lam, T)
+               for lab in itertools.product(range(D), repeat=n))
+    disp, _, _ = oracle.bp_solve(C, 1, [4 * n], lam, T, want_msgs=False)
+    assert oracle.energy(C, disp, lam, T) == best
+
+
+def test_tiny_loopy_grids_not_below_optimum():
+    rng = np.random.default_rng(13)
+    for (H, W, D) in [(2, 2, 3), (2, 3, 3), (3, 3, 2)]:
+        C = rng.integers(0, 60, (H, W, D)).astype(np.int16)
+        best = min(oracle.energy(C, np.array(lab, np.int16).reshape(H, W), 20, 2)
+                   for lab in itertools.product(range(D), repeat=H * W))
+        disp, _, _ = oracle.bp_solve(C, 1, [20], 20, 2, want_msgs=False)
+        assert oracle.energy(C, disp, 20, 2) >= best
+
+
+# ---------------------------------------------------------------- schedules
+def test_checkerboard_equals_jacobi_parity_chains():
+    """Half-step t of the in-place checkerboard = Jacobi iteration t+1 for senders of colour t&1."""
+    rng = np.random.default_rng(20)
+    H, W, D = 5, 6, 7
+    cost = rng.integers(0, 300, (H, W, D)).astype(np.int16)
+    init = rng.integers(0, 200, (4, H, W, D)).astype(np.int16)
+    ys, xs = np.mgrid[0:H, 0:W]
+    colour = (xs + ys) & 1
+    # slot k at pixel p holds the message from p's neighbour on side k; that sender's colour
+    # is the opposite of p's colour.
+    for t in range(0, 6):
+        cb = oracle.flat_checkerboard(cost, 64, 4, t + 1, init)
+        jc = oracle.flat_jacobi(cost, 64, 4, t + 1, init)
+        recv_colour = 1 - (t & 1)
+        mask = colour == recv_colour
+        for k in range(4):
+            # border slots are never written by either schedule
+            assert np.array_equal(cb[k][mask], jc[k][mask])
+
+
+# ---------------------------------------------------------------- hierarchy and skip modes
+def _synthetic(D=16, seed=1, H=24, W=32):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 600, (H, W, D)).astype(np.int16)
+
+
+def test_exact_skip_equals_plain():
+    cost = _synthetic()
+    d0, m0, s0 = oracle.bp_solve(cost, 3, [8, 8, 8], 64, 4, skip_mode=0)
+    d2, m2, s2 = oracle.bp_solve(cost, 3, [8, 8, 8], 64, 4, skip_mode=2)
+    assert np.array_equal(d0, d2) and np.array_equal(m0, m2)
+    assert s2["pixel_updates"] <= s0["pixel_updates"]
+
+
+def test_freeze_skip_is_deterministic_and_close():
+    from paper_1709_06509_amd import synth
+
+    p = synth.workload_pair("tiny")
+    cost = oracle.cost_volume(p["left"], p["right"], 16, 5)
+    d0, _, s0 = oracle.bp_solve(cost, 3, [8] * 3, 64, 4, skip_mode=0, want_msgs=False)
+    d1, _, s1 = oracle.bp_solve(cost, 3, [8] * 3, 64, 4, skip_mode=1, want_msgs=False)
+    d1b, _, _ = oracle.bp_solve(cost, 3, [8] * 3, 64, 4, skip_mode=1, want_msgs=False)
+    assert np.array_equal(d1, d1b)
+    e0, e1 = oracle.energy(cost, d0, 64, 4), oracle.energy(cost, d1, 64, 4)
+    assert abs(e1 - e0) <= 0.005 * e0
+    assert s1["pixel_updates"] < s0["pixel_updates"]
+    act = s1["active"][0][:8]
+    assert act[7] < act[1]  # most pixels stop being updated after a few half-steps
+
+
+def test_offset_invariance_flat_and_hierarchical():
+    cost = _synthetic(D=8, seed=3)
+    rng = np.random.default_rng(4)
+    off = rng.integers(-500, 500, cost.shape[:2] + (1,)).astype(np.int16)
+    for scales in (1, 3):
+        a = oracle.bp_solve(cost, scales, [6] * scales, 40, 3)
+        b = oracle.bp_solve(cost + off, scales, [6] * scales, 40, 3)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_degenerate_cases():
+    cost = _synthetic(D=8, seed=5)
+    # lambda = 0 or T = 0: messages vanish, winner-take-all on the data cost
+    for lam, T in [(0, 4), (64, 0)]:
+        d, m, _ = oracle.bp_solve(cost, 2, [4, 4], lam, T)
+        assert not m.any()
+        assert np.array_equal(d, np.argmin(cost, axis=2).astype(np.int16))
+    # D = 1: everything is zero
+    c1 = _synthetic(D=1, seed=6)
+    d, m, _ = oracle.bp_solve(c1, 2, [4, 4], 64, 4)
+    assert not d.any() and not m.any()
+    # constant cost: zero messages, disparity 0
+    d, m, _ = oracle.bp_solve(np.full((9, 10, 5), 42, np.int16), 3, [3, 3, 3], 64, 4)
+    assert not d.any() and not m.any()
+    # zero half-steps everywhere: winner-take-all on the data cost
+    d, m, _ = oracle.bp_solve(cost, 3, [0, 0, 0], 64, 4)
+    assert np.array_equal(d, np.argmin(cost, axis=2).astype(np.int16)) and not m.any()
+
+
+def test_warm_injection_of_own_state_reproduces_plain():
+    """Starting at scale L-2 from the messages plain BP had there reproduces plain BP."""
+    cost = _synthetic(D=8, seed=8, H=20, W=28)
+    L, iters = 3, [4, 4, 4]
+    d_plain, m_plain, _ = oracle.bp_solve(cost, L, iters, 50, 3)
+    # plain's initial messages at scale 1 = its scale-2 result copied to children:
+    # obtain the scale-2 result by solving the scale-1 problem only for scale 2's part.
+    c1 = oracle.pyramid_level(cost)
+    c2 = oracle.pyramid_level(c1)
+    _, m2, _ = oracle.bp_solve(c2, 1, [iters[2]], 50, 3)
+    H1, W1 = c1.shape[:2]
+    warm = np.zeros((4, H1, W1, 8), np.int16)
+    for k in range(4):
+        warm[k] = m2[k][np.arange(H1)[:, None] >> 1, np.arange(W1)[None, :] >> 1]
+    warm[0][:, 0] = 0
+    warm[1][:, W1 - 1] = 0
+    warm[2][0, :] = 0
+    warm[3][H1 - 1, :] = 0
+    d_w, m_w, _ = oracle.bp_solve(cost, L, iters, 50, 3, warm_msgs=warm)
+    assert np.array_equal(d_w, d_plain) and np.array_equal(m_w, m_plain)
+
+
+def test_stats_plain_counts():
+    cost = _synthetic(D=4, seed=9, H=5, W=7)
+    _, _, s = oracle.bp_solve(cost, 1, [3], 10, 2, want_msgs=False)
+    # colour-0 pixels of a 5x7 grid: 18, colour-1: 17; 4-edges: 5*6 + 4*7 = 58, each sending both ways
+    assert s["active"][0][:3].tolist() == [18, 17, 18]
+    assert s["pixel_updates"] == 53
+    # a half-step sends along every edge once in one direction: 58 messages per half-step
+    assert s["msg_updates"] == 3 * 58
+
+
+def test_freeze_rule_timing_on_flat_cost():
+    """Constant cost: every message is 0 at every update, so each pixel's second update
+    (half-step 2 or 3) is its first unchanged one.  With K = 2 it freezes right there;
+    with K = 4 it needs one more unchanged update; K counts half-steps."""
+    H, W = 5, 7  # 18 pixels of colour 0, 17 of colour 1
+    cost = np.full((H, W, 3), 9, np.int16)
+    _, _, s2 = oracle.bp_solve(cost, 1, [9], 64, 4, skip_mode=1, converge_iters=2, want_msgs=False)
+    assert s2["active"][0][:9].tolist() == [18, 17, 18, 17, 0, 0, 0, 0, 0]
+    _, _, s4 = oracle.bp_solve(cost, 1, [9], 64, 4, skip_mode=1, converge_iters=4, want_msgs=False)
+    assert s4["active"][0][:9].tolist() == [18, 17, 18, 17, 18, 17, 0, 0, 0]
+    # every scale starts with all pixels active again
+    _, _, s = oracle.bp_solve(np.full((8, 8, 3), 9, np.int16), 2, [5, 5], 64, 4, skip_mode=1, want_msgs=False)
+    assert s["active"][1][:5].tolist() == [8, 8, 8, 8, 0] and s["active"][0][:5].tolist() == [32, 32, 32, 32, 0]
