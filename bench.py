@@ -1,0 +1,189 @@
+"""Benchmark: stereo pairs/s of the whole GPU path on the production-shape workload.
+
+One step = one synthetic 384x288 pair (D = 16, 7x7 NCC window) through the correlation
+volume, the 4-scale x 10-half-step hierarchical solve with the converged-pixel freeze
+(K = 2), winner-take-all and the energy.  Inputs are resident in HBM before timing.
+
+Prints one JSON line.  Besides the headline pairs/s it reports message updates/s, the
+energy against plain BP on the same pair, the roofline of the dominant kernel (the
+half-step message update, timed with HIP events on its own stream) and the CPU
+checker's throughput on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "stereo pairs/s and Gmsg-updates/s at equal energy vs plain BP; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="production", choices=["production", "tiny", "large"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-checker sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-checker leg")
+    return ap.parse_args()
+
+
+def halfstep_bytes(stats, D, levels, skip):
+    """Algorithmic bytes of the half-step launches of one solve: 18*D per pixel update
+    (data term + 4 incoming messages read, 4 outgoing written, int16), plus 8*D for the
+    comparison with the previous outgoing messages where the freeze rule checks it."""
+    total = 0
+    for l in range(levels):
+        for t in range(min(stats["n_halfsteps"][l], 64)):
+            n = stats["active"][l][t]
+            total += 18 * D * n
+            if skip == 1 and t >= 2:
+                total += 8 * D * n
+            elif skip == 2:
+                total += 8 * D * n
+    return total
+
+
+def cpu_baseline(w, seconds):
+    import numpy as np  # noqa: F401
+
+    import oracle
+    from paper_1709_06509_amd import synth
+
+    p = synth.workload_pair(w["name"])
+    if w["rgb"]:
+        return None
+    iters = [w["iters"]] * w["num_scales"]
+    n, t0 = 0, time.perf_counter()
+    while True:
+        cost = oracle.cost_volume(p["left"], p["right"], w["num_disp"], w["window"], w["cost_scale"], w["cost_trunc"])
+        d, _, _ = oracle.bp_solve(cost, w["num_scales"], iters, w["lam"], w["trunc"], w["skip"], 2, want_msgs=False)
+        oracle.energy(cost, d, w["lam"], w["trunc"])
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 1000:
+            break
+    return {"value": n / el, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} full {w['width']}x{w['height']} pairs (cost volume + {w['num_scales']}x{w['iters']} "
+                      f"solve, skip={w['skip']} + energy), single-threaded, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1709_06509_amd import bpstereo as B
+    from paper_1709_06509_amd import synth
+
+    w = dict(synth.WORKLOADS[args.workload])
+    w["name"] = args.workload
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = synth.workload_pair(args.workload)
+    D, L, iters = w["num_disp"], w["num_scales"], [w["iters"]] * w["num_scales"]
+    H, W = w["height"], w["width"]
+    rgb = w["rgb"]
+    left = torch.from_numpy(p["left"]).to(dev)
+    right = torch.from_numpy(p["right"]).to(dev)
+    gl = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    gr = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    cost = torch.empty((H, W, D), dtype=torch.int16, device=dev)
+    disp = torch.empty((H, W), dtype=torch.int16, device=dev)
+    energy = torch.empty(1, dtype=torch.int64, device=dev)
+    params = B.make_params(D, L, iters, w["lam"], w["trunc"], w["skip"], 2)
+    ws = torch.empty(B.bp_workspace_bytes(W, H, params), dtype=torch.uint8, device=dev)
+    ews = torch.empty(B.bp_energy_workspace_bytes(W, H), dtype=torch.uint8, device=dev)
+    ctx = B.Context()
+
+    def step():
+        if rgb:
+            B.stereo_luma(left, gl)
+            B.stereo_luma(right, gr)
+            a, b = gl, gr
+        else:
+            a, b = left, right
+        B.stereo_cost_volume(a, b, D, w["window"], w["cost_scale"], w["cost_trunc"], out=cost)
+        B.bp_hierarchical_solve(cost, L, iters, w["lam"], w["trunc"], w["skip"], 2, ctx=ctx, workspace=ws,
+                                disparity=disp)
+        B.bp_energy(cost, disp, w["lam"], w["trunc"], workspace=ews, out=energy)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timing = ctx.take_timing()
+    ctx.set_timing(False)
+
+    # counters and energies (outside the timed region; the solve is deterministic)
+    _, _, st = B.bp_hierarchical_solve(cost, L, iters, w["lam"], w["trunc"], w["skip"], 2, want_stats=True)
+    e_run = int(B.bp_energy(cost, disp, w["lam"], w["trunc"]).cpu()[0])
+    d_plain, _, st_plain = B.bp_hierarchical_solve(cost, L, iters, w["lam"], w["trunc"], 0, 2, want_stats=True)
+    e_plain = int(B.bp_energy(cost, d_plain, w["lam"], w["trunc"]).cpu()[0])
+
+    ms_per_step = 1000.0 * elapsed / args.steps
+    pairs_per_s = args.steps / elapsed
+    hs_bytes = halfstep_bytes(st, D, L, w["skip"])
+    n_launch = timing["halfstep_launches"] // args.steps if args.steps else 0
+    avg_launch_s = timing["halfstep_ms"] / 1000.0 / max(1, timing["halfstep_launches"])
+    bytes_per_launch = hs_bytes / max(1, n_launch)
+    achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": pairs_per_s,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int16",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} {W}x{H} D={D}, {w['window']}x{w['window']} NCC, "
+                               f"{L} scales x {w['iters']} half-steps, lambda={w['lam']} T={w['trunc']}, "
+                               f"skip={w['skip']} (K=2), seed={w['seed']}",
+                   "pairs_per_step": 1},
+        "gmsg_updates_per_s": st["msg_updates"] * pairs_per_s / 1e9,
+        "effective_gmsg_updates_per_s": st_plain["msg_updates"] * pairs_per_s / 1e9,
+        "energy": e_run,
+        "energy_plain": e_plain,
+        "energy_ratio_vs_plain": e_run / e_plain if e_plain else None,
+        "msg_updates_per_pair": st["msg_updates"],
+        "msg_updates_per_pair_plain": st_plain["msg_updates"],
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_halfstep (message update, all scales)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": avg_launch_s * 1e6,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "launches_per_step": n_launch,
+        },
+        "halfstep_share_of_step": (timing["halfstep_ms"] / args.steps) / ms_per_step if ms_per_step else None,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

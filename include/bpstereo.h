@@ -1,0 +1,167 @@
+/*
+ * bpstereo — dense stereo correspondence on MI355X (gfx950): a normalised-cross-
+ * correlation volume followed by hierarchical, fast-converging min-sum loopy belief
+ * propagation on the 4-connected pixel grid.
+ *
+ * Method: "A LBP Based Correspondence Identification Scheme for Multi-view Sensing
+ * Network" (arXiv:1709.06509).  The labelling d minimises E(d) = E_D(d) + E_S(d)
+ * (section "Approach Description"); E_D comes from the correlation volume (Abstract;
+ * "Correlation volume computation"); E_S is the jump cost between 4-neighbours, here
+ * truncated linear lambda*min(|d_p - d_q|, T); messages are recomputed from a pixel's
+ * data term, its neighbours' previous messages and the jump cost, and only pixels
+ * that have not converged keep being updated ("Fast Converging BP"); the solve runs
+ * coarse to fine over a hierarchy of scales with the same process on every scale
+ * ("GPU Implementation").
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked [device] are HIP device memory; [host] are host memory.  The
+ *    caller owns all memory; the library never frees or keeps caller pointers.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it
+ *    asynchronously; the call returns once every launch is enqueued.
+ *  - Return 0 on success, or a negative BP_E_* code; the message of the last error on
+ *    the calling thread is bp_last_error().  Arguments are validated before anything is
+ *    launched: an invalid call enqueues nothing.  Errors raised later on the device
+ *    (none are expected from valid arguments) surface at the next synchronisation.
+ *  - Layouts: images uint8 [H][W] row-major, contiguous; cost volume int16
+ *    [H][W][D] (D fastest); messages int16 [4][H][W][D] with direction
+ *    k = 0 from-left, 1 from-right, 2 from-up, 3 from-down (slot k of pixel p holds the
+ *    message p received from its neighbour on side k; 0 where there is no neighbour).
+ */
+#ifndef BPSTEREO_H
+#define BPSTEREO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BP_OK 0
+#define BP_E_INVAL (-1)       /* an argument is out of range or inconsistent     */
+#define BP_E_NOMEM (-2)       /* a host-side allocation failed                    */
+#define BP_E_HIP (-3)         /* a HIP runtime call failed                        */
+#define BP_E_UNSUPPORTED (-4) /* valid but not supported by this build            */
+#define BP_E_WORKSPACE (-5)   /* the workspace is missing or too small            */
+
+/* Opaque per-caller state: kernel timing events.  Not thread-safe; use one per stream. */
+typedef struct bp_context bp_context;
+
+/* Solver parameters, passed [host]. */
+typedef struct {
+    int32_t num_disp;        /* D, 1..256 disparity levels                                   */
+    int32_t num_scales;      /* L, 1..8 scales; scale l+1 halves scale l (ceil)             */
+    int32_t iters[8];        /* half-steps per scale, [0] = finest, each 0..1024           */
+    int32_t lambda;          /* smoothness weight, 0..65535                                 */
+    int32_t trunc;           /* T, truncation of |d_p - d_q| in levels, >= 0                */
+    int32_t skip_mode;       /* 0 plain; 1 freeze converged pixels; 2 exact dirty-skip      */
+    int32_t converge_iters;  /* K for skip_mode 1, in half-steps: even, 2..64               */
+    const int16_t* warm_msgs; /* [device] nullable: [4][H_s][W_s][D] initial messages at
+                                 scale s = L-2 (needs L >= 2); the solve then skips scale
+                                 L-1 and starts at s.  Slots without a neighbour are ignored. */
+} bp_params;
+
+/* Counters of one solve, returned [host]. */
+typedef struct {
+    int64_t msg_updates;    /* directed messages recomputed, all scales                  */
+    int64_t pixel_updates;  /* pixel updates (each recomputes all its outgoing messages) */
+    int32_t n_halfsteps[8]; /* half-steps run per scale                                  */
+    int32_t active[8][64];  /* pixels recomputed in half-step t of scale l (t < 64)      */
+} bp_stats;
+
+/* Device time of the message-update launches since the last bp_context_take_timing. */
+typedef struct {
+    double halfstep_ms;         /* summed device time of the half-step kernels          */
+    int64_t halfstep_launches;  /* number of half-step launches measured                */
+    int64_t halfstep_pixel_updates_max; /* pixels those launches could update (all active) */
+} bp_timing;
+
+int32_t bp_context_create(bp_context** out);
+int32_t bp_context_destroy(bp_context* ctx);
+
+/*
+ * When `on` is non-zero, every later bp_hierarchical_solve on this context records a HIP
+ * event pair around each half-step launch, on the stream the launch goes to.
+ */
+int32_t bp_context_set_timing(bp_context* ctx, int32_t on);
+/* Synchronises on the recorded events, returns their sums in *out [host] and clears them. */
+int32_t bp_context_take_timing(bp_context* ctx, bp_timing* out);
+
+/*
+ * Luma of an interleaved RGB image: Y = (77 R + 150 G + 29 B + 128) >> 8 (integer
+ * BT.601 weights).  rgb [device] uint8 [H][W][3]; luma [device] uint8 [H][W].
+ * The method takes one channel per view (Abstract: views of a regular RGB camera).
+ */
+int32_t stereo_luma(const uint8_t* rgb, int32_t width, int32_t height, uint8_t* luma, void* stream);
+
+/*
+ * Correlation volume (Abstract; "Correlation volume computation").  For every pixel
+ * (x, y) of the left view and disparity d in [0, D): zero-mean normalised cross-
+ * correlation of the window x window patch around left(x, y) with the patch around
+ * right(x - d, y), windows clamped to the image edge.  A patch without variance has
+ * correlation 0.  The data cost is round-half-up(cost_scale * (1 - ncc)) clamped to
+ * [0, cost_trunc], decided exactly (no floating-point rounding on the way); where
+ * x - d < 0 the cost is cost_trunc and the reported ncc is -2.
+ *   left, right   [device] uint8 [H][W]
+ *   width, height 1..16384 each
+ *   num_disp      D, 1..256;  window odd, 1..13;  cost_scale 1..4096;  cost_trunc 0..32767
+ *   cost          [device] int16 [H][W][D] output
+ *   ncc_or_null   [device] float [H][W][D] output, or NULL
+ */
+int32_t stereo_cost_volume(const uint8_t* left, const uint8_t* right, int32_t width, int32_t height,
+                           int32_t num_disp, int32_t window, int32_t cost_scale, int32_t cost_trunc,
+                           int16_t* cost, float* ncc_or_null, void* stream);
+
+/* Bytes of device workspace bp_hierarchical_solve needs for this shape; 0 if invalid. */
+size_t bp_workspace_bytes(int32_t width, int32_t height, const bp_params* params);
+
+/*
+ * Hierarchical min-sum BP ("Fast Converging BP"; "GPU Implementation").
+ *  - Scale l+1 data cost: sum of the (up to 4) children's costs minus its minimum over d,
+ *    saturated to 32767.  Scale sizes: W_{l+1} = ceil(W_l / 2).
+ *  - The coarsest scale starts from zero messages; each finer scale starts from its
+ *    parent's messages in the same direction.
+ *  - Half-step t of a scale updates the pixels with (x + y) & 1 == t & 1: each computes
+ *    H = C + sum of incoming messages and, for each neighbour q, the message
+ *    m(d) = min_d' [H(d') - M_q(d') + lambda*min(|d - d'|, T)] minus its minimum,
+ *    saturated to int16, stored in q's slot.
+ *  - skip_mode 1: after a pixel's update at half-step t >= 2 leaves every outgoing message
+ *    unchanged K/2 times in a row, it is no longer updated on that scale.
+ *    skip_mode 2: a pixel is recomputed only if an incoming message changed since its
+ *    last update (same result as plain).
+ *  - Output disparity = argmin_d of C + sum of incoming messages at the finest scale,
+ *    smallest d on ties.
+ *   cost           [device] int16 [H][W][D], any values
+ *   workspace      [device] at least bp_workspace_bytes(...) bytes, 256-byte aligned;
+ *                  its content on entry does not matter; one solve at a time per workspace
+ *   disparity      [device] int16 [H][W] output
+ *   final_msgs_or_null [device] int16 [4][H][W][D] output: finest-scale messages, or NULL
+ *   stats_or_null  [host] if non-NULL the call synchronises the stream and fills it
+ */
+int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32_t width, int32_t height,
+                              const bp_params* params, void* workspace, size_t workspace_bytes,
+                              int16_t* disparity, int16_t* final_msgs_or_null, bp_stats* stats_or_null,
+                              void* stream);
+
+/* Bytes of device workspace bp_energy needs (a fixed small amount). */
+size_t bp_energy_workspace_bytes(int32_t width, int32_t height);
+
+/*
+ * Energy E(d) = E_D(d) + E_S(d) ("Approach Description"):
+ * sum_p cost(p, d_p) + lambda * sum over 4-neighbour pairs of min(|d_p - d_q|, trunc).
+ *   cost       [device] int16 [H][W][D];  disparity [device] int16 [H][W]
+ *   energy     [device] int64, 1 element, output; INT64_MIN if any disparity lies
+ *              outside [0, D) (those pixels are never read out of bounds)
+ *   workspace  [device] at least bp_energy_workspace_bytes(...) bytes
+ */
+int32_t bp_energy(const int16_t* cost, const int16_t* disparity, int32_t width, int32_t height,
+                  int32_t num_disp, int32_t lambda, int32_t trunc, int64_t* energy, void* workspace,
+                  size_t workspace_bytes, void* stream);
+
+/* Message of the last failed call on this thread ("" if none); valid until the next call. */
+const char* bp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -72,6 +72,10 @@ def _load():
             fn.argtypes = [_i16p, _i32, _i32, _i32, _i32, _i32, _i32, _i16p, _i16p]
             fn.restype = ctypes.c_int32
         lib.oracle_wta.argtypes = [_i16p, _i16p, _i32, _i32, _i32, _i16p]
+        lib.oracle_message_at.argtypes = [_i16p, _i16p] + [_i32] * 8 + [_i16p]
+        lib.oracle_message_at.restype = ctypes.c_int32
+        lib.oracle_wta_at.argtypes = [_i16p, _i16p] + [_i32] * 5
+        lib.oracle_wta_at.restype = ctypes.c_int32
         lib.oracle_bp_energy.argtypes = [_i16p, _i16p, _i32, _i32, _i32, _i32, _i32]
         lib.oracle_bp_energy.restype = ctypes.c_int64
         _lib = lib
@@ -202,3 +206,18 @@ def energy(cost, disparity, lam, trunc):
     cost, disparity = _c(cost, np.int16), _c(disparity, np.int16)
     H, W, D = cost.shape
     return int(_load().oracle_bp_energy(_p(cost, _i16p), _p(disparity, _i16p), W, H, D, lam, trunc))
+
+
+def message_at(cost, msgs, lam, trunc, x, y, k):
+    """Message pixel (x, y) sends to its neighbour on side k, from the state (cost, msgs)."""
+    cost, msgs = _c(cost, np.int16), _c(msgs, np.int16)
+    H, W, D = cost.shape
+    out = np.empty(D, np.int16)
+    rc = _load().oracle_message_at(_p(cost, _i16p), _p(msgs, _i16p), W, H, D, lam, trunc, x, y, k, _p(out, _i16p))
+    return out if rc == 0 else None
+
+
+def wta_at(cost, msgs, x, y):
+    cost, msgs = _c(cost, np.int16), _c(msgs, np.int16)
+    H, W, D = cost.shape
+    return int(_load().oracle_wta_at(_p(cost, _i16p), _p(msgs, _i16p), W, H, D, x, y))

@@ -368,9 +368,9 @@ int32_t oracle_bp_solve(const int16_t* cost, int32_t W, int32_t H, const oracle_
     if (!valid_common(W, H, D, p->lambda, p->trunc) || L < 1 || L > 8 || p->skip_mode < 0 ||
         p->skip_mode > 2)
         return -1;
-    if (p->skip_mode == 1 && (p->converge_iters < 2 || (p->converge_iters & 1))) return -1;
+    if (p->skip_mode == 1 && (p->converge_iters < 2 || p->converge_iters > 64 || (p->converge_iters & 1))) return -1;
     if (p->warm_msgs && L < 2) return -1;
-    for (int l = 0; l < L; ++l) if (p->iters[l] < 0 || p->iters[l] > 64) return -1;
+    for (int l = 0; l < L; ++l) if (p->iters[l] < 0 || p->iters[l] > 1024) return -1;
 
     int Ws[8], Hs[8];
     Ws[0] = W; Hs[0] = H;
@@ -446,4 +446,41 @@ int32_t oracle_bp_solve(const int16_t* cost, int32_t W, int32_t H, const oracle_
     free(Hb); free(hb); free(mb);
     for (int l = 1; l < L; ++l) free(C[l]);
     return 0;
+}
+
+/*
+ * ---- sampled checks at full size ----
+ * The message pixel (x,y) sends to its neighbour on side k, recomputed from a given
+ * message state (the O5 update of one pixel, read-only).  Returns 0, or -1 if there is
+ * no neighbour on that side.
+ */
+int32_t oracle_message_at(const int16_t* cost, const int16_t* msgs, int32_t W, int32_t H, int32_t D,
+                          int32_t lambda, int32_t T, int32_t x, int32_t y, int32_t k, int16_t* out)
+{
+    int qx, qy;
+    if (!neighbour(k, x, y, W, H, &qx, &qy)) return -1;
+    int32_t* h = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
+    const int16_t* c = cost + ((size_t)y * W + x) * D;
+    for (int d = 0; d < D; ++d) h[d] = c[d];
+    for (int j = 0; j < 4; ++j)
+        if (neighbour(j, x, y, W, H, &qx, &qy) && j != k)
+            for (int d = 0; d < D; ++d) h[d] += msgs[(((size_t)j * H + y) * W + x) * D + d];
+    oracle_message(h, D, lambda, T, out);
+    free(h);
+    return 0;
+}
+
+/* Winner-take-all of one pixel (O7). */
+int32_t oracle_wta_at(const int16_t* cost, const int16_t* msgs, int32_t W, int32_t H, int32_t D, int32_t x,
+                      int32_t y)
+{
+    int64_t best = INT64_MAX;
+    int bd = 0, qx, qy;
+    for (int d = 0; d < D; ++d) {
+        int64_t b = cost[((size_t)y * W + x) * D + d];
+        for (int k = 0; k < 4; ++k)
+            if (neighbour(k, x, y, W, H, &qx, &qy)) b += msgs[(((size_t)k * H + y) * W + x) * D + d];
+        if (b < best) { best = b; bd = d; }
+    }
+    return bd;
 }

@@ -27,7 +27,7 @@ extern "C" {
 typedef struct {
     int32_t num_disp;        /* D */
     int32_t num_scales;      /* L */
-    int32_t iters[8];        /* half-steps per scale, [0] = finest */
+    int32_t iters[8];        /* half-steps per scale, [0] = finest, 0..1024 */
     int32_t lambda;          /* smoothness weight */
     int32_t trunc;           /* truncation T, in disparity levels */
     int32_t skip_mode;       /* 0 plain, 1 freeze converged pixels, 2 exact dirty-skip */
@@ -70,6 +70,12 @@ int32_t oracle_bp_flat_jacobi(const int16_t* cost, int32_t width, int32_t height
 
 void oracle_wta(const int16_t* cost, const int16_t* msgs, int32_t width, int32_t height,
                 int32_t num_disp, int16_t* disparity);
+
+int32_t oracle_message_at(const int16_t* cost, const int16_t* msgs, int32_t width, int32_t height,
+                          int32_t num_disp, int32_t lambda, int32_t trunc, int32_t x, int32_t y, int32_t k,
+                          int16_t* out);
+int32_t oracle_wta_at(const int16_t* cost, const int16_t* msgs, int32_t width, int32_t height, int32_t num_disp,
+                      int32_t x, int32_t y);
 
 int64_t oracle_bp_energy(const int16_t* cost, const int16_t* disparity, int32_t width, int32_t height,
                          int32_t num_disp, int32_t lambda, int32_t trunc);

@@ -1,0 +1,241 @@
+"""Python binding of the C ABI in include/bpstereo.h (libbpstereo.so, built in-tree).
+
+Argument marshalling only: tensors are checked for device, dtype, layout and shape,
+outputs and workspaces are allocated with PyTorch on the current device, and each call
+goes straight to the library on torch's current stream.  Every step of the method runs
+in the library's HIP kernels; if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbpstereo.so")
+
+BP_OK, BP_E_INVAL, BP_E_NOMEM, BP_E_HIP, BP_E_UNSUPPORTED, BP_E_WORKSPACE = 0, -1, -2, -3, -4, -5
+
+
+class BPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bpstereo error {code}: {msg}")
+        self.code = code
+
+
+class BPParams(ctypes.Structure):
+    _fields_ = [
+        ("num_disp", ctypes.c_int32),
+        ("num_scales", ctypes.c_int32),
+        ("iters", ctypes.c_int32 * 8),
+        ("lambda_", ctypes.c_int32),
+        ("trunc", ctypes.c_int32),
+        ("skip_mode", ctypes.c_int32),
+        ("converge_iters", ctypes.c_int32),
+        ("warm_msgs", ctypes.c_void_p),
+    ]
+
+
+class BPStats(ctypes.Structure):
+    _fields_ = [
+        ("msg_updates", ctypes.c_int64),
+        ("pixel_updates", ctypes.c_int64),
+        ("n_halfsteps", ctypes.c_int32 * 8),
+        ("active", (ctypes.c_int32 * 64) * 8),
+    ]
+
+
+class BPTiming(ctypes.Structure):
+    _fields_ = [
+        ("halfstep_ms", ctypes.c_double),
+        ("halfstep_launches", ctypes.c_int64),
+        ("halfstep_pixel_updates_max", ctypes.c_int64),
+    ]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() first")
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.bp_last_error.restype = ctypes.c_char_p
+        lib.bp_context_create.argtypes = [ctypes.POINTER(_vp)]
+        lib.bp_context_destroy.argtypes = [_vp]
+        lib.bp_context_set_timing.argtypes = [_vp, _i32]
+        lib.bp_context_take_timing.argtypes = [_vp, ctypes.POINTER(BPTiming)]
+        lib.stereo_luma.argtypes = [_vp, _i32, _i32, _vp, _vp]
+        lib.stereo_cost_volume.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp]
+        lib.bp_workspace_bytes.argtypes = [_i32, _i32, ctypes.POINTER(BPParams)]
+        lib.bp_workspace_bytes.restype = ctypes.c_size_t
+        lib.bp_hierarchical_solve.argtypes = [_vp, _vp, _i32, _i32, ctypes.POINTER(BPParams), _vp, ctypes.c_size_t,
+                                              _vp, _vp, ctypes.POINTER(BPStats), _vp]
+        lib.bp_energy_workspace_bytes.argtypes = [_i32, _i32]
+        lib.bp_energy_workspace_bytes.restype = ctypes.c_size_t
+        lib.bp_energy.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t, _vp]
+        for name in ("bp_context_create", "bp_context_destroy", "bp_context_set_timing", "bp_context_take_timing",
+                     "stereo_luma", "stereo_cost_volume", "bp_hierarchical_solve", "bp_energy"):
+            getattr(lib, name).restype = ctypes.c_int32
+        _lib = lib
+    return _lib
+
+
+def library():
+    """The loaded ctypes library (loads it on first use)."""
+    return _load()
+
+
+def _check(rc):
+    if rc != BP_OK:
+        raise BPError(rc, _load().bp_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, ndim, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owner of a bp_context (timing events); one per stream."""
+
+    def __init__(self):
+        h = _vp()
+        _check(_load().bp_context_create(ctypes.byref(h)))
+        self.handle = h
+
+    def set_timing(self, on=True):
+        _check(_load().bp_context_set_timing(self.handle, 1 if on else 0))
+
+    def take_timing(self):
+        t = BPTiming()
+        _check(_load().bp_context_take_timing(self.handle, ctypes.byref(t)))
+        return {"halfstep_ms": t.halfstep_ms, "halfstep_launches": t.halfstep_launches,
+                "halfstep_pixel_updates_max": t.halfstep_pixel_updates_max}
+
+    def close(self):
+        if self.handle:
+            _check(_load().bp_context_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stereo_luma(rgb, out=None, stream=None):
+    H, W, C = rgb.shape
+    if C != 3:
+        raise ValueError("rgb must be [H, W, 3]")
+    p = _dev(rgb, torch.uint8, 3, "rgb")
+    out = torch.empty((H, W), dtype=torch.uint8, device=rgb.device) if out is None else out
+    _check(_load().stereo_luma(p, W, H, _dev(out, torch.uint8, 2, "out"), _stream(stream)))
+    return out
+
+
+def stereo_cost_volume(left, right, num_disp, window, cost_scale=256, cost_trunc=1024, want_ncc=False, out=None,
+                       stream=None):
+    """Quantised NCC cost volume int16 [H, W, D] (and the float NCC if want_ncc)."""
+    H, W = left.shape
+    if tuple(right.shape) != (H, W):
+        raise ValueError("left and right must have the same shape")
+    lp, rp = _dev(left, torch.uint8, 2, "left"), _dev(right, torch.uint8, 2, "right")
+    cost = torch.empty((H, W, num_disp), dtype=torch.int16, device=left.device) if out is None else out
+    if tuple(cost.shape) != (H, W, num_disp):
+        raise ValueError("out has the wrong shape")
+    ncc = torch.empty((H, W, num_disp), dtype=torch.float32, device=left.device) if want_ncc else None
+    _check(_load().stereo_cost_volume(lp, rp, W, H, num_disp, window, cost_scale, cost_trunc,
+                                      _dev(cost, torch.int16, 3, "cost"),
+                                      _dev(ncc, torch.float32, 3, "ncc") if want_ncc else None, _stream(stream)))
+    return (cost, ncc) if want_ncc else cost
+
+
+def make_params(num_disp, num_scales, iters, lam, trunc, skip_mode=0, converge_iters=2, warm_msgs=None):
+    p = BPParams()
+    p.num_disp = num_disp
+    p.num_scales = num_scales
+    its = list(iters) if hasattr(iters, "__len__") else [int(iters)] * num_scales
+    for i in range(8):
+        p.iters[i] = its[i] if i < len(its) else 0
+    p.lambda_ = lam
+    p.trunc = trunc
+    p.skip_mode = skip_mode
+    p.converge_iters = converge_iters
+    p.warm_msgs = _dev(warm_msgs, torch.int16, 4, "warm_msgs").value if warm_msgs is not None else None
+    return p
+
+
+def bp_workspace_bytes(width, height, params):
+    return int(_load().bp_workspace_bytes(width, height, ctypes.byref(params)))
+
+
+def bp_hierarchical_solve(cost, num_scales, iters, lam, trunc, skip_mode=0, converge_iters=2, warm_msgs=None,
+                          want_msgs=False, want_stats=False, ctx=None, workspace=None, disparity=None, stream=None):
+    """Returns (disparity int16 [H, W], messages int16 [4, H, W, D] or None, stats dict or None)."""
+    H, W, D = cost.shape
+    cp = _dev(cost, torch.int16, 3, "cost")
+    if warm_msgs is not None:
+        hs, ws = H, W
+        for _ in range(num_scales - 2):
+            hs, ws = (hs + 1) // 2, (ws + 1) // 2
+        if tuple(warm_msgs.shape) != (4, hs, ws, D):
+            raise ValueError(f"warm_msgs must be [4, {hs}, {ws}, {D}] (scale {num_scales - 2}), got "
+                             f"{tuple(warm_msgs.shape)}")
+    p = make_params(D, num_scales, iters, lam, trunc, skip_mode, converge_iters, warm_msgs)
+    need = bp_workspace_bytes(W, H, p)
+    if need == 0:
+        raise BPError(BP_E_INVAL, "invalid solve parameters")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=cost.device)
+    disp = torch.empty((H, W), dtype=torch.int16, device=cost.device) if disparity is None else disparity
+    msgs = torch.empty((4, H, W, D), dtype=torch.int16, device=cost.device) if want_msgs else None
+    st = BPStats() if want_stats else None
+    _check(_load().bp_hierarchical_solve(ctx.handle if ctx is not None else None, cp, W, H, ctypes.byref(p),
+                                         ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                         _dev(disp, torch.int16, 2, "disparity"),
+                                         _dev(msgs, torch.int16, 4, "msgs") if want_msgs else None,
+                                         ctypes.byref(st) if want_stats else None, _stream(stream)))
+    stats = None
+    if want_stats:
+        stats = {"msg_updates": st.msg_updates, "pixel_updates": st.pixel_updates,
+                 "n_halfsteps": list(st.n_halfsteps),
+                 "active": [[st.active[l][t] for t in range(64)] for l in range(8)]}
+    return disp, msgs, stats
+
+
+def bp_energy_workspace_bytes(width, height):
+    return int(_load().bp_energy_workspace_bytes(width, height))
+
+
+def bp_energy(cost, disparity, lam, trunc, workspace=None, out=None, stream=None):
+    """E(d) as an int64 GPU tensor of one element (INT64_MIN if a disparity is out of range)."""
+    H, W, D = cost.shape
+    if tuple(disparity.shape) != (H, W):
+        raise ValueError("disparity must be [H, W]")
+    need = bp_energy_workspace_bytes(W, H)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=cost.device)
+    out = torch.empty(1, dtype=torch.int64, device=cost.device) if out is None else out
+    _check(_load().bp_energy(_dev(cost, torch.int16, 3, "cost"), _dev(disparity, torch.int16, 2, "disparity"), W, H,
+                             D, lam, trunc, _dev(out, torch.int64, 1, "energy"),
+                             ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream)))
+    return out

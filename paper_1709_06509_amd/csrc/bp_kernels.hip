@@ -1,0 +1,573 @@
+// Message-passing kernels of the hierarchical min-sum solve.
+//
+// Every kernel maps one pixel to G consecutive lanes of a wave64; lane g holds labels
+// [8g, 8g + 8) of that pixel in registers as int32.  Cross-label work (minimum, prefix
+// and suffix minima of the distance transform) runs across the G lanes with shuffles,
+// so no LDS is needed and every global access is a coalesced 16-byte vector.
+#include "internal.h"
+
+namespace bpst {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kBig = 1 << 29;      // value of a padded label (d >= D): never the minimum
+constexpr int kScanId = 1 << 30;   // identity of the min-scans
+
+__device__ __forceinline__ void unpack8(const int4 v, int o[8])
+{
+    o[0] = (int)(short)(v.x & 0xffff); o[1] = v.x >> 16;
+    o[2] = (int)(short)(v.y & 0xffff); o[3] = v.y >> 16;
+    o[4] = (int)(short)(v.z & 0xffff); o[5] = v.z >> 16;
+    o[6] = (int)(short)(v.w & 0xffff); o[7] = v.w >> 16;
+}
+
+__device__ __forceinline__ int4 pack8(const int o[8])
+{
+    int4 v;
+    v.x = (o[0] & 0xffff) | (o[1] << 16);
+    v.y = (o[2] & 0xffff) | (o[3] << 16);
+    v.z = (o[4] & 0xffff) | (o[5] << 16);
+    v.w = (o[6] & 0xffff) | (o[7] << 16);
+    return v;
+}
+
+__device__ __forceinline__ long long slot_of(int x, int y, int Wh)
+{
+    return (long long)(2 * y + ((x + y) & 1)) * Wh + (x >> 1);
+}
+
+template <int G>
+__device__ __forceinline__ int group_min(int v)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v = min(v, __shfl_xor(v, o, G));
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int group_excl_prefix_min(int v, int lane)
+{
+    if (G == 1) return kScanId;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        int t = __shfl_up(v, o, G);
+        if (lane >= o) v = min(v, t);
+    }
+    int e = __shfl_up(v, 1, G);
+    return lane == 0 ? kScanId : e;
+}
+
+template <int G>
+__device__ __forceinline__ int group_excl_suffix_min(int v, int lane)
+{
+    if (G == 1) return kScanId;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        int t = __shfl_down(v, o, G);
+        if (lane + o < G) v = min(v, t);
+    }
+    int e = __shfl_down(v, 1, G);
+    return lane == G - 1 ? kScanId : e;
+}
+
+// m(d) = min( min_d' h(d') + lambda*|d - d'|,  min h + lambda*T ) - min h, saturated.
+// The inner minimum is the lower envelope of cones: lambda*d + prefix-min of
+// (h - lambda*d) and -lambda*d + suffix-min of (h + lambda*d); integer min/+ are exact,
+// so the lane-then-group association gives the same value as any other order.
+template <int G>
+__device__ __forceinline__ void transform(const int h[8], int d0, int lam, int lam_t, int lane, int out[8])
+{
+    int hm = h[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) hm = min(hm, h[j]);
+    hm = group_min<G>(hm);
+    const int ld = lam * d0;
+    int pa[8], sb[8];
+    pa[0] = h[0] - ld;
+#pragma unroll
+    for (int j = 1; j < 8; ++j) pa[j] = min(pa[j - 1], h[j] - (ld + lam * j));
+    sb[7] = h[7] + ld + 7 * lam;
+#pragma unroll
+    for (int j = 6; j >= 0; --j) sb[j] = min(sb[j + 1], h[j] + ld + lam * j);
+    const int ep = group_excl_prefix_min<G>(pa[7], lane);
+    const int es = group_excl_suffix_min<G>(sb[0], lane);
+    const int cap = hm + lam_t;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        int F = min(pa[j], ep) + ld + lam * j;
+        int B = min(sb[j], es) - (ld + lam * j);
+        int f = min(min(F, B), cap) - hm;
+        out[j] = min(f, 32767);
+    }
+}
+
+struct ColourPix {
+    int x, y;
+    long long slot;
+    bool valid;
+};
+
+__device__ __forceinline__ ColourPix colour_pixel(long long gi, const Level lv, int colour)
+{
+    ColourPix p;
+    p.y = (int)(gi / lv.Wh);
+    int xi = (int)(gi - (long long)p.y * lv.Wh);
+    p.x = 2 * xi + ((colour ^ p.y) & 1);
+    p.valid = p.y < lv.H && p.x < lv.W;
+    p.slot = (long long)(2 * p.y + colour) * lv.Wh + xi;
+    return p;
+}
+
+// Pixel of slot index gi over both colours (gi == its slot).
+__device__ __forceinline__ ColourPix any_pixel(long long gi, const Level lv)
+{
+    ColourPix p;
+    int r = (int)(gi / lv.Wh);
+    int xi = (int)(gi - (long long)r * lv.Wh);
+    p.y = r >> 1;
+    p.x = 2 * xi + (((r & 1) ^ p.y) & 1);
+    p.valid = p.y < lv.H && p.x < lv.W;
+    p.slot = gi;
+    return p;
+}
+
+__global__ void k_zero_stats(DevStats* s)
+{
+    int* w = reinterpret_cast<int*>(s);
+    const int n = (int)(sizeof(DevStats) / sizeof(int));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = 0;
+}
+
+template <int G, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_prep_level0(const int16_t* __restrict__ user,
+                                                           int16_t* __restrict__ c0, Level lv, int D)
+{
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const long long gi = t / G;
+    const int lane = (int)(t & (G - 1));
+    if (gi >= lv.slots()) return;
+    ColourPix p = any_pixel(gi, lv);
+    if (!p.valid) return;
+    const int d0 = lane * 8;
+    const int16_t* src = user + ((long long)p.y * lv.W + p.x) * D + d0;
+    int v[8];
+    if (VEC) {
+        if (d0 < D) unpack8(*reinterpret_cast<const int4*>(src), v);
+        else for (int j = 0; j < 8; ++j) v[j] = 0;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (d0 + j < D) ? (int)src[j] : 0;
+    }
+    *reinterpret_cast<int4*>(c0 + gi * (8 * G) + d0) = pack8(v);
+}
+
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_pyramid(const int16_t* __restrict__ fine, Level lf,
+                                                       int16_t* __restrict__ coarse, Level lc, int D)
+{
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const long long gi = t / G;
+    const int lane = (int)(t & (G - 1));
+    const bool in = gi < lc.slots();
+    ColourPix p = any_pixel(in ? gi : 0, lc);
+    const bool valid = in && p.valid;
+    const int d0 = lane * 8;
+    int s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                int x = 2 * p.x + a, y = 2 * p.y + b;
+                if (x < lf.W && y < lf.H) {
+                    int v[8];
+                    unpack8(*reinterpret_cast<const int4*>(fine + slot_of(x, y, lf.Wh) * (8 * G) + d0), v);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) s[j] += v[j];
+                }
+            }
+    }
+    int mn = kBig;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) if (d0 + j < D) mn = min(mn, s[j]);
+    mn = group_min<G>(mn);
+    int o[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = (d0 + j < D) ? min(s[j] - mn, 32767) : 0;
+    if (valid) *reinterpret_cast<int4*>(coarse + gi * (8 * G) + d0) = pack8(o);
+}
+
+// Start a scale: copy each pixel's parent messages (zero for a missing neighbour or for
+// the coarsest scale) and reset the skip state.
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_init(const int16_t* __restrict__ parent, Level lp,
+                                                    long long pvol, int16_t* __restrict__ msgs, Level lv,
+                                                    long long vol, uint8_t* sa, uint8_t* sb, int mode)
+{
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const long long gi = t / G;
+    const int lane = (int)(t & (G - 1));
+    if (gi >= lv.slots()) return;
+    ColourPix p = any_pixel(gi, lv);
+    if (!p.valid) return;
+    const int d0 = lane * 8;
+    const bool has[4] = {p.x > 0, p.x < lv.W - 1, p.y > 0, p.y < lv.H - 1};
+    const long long ps = parent ? slot_of(p.x >> 1, p.y >> 1, lp.Wh) : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int4 v = make_int4(0, 0, 0, 0);
+        if (parent && has[k]) v = *reinterpret_cast<const int4*>(parent + k * pvol + ps * (8 * G) + d0);
+        *reinterpret_cast<int4*>(msgs + k * vol + gi * (8 * G) + d0) = v;
+    }
+    if (lane == 0) {
+        if (mode == 1) { sa[gi] = 1; sb[gi] = 0; }
+        if (mode == 2) sa[gi] = 1;
+    }
+}
+
+// Start scale s from caller-given messages [4][H][W][D].
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_import(const int16_t* __restrict__ warm, int16_t* __restrict__ msgs,
+                                                      Level lv, long long vol, int D, uint8_t* sa, uint8_t* sb,
+                                                      int mode)
+{
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const long long gi = t / G;
+    const int lane = (int)(t & (G - 1));
+    if (gi >= lv.slots()) return;
+    ColourPix p = any_pixel(gi, lv);
+    if (!p.valid) return;
+    const int d0 = lane * 8;
+    const bool has[4] = {p.x > 0, p.x < lv.W - 1, p.y > 0, p.y < lv.H - 1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int v[8];
+        const int16_t* src = warm + (((long long)k * lv.H + p.y) * lv.W + p.x) * D + d0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (has[k] && d0 + j < D) ? (int)src[j] : 0;
+        *reinterpret_cast<int4*>(msgs + k * vol + gi * (8 * G) + d0) = pack8(v);
+    }
+    if (lane == 0) {
+        if (mode == 1) { sa[gi] = 1; sb[gi] = 0; }
+        if (mode == 2) sa[gi] = 1;
+    }
+}
+
+// One half-step: every pixel of colour a.colour (that is still being updated) sends a
+// new message to each of its neighbours.  Reads only slots of its own colour, writes only
+// slots of the other colour, so the in-place update is race-free.
+template <int G, int MODE>
+__global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
+{
+    constexpr int Dp = 8 * G;
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const long long gi = t / G;
+    const int lane = (int)(t & (G - 1));
+    const bool in = gi < (long long)a.lv.H * a.lv.Wh;
+    ColourPix p = colour_pixel(in ? gi : 0, a.lv, a.colour);
+    const bool valid = in && p.valid;
+    const int W = a.lv.W, H = a.lv.H, Wh = a.lv.Wh;
+    const bool has[4] = {p.x > 0, p.x < W - 1, p.y > 0, p.y < H - 1};
+    const long long nb[4] = {
+        (long long)(2 * p.y + 1 - a.colour) * Wh + ((p.x - 1) >> 1),
+        (long long)(2 * p.y + 1 - a.colour) * Wh + ((p.x + 1) >> 1),
+        (long long)(2 * (p.y - 1) + 1 - a.colour) * Wh + (p.x >> 1),
+        (long long)(2 * (p.y + 1) + 1 - a.colour) * Wh + (p.x >> 1)};
+    bool act = valid;
+    if (MODE != 0) act = act && a.state_a[p.slot] != 0;
+    const int d0 = lane * 8;
+    int Hs[8], m[4][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Hs[j] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) m[k][j] = 0;
+    if (act) {
+        unpack8(*reinterpret_cast<const int4*>(a.cost + p.slot * Dp + d0), Hs);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (has[k]) {
+                unpack8(*reinterpret_cast<const int4*>(a.msgs + k * a.vol + p.slot * Dp + d0), m[k]);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) Hs[j] += m[k][j];
+            }
+    }
+    if (MODE == 2 && act && lane == 0) a.state_a[p.slot] = 0;
+    const bool check = (MODE == 2) || (MODE == 1 && a.t >= 2);
+    bool all_eq = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int h[8], o[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) h[j] = (d0 + j < a.D) ? Hs[j] - m[k][j] : kBig;
+        transform<G>(h, d0, a.lambda, a.lam_t, lane, o);
+        bool store = act && has[k];
+        int16_t* dst = a.msgs + (k ^ 1) * a.vol + nb[k] * Dp + d0;
+        if (check) {
+            int old[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (store) unpack8(*reinterpret_cast<const int4*>(dst), old);
+            int e = 1;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) if (d0 + j < a.D && old[j] != o[j]) e = 0;
+            e = group_min<G>(e);
+            if (store && !e) all_eq = false;
+            if (e) store = false;
+            if (MODE == 2 && store && lane == 0) a.state_a[nb[k]] = 1;
+        }
+        if (store) *reinterpret_cast<int4*>(dst) = pack8(o);
+    }
+    if (MODE == 1 && act && a.t >= 2 && lane == 0) {
+        int s = all_eq ? (int)a.state_b[p.slot] + 1 : 0;
+        a.state_b[p.slot] = (uint8_t)s;
+        if (2 * s >= a.K) a.state_a[p.slot] = 0;
+    }
+    // counters: one atomic per wave
+    const bool lead = act && lane == 0;
+    const unsigned long long bl = __ballot(lead);
+    const int npix = __popcll(bl);
+    int nmsg = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) nmsg += __popcll(__ballot(lead && has[k]));
+    if ((threadIdx.x & 63) == 0 && npix) {
+        atomicAdd(&a.stats->pixel_updates, (unsigned long long)npix);
+        atomicAdd(&a.stats->msg_updates, (unsigned long long)nmsg);
+        if (a.t < kStatHalfsteps) atomicAdd(&a.stats->active[a.level][a.t], npix);
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_wta(const int16_t* __restrict__ c0, const int16_t* __restrict__ msgs,
+                                                   long long vol, Level lv, int D, int16_t* __restrict__ disp)
+{
+    constexpr int Dp = 8 * G;
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const long long gi = t / G;
+    const int lane = (int)(t & (G - 1));
+    const bool in = gi < lv.slots();
+    ColourPix p = any_pixel(in ? gi : 0, lv);
+    const bool valid = in && p.valid;
+    const int d0 = lane * 8;
+    const bool has[4] = {p.x > 0, p.x < lv.W - 1, p.y > 0, p.y < lv.H - 1};
+    int b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (valid) {
+        unpack8(*reinterpret_cast<const int4*>(c0 + gi * Dp + d0), b);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (has[k]) {
+                int v[8];
+                unpack8(*reinterpret_cast<const int4*>(msgs + k * vol + gi * Dp + d0), v);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) b[j] += v[j];
+            }
+    }
+    // key = belief * 256 + d: the minimum key is the smallest d among the minimal beliefs
+    int key = 0x7fffffff;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) if (d0 + j < D) key = min(key, b[j] * 256 + d0 + j);
+    key = group_min<G>(key);
+    if (valid && lane == 0) disp[(long long)p.y * lv.W + p.x] = (int16_t)(key & 255);
+}
+
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_export(const int16_t* __restrict__ msgs, long long vol, Level lv,
+                                                      int D, int16_t* __restrict__ out)
+{
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const long long gi = t / G;
+    const int lane = (int)(t & (G - 1));
+    if (gi >= lv.slots()) return;
+    ColourPix p = any_pixel(gi, lv);
+    if (!p.valid) return;
+    const int d0 = lane * 8;
+    for (int k = 0; k < 4; ++k) {
+        int v[8];
+        unpack8(*reinterpret_cast<const int4*>(msgs + k * vol + gi * (8 * G) + d0), v);
+        int16_t* dst = out + (((long long)k * lv.H + p.y) * lv.W + p.x) * D + d0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) if (d0 + j < D) dst[j] = (int16_t)v[j];
+    }
+}
+
+constexpr int kEnergyBlocks = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_energy_partial(const int16_t* __restrict__ cost,
+                                                              const int16_t* __restrict__ disp, int W, int H,
+                                                              int D, int lam, int T, long long* part, int* bad)
+{
+    __shared__ long long red[kThreads];
+    __shared__ int anybad;
+    if (threadIdx.x == 0) anybad = 0;
+    __syncthreads();
+    long long e = 0;
+    int mybad = 0;
+    const long long n = (long long)W * H;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+        const int y = (int)(i / W), x = (int)(i - (long long)y * W);
+        const int dp = disp[i];
+        if (dp < 0 || dp >= D) { mybad = 1; continue; }
+        e += cost[i * D + dp];
+        if (x + 1 < W) {
+            int dq = disp[i + 1];
+            if (dq >= 0 && dq < D) e += (long long)lam * min(abs(dp - dq), T);
+        }
+        if (y + 1 < H) {
+            int dq = disp[i + W];
+            if (dq >= 0 && dq < D) e += (long long)lam * min(abs(dp - dq), T);
+        }
+    }
+    red[threadIdx.x] = e;
+    if (mybad) anybad = 1;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { part[blockIdx.x] = red[0]; bad[blockIdx.x] = anybad; }
+}
+
+__global__ __launch_bounds__(kThreads) void k_energy_final(const long long* part, const int* bad, int nb,
+                                                            int64_t* out)
+{
+    __shared__ long long red[kThreads];
+    __shared__ int anybad;
+    if (threadIdx.x == 0) anybad = 0;
+    __syncthreads();
+    long long e = 0;
+    int b = 0;
+    for (int i = threadIdx.x; i < nb; i += kThreads) { e += part[i]; b |= bad[i]; }
+    red[threadIdx.x] = e;
+    if (b) anybad = 1;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = anybad ? (int64_t)(-9223372036854775807LL - 1) : (int64_t)red[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_luma(const uint8_t* __restrict__ rgb, long long n, uint8_t* __restrict__ y)
+{
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+        int r = rgb[3 * i], g = rgb[3 * i + 1], b = rgb[3 * i + 2];
+        y[i] = (uint8_t)((77 * r + 150 * g + 29 * b + 128) >> 8);
+    }
+}
+
+inline unsigned grid_for(long long items, int G)
+{
+    long long threads = items * G;
+    return (unsigned)((threads + kThreads - 1) / kThreads);
+}
+
+}  // namespace
+
+#define BPST_DISPATCH_G(G, CALL)                                 \
+    switch (G) {                                                 \
+    case 1: { constexpr int GG = 1; CALL; } break;               \
+    case 2: { constexpr int GG = 2; CALL; } break;               \
+    case 4: { constexpr int GG = 4; CALL; } break;               \
+    case 8: { constexpr int GG = 8; CALL; } break;               \
+    case 16: { constexpr int GG = 16; CALL; } break;             \
+    case 32: { constexpr int GG = 32; CALL; } break;             \
+    default: return hipErrorInvalidValue;                        \
+    }
+
+hipError_t launch_zero_stats(DevStats* s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(kThreads), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_level0(const int16_t* user, int16_t* c0, Level lv, int D, int G, hipStream_t st)
+{
+    const bool vec = (D % 8 == 0) && ((reinterpret_cast<uintptr_t>(user) & 15) == 0);
+    const unsigned g = grid_for(lv.slots(), G);
+    if (vec) {
+        BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_prep_level0<GG, true>), dim3(g), dim3(kThreads), 0, st, user, c0, lv, D));
+    } else {
+        BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_prep_level0<GG, false>), dim3(g), dim3(kThreads), 0, st, user, c0, lv, D));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pyramid(const int16_t* fine, Level lf, int16_t* coarse, Level lc, int D, int G, hipStream_t st)
+{
+    const unsigned g = grid_for(lc.slots(), G);
+    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_pyramid<GG>), dim3(g), dim3(kThreads), 0, st, fine, lf, coarse, lc, D));
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const int16_t* parent, Level lp, long long pvol, int16_t* msgs, Level lv, long long vol,
+                       int G, uint8_t* sa, uint8_t* sb, int mode, hipStream_t st)
+{
+    const unsigned g = grid_for(lv.slots(), G);
+    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_init<GG>), dim3(g), dim3(kThreads), 0, st, parent, lp, pvol, msgs, lv,
+                                          vol, sa, sb, mode));
+    return hipGetLastError();
+}
+
+hipError_t launch_import(const int16_t* warm, int16_t* msgs, Level lv, long long vol, int D, int G, uint8_t* sa,
+                         uint8_t* sb, int mode, hipStream_t st)
+{
+    const unsigned g = grid_for(lv.slots(), G);
+    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_import<GG>), dim3(g), dim3(kThreads), 0, st, warm, msgs, lv, vol, D, sa,
+                                          sb, mode));
+    return hipGetLastError();
+}
+
+hipError_t launch_halfstep(const HalfstepArgs& a, hipStream_t st)
+{
+    const unsigned g = grid_for((long long)a.lv.H * a.lv.Wh, a.G);
+    switch (a.mode) {
+    case 0: BPST_DISPATCH_G(a.G, hipLaunchKernelGGL((k_halfstep<GG, 0>), dim3(g), dim3(kThreads), 0, st, a)); break;
+    case 1: BPST_DISPATCH_G(a.G, hipLaunchKernelGGL((k_halfstep<GG, 1>), dim3(g), dim3(kThreads), 0, st, a)); break;
+    case 2: BPST_DISPATCH_G(a.G, hipLaunchKernelGGL((k_halfstep<GG, 2>), dim3(g), dim3(kThreads), 0, st, a)); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G, int16_t* disp,
+                      hipStream_t st)
+{
+    const unsigned g = grid_for(lv.slots(), G);
+    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_wta<GG>), dim3(g), dim3(kThreads), 0, st, c0, msgs, vol, lv, D, disp));
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const int16_t* msgs, long long vol, Level lv, int D, int G, int16_t* out, hipStream_t st)
+{
+    const unsigned g = grid_for(lv.slots(), G);
+    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_export<GG>), dim3(g), dim3(kThreads), 0, st, msgs, vol, lv, D, out));
+    return hipGetLastError();
+}
+
+size_t energy_ws_bytes() { return (size_t)kEnergyBlocks * (sizeof(long long) + sizeof(int)); }
+
+hipError_t launch_energy(const int16_t* cost, const int16_t* disp, int W, int H, int D, int lambda, int trunc,
+                         int64_t* out, void* ws, hipStream_t st)
+{
+    long long* part = reinterpret_cast<long long*>(ws);
+    int* bad = reinterpret_cast<int*>(part + kEnergyBlocks);
+    const long long n = (long long)W * H;
+    long long nb = (n + kThreads - 1) / kThreads;
+    if (nb > kEnergyBlocks) nb = kEnergyBlocks;
+    hipLaunchKernelGGL(k_energy_partial, dim3((unsigned)nb), dim3(kThreads), 0, st, cost, disp, W, H, D, lambda,
+                       trunc, part, bad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kThreads), 0, st, part, bad, (int)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_luma(const uint8_t* rgb, int W, int H, uint8_t* y, hipStream_t st)
+{
+    const long long n = (long long)W * H;
+    long long nb = (n + kThreads - 1) / kThreads;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_luma, dim3((unsigned)nb), dim3(kThreads), 0, st, rgb, n, y);
+    return hipGetLastError();
+}
+
+}  // namespace bpst

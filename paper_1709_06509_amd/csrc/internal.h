@@ -1,0 +1,77 @@
+// Internal declarations shared by the host runtime (api.cpp) and the kernel files.
+//
+// Device data layout of one scale (W x H pixels, D labels):
+//  - Labels are padded to Dp = 8 * G, G = lanes per pixel (a power of two with
+//    8 * G >= D); lane g of a pixel owns labels [8g, 8g + 8) as one 16-byte vector.
+//  - Pixels are stored colour-split: the pixels of colour c = (x + y) & 1 in row y
+//    are contiguous, slot(x, y) = (2y + c) * Wh + (x >> 1), Wh = ceil(W / 2).  A
+//    half-step touches one colour, so its reads and writes are dense streams.
+//  - The four message volumes of a scale are consecutive, each slots * Dp int16.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bpst {
+
+constexpr int kMaxScales = 8;
+constexpr int kStatHalfsteps = 64;
+
+inline int lanes_for(int D)
+{
+    int g = 1;
+    while (8 * g < D) g <<= 1;
+    return g;
+}
+
+struct Level {
+    int W, H, Wh;
+    __host__ __device__ long long slots() const { return 2LL * H * Wh; }
+};
+
+inline Level make_level(int W, int H) { return Level{W, H, (W + 1) / 2}; }
+
+// Device counters of one solve (kept in the workspace).
+struct DevStats {
+    unsigned long long msg_updates;
+    unsigned long long pixel_updates;
+    int active[kMaxScales][kStatHalfsteps];
+};
+
+struct HalfstepArgs {
+    const int16_t* cost;  // this scale's cost, colour-split, Dp labels
+    int16_t* msgs;        // 4 volumes
+    long long vol;        // elements per volume
+    uint8_t* state_a;     // skip 1: active; skip 2: dirty
+    uint8_t* state_b;     // skip 1: stable count
+    Level lv;
+    int D, Dp, G;
+    int lambda, lam_t;    // lambda and lambda * min(T, D)
+    int colour, t, K, mode;
+    DevStats* stats;
+    int level;
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_zero_stats(DevStats* s, hipStream_t st);
+hipError_t launch_prep_level0(const int16_t* user, int16_t* c0, Level lv, int D, int G, hipStream_t st);
+hipError_t launch_pyramid(const int16_t* fine, Level lf, int16_t* coarse, Level lc, int D, int G,
+                          hipStream_t st);
+hipError_t launch_init(const int16_t* parent, Level lp, long long pvol, int16_t* msgs, Level lv,
+                       long long vol, int G, uint8_t* state_a, uint8_t* state_b, int mode, hipStream_t st);
+hipError_t launch_import(const int16_t* warm, int16_t* msgs, Level lv, long long vol, int D, int G,
+                         uint8_t* state_a, uint8_t* state_b, int mode, hipStream_t st);
+hipError_t launch_halfstep(const HalfstepArgs& a, hipStream_t st);
+hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G,
+                      int16_t* disparity, hipStream_t st);
+hipError_t launch_export(const int16_t* msgs, long long vol, Level lv, int D, int G, int16_t* out,
+                         hipStream_t st);
+hipError_t launch_energy(const int16_t* cost, const int16_t* disp, int W, int H, int D, int lambda,
+                         int trunc, int64_t* out, void* ws, hipStream_t st);
+size_t energy_ws_bytes();
+hipError_t launch_luma(const uint8_t* rgb, int W, int H, uint8_t* y, hipStream_t st);
+hipError_t launch_ncc(const uint8_t* L, const uint8_t* R, int W, int H, int D, int win, int scale,
+                      int trunc, int16_t* cost, float* ncc, hipStream_t st);
+
+}  // namespace bpst

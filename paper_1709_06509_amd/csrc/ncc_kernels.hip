@@ -1,0 +1,166 @@
+// Correlation volume: zero-mean NCC of window x window patches, quantised to an int16 cost.
+//
+// One workgroup produces one image row y and a tile of kTileX columns for every
+// disparity.  The window rows y-r..y+r of both views are staged in LDS as packed byte
+// columns (4 dwords = up to 16 rows), so every window sum is a handful of 4-way byte
+// dot products (v_dot4_u32_u8), all in exact integer arithmetic:
+//   V[u][d]  = sum_rows  left(u, .) * right(u - d, .)     (column products)
+//   S_IJ     = sum_{i=-r..r} V[x + i][d]
+//   S_I, S_II, S_J, S_JJ from per-column byte sums and squares.
+// With n = w^2, num = n S_IJ - S_I S_J, vI = n S_II - S_I^2, vJ = n S_JJ - S_J^2 the
+// correlation is num / sqrt(vI vJ).  The quantised cost round-half-up(scale (1 - ncc))
+// is taken from a double estimate and, when that estimate lies within 1e-6 of a rounding
+// boundary, settled exactly by comparing squares in 128-bit integers.
+#include "internal.h"
+
+namespace bpst {
+namespace {
+
+constexpr int kTileX = 32;
+constexpr int kThreads = 256;
+constexpr int kMaxR = 6;  // window <= 13 rows: fits 4 packed dwords per column
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Is B <= A * sqrt(P) exactly?  (P > 0)
+__device__ bool le_times_sqrt(long long B, long long A, unsigned long long P)
+{
+    typedef unsigned __int128 u128;
+    const unsigned long long ab = (unsigned long long)(B < 0 ? -B : B);
+    const unsigned long long aa = (unsigned long long)(A < 0 ? -A : A);
+    const u128 b2 = (u128)ab * ab;
+    const u128 a2p = (u128)(aa * aa) * P;
+    if (A >= 0) return B <= 0 ? true : (b2 <= a2p);
+    return B >= 0 ? false : (b2 >= a2p);
+}
+
+__global__ __launch_bounds__(kThreads) void k_ncc(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R,
+                                                   int W, int H, int D, int win, int scale, int trunc,
+                                                   int16_t* __restrict__ cost, float* __restrict__ ncc_out)
+{
+    extern __shared__ unsigned smem[];
+    const int r = win >> 1;
+    const int y = blockIdx.y;
+    const int x0 = blockIdx.x * kTileX;
+    const int nI = kTileX + 2 * r;          // left columns  x0-r .. x0+kTileX-1+r
+    const int nJ = kTileX + 2 * r + D - 1;  // right columns x0-r-(D-1) .. x0+kTileX-1+r
+    const int uI0 = x0 - r, uJ0 = x0 - r - (D - 1);
+    uint4* colI = reinterpret_cast<uint4*>(smem);
+    uint4* colJ = colI + nI;
+    int* cI = reinterpret_cast<int*>(colJ + nJ);   // per-column sums
+    int* cII = cI + nI;
+    int* cJ = cII + nI;
+    int* cJJ = cJ + nJ;
+    int* SI = cJJ + nJ;                            // window sums, kTileX of them
+    int* SII = SI + kTileX;
+    int* SJ = SII + kTileX;                        // kTileX + D - 1 of them, for u = x0-(D-1) ..
+    int* SJJ = SJ + kTileX + D - 1;
+    int* V = SJJ + kTileX + D - 1;                 // [nI][D]
+
+    // 1. packed byte columns of the window rows (clamped), zero beyond the window
+    for (int c = threadIdx.x; c < nI + nJ; c += kThreads) {
+        const bool left = c < nI;
+        const uint8_t* img = left ? L : R;
+        const int u = left ? uI0 + c : uJ0 + (c - nI);
+        const int xx = clampi(u, 0, W - 1);
+        unsigned w4[4] = {0u, 0u, 0u, 0u};
+        for (int j = 0; j < win; ++j) {
+            const unsigned v = img[(long long)clampi(y - r + j, 0, H - 1) * W + xx];
+            w4[j >> 2] |= v << (8 * (j & 3));
+        }
+        const uint4 pk = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+        unsigned s = 0, ss = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s = __builtin_amdgcn_udot4(w4[k], 0x01010101u, s, false);
+            ss = __builtin_amdgcn_udot4(w4[k], w4[k], ss, false);
+        }
+        if (left) { colI[c] = pk; cI[c] = (int)s; cII[c] = (int)ss; }
+        else { colJ[c - nI] = pk; cJ[c - nI] = (int)s; cJJ[c - nI] = (int)ss; }
+    }
+    __syncthreads();
+
+    // 2. horizontal window sums of the left columns and the right columns
+    for (int i = threadIdx.x; i < kTileX; i += kThreads) {
+        int s = 0, ss = 0;
+        for (int k = 0; k < win; ++k) { s += cI[i + k]; ss += cII[i + k]; }
+        SI[i] = s; SII[i] = ss;
+    }
+    for (int i = threadIdx.x; i < kTileX + D - 1; i += kThreads) {
+        int s = 0, ss = 0;
+        for (int k = 0; k < win; ++k) { s += cJ[i + k]; ss += cJJ[i + k]; }
+        SJ[i] = s; SJJ[i] = ss;
+    }
+    // 3. column products V[u][d] = sum over the window rows of left(u) * right(u - d)
+    for (int e = threadIdx.x; e < nI * D; e += kThreads) {
+        const int u = e / D, d = e - u * D;
+        const uint4 a = colI[u];
+        const uint4 b = colJ[u - d + (D - 1)];  // right column uI0 + u - d
+        unsigned s = __builtin_amdgcn_udot4(a.x, b.x, 0u, false);
+        s = __builtin_amdgcn_udot4(a.y, b.y, s, false);
+        s = __builtin_amdgcn_udot4(a.z, b.z, s, false);
+        s = __builtin_amdgcn_udot4(a.w, b.w, s, false);
+        V[e] = (int)s;
+    }
+    __syncthreads();
+
+    // 4. finish every (x, d) of the tile; consecutive threads write consecutive d
+    const long long n = (long long)win * win;
+    const int tileW = min(kTileX, W - x0);
+    for (int e = threadIdx.x; e < tileW * D; e += kThreads) {
+        const int i = e / D, d = e - i * D;
+        const int x = x0 + i;
+        const long long o = ((long long)y * W + x) * D + d;
+        if (x - d < 0) {
+            cost[o] = (int16_t)trunc;
+            if (ncc_out) ncc_out[o] = -2.0f;
+            continue;
+        }
+        long long sij = 0;
+        for (int k = 0; k < win; ++k) sij += V[(i + k) * D + d];
+        const long long si = SI[i], sii = SII[i];
+        const long long sj = SJ[i - d + (D - 1)], sjj = SJJ[i - d + (D - 1)];
+        const long long num = n * sij - si * sj;
+        const long long vi = n * sii - si * si;
+        const long long vj = n * sjj - sj * sj;
+        long long k;
+        float nv;
+        if (vi == 0 || vj == 0) {
+            k = scale;
+            nv = 0.0f;
+        } else {
+            const double c = (double)num / (sqrt((double)vi) * sqrt((double)vj));
+            nv = (float)c;
+            const double v = (double)scale * (1.0 - c) + 0.5;
+            k = (long long)floor(v);
+            const double fr = v - (double)k;
+            if (fr < 1e-6 || fr > 1.0 - 1e-6) {
+                const unsigned long long P = (unsigned long long)vi * (unsigned long long)vj;
+                const long long B = 2LL * scale * num;
+                while (!le_times_sqrt(B, 2LL * scale - 2 * k + 1, P)) --k;
+                while (le_times_sqrt(B, 2LL * scale - 2 * (k + 1) + 1, P)) ++k;
+            }
+        }
+        if (k < 0) k = 0;
+        if (k > trunc) k = trunc;
+        cost[o] = (int16_t)k;
+        if (ncc_out) ncc_out[o] = nv;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_ncc(const uint8_t* L, const uint8_t* R, int W, int H, int D, int win, int scale, int trunc,
+                      int16_t* cost, float* ncc, hipStream_t st)
+{
+    const int r = win >> 1;
+    if (r > kMaxR) return hipErrorInvalidValue;
+    const int nI = kTileX + 2 * r, nJ = kTileX + 2 * r + D - 1;
+    const size_t lds = (size_t)(nI + nJ) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 + (size_t)2 * kTileX * 4 +
+                       (size_t)2 * (kTileX + D - 1) * 4 + (size_t)nI * D * 4;
+    dim3 grid((unsigned)((W + kTileX - 1) / kTileX), (unsigned)H);
+    hipLaunchKernelGGL(k_ncc, grid, dim3(kThreads), lds, st, L, R, W, H, D, win, scale, trunc, cost, ncc);
+    return hipGetLastError();
+}
+
+}  // namespace bpst

@@ -1,0 +1,74 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry point,
+and validates arguments on the host before anything reaches a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bpstereo.h")
+LIB = os.path.join(ROOT, "paper_1709_06509_amd", "libbpstereo.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libbpstereo.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ["stereo_cost_volume", "bp_hierarchical_solve", "bp_energy", "bp_workspace_bytes", "bp_last_error",
+              "stereo_luma", "bp_context_create", "bp_context_destroy"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_validation_without_gpu(lib):
+    from paper_1709_06509_amd import bpstereo as B
+
+    L = B.library()
+    p = B.make_params(16, 3, [8, 8, 8], 64, 4)
+    need = L.bp_workspace_bytes(128, 96, ctypes.byref(p))
+    assert need > 4 * 128 * 96 * 16 * 2  # at least the finest scale's four message volumes
+    for bad in [B.make_params(0, 3, 8, 64, 4), B.make_params(300, 3, 8, 64, 4), B.make_params(16, 9, 8, 64, 4),
+                B.make_params(16, 3, 8, -1, 4), B.make_params(16, 3, 8, 64, -1), B.make_params(16, 3, 2000, 64, 4),
+                B.make_params(16, 3, 8, 64, 4, skip_mode=3), B.make_params(16, 3, 8, 64, 4, skip_mode=1, converge_iters=3)]:
+        assert L.bp_workspace_bytes(128, 96, ctypes.byref(bad)) == 0
+    assert L.bp_workspace_bytes(0, 96, ctypes.byref(p)) == 0
+    # invalid calls are rejected before any launch, with a message
+    rc = L.bp_hierarchical_solve(None, ctypes.c_void_p(16), 128, 96, ctypes.byref(B.make_params(0, 3, 8, 64, 4)),
+                                 ctypes.c_void_p(256), 1 << 30, ctypes.c_void_p(16), None, None, None)
+    assert rc == B.BP_E_INVAL and b"num_disp" in L.bp_last_error()
+    rc = L.bp_hierarchical_solve(None, ctypes.c_void_p(16), 128, 96, ctypes.byref(p), ctypes.c_void_p(256), need - 1,
+                                 ctypes.c_void_p(16), None, None, None)
+    assert rc == B.BP_E_WORKSPACE
+    rc = L.stereo_cost_volume(ctypes.c_void_p(16), ctypes.c_void_p(16), 64, 64, 16, 4, 256, 1024,
+                              ctypes.c_void_p(16), None, None)
+    assert rc == B.BP_E_INVAL and b"window" in L.bp_last_error()
+    rc = L.bp_energy(ctypes.c_void_p(16), ctypes.c_void_p(16), 8, 8, 4, 1, 1, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                     1, None)
+    assert rc == B.BP_E_WORKSPACE
+
+
+def test_workspace_grows_with_shape(lib):
+    from paper_1709_06509_amd import bpstereo as B
+
+    L = B.library()
+    p = B.make_params(128, 5, 12, 64, 4)
+    big = L.bp_workspace_bytes(1920, 1080, ctypes.byref(p))
+    # cost pyramid (~4/3 of the finest) + two message buffers (finest and next) + state
+    assert 5 * 1920 * 1080 * 128 * 2 < big < 8 * 1920 * 1080 * 128 * 2

@@ -1,0 +1,200 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same inputs.
+
+Integer results (quantised costs, messages, disparities, energies, counters) must be
+bit-exact; the float NCC output must be within 1e-5 of the oracle's double value.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1709_06509_amd import bpstereo as B
+from paper_1709_06509_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ------------------------------------------------------------------ luma and NCC
+def test_luma():
+    rng = np.random.default_rng(0)
+    rgb = rng.integers(0, 256, (37, 53, 3), dtype=np.uint8)
+    say("luma 37x53")
+    assert np.array_equal(host(B.stereo_luma(gpu(rgb))), oracle.luma(rgb))
+
+
+@pytest.mark.parametrize("H,W,D,win", [(9, 77, 5, 3), (12, 40, 16, 5), (7, 33, 33, 7), (5, 70, 64, 9),
+                                       (6, 20, 1, 1), (4, 31, 3, 13), (3, 65, 128, 9), (2, 300, 256, 5)])
+def test_cost_volume_random(H, W, D, win):
+    rng = np.random.default_rng(H * 1000 + W + D)
+    L = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    R = np.clip(np.roll(L, -min(D - 1, 3), axis=1).astype(int) + rng.integers(-20, 21, (H, W)), 0, 255).astype(np.uint8)
+    R[:, : W // 4] = 77  # a flat band: zero-variance windows
+    say(f"cost volume random H={H} W={W} D={D} win={win}")
+    cost, ncc = B.stereo_cost_volume(gpu(L), gpu(R), D, win, want_ncc=True)
+    ref_cost, ref_ncc = oracle.cost_volume(L, R, D, win, want_ncc=True)
+    assert np.array_equal(host(cost), ref_cost)
+    assert np.max(np.abs(host(ncc).astype(np.float64) - ref_ncc)) <= 1e-5
+
+
+def test_cost_volume_tiny_workload():
+    w = synth.WORKLOADS["tiny"]
+    p = synth.workload_pair("tiny")
+    say("cost volume tiny 128x96 D=16 win=5")
+    cost, ncc = B.stereo_cost_volume(gpu(p["left"]), gpu(p["right"]), 16, w["window"], want_ncc=True)
+    ref_cost, ref_ncc = oracle.cost_volume(p["left"], p["right"], 16, w["window"], want_ncc=True)
+    assert np.array_equal(host(cost), ref_cost)
+    assert np.max(np.abs(host(ncc).astype(np.float64) - ref_ncc)) <= 1e-5
+
+
+def test_cost_volume_other_scale_and_trunc():
+    rng = np.random.default_rng(5)
+    L = rng.integers(0, 256, (8, 45), dtype=np.uint8)
+    R = rng.integers(0, 256, (8, 45), dtype=np.uint8)
+    for scale, trunc in [(1, 1), (3, 2), (4096, 32767), (255, 100)]:
+        say(f"cost volume scale={scale} trunc={trunc}")
+        got = host(B.stereo_cost_volume(gpu(L), gpu(R), 12, 5, cost_scale=scale, cost_trunc=trunc))
+        assert np.array_equal(got, oracle.cost_volume(L, R, 12, 5, scale, trunc))
+
+
+# ------------------------------------------------------------------ hierarchical solve
+def run_both(cost, L, iters, lam, T, skip=0, K=2, warm=None):
+    say(f"solve shape={cost.shape} L={L} iters={iters} lam={lam} T={T} skip={skip} K={K} warm={warm is not None}")
+    d, m, s = B.bp_hierarchical_solve(gpu(cost), L, iters, lam, T, skip, K,
+                                      warm_msgs=gpu(warm) if warm is not None else None,
+                                      want_msgs=True, want_stats=True)
+    rd, rm, rs = oracle.bp_solve(cost, L, iters, lam, T, skip, K, warm_msgs=warm)
+    return host(d), host(m), s, rd, rm, rs
+
+
+def assert_same(got, ref, levels):
+    d, m, s = got
+    rd, rm, rs = ref
+    assert np.array_equal(m, rm), "messages differ"
+    assert np.array_equal(d, rd), "disparities differ"
+    assert s["pixel_updates"] == rs["pixel_updates"]
+    assert s["msg_updates"] == rs["msg_updates"]
+    assert np.array_equal(np.array(s["active"])[:levels], rs["active"][:levels])
+
+
+CASES = [
+    # H, W, D, L, iters, lam, T, skip
+    (24, 32, 16, 3, [8, 8, 8], 64, 4, 0),
+    (23, 37, 16, 3, [7, 5, 3], 64, 4, 0),
+    (17, 29, 8, 2, [6, 6], 40, 3, 0),
+    (31, 19, 1, 3, [4, 4, 4], 64, 4, 0),
+    (13, 21, 3, 2, [5, 4], 10, 1, 0),
+    (16, 24, 17, 3, [6, 5, 4], 64, 4, 0),
+    (20, 18, 32, 3, [6, 6, 6], 30, 8, 0),
+    (12, 15, 64, 2, [5, 5], 64, 4, 0),
+    (9, 11, 128, 2, [4, 4], 64, 4, 0),
+    (6, 10, 256, 2, [3, 3], 5, 300, 0),
+    (1, 40, 9, 3, [20, 4, 4], 37, 3, 0),
+    (40, 1, 9, 3, [20, 4, 4], 37, 3, 0),
+    (1, 1, 5, 1, [3], 64, 4, 0),
+    (2, 2, 3, 5, [3, 3, 3, 3, 3], 64, 4, 0),
+    (25, 33, 16, 4, [10, 10, 10, 10], 64, 4, 1),
+    (25, 33, 16, 4, [10, 10, 10, 10], 64, 4, 2),
+    (18, 27, 24, 3, [9, 7, 5], 50, 2, 1),
+    (18, 27, 24, 3, [9, 7, 5], 50, 2, 2),
+    (22, 30, 16, 3, [1, 0, 2], 64, 4, 0),
+    (22, 30, 16, 3, [0, 3, 0], 64, 4, 1),
+    (14, 14, 16, 3, [8, 8, 8], 0, 4, 0),
+    (14, 14, 16, 3, [8, 8, 8], 64, 0, 0),
+    (14, 14, 16, 3, [8, 8, 8], 65535, 100, 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:4])) + f"-s{c[7]}")
+def test_solve_random(case):
+    H, W, D, L, iters, lam, T, skip = case
+    rng = np.random.default_rng(H * 7919 + W * 31 + D + skip)
+    cost = rng.integers(0, 700, (H, W, D)).astype(np.int16)
+    got = run_both(cost, L, iters, lam, T, skip)
+    assert_same(got[:3], got[3:], L)
+
+
+def test_solve_negative_and_saturating_costs():
+    rng = np.random.default_rng(11)
+    cost = rng.integers(-32768, 32768, (19, 26, 16)).astype(np.int16)
+    got = run_both(cost, 4, [6, 6, 6, 6], 64, 4)
+    assert_same(got[:3], got[3:], 4)
+    cost = rng.integers(20000, 32768, (19, 26, 16)).astype(np.int16)  # coarse scales saturate
+    got = run_both(cost, 4, [6, 6, 6, 6], 64, 4)
+    assert_same(got[:3], got[3:], 4)
+
+
+def test_solve_freeze_k4():
+    rng = np.random.default_rng(12)
+    cost = rng.integers(0, 300, (21, 26, 16)).astype(np.int16)
+    got = run_both(cost, 3, [12, 12, 12], 64, 4, skip=1, K=4)
+    assert_same(got[:3], got[3:], 3)
+
+
+def test_solve_warm_start_injection():
+    rng = np.random.default_rng(13)
+    cost = rng.integers(0, 500, (27, 35, 16)).astype(np.int16)
+    H1, W1 = 14, 18
+    warm = rng.integers(0, 257, (4, H1, W1, 16)).astype(np.int16)
+    for skip in (0, 1):
+        got = run_both(cost, 3, [6, 6, 6], 64, 4, skip=skip, warm=warm)
+        assert_same(got[:3], got[3:], 3)
+
+
+def test_solve_tiny_workload_end_to_end():
+    w = synth.WORKLOADS["tiny"]
+    p = synth.workload_pair("tiny")
+    say("tiny workload end to end")
+    cost = B.stereo_cost_volume(gpu(p["left"]), gpu(p["right"]), w["num_disp"], w["window"])
+    c = host(cost)
+    assert np.array_equal(c, oracle.cost_volume(p["left"], p["right"], w["num_disp"], w["window"]))
+    got = run_both(c, w["num_scales"], [w["iters"]] * w["num_scales"], w["lam"], w["trunc"], w["skip"])
+    assert_same(got[:3], got[3:], w["num_scales"])
+
+
+def test_solve_production_workload_with_freeze():
+    w = synth.WORKLOADS["production"]
+    p = synth.workload_pair("production")
+    say("production workload 384x288 D=16, 4 scales x 10, freeze")
+    cost = host(B.stereo_cost_volume(gpu(p["left"]), gpu(p["right"]), w["num_disp"], w["window"]))
+    ref = oracle.cost_volume(p["left"], p["right"], w["num_disp"], w["window"])
+    assert np.array_equal(cost, ref)
+    got = run_both(cost, w["num_scales"], [w["iters"]] * w["num_scales"], w["lam"], w["trunc"], w["skip"])
+    assert_same(got[:3], got[3:], w["num_scales"])
+
+
+def test_solve_is_deterministic():
+    rng = np.random.default_rng(14)
+    cost = gpu(rng.integers(0, 900, (64, 80, 32)).astype(np.int16))
+    say("determinism 64x80 D=32")
+    a = B.bp_hierarchical_solve(cost, 4, 9, 64, 4, 1, want_msgs=True)
+    b = B.bp_hierarchical_solve(cost, 4, 9, 64, 4, 1, want_msgs=True)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+# ------------------------------------------------------------------ energy
+def test_energy():
+    rng = np.random.default_rng(15)
+    for (H, W, D) in [(1, 1, 1), (17, 23, 16), (64, 70, 64), (300, 301, 8)]:
+        cost = rng.integers(-1000, 1000, (H, W, D)).astype(np.int16)
+        disp = rng.integers(0, D, (H, W)).astype(np.int16)
+        say(f"energy {H}x{W} D={D}")
+        e = host(B.bp_energy(gpu(cost), gpu(disp), 64, 4))[0]
+        assert e == oracle.energy(cost, disp, 64, 4)
+        disp[H // 2, W // 2] = D  # out of range
+        assert host(B.bp_energy(gpu(cost), gpu(disp), 64, 4))[0] == -(2**63)
