@@ -213,26 +213,43 @@ BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32
     uint8_t* sa = reinterpret_cast<uint8_t*>(ws + pl.off_sa);
     uint8_t* sb = reinterpret_cast<uint8_t*>(ws + pl.off_sb);
     const int mode = params->skip_mode;
-    const int lam_t = params->lambda * (params->trunc < pl.D ? params->trunc : pl.D);
+    const int tq = params->trunc < pl.D ? params->trunc : pl.D;
+    const int capv = params->lambda * tq < 32767 ? params->lambda * tq : 32767;
+    const bool count = stats_or_null != nullptr;
 
-    HIP_TRY(bpst::launch_zero_stats(stats, st));
+    if (count) HIP_TRY(bpst::launch_zero_stats(stats, st));
     HIP_TRY(bpst::launch_prep_level0(cost, C[0], pl.lv[0], pl.D, pl.G, st));
     for (int l = 0; l + 1 < pl.L; ++l) HIP_TRY(bpst::launch_pyramid(C[l], pl.lv[l], C[l + 1], pl.lv[l + 1], pl.D, pl.G, st));
 
     const int start = params->warm_msgs ? pl.L - 2 : pl.L - 1;
     for (int l = start; l >= 0; --l) {
         int16_t* msgs = M[l & 1];
-        if (l == start && params->warm_msgs)
+        const int iters = params->iters[l];
+        // The first half-step reads the parent's (or zero) messages directly, unless the
+        // scale needs its initial messages materialised: fewer than two half-steps (the
+        // colour-0 slots would never be written), a warm start, or the exact dirty-skip,
+        // whose change test compares against the initial messages.
+        const bool fuse = iters >= 2 && mode != 2 && !(l == start && params->warm_msgs);
+        int source = bpst::kSrcOwn;
+        if (fuse) {
+            source = (l == start) ? bpst::kSrcZero : bpst::kSrcParent;
+        } else if (l == start && params->warm_msgs) {
             HIP_TRY(bpst::launch_import(params->warm_msgs, msgs, pl.lv[l], pl.vol[l], pl.D, pl.G, sa, sb, mode, st));
-        else if (l == start)
+        } else if (l == start) {
             HIP_TRY(bpst::launch_init(nullptr, pl.lv[l], 0, msgs, pl.lv[l], pl.vol[l], pl.G, sa, sb, mode, st));
-        else
+        } else {
             HIP_TRY(bpst::launch_init(M[(l + 1) & 1], pl.lv[l + 1], pl.vol[l + 1], msgs, pl.lv[l], pl.vol[l], pl.G, sa,
                                       sb, mode, st));
+        }
         bpst::HalfstepArgs a{};
         a.cost = C[l];
         a.msgs = msgs;
         a.vol = pl.vol[l];
+        if (l + 1 < pl.L) {
+            a.pmsgs = M[(l + 1) & 1];
+            a.pvol = pl.vol[l + 1];
+            a.plv = pl.lv[l + 1];
+        }
         a.state_a = sa;
         a.state_b = sb;
         a.lv = pl.lv[l];
@@ -240,14 +257,16 @@ BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32
         a.Dp = pl.Dp;
         a.G = pl.G;
         a.lambda = params->lambda;
-        a.lam_t = lam_t;
+        a.capv = capv;
         a.K = params->converge_iters;
         a.mode = mode;
+        a.count = count ? 1 : 0;
         a.stats = stats;
         a.level = l;
-        for (int t = 0; t < params->iters[l]; ++t) {
+        for (int t = 0; t < iters; ++t) {
             a.t = t;
             a.colour = t & 1;
+            a.source = (t == 0) ? source : bpst::kSrcOwn;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (ctx && ctx->timing) {
                 if (ctx->used == ctx->events.size()) {

@@ -70,35 +70,58 @@ __device__ __forceinline__ int group_excl_suffix_min(int v, int lane)
     return lane == G - 1 ? kScanId : e;
 }
 
-// m(d) = min( min_d' h(d') + lambda*|d - d'|,  min h + lambda*T ) - min h, saturated.
-// The inner minimum is the lower envelope of cones: lambda*d + prefix-min of
-// (h - lambda*d) and -lambda*d + suffix-min of (h + lambda*d); integer min/+ are exact,
-// so the lane-then-group association gives the same value as any other order.
+// Min-sum message with truncated-linear jump cost, normalised:
+//   m(d) = min( min_d' h(d') + lambda*|d - d'|,  min h + lambda*T ) - min h,
+// saturated to int16.  The inner minimum is the classic two-pass lower envelope:
+// forward f(d) = min(h(d), f(d-1) + lambda), then backward f(d) = min(f(d), f(d+1) + lambda).
+// Each pass runs sequentially over a lane's 8 labels; the value carried into a lane from
+// the lanes before it (after it) is a scan over the G lanes with the operator
+// (a, b) -> min(b, a + 8*lambda*distance).  Integer min/+ are exact, so this association
+// gives the same value as one sequential pass.  Padded labels hold kBig and never win.
 template <int G>
-__device__ __forceinline__ void transform(const int h[8], int d0, int lam, int lam_t, int lane, int out[8])
+__device__ __forceinline__ void transform(const int h[8], int lam, int capv, int lane, int out[8])
 {
-    int hm = h[0];
-#pragma unroll
-    for (int j = 1; j < 8; ++j) hm = min(hm, h[j]);
+    int hm = min(min(min(h[0], h[1]), min(h[2], h[3])), min(min(h[4], h[5]), min(h[6], h[7])));
     hm = group_min<G>(hm);
-    const int ld = lam * d0;
-    int pa[8], sb[8];
-    pa[0] = h[0] - ld;
+    int f[8];
+    // forward: carry = min over the lanes before of (their last forward value + lambda*gap)
+    int last = h[0];
 #pragma unroll
-    for (int j = 1; j < 8; ++j) pa[j] = min(pa[j - 1], h[j] - (ld + lam * j));
-    sb[7] = h[7] + ld + 7 * lam;
+    for (int j = 1; j < 8; ++j) last = min(h[j], last + lam);
+    int cin = kScanId;
+    if (G > 1) {
+        int c = last;
 #pragma unroll
-    for (int j = 6; j >= 0; --j) sb[j] = min(sb[j + 1], h[j] + ld + lam * j);
-    const int ep = group_excl_prefix_min<G>(pa[7], lane);
-    const int es = group_excl_suffix_min<G>(sb[0], lane);
-    const int cap = hm + lam_t;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        int F = min(pa[j], ep) + ld + lam * j;
-        int B = min(sb[j], es) - (ld + lam * j);
-        int f = min(min(F, B), cap) - hm;
-        out[j] = min(f, 32767);
+        for (int o = 1; o < G; o <<= 1) {
+            int t = __shfl_up(c, o, G);
+            if (lane >= o) c = min(c, t + 8 * lam * o);
+        }
+        cin = __shfl_up(c, 1, G);
+        if (lane == 0) cin = kScanId;
     }
+    f[0] = min(h[0], cin + lam);
+#pragma unroll
+    for (int j = 1; j < 8; ++j) f[j] = min(h[j], f[j - 1] + lam);
+    // backward on the forward result
+    int first = f[7];
+#pragma unroll
+    for (int j = 6; j >= 0; --j) first = min(f[j], first + lam);
+    int cb = kScanId;
+    if (G > 1) {
+        int c = first;
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            int t = __shfl_down(c, o, G);
+            if (lane + o < G) c = min(c, t + 8 * lam * o);
+        }
+        cb = __shfl_down(c, 1, G);
+        if (lane == G - 1) cb = kScanId;
+    }
+    f[7] = min(f[7], cb + lam);
+#pragma unroll
+    for (int j = 6; j >= 0; --j) f[j] = min(f[j], f[j + 1] + lam);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) out[j] = min(f[j] - hm, capv);
 }
 
 struct ColourPix {
@@ -106,17 +129,6 @@ struct ColourPix {
     long long slot;
     bool valid;
 };
-
-__device__ __forceinline__ ColourPix colour_pixel(long long gi, const Level lv, int colour)
-{
-    ColourPix p;
-    p.y = (int)(gi / lv.Wh);
-    int xi = (int)(gi - (long long)p.y * lv.Wh);
-    p.x = 2 * xi + ((colour ^ p.y) & 1);
-    p.valid = p.y < lv.H && p.x < lv.W;
-    p.slot = (long long)(2 * p.y + colour) * lv.Wh + xi;
-    return p;
-}
 
 // Pixel of slot index gi over both colours (gi == its slot).
 __device__ __forceinline__ ColourPix any_pixel(long long gi, const Level lv)
@@ -212,11 +224,14 @@ __global__ __launch_bounds__(kThreads) void k_init(const int16_t* __restrict__ p
     if (!p.valid) return;
     const int d0 = lane * 8;
     const bool has[4] = {p.x > 0, p.x < lv.W - 1, p.y > 0, p.y < lv.H - 1};
-    const long long ps = parent ? slot_of(p.x >> 1, p.y >> 1, lp.Wh) : 0;
+    const int px = p.x >> 1, py = p.y >> 1;
+    const bool phas[4] = {px > 0, px < lp.W - 1, py > 0, py < lp.H - 1};
+    const long long ps = parent ? slot_of(px, py, lp.Wh) : 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         int4 v = make_int4(0, 0, 0, 0);
-        if (parent && has[k]) v = *reinterpret_cast<const int4*>(parent + k * pvol + ps * (8 * G) + d0);
+        // a slot is only ever read where its neighbour exists, on both scales
+        if (parent && has[k] && phas[k]) v = *reinterpret_cast<const int4*>(parent + k * pvol + ps * (8 * G) + d0);
         *reinterpret_cast<int4*>(msgs + k * vol + gi * (8 * G) + d0) = v;
     }
     if (lane == 0) {
@@ -256,52 +271,68 @@ __global__ __launch_bounds__(kThreads) void k_import(const int16_t* __restrict__
 // One half-step: every pixel of colour a.colour (that is still being updated) sends a
 // new message to each of its neighbours.  Reads only slots of its own colour, writes only
 // slots of the other colour, so the in-place update is race-free.
-template <int G, int MODE>
+//   SRC == kSrcParent: first half-step of a scale; the incoming messages are read from the
+//     parent's slots (the scale's own slots of this colour are never materialised);
+//   SRC == kSrcZero: first half-step of the coarsest scale; incoming messages are zero.
+// Skip mode 1 resets a pixel's state at its first update of the scale (t < 2).
+template <int G, int MODE, int SRC, bool COUNT>
 __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
 {
     constexpr int Dp = 8 * G;
-    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
-    const long long gi = t / G;
-    const int lane = (int)(t & (G - 1));
-    const bool in = gi < (long long)a.lv.H * a.lv.Wh;
-    ColourPix p = colour_pixel(in ? gi : 0, a.lv, a.colour);
-    const bool valid = in && p.valid;
+    const int t = blockIdx.x * kThreads + threadIdx.x;
+    const int gi = t / G;
+    const int lane = t & (G - 1);
     const int W = a.lv.W, H = a.lv.H, Wh = a.lv.Wh;
-    const bool has[4] = {p.x > 0, p.x < W - 1, p.y > 0, p.y < H - 1};
-    const long long nb[4] = {
-        (long long)(2 * p.y + 1 - a.colour) * Wh + ((p.x - 1) >> 1),
-        (long long)(2 * p.y + 1 - a.colour) * Wh + ((p.x + 1) >> 1),
-        (long long)(2 * (p.y - 1) + 1 - a.colour) * Wh + (p.x >> 1),
-        (long long)(2 * (p.y + 1) + 1 - a.colour) * Wh + (p.x >> 1)};
+    const bool in = gi < H * Wh;
+    const int y = in ? gi / Wh : 0;
+    const int xi = gi - y * Wh;
+    const int x = 2 * xi + ((a.colour ^ y) & 1);
+    const bool valid = in && x < W;
+    const long long slot = (long long)(2 * y + a.colour) * Wh + xi;
+    const bool has[4] = {x > 0, x < W - 1, y > 0, y < H - 1};
+    const long long nb[4] = {(long long)(2 * y + 1 - a.colour) * Wh + ((x - 1) >> 1),
+                             (long long)(2 * y + 1 - a.colour) * Wh + ((x + 1) >> 1),
+                             (long long)(2 * (y - 1) + 1 - a.colour) * Wh + (x >> 1),
+                             (long long)(2 * (y + 1) + 1 - a.colour) * Wh + (x >> 1)};
     bool act = valid;
-    if (MODE != 0) act = act && a.state_a[p.slot] != 0;
+    if (MODE == 2 || (MODE == 1 && a.t >= 2)) act = act && a.state_a[slot] != 0;
     const int d0 = lane * 8;
     int Hs[8], m[4][8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) Hs[j] = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int j = 0; j < 8; ++j) m[k][j] = 0;
     if (act) {
-        unpack8(*reinterpret_cast<const int4*>(a.cost + p.slot * Dp + d0), Hs);
+        unpack8(*reinterpret_cast<const int4*>(a.cost + slot * Dp + d0), Hs);
+        if (SRC == kSrcOwn) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (has[k]) {
-                unpack8(*reinterpret_cast<const int4*>(a.msgs + k * a.vol + p.slot * Dp + d0), m[k]);
+            for (int k = 0; k < 4; ++k)
+                if (has[k]) unpack8(*reinterpret_cast<const int4*>(a.msgs + k * a.vol + slot * Dp + d0), m[k]);
+        } else if (SRC == kSrcParent) {
+            const int px = x >> 1, py = y >> 1;
+            const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
+            const long long ps = (long long)(2 * py + ((px + py) & 1)) * a.plv.Wh + (px >> 1);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) Hs[j] += m[k][j];
-            }
+            for (int k = 0; k < 4; ++k)
+                if (has[k] && phas[k])
+                    unpack8(*reinterpret_cast<const int4*>(a.pmsgs + k * a.pvol + ps * Dp + d0), m[k]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Hs[j] = 0;
     }
-    if (MODE == 2 && act && lane == 0) a.state_a[p.slot] = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        Hs[j] = (d0 + j < a.D) ? Hs[j] + m[0][j] + m[1][j] + m[2][j] + m[3][j] : kBig;
+    if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;
     const bool check = (MODE == 2) || (MODE == 1 && a.t >= 2);
     bool all_eq = true;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         int h[8], o[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) h[j] = (d0 + j < a.D) ? Hs[j] - m[k][j] : kBig;
-        transform<G>(h, d0, a.lambda, a.lam_t, lane, o);
+        for (int j = 0; j < 8; ++j) h[j] = Hs[j] - m[k][j];
+        transform<G>(h, a.lambda, a.capv, lane, o);
         bool store = act && has[k];
         int16_t* dst = a.msgs + (k ^ 1) * a.vol + nb[k] * Dp + d0;
         if (check) {
@@ -317,22 +348,35 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
         }
         if (store) *reinterpret_cast<int4*>(dst) = pack8(o);
     }
-    if (MODE == 1 && act && a.t >= 2 && lane == 0) {
-        int s = all_eq ? (int)a.state_b[p.slot] + 1 : 0;
-        a.state_b[p.slot] = (uint8_t)s;
-        if (2 * s >= a.K) a.state_a[p.slot] = 0;
+    if (MODE == 1 && act && lane == 0) {
+        if (a.t < 2) {
+            a.state_a[slot] = 1;
+            a.state_b[slot] = 0;
+        } else {
+            int s = all_eq ? (int)a.state_b[slot] + 1 : 0;
+            a.state_b[slot] = (uint8_t)s;
+            if (2 * s >= a.K) a.state_a[slot] = 0;
+        }
     }
-    // counters: one atomic per wave
-    const bool lead = act && lane == 0;
-    const unsigned long long bl = __ballot(lead);
-    const int npix = __popcll(bl);
-    int nmsg = 0;
+    if (COUNT) {
+        __shared__ int cnt[2];
+        if (threadIdx.x == 0) { cnt[0] = 0; cnt[1] = 0; }
+        __syncthreads();
+        const bool lead = act && lane == 0;
+        const int npix = __popcll(__ballot(lead));
+        int nmsg = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) nmsg += __popcll(__ballot(lead && has[k]));
-    if ((threadIdx.x & 63) == 0 && npix) {
-        atomicAdd(&a.stats->pixel_updates, (unsigned long long)npix);
-        atomicAdd(&a.stats->msg_updates, (unsigned long long)nmsg);
-        if (a.t < kStatHalfsteps) atomicAdd(&a.stats->active[a.level][a.t], npix);
+        for (int k = 0; k < 4; ++k) nmsg += __popcll(__ballot(lead && has[k]));
+        if ((threadIdx.x & 63) == 0 && npix) {
+            atomicAdd(&cnt[0], npix);
+            atomicAdd(&cnt[1], nmsg);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && cnt[0]) {
+            atomicAdd(&a.stats->pixel_updates, (unsigned long long)cnt[0]);
+            atomicAdd(&a.stats->msg_updates, (unsigned long long)cnt[1]);
+            if (a.t < kStatHalfsteps) atomicAdd(&a.stats->active[a.level][a.t], cnt[0]);
+        }
     }
 }
 
@@ -380,9 +424,10 @@ __global__ __launch_bounds__(kThreads) void k_export(const int16_t* __restrict__
     ColourPix p = any_pixel(gi, lv);
     if (!p.valid) return;
     const int d0 = lane * 8;
+    const bool has[4] = {p.x > 0, p.x < lv.W - 1, p.y > 0, p.y < lv.H - 1};
     for (int k = 0; k < 4; ++k) {
-        int v[8];
-        unpack8(*reinterpret_cast<const int4*>(msgs + k * vol + gi * (8 * G) + d0), v);
+        int v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (has[k]) unpack8(*reinterpret_cast<const int4*>(msgs + k * vol + gi * (8 * G) + d0), v);
         int16_t* dst = out + (((long long)k * lv.H + p.y) * lv.W + p.x) * D + d0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) if (d0 + j < D) dst[j] = (int16_t)v[j];
@@ -516,16 +561,39 @@ hipError_t launch_import(const int16_t* warm, int16_t* msgs, Level lv, long long
     return hipGetLastError();
 }
 
+template <int MODE, int SRC, bool COUNT>
+static hipError_t launch_halfstep_t(const HalfstepArgs& a, unsigned g, hipStream_t st)
+{
+    BPST_DISPATCH_G(a.G, hipLaunchKernelGGL((k_halfstep<GG, MODE, SRC, COUNT>), dim3(g), dim3(kThreads), 0, st, a));
+    return hipGetLastError();
+}
+
+template <int MODE, int SRC>
+static hipError_t launch_halfstep_c(const HalfstepArgs& a, unsigned g, hipStream_t st)
+{
+    return a.count ? launch_halfstep_t<MODE, SRC, true>(a, g, st) : launch_halfstep_t<MODE, SRC, false>(a, g, st);
+}
+
+template <int MODE>
+static hipError_t launch_halfstep_m(const HalfstepArgs& a, unsigned g, hipStream_t st)
+{
+    switch (a.source) {
+    case kSrcOwn: return launch_halfstep_c<MODE, kSrcOwn>(a, g, st);
+    case kSrcParent: return launch_halfstep_c<MODE, kSrcParent>(a, g, st);
+    case kSrcZero: return launch_halfstep_c<MODE, kSrcZero>(a, g, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_halfstep(const HalfstepArgs& a, hipStream_t st)
 {
     const unsigned g = grid_for((long long)a.lv.H * a.lv.Wh, a.G);
     switch (a.mode) {
-    case 0: BPST_DISPATCH_G(a.G, hipLaunchKernelGGL((k_halfstep<GG, 0>), dim3(g), dim3(kThreads), 0, st, a)); break;
-    case 1: BPST_DISPATCH_G(a.G, hipLaunchKernelGGL((k_halfstep<GG, 1>), dim3(g), dim3(kThreads), 0, st, a)); break;
-    case 2: BPST_DISPATCH_G(a.G, hipLaunchKernelGGL((k_halfstep<GG, 2>), dim3(g), dim3(kThreads), 0, st, a)); break;
+    case 0: return launch_halfstep_m<0>(a, g, st);
+    case 1: return launch_halfstep_m<1>(a, g, st);
+    case 2: return a.source == kSrcOwn ? launch_halfstep_c<2, kSrcOwn>(a, g, st) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G, int16_t* disp,

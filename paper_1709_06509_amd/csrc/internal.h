@@ -39,16 +39,23 @@ struct DevStats {
     int active[kMaxScales][kStatHalfsteps];
 };
 
+// Where the first half-step of a scale reads its incoming messages from.
+enum MsgSource { kSrcOwn = 0, kSrcParent = 1, kSrcZero = 2 };
+
 struct HalfstepArgs {
-    const int16_t* cost;  // this scale's cost, colour-split, Dp labels
-    int16_t* msgs;        // 4 volumes
-    long long vol;        // elements per volume
-    uint8_t* state_a;     // skip 1: active; skip 2: dirty
-    uint8_t* state_b;     // skip 1: stable count
+    const int16_t* cost;     // this scale's cost, colour-split, Dp labels
+    int16_t* msgs;           // 4 volumes
+    long long vol;           // elements per volume
+    const int16_t* pmsgs;    // parent scale's volumes (source kSrcParent)
+    long long pvol;
+    Level plv;
+    uint8_t* state_a;        // skip 1: active; skip 2: dirty
+    uint8_t* state_b;        // skip 1: stable count
     Level lv;
     int D, Dp, G;
-    int lambda, lam_t;    // lambda and lambda * min(T, D)
-    int colour, t, K, mode;
+    int lambda;
+    int capv;                // min(lambda * min(T, D), 32767): clamp of a normalised message
+    int colour, t, K, mode, source, count;
     DevStats* stats;
     int level;
 };
