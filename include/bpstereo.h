@@ -88,6 +88,18 @@ int32_t bp_context_set_timing(bp_context* ctx, int32_t on);
 int32_t bp_context_take_timing(bp_context* ctx, bp_timing* out);
 
 /*
+ * When `on` is non-zero, bp_hierarchical_solve on this context records its launch
+ * sequence into a HIP graph the first time it sees a given set of arguments (shape,
+ * parameters and every pointer) and replays that graph on later identical calls.  Applies
+ * only to calls on a non-NULL stream that is not already being captured, without stats
+ * and with timing off; other calls, or a capture that fails, launch eagerly with the same
+ * result.  Up to 32 graphs are kept per context (oldest dropped first).
+ */
+int32_t bp_context_set_graphs(bp_context* ctx, int32_t on);
+/* counts[0..2] [host] = graphs captured, graph replays, eager fallbacks after a failed capture. */
+int32_t bp_context_graph_counts(bp_context* ctx, int64_t* counts);
+
+/*
  * Luma of an interleaved RGB image: Y = (77 R + 150 G + 29 B + 128) >> 8 (integer
  * BT.601 weights).  rgb [device] uint8 [H][W][3]; luma [device] uint8 [H][W].
  * The method takes one channel per view (Abstract: views of a regular RGB camera).

@@ -69,6 +69,8 @@ def _load():
         lib.bp_context_create.argtypes = [ctypes.POINTER(_vp)]
         lib.bp_context_destroy.argtypes = [_vp]
         lib.bp_context_set_timing.argtypes = [_vp, _i32]
+        lib.bp_context_set_graphs.argtypes = [_vp, _i32]
+        lib.bp_context_graph_counts.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
         lib.bp_context_take_timing.argtypes = [_vp, ctypes.POINTER(BPTiming)]
         lib.stereo_luma.argtypes = [_vp, _i32, _i32, _vp, _vp]
         lib.stereo_cost_volume.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp]
@@ -80,6 +82,7 @@ def _load():
         lib.bp_energy_workspace_bytes.restype = ctypes.c_size_t
         lib.bp_energy.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t, _vp]
         for name in ("bp_context_create", "bp_context_destroy", "bp_context_set_timing", "bp_context_take_timing",
+                     "bp_context_set_graphs", "bp_context_graph_counts",
                      "stereo_luma", "stereo_cost_volume", "bp_hierarchical_solve", "bp_energy"):
             getattr(lib, name).restype = ctypes.c_int32
         _lib = lib
@@ -123,6 +126,14 @@ class Context:
 
     def set_timing(self, on=True):
         _check(_load().bp_context_set_timing(self.handle, 1 if on else 0))
+
+    def set_graphs(self, on=True):
+        _check(_load().bp_context_set_graphs(self.handle, 1 if on else 0))
+
+    def graph_counts(self):
+        c = (ctypes.c_int64 * 3)()
+        _check(_load().bp_context_graph_counts(self.handle, c))
+        return {"captures": c[0], "replays": c[1], "fallbacks": c[2]}
 
     def take_timing(self):
         t = BPTiming()

@@ -4,6 +4,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -107,12 +108,50 @@ Plan make_plan(int W, int H, const bp_params* p)
 
 }  // namespace
 
+// Everything that determines the launch sequence of a solve, pointers included.
+struct SolveKey {
+    int32_t width, height;
+    bp_params params;
+    const void *cost, *workspace, *disparity, *final_msgs;
+    size_t workspace_bytes;
+};
+
 struct bp_context {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t used = 0;
     long long pixels_max = 0;
+    bool graphs = false;
+    std::vector<std::pair<SolveKey, hipGraphExec_t>> cache;  // oldest first
+    long long graph_hits = 0, graph_captures = 0, graph_fallbacks = 0;
 };
+
+namespace {
+constexpr size_t kMaxGraphs = 32;
+
+SolveKey make_key(int32_t W, int32_t H, const bp_params* p, const void* cost, const void* ws, size_t wsb,
+                  const void* disp, const void* msgs)
+{
+    SolveKey k;
+    std::memset(&k, 0, sizeof k);  // padding too: keys are compared bytewise
+    k.width = W;
+    k.height = H;
+    k.params.num_disp = p->num_disp;
+    k.params.num_scales = p->num_scales;
+    for (int l = 0; l < p->num_scales; ++l) k.params.iters[l] = p->iters[l];
+    k.params.lambda = p->lambda;
+    k.params.trunc = p->trunc;
+    k.params.skip_mode = p->skip_mode;
+    k.params.converge_iters = p->skip_mode == 1 ? p->converge_iters : 0;
+    k.params.warm_msgs = p->warm_msgs;
+    k.cost = cost;
+    k.workspace = ws;
+    k.workspace_bytes = wsb;
+    k.disparity = disp;
+    k.final_msgs = msgs;
+    return k;
+}
+}  // namespace
 
 BP_API const char* bp_last_error(void) { return g_last_error.c_str(); }
 
@@ -132,7 +171,24 @@ BP_API int32_t bp_context_destroy(bp_context* ctx)
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    for (auto& e : ctx->cache) (void)hipGraphExecDestroy(e.second);
     delete ctx;
+    return ok();
+}
+
+BP_API int32_t bp_context_set_graphs(bp_context* ctx, int32_t on)
+{
+    if (!ctx) return fail(BP_E_INVAL, "ctx is NULL");
+    ctx->graphs = on != 0;
+    return ok();
+}
+
+BP_API int32_t bp_context_graph_counts(bp_context* ctx, int64_t* counts)
+{
+    if (!ctx || !counts) return fail(BP_E_INVAL, "ctx/counts is NULL");
+    counts[0] = ctx->graph_captures;
+    counts[1] = ctx->graph_hits;
+    counts[2] = ctx->graph_fallbacks;
     return ok();
 }
 
@@ -191,20 +247,11 @@ BP_API size_t bp_workspace_bytes(int32_t width, int32_t height, const bp_params*
     return make_plan(width, height, params).total;
 }
 
-BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32_t width, int32_t height,
-                                     const bp_params* params, void* workspace, size_t workspace_bytes,
-                                     int16_t* disparity, int16_t* final_msgs_or_null, bp_stats* stats_or_null,
-                                     void* stream)
+// Enqueue every launch of one solve on `st` (no synchronisation, no allocation).
+static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cost, const bp_params* params,
+                             void* workspace, int16_t* disparity, int16_t* final_msgs_or_null, bool count,
+                             hipStream_t st)
 {
-    std::string why;
-    if (!params_valid(width, height, params, &why)) return fail(BP_E_INVAL, "%s", why.c_str());
-    if (!cost || !disparity) return fail(BP_E_INVAL, "cost/disparity is NULL");
-    const Plan pl = make_plan(width, height, params);
-    if (!workspace || workspace_bytes < pl.total)
-        return fail(BP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, pl.total);
-    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
-        return fail(BP_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
-    hipStream_t st = (hipStream_t)stream;
     char* ws = static_cast<char*>(workspace);
     auto* stats = reinterpret_cast<bpst::DevStats*>(ws + pl.off_stats);
     int16_t* C[bpst::kMaxScales];
@@ -215,11 +262,24 @@ BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32
     const int mode = params->skip_mode;
     const int tq = params->trunc < pl.D ? params->trunc : pl.D;
     const int capv = params->lambda * tq < 32767 ? params->lambda * tq : 32767;
-    const bool count = stats_or_null != nullptr;
 
     if (count) HIP_TRY(bpst::launch_zero_stats(stats, st));
-    HIP_TRY(bpst::launch_prep_level0(cost, C[0], pl.lv[0], pl.D, pl.G, st));
-    for (int l = 0; l + 1 < pl.L; ++l) HIP_TRY(bpst::launch_pyramid(C[l], pl.lv[l], C[l + 1], pl.lv[l + 1], pl.D, pl.G, st));
+    {
+        bpst::PyramidArgs pa{};
+        for (int l = 0; l < pl.L; ++l) {
+            pa.c[l] = C[l];
+            pa.lv[l] = pl.lv[l];
+        }
+        pa.L = pl.L;
+        pa.D = pl.D;
+        bool done = false;
+        HIP_TRY(bpst::launch_pyramid_tree(cost, pa, pl.G, &done, st));
+        if (!done) {
+            HIP_TRY(bpst::launch_prep_level0(cost, C[0], pl.lv[0], pl.D, pl.G, st));
+            for (int l = 0; l + 1 < pl.L; ++l)
+                HIP_TRY(bpst::launch_pyramid(C[l], pl.lv[l], C[l + 1], pl.lv[l + 1], pl.D, pl.G, st));
+        }
+    }
 
     const int start = params->warm_msgs ? pl.L - 2 : pl.L - 1;
     for (int l = start; l >= 0; --l) {
@@ -288,6 +348,67 @@ BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32
     HIP_TRY(bpst::launch_wta(C[0], M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, disparity, st));
     if (final_msgs_or_null)
         HIP_TRY(bpst::launch_export(M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, final_msgs_or_null, st));
+    return BP_OK;
+}
+
+BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32_t width, int32_t height,
+                                     const bp_params* params, void* workspace, size_t workspace_bytes,
+                                     int16_t* disparity, int16_t* final_msgs_or_null, bp_stats* stats_or_null,
+                                     void* stream)
+{
+    std::string why;
+    if (!params_valid(width, height, params, &why)) return fail(BP_E_INVAL, "%s", why.c_str());
+    if (!cost || !disparity) return fail(BP_E_INVAL, "cost/disparity is NULL");
+    const Plan pl = make_plan(width, height, params);
+    if (!workspace || workspace_bytes < pl.total)
+        return fail(BP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, pl.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(BP_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    hipStream_t st = (hipStream_t)stream;
+    const bool count = stats_or_null != nullptr;
+    if (ctx && ctx->graphs && !count && !ctx->timing && st != nullptr) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(st, &cs));
+        if (cs == hipStreamCaptureStatusNone) {
+            const SolveKey key = make_key(width, height, params, cost, workspace, workspace_bytes, disparity,
+                                          final_msgs_or_null);
+            for (auto& e : ctx->cache)
+                if (std::memcmp(&e.first, &key, sizeof key) == 0) {
+                    HIP_TRY(hipGraphLaunch(e.second, st));
+                    ctx->graph_hits++;
+                    return ok();
+                }
+            const char* force = getenv("BPSTEREO_GRAPH_FORCE_FAIL");
+            if (!(force && force[0] == '1') &&
+                hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                const int32_t rc = enqueue_solve(ctx, pl, cost, params, workspace, disparity, final_msgs_or_null,
+                                                 false, st);
+                hipGraph_t g = nullptr;
+                const hipError_t ee = hipStreamEndCapture(st, &g);
+                hipGraphExec_t ex = nullptr;
+                const bool good = rc == BP_OK && ee == hipSuccess && g &&
+                                  hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+                if (g) (void)hipGraphDestroy(g);
+                if (good) {
+                    if (ctx->cache.size() >= kMaxGraphs) {
+                        (void)hipGraphExecDestroy(ctx->cache.front().second);
+                        ctx->cache.erase(ctx->cache.begin());
+                    }
+                    ctx->cache.emplace_back(key, ex);
+                    ctx->graph_captures++;
+                    HIP_TRY(hipGraphLaunch(ex, st));
+                    return ok();
+                }
+            }
+            (void)hipGetLastError();  // a failed capture leaves nothing enqueued: run eagerly
+            ctx->graph_fallbacks++;
+        }
+    }
+    {
+        const int32_t rc = enqueue_solve(ctx, pl, cost, params, workspace, disparity, final_msgs_or_null, count, st);
+        if (rc != BP_OK) return rc;
+    }
+    auto* stats = reinterpret_cast<bpst::DevStats*>(static_cast<char*>(workspace) + pl.off_stats);
     if (stats_or_null) {
         bpst::DevStats hs;
         HIP_TRY(hipMemcpyAsync(&hs, stats, sizeof hs, hipMemcpyDeviceToHost, st));

@@ -209,6 +209,107 @@ __global__ __launch_bounds__(kThreads) void k_pyramid(const int16_t* __restrict_
     if (valid) *reinterpret_cast<int4*>(coarse + gi * (8 * G) + d0) = pack8(o);
 }
 
+// The whole cost pyramid in one launch.  One workgroup per pixel (X, Y) of the coarsest
+// scale: it re-lays the finest costs of the block of pixels under (X, Y) into the internal
+// layout and builds every coarser scale of that block, handing each scale to the next in
+// LDS.  Scale sizes halve with ceil, so the block's pixels at scale l are exactly
+// [X s_l, (X+1) s_l) x [Y s_l, (Y+1) s_l) clipped to the scale, s_l = 2^(L-1-l).
+template <int G, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_pyramid_tree(const int16_t* __restrict__ user, PyramidArgs a)
+{
+    constexpr int Dp = 8 * G;
+    extern __shared__ int lds[];
+    const int L = a.L, D = a.D;
+    const int X = blockIdx.x, Y = blockIdx.y;
+    const int s1 = 1 << (L - 2);
+    int* cur = lds;                 // scale l-1 of the block, [s_{l-1}^2][Dp]
+    int* nxt = lds + s1 * s1 * Dp;  // scale l
+    // scale 1 from the caller's finest costs; also writes the internal finest layout
+    {
+        const Level l0 = a.lv[0], l1 = a.lv[1];
+        const int tasks = s1 * s1 * G;
+        for (int task = threadIdx.x; task < tasks; task += blockDim.x) {
+            const int p = task / G, lane = task & (G - 1), d0 = lane * 8;
+            const int px = X * s1 + (p % s1), py = Y * s1 + (p / s1);
+            const bool valid = px < l1.W && py < l1.H;
+            int s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (valid) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int x = 2 * px + c, y = 2 * py + b;
+                        if (x >= l0.W || y >= l0.H) continue;
+                        const int16_t* src = user + ((long long)y * l0.W + x) * D + d0;
+                        int v[8];
+                        if (VEC) {
+                            if (d0 < D) unpack8(*reinterpret_cast<const int4*>(src), v);
+                            else for (int j = 0; j < 8; ++j) v[j] = 0;
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) v[j] = (d0 + j < D) ? (int)src[j] : 0;
+                        }
+                        *reinterpret_cast<int4*>(a.c[0] + slot_of(x, y, l0.Wh) * Dp + d0) = pack8(v);
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) s[j] += v[j];
+                    }
+            }
+            int mn = kBig;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) if (d0 + j < D) mn = min(mn, s[j]);
+            mn = group_min<G>(mn);
+            int o[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) o[j] = (d0 + j < D) ? min(s[j] - mn, 32767) : 0;
+            if (valid) {
+                *reinterpret_cast<int4*>(a.c[1] + slot_of(px, py, l1.Wh) * Dp + d0) = pack8(o);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) cur[p * Dp + d0 + j] = o[j];
+            }
+        }
+    }
+    __syncthreads();
+    for (int l = 2; l < L; ++l) {
+        const Level lf = a.lv[l - 1], lc = a.lv[l];
+        const int sl = 1 << (L - 1 - l), sf = 2 * sl;
+        const int tasks = sl * sl * G;
+        for (int task = threadIdx.x; task < tasks; task += blockDim.x) {
+            const int p = task / G, lane = task & (G - 1), d0 = lane * 8;
+            const int qx = p % sl, qy = p / sl;
+            const int px = X * sl + qx, py = Y * sl + qy;
+            const bool valid = px < lc.W && py < lc.H;
+            int s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (valid) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        if (2 * px + c >= lf.W || 2 * py + b >= lf.H) continue;
+                        const int* src = cur + ((2 * qy + b) * sf + (2 * qx + c)) * Dp + d0;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) s[j] += src[j];
+                    }
+            }
+            int mn = kBig;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) if (d0 + j < D) mn = min(mn, s[j]);
+            mn = group_min<G>(mn);
+            int o[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) o[j] = (d0 + j < D) ? min(s[j] - mn, 32767) : 0;
+            if (valid) {
+                *reinterpret_cast<int4*>(a.c[l] + slot_of(px, py, lc.Wh) * Dp + d0) = pack8(o);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) nxt[p * Dp + d0 + j] = o[j];
+            }
+        }
+        __syncthreads();
+        int* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+}
+
 // Start a scale: copy each pixel's parent messages (zero for a missing neighbour or for
 // the coarsest scale) and reset the skip state.
 template <int G>
@@ -540,6 +641,26 @@ hipError_t launch_pyramid(const int16_t* fine, Level lf, int16_t* coarse, Level 
 {
     const unsigned g = grid_for(lc.slots(), G);
     BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_pyramid<GG>), dim3(g), dim3(kThreads), 0, st, fine, lf, coarse, lc, D));
+    return hipGetLastError();
+}
+
+hipError_t launch_pyramid_tree(const int16_t* user, const PyramidArgs& a, int G, bool* done, hipStream_t st)
+{
+    *done = false;
+    if (a.L < 2) return hipSuccess;
+    const long long s1 = 1LL << (a.L - 2), s2 = s1 / 2;
+    const size_t lds = (size_t)(s1 * s1 + s2 * s2) * 8 * G * sizeof(int);
+    if (lds > 64 * 1024) return hipSuccess;
+    const bool vec = (a.D % 8 == 0) && ((reinterpret_cast<uintptr_t>(user) & 15) == 0);
+    const long long tasks = s1 * s1 * G;
+    const unsigned threads = (unsigned)(tasks >= kThreads ? kThreads : ((tasks + 63) / 64) * 64);
+    const dim3 grid((unsigned)a.lv[a.L - 1].W, (unsigned)a.lv[a.L - 1].H);
+    if (vec) {
+        BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_pyramid_tree<GG, true>), grid, dim3(threads), lds, st, user, a));
+    } else {
+        BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_pyramid_tree<GG, false>), grid, dim3(threads), lds, st, user, a));
+    }
+    *done = true;
     return hipGetLastError();
 }
 

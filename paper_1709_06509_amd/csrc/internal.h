@@ -60,7 +60,17 @@ struct HalfstepArgs {
     int level;
 };
 
+struct PyramidArgs {
+    int16_t* c[kMaxScales];  // internal cost of every scale
+    Level lv[kMaxScales];
+    int L, D;
+};
+
 // Launchers (return hipError_t of the launch).
+// launch_pyramid_tree: re-layout of the finest scale plus every coarser scale in one launch;
+// sets *done = false (and launches nothing) when the block of one coarsest pixel does not
+// fit in LDS, in which case the caller uses launch_prep_level0 + launch_pyramid.
+hipError_t launch_pyramid_tree(const int16_t* user, const PyramidArgs& a, int G, bool* done, hipStream_t st);
 hipError_t launch_zero_stats(DevStats* s, hipStream_t st);
 hipError_t launch_prep_level0(const int16_t* user, int16_t* c0, Level lv, int D, int G, hipStream_t st);
 hipError_t launch_pyramid(const int16_t* fine, Level lf, int16_t* coarse, Level lc, int D, int G,

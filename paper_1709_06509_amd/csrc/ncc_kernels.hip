@@ -9,8 +9,9 @@
 //   S_I, S_II, S_J, S_JJ from per-column byte sums and squares.
 // With n = w^2, num = n S_IJ - S_I S_J, vI = n S_II - S_I^2, vJ = n S_JJ - S_J^2 the
 // correlation is num / sqrt(vI vJ).  The quantised cost round-half-up(scale (1 - ncc))
-// is taken from a double estimate and, when that estimate lies within 1e-6 of a rounding
-// boundary, settled exactly by comparing squares in 128-bit integers.
+// is taken from a float estimate and, when that estimate lies within a margin of a
+// rounding boundary (several times its worst-case error), settled exactly by comparing
+// squares in 128-bit integers, so the result never depends on floating-point rounding.
 #include "internal.h"
 
 namespace bpst {
@@ -36,7 +37,8 @@ __device__ bool le_times_sqrt(long long B, long long A, unsigned long long P)
 
 __global__ __launch_bounds__(kThreads) void k_ncc(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R,
                                                    int W, int H, int D, int win, int scale, int trunc,
-                                                   int16_t* __restrict__ cost, float* __restrict__ ncc_out)
+                                                   float margin, int16_t* __restrict__ cost,
+                                                   float* __restrict__ ncc_out)
 {
     extern __shared__ unsigned smem[];
     const int r = win >> 1;
@@ -116,25 +118,28 @@ __global__ __launch_bounds__(kThreads) void k_ncc(const uint8_t* __restrict__ L,
             if (ncc_out) ncc_out[o] = -2.0f;
             continue;
         }
-        long long sij = 0;
+        int sij = 0;
         for (int k = 0; k < win; ++k) sij += V[(i + k) * D + d];
-        const long long si = SI[i], sii = SII[i];
-        const long long sj = SJ[i - d + (D - 1)], sjj = SJJ[i - d + (D - 1)];
-        const long long num = n * sij - si * sj;
-        const long long vi = n * sii - si * si;
-        const long long vj = n * sjj - sj * sj;
+        // window <= 13: every product and difference below fits in int32
+        const int si = SI[i], sii = SII[i];
+        const int sj = SJ[i - d + (D - 1)], sjj = SJJ[i - d + (D - 1)];
+        const int num = (int)n * sij - si * sj;
+        const int vi = (int)n * sii - si * si;
+        const int vj = (int)n * sjj - sj * sj;
         long long k;
         float nv;
         if (vi == 0 || vj == 0) {
             k = scale;
             nv = 0.0f;
         } else {
-            const double c = (double)num / (sqrt((double)vi) * sqrt((double)vj));
-            nv = (float)c;
-            const double v = (double)scale * (1.0 - c) + 0.5;
-            k = (long long)floor(v);
-            const double fr = v - (double)k;
-            if (fr < 1e-6 || fr > 1.0 - 1e-6) {
+            // fp32 estimate: relative error of c below ~4e-7, so |error of v| < 3.1e-7 * scale;
+            // within `margin` (>= 2e-6 * scale) of a boundary the exact test decides
+            const float c = (float)num * rsqrtf((float)vi * (float)vj);
+            nv = c;
+            const float v = (float)scale * (1.0f - c) + 0.5f;
+            k = (long long)floorf(v);
+            const float fr = v - (float)k;
+            if (fr < margin || fr > 1.0f - margin) {
                 const unsigned long long P = (unsigned long long)vi * (unsigned long long)vj;
                 const long long B = 2LL * scale * num;
                 while (!le_times_sqrt(B, 2LL * scale - 2 * k + 1, P)) --k;
@@ -159,7 +164,8 @@ hipError_t launch_ncc(const uint8_t* L, const uint8_t* R, int W, int H, int D, i
     const size_t lds = (size_t)(nI + nJ) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 + (size_t)2 * kTileX * 4 +
                        (size_t)2 * (kTileX + D - 1) * 4 + (size_t)nI * D * 4;
     dim3 grid((unsigned)((W + kTileX - 1) / kTileX), (unsigned)H);
-    hipLaunchKernelGGL(k_ncc, grid, dim3(kThreads), lds, st, L, R, W, H, D, win, scale, trunc, cost, ncc);
+    const float margin = 1e-4f + 2e-6f * (float)(2 * scale + 1);
+    hipLaunchKernelGGL(k_ncc, grid, dim3(kThreads), lds, st, L, R, W, H, D, win, scale, trunc, margin, cost, ncc);
     return hipGetLastError();
 }
 

@@ -117,6 +117,10 @@ CASES = [
     (14, 14, 16, 3, [8, 8, 8], 0, 4, 0),
     (14, 14, 16, 3, [8, 8, 8], 64, 0, 0),
     (14, 14, 16, 3, [8, 8, 8], 65535, 100, 0),
+    # deep hierarchies: the one-launch pyramid is too large for LDS here and falls back
+    (70, 90, 64, 6, [4, 3, 3, 3, 3, 3], 64, 4, 1),
+    (37, 45, 256, 5, [3, 3, 3, 3, 3], 64, 4, 0),
+    (33, 29, 5, 8, [3, 3, 3, 3, 3, 3, 3, 3], 64, 4, 0),
 ]
 
 
@@ -198,3 +202,44 @@ def test_energy():
         assert e == oracle.energy(cost, disp, 64, 4)
         disp[H // 2, W // 2] = D  # out of range
         assert host(B.bp_energy(gpu(cost), gpu(disp), 64, 4))[0] == -(2**63)
+
+
+# ------------------------------------------------------------------ graph capture and replay
+def test_graph_replay_matches_eager():
+    rng = np.random.default_rng(16)
+    H, W, D = 40, 52, 16
+    costs = [gpu(rng.integers(0, 600, (H, W, D)).astype(np.int16)) for _ in range(2)]
+    ref = [oracle.bp_solve(host(c), 3, [6, 6, 6], 64, 4, 1, want_msgs=False)[0] for c in costs]
+    ctx = B.Context()
+    ctx.set_graphs(True)
+    s = torch.cuda.Stream()
+    ws = torch.empty(B.bp_workspace_bytes(W, H, B.make_params(D, 3, 6, 64, 4, 1)), dtype=torch.uint8, device="cuda")
+    disp = torch.empty((H, W), dtype=torch.int16, device="cuda")
+    say("graph replay: capture once, replay with eager work in between")
+    with torch.cuda.stream(s):
+        for rep in range(4):
+            for i, c in enumerate(costs):
+                B.bp_hierarchical_solve(c, 3, 6, 64, 4, 1, ctx=ctx, workspace=ws, disparity=disp)
+                got = disp.clone()
+                torch.cuda.synchronize()
+                assert np.array_equal(host(got), ref[i]), f"replay {rep} pair {i}"
+                # eager work on the same stream between replays
+                B.bp_hierarchical_solve(costs[1 - i], 2, 3, 10, 2, 0, workspace=ws, disparity=disp)
+    counts = ctx.graph_counts()
+    assert counts["captures"] >= 2 and counts["replays"] >= 6 and counts["fallbacks"] == 0
+
+
+def test_graph_forced_failure_falls_back(monkeypatch):
+    monkeypatch.setenv("BPSTEREO_GRAPH_FORCE_FAIL", "1")
+    rng = np.random.default_rng(17)
+    c = rng.integers(0, 600, (20, 24, 8)).astype(np.int16)
+    ref = oracle.bp_solve(c, 2, [5, 5], 64, 4, want_msgs=False)[0]
+    ctx = B.Context()
+    ctx.set_graphs(True)
+    s = torch.cuda.Stream()
+    say("graph forced failure")
+    with torch.cuda.stream(s):
+        d, _, _ = B.bp_hierarchical_solve(gpu(c), 2, 5, 64, 4, ctx=ctx)
+        torch.cuda.synchronize()
+    assert np.array_equal(host(d), ref)
+    assert ctx.graph_counts()["fallbacks"] == 1
