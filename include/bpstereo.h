@@ -170,6 +170,72 @@ int32_t bp_energy(const int16_t* cost, const int16_t* disparity, int32_t width, 
                   int32_t num_disp, int32_t lambda, int32_t trunc, int64_t* energy, void* workspace,
                   size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Batched solve: the whole method (correlation volume, hierarchy, half-steps, winner-take-
+ * all) for many independent pairs of different sizes and disparity ranges.  It enqueues
+ * one launch for every pair's correlation volume and ONE persistent launch that solves
+ * every pair.  That launch walks the same phase sequence as bp_hierarchical_solve (pyramid;
+ * per scale, coarsest first, its start and its half-steps; winner-take-all) for all pairs
+ * together, with a grid-wide barrier between phases.  Each pair's cost volume and
+ * disparity are bit-identical to stereo_cost_volume + bp_hierarchical_solve on that pair
+ * alone.
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+    const uint8_t* left;   /* [device] uint8 [H][W] */
+    const uint8_t* right;  /* [device] uint8 [H][W] */
+    int16_t* cost;         /* [device] int16 [H][W][D] output: the pair's correlation volume */
+    int16_t* disparity;    /* [device] int16 [H][W] output */
+    int32_t width, height, num_disp, pad_;  /* width/height 1..16384, num_disp 1..256 */
+} bp_pair_desc;
+
+typedef struct {
+    int32_t window, cost_scale, cost_trunc;  /* as stereo_cost_volume */
+    int32_t num_scales;                      /* 2..8, the same for every pair */
+    int32_t iters[8];                        /* as bp_params */
+    int32_t lambda, trunc, skip_mode, converge_iters;
+} bp_batch_params;
+
+/*
+ * Bytes of device workspace for this batch (pairs [host], n >= 1); 0 if the batch is
+ * invalid or unsupported (a pair whose finest 2^(L-1) x 2^(L-1) block of costs does not
+ * fit the 64 KB LDS of one workgroup: D * (4^(L-2) + 4^(L-3)) * 32 bytes must be <= 64 KB).
+ */
+size_t bp_batch_workspace_bytes(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params);
+
+/*
+ * Solve a batch.  ctx is required: it owns the pinned staging buffer the per-batch tables
+ * are uploaded from (a stream-ordered copy into the workspace at every call), the tuned
+ * launch shape (bp_autotune_batched) and, when graphs are enabled, the captured graph of
+ * the launches.  workspace [device], 256-byte aligned, at least bp_batch_workspace_bytes.
+ * Asynchronous; a persistent-launch failure (a grid barrier that timed out because not all
+ * workgroups could be resident) is reported by bp_batch_status.
+ */
+int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* Synchronises `stream` and stores 0 in *status [host] if the last batched solve on this
+   workspace completed, 1 if its persistent launch gave up at a grid barrier. */
+int32_t bp_batch_status(const void* workspace, void* stream, int32_t* status);
+
+/* Launch shapes tried by the autotuner, with their measured time. */
+typedef struct {
+    int32_t n_candidates;
+    int32_t blocks_per_cu[16]; /* resident workgroups per compute unit */
+    int32_t order[16];         /* 0: tiles dealt round-robin; 1: one contiguous eighth per XCD */
+    float ms[16];              /* device time of the persistent launch */
+    int32_t best;              /* index of the fastest */
+} bp_batch_tuning;
+
+/*
+ * Autotune the persistent launch for this batch: times every candidate shape (workgroups
+ * per compute unit x tile order) on the real batch with HIP events, keeps the fastest in
+ * ctx for later bp_solve_batched calls with the same pair shapes and parameters, and
+ * reports the table in *out [host].  Synchronises the stream.  Results do not depend on the
+ * shape chosen.
+ */
+int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params,
+                            void* workspace, size_t workspace_bytes, void* stream, bp_batch_tuning* out);
+
 /* Message of the last failed call on this thread ("" if none); valid until the next call. */
 const char* bp_last_error(void);
 

@@ -250,3 +250,97 @@ def bp_energy(cost, disparity, lam, trunc, workspace=None, out=None, stream=None
                              D, lam, trunc, _dev(out, torch.int64, 1, "energy"),
                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------------------------------- batched solve
+class PairDesc(ctypes.Structure):
+    _fields_ = [("left", ctypes.c_void_p), ("right", ctypes.c_void_p), ("cost", ctypes.c_void_p),
+                ("disparity", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("num_disp", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int32), ("cost_scale", ctypes.c_int32), ("cost_trunc", ctypes.c_int32),
+                ("num_scales", ctypes.c_int32), ("iters", ctypes.c_int32 * 8), ("lambda_", ctypes.c_int32),
+                ("trunc", ctypes.c_int32), ("skip_mode", ctypes.c_int32), ("converge_iters", ctypes.c_int32)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32 * 16),
+                ("order", ctypes.c_int32 * 16), ("ms", ctypes.c_float * 16), ("best", ctypes.c_int32)]
+
+
+def _batch_sigs(lib):
+    if getattr(lib, "_batch_ready", False):
+        return
+    lib.bp_batch_workspace_bytes.argtypes = [ctypes.POINTER(PairDesc), _i32, ctypes.POINTER(BatchParams)]
+    lib.bp_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.bp_solve_batched.argtypes = [_vp, ctypes.POINTER(PairDesc), _i32, ctypes.POINTER(BatchParams), _vp,
+                                     ctypes.c_size_t, _vp]
+    lib.bp_solve_batched.restype = ctypes.c_int32
+    lib.bp_batch_status.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.bp_batch_status.restype = ctypes.c_int32
+    lib.bp_autotune_batched.argtypes = [_vp, ctypes.POINTER(PairDesc), _i32, ctypes.POINTER(BatchParams), _vp,
+                                        ctypes.c_size_t, _vp, ctypes.POINTER(BatchTuning)]
+    lib.bp_autotune_batched.restype = ctypes.c_int32
+    lib._batch_ready = True
+
+
+def make_batch_params(window, num_scales, iters, lam, trunc, skip_mode=0, converge_iters=2, cost_scale=256,
+                      cost_trunc=1024):
+    p = BatchParams()
+    p.window, p.cost_scale, p.cost_trunc, p.num_scales = window, cost_scale, cost_trunc, num_scales
+    its = list(iters) if hasattr(iters, "__len__") else [int(iters)] * num_scales
+    for i in range(8):
+        p.iters[i] = its[i] if i < len(its) else 0
+    p.lambda_, p.trunc, p.skip_mode, p.converge_iters = lam, trunc, skip_mode, converge_iters
+    return p
+
+
+class Batch:
+    """A batch of pairs with its GPU buffers: per-pair cost volumes and disparities and the
+    workspace of bp_solve_batched.  lefts/rights: lists of uint8 [H, W] GPU tensors."""
+
+    def __init__(self, lefts, rights, num_disps, params):
+        if not (len(lefts) == len(rights) == len(num_disps)) or not lefts:
+            raise ValueError("lefts, rights and num_disps must be non-empty lists of one length")
+        lib = _load()
+        _batch_sigs(lib)
+        self.params = params
+        self.lefts, self.rights = list(lefts), list(rights)
+        self.costs, self.disps = [], []
+        n = len(lefts)
+        self.descs = (PairDesc * n)()
+        for i, (l, r, D) in enumerate(zip(lefts, rights, num_disps)):
+            H, W = l.shape
+            if tuple(r.shape) != (H, W):
+                raise ValueError(f"pair {i}: left and right differ in shape")
+            c = torch.empty((H, W, D), dtype=torch.int16, device=l.device)
+            d = torch.empty((H, W), dtype=torch.int16, device=l.device)
+            self.costs.append(c)
+            self.disps.append(d)
+            self.descs[i] = PairDesc(_dev(l, torch.uint8, 2, "left").value, _dev(r, torch.uint8, 2, "right").value,
+                                     c.data_ptr(), d.data_ptr(), W, H, D, 0)
+        need = int(lib.bp_batch_workspace_bytes(self.descs, n, ctypes.byref(params)))
+        if need == 0:
+            raise BPError(BP_E_INVAL, "invalid or unsupported batch")
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=lefts[0].device)
+
+    def solve(self, ctx, stream=None):
+        _check(_load().bp_solve_batched(ctx.handle, self.descs, len(self.descs), ctypes.byref(self.params),
+                                        ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                        _stream(stream)))
+        return self.disps
+
+    def status(self, stream=None):
+        s = ctypes.c_int32()
+        _check(_load().bp_batch_status(ctypes.c_void_p(self.workspace.data_ptr()), _stream(stream), ctypes.byref(s)))
+        return s.value
+
+    def autotune(self, ctx, stream=None):
+        t = BatchTuning()
+        _check(_load().bp_autotune_batched(ctx.handle, self.descs, len(self.descs), ctypes.byref(self.params),
+                                           ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                           _stream(stream), ctypes.byref(t)))
+        return {"candidates": [{"blocks_per_cu": t.blocks_per_cu[i], "order": t.order[i], "ms": t.ms[i]}
+                               for i in range(t.n_candidates)], "best": t.best}

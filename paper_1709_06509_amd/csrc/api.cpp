@@ -2,6 +2,7 @@
 // workspace carving, the per-scale launch sequence and optional event timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -124,6 +125,18 @@ struct bp_context {
     bool graphs = false;
     std::vector<std::pair<SolveKey, hipGraphExec_t>> cache;  // oldest first
     long long graph_hits = 0, graph_captures = 0, graph_fallbacks = 0;
+    // batched solve: pinned staging for the per-batch tables (two, each guarded by the event
+    // of its last upload), tuned launch shapes and captured graphs
+    void* staging[2] = {nullptr, nullptr};
+    size_t staging_bytes[2] = {0, 0};
+    hipEvent_t staging_done[2] = {nullptr, nullptr};
+    int staging_next = 0;
+    struct Tuned {
+        std::vector<int32_t> sig;
+        int bpc, order;
+    };
+    std::vector<Tuned> tuned;
+    std::vector<std::pair<std::vector<char>, hipGraphExec_t>> batch_graphs;
 };
 
 namespace {
@@ -172,6 +185,14 @@ BP_API int32_t bp_context_destroy(bp_context* ctx)
         (void)hipEventDestroy(e.second);
     }
     for (auto& e : ctx->cache) (void)hipGraphExecDestroy(e.second);
+    for (auto& e : ctx->batch_graphs) (void)hipGraphExecDestroy(e.second);
+    for (int i = 0; i < 2; ++i) {
+        if (ctx->staging_done[i]) {
+            (void)hipEventSynchronize(ctx->staging_done[i]);
+            (void)hipEventDestroy(ctx->staging_done[i]);
+        }
+        if (ctx->staging[i]) (void)hipHostFree(ctx->staging[i]);
+    }
     delete ctx;
     return ok();
 }
@@ -444,5 +465,418 @@ BP_API int32_t bp_energy(const int16_t* cost, const int16_t* disparity, int32_t 
     if (reinterpret_cast<uintptr_t>(workspace) % 8 != 0) return fail(BP_E_WORKSPACE, "workspace must be 8-byte aligned");
     HIP_TRY(bpst::launch_energy(cost, disparity, width, height, num_disp, lambda, trunc, energy, workspace,
                                 (hipStream_t)stream));
+    return ok();
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched solve
+// ---------------------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kBatchHeader = 256;  // barrier[2] (u32) at 0, error flag (i32) at 8
+
+struct BatchPlan {
+    int n = 0, L = 0, nphases = 0, ncc_total = 0, max_d = 0;
+    size_t off_ncc = 0, off_pairs = 0, off_phases = 0, off_tiles = 0, off_ncc_tiles = 0;
+    size_t table_end = 0, total = 0, lds = 0;
+    std::vector<size_t> pair_off;
+    std::vector<Plan> plans;
+    std::vector<bpst::PhaseDesc> phases;
+    std::vector<int> tiles;      // nphases x (n + 1)
+    std::vector<int> ncc_tiles;  // n + 1
+};
+
+bp_params pair_params(const bp_pair_desc& d, const bp_batch_params* p)
+{
+    bp_params q{};
+    q.num_disp = d.num_disp;
+    q.num_scales = p->num_scales;
+    for (int l = 0; l < 8; ++l) q.iters[l] = p->iters[l];
+    q.lambda = p->lambda;
+    q.trunc = p->trunc;
+    q.skip_mode = p->skip_mode;
+    q.converge_iters = p->converge_iters;
+    q.warm_msgs = nullptr;
+    return q;
+}
+
+size_t tree_lds_bytes(int L, int G)
+{
+    const long long s1 = 1LL << (L - 2), s2 = s1 / 2;
+    return (size_t)(s1 * s1 + s2 * s2) * 8 * G * sizeof(int);
+}
+
+// Validates the batch and lays out its workspace; returns 0 or a BP_E_* code.
+int32_t plan_batch(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* p, BatchPlan* bp, bool check_ptrs)
+{
+    if (!pairs || !p) return fail(BP_E_INVAL, "pairs/params is NULL");
+    if (n < 1 || n > 65536) return fail(BP_E_INVAL, "n must be in 1..65536");
+    if (p->window < 1 || p->window > 13 || (p->window & 1) == 0) return fail(BP_E_INVAL, "window must be odd, 1..13");
+    if (p->cost_scale < 1 || p->cost_scale > 4096) return fail(BP_E_INVAL, "cost_scale must be in 1..4096");
+    if (p->cost_trunc < 0 || p->cost_trunc > 32767) return fail(BP_E_INVAL, "cost_trunc must be in 0..32767");
+    if (p->num_scales < 2) return fail(BP_E_UNSUPPORTED, "a batch needs num_scales >= 2");
+    BatchPlan& b = *bp;
+    b.n = n;
+    b.L = p->num_scales;
+    b.plans.resize(n);
+    b.pair_off.resize(n);
+    std::string why;
+    for (int i = 0; i < n; ++i) {
+        const bp_pair_desc& d = pairs[i];
+        const bp_params q = pair_params(d, p);
+        if (!params_valid(d.width, d.height, &q, &why)) return fail(BP_E_INVAL, "pair %d: %s", i, why.c_str());
+        if (check_ptrs && (!d.left || !d.right || !d.cost || !d.disparity))
+            return fail(BP_E_INVAL, "pair %d: a pointer is NULL", i);
+        b.plans[i] = make_plan(d.width, d.height, &q);
+        if (tree_lds_bytes(b.L, b.plans[i].G) > 64 * 1024)
+            return fail(BP_E_UNSUPPORTED, "pair %d: D=%d with %d scales exceeds the pyramid's LDS", i, d.num_disp, b.L);
+        b.lds = std::max(b.lds, tree_lds_bytes(b.L, b.plans[i].G));
+        b.max_d = std::max(b.max_d, d.num_disp);
+    }
+    // phase sequence (the same as a single solve without a warm start)
+    b.phases.push_back({bpst::kPhPyramid, 0, 0, 0, 0});
+    for (int l = b.L - 1; l >= 0; --l) {
+        const bool fuse = p->iters[l] >= 2 && p->skip_mode != 2;
+        if (!fuse) b.phases.push_back({bpst::kPhInit, l, 0, bpst::kSrcOwn, 0});
+        for (int t = 0; t < p->iters[l]; ++t) {
+            int src = bpst::kSrcOwn;
+            if (t == 0 && fuse) src = (l == b.L - 1) ? bpst::kSrcZero : bpst::kSrcParent;
+            b.phases.push_back({bpst::kPhHalfstep, l, t, src, 0});
+        }
+    }
+    b.phases.push_back({bpst::kPhWta, 0, 0, 0, 0});
+    b.nphases = (int)b.phases.size();
+    b.tiles.assign((size_t)b.nphases * (n + 1), 0);
+    for (int ph = 0; ph < b.nphases; ++ph) {
+        bpst::PhaseDesc& d = b.phases[ph];
+        d.table = ph * (n + 1);
+        int* ts = &b.tiles[(size_t)ph * (n + 1)];
+        long long acc = 0;
+        for (int i = 0; i < n; ++i) {
+            ts[i] = (int)acc;
+            const Plan& pl = b.plans[i];
+            const long long px = bpst::kThreadsPerTile / pl.G;
+            const bpst::Level& lv = pl.lv[d.level];
+            long long nt = 0;
+            switch (d.type) {
+            case bpst::kPhPyramid: nt = (long long)pl.lv[b.L - 1].W * pl.lv[b.L - 1].H; break;
+            case bpst::kPhInit:
+            case bpst::kPhWta: nt = (lv.slots() + px - 1) / px; break;
+            case bpst::kPhHalfstep: nt = ((long long)lv.H * lv.Wh + px - 1) / px; break;
+            }
+            acc += nt;
+            if (acc > 2000000000LL) return fail(BP_E_UNSUPPORTED, "batch too large for one launch");
+        }
+        ts[n] = (int)acc;
+    }
+    b.ncc_tiles.assign(n + 1, 0);
+    long long acc = 0;
+    for (int i = 0; i < n; ++i) {
+        b.ncc_tiles[i] = (int)acc;
+        acc += bpst::ncc_tiles(pairs[i].width, pairs[i].height);
+    }
+    b.ncc_tiles[n] = (int)acc;
+    b.ncc_total = (int)acc;
+    // workspace: header | NccPair[n] | PairDev[n] | PhaseDesc[] | tiles | ncc tiles | pair regions
+    size_t o = kBatchHeader;
+    b.off_ncc = o;
+    o = align_up(o + sizeof(bpst::NccPair) * n);
+    b.off_pairs = o;
+    o = align_up(o + sizeof(bpst::PairDev) * n);
+    b.off_phases = o;
+    o = align_up(o + sizeof(bpst::PhaseDesc) * b.nphases);
+    b.off_tiles = o;
+    o = align_up(o + sizeof(int) * b.tiles.size());
+    b.off_ncc_tiles = o;
+    o = align_up(o + sizeof(int) * b.ncc_tiles.size());
+    b.table_end = o;
+    for (int i = 0; i < n; ++i) {
+        b.pair_off[i] = o;
+        o = align_up(o + b.plans[i].total);
+    }
+    b.total = o;
+    return BP_OK;
+}
+
+// Host image of the table region [kBatchHeader, table_end) for workspace base ws.
+void fill_tables(const BatchPlan& b, const bp_pair_desc* pairs, char* ws, std::vector<char>* img)
+{
+    img->assign(b.table_end - kBatchHeader, 0);
+    char* base = img->data() - kBatchHeader;  // so that base + off matches workspace offsets
+    auto* ncc = reinterpret_cast<bpst::NccPair*>(base + b.off_ncc);
+    auto* pd = reinterpret_cast<bpst::PairDev*>(base + b.off_pairs);
+    for (int i = 0; i < b.n; ++i) {
+        const bp_pair_desc& d = pairs[i];
+        const Plan& pl = b.plans[i];
+        char* r = ws + b.pair_off[i];
+        ncc[i] = bpst::NccPair{d.left, d.right, d.cost, d.width, d.height, d.num_disp, 0};
+        bpst::PairDev q{};
+        q.cost = d.cost;
+        q.disparity = d.disparity;
+        for (int l = 0; l < pl.L; ++l) {
+            q.c[l] = reinterpret_cast<int16_t*>(r + pl.off_cost[l]);
+            q.lv[l] = pl.lv[l];
+            q.vol[l] = pl.vol[l];
+        }
+        q.m[0] = reinterpret_cast<int16_t*>(r + pl.off_msgs[0]);
+        q.m[1] = reinterpret_cast<int16_t*>(r + pl.off_msgs[1]);
+        q.sa = reinterpret_cast<uint8_t*>(r + pl.off_sa);
+        q.sb = reinterpret_cast<uint8_t*>(r + pl.off_sb);
+        q.D = pl.D;
+        q.G = pl.G;
+        q.vec = (pl.D % 8 == 0) && ((reinterpret_cast<uintptr_t>(d.cost) & 15) == 0);
+        pd[i] = q;
+    }
+    std::memcpy(base + b.off_phases, b.phases.data(), sizeof(bpst::PhaseDesc) * b.nphases);
+    std::memcpy(base + b.off_tiles, b.tiles.data(), sizeof(int) * b.tiles.size());
+    std::memcpy(base + b.off_ncc_tiles, b.ncc_tiles.data(), sizeof(int) * b.ncc_tiles.size());
+}
+
+std::vector<int32_t> batch_signature(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* p)
+{
+    std::vector<int32_t> s;
+    s.reserve(3 * n + 32);
+    s.push_back(n);
+    const int32_t* pp = reinterpret_cast<const int32_t*>(p);
+    for (size_t i = 0; i < sizeof(bp_batch_params) / 4; ++i) s.push_back(pp[i]);
+    for (int i = 0; i < n; ++i) {
+        s.push_back(pairs[i].width);
+        s.push_back(pairs[i].height);
+        s.push_back(pairs[i].num_disp);
+    }
+    return s;
+}
+
+int32_t device_limits(int mode, size_t lds, int* cus, int* max_bpc, long long* ticks_per_s)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    *ticks_per_s = (long long)(khz > 0 ? khz : 100000) * 1000LL;
+    HIP_TRY(bpst::batch_max_blocks_per_cu(mode, lds, max_bpc));
+    if (*max_bpc < 1) return fail(BP_E_UNSUPPORTED, "the persistent kernel cannot be resident");
+    return BP_OK;
+}
+
+// Upload the tables through a pinned staging buffer, stream-ordered.
+int32_t upload_tables(bp_context* ctx, const std::vector<char>& img, char* ws, hipStream_t st)
+{
+    const int i = ctx->staging_next;
+    ctx->staging_next ^= 1;
+    if (ctx->staging_done[i]) HIP_TRY(hipEventSynchronize(ctx->staging_done[i]));  // previous copy finished
+    else HIP_TRY(hipEventCreateWithFlags(&ctx->staging_done[i], hipEventDisableTiming));
+    if (ctx->staging_bytes[i] < img.size()) {
+        if (ctx->staging[i]) HIP_TRY(hipHostFree(ctx->staging[i]));
+        ctx->staging[i] = nullptr;
+        ctx->staging_bytes[i] = 0;
+        HIP_TRY(hipHostMalloc(&ctx->staging[i], img.size(), hipHostMallocDefault));
+        ctx->staging_bytes[i] = img.size();
+    }
+    std::memcpy(ctx->staging[i], img.data(), img.size());
+    HIP_TRY(hipMemcpyAsync(ws + kBatchHeader, ctx->staging[i], img.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(ctx->staging_done[i], st));
+    return BP_OK;
+}
+
+bpst::BatchArgs batch_args(const BatchPlan& b, const bp_batch_params* p, char* ws, int order, long long ticks)
+{
+    bpst::BatchArgs a{};
+    a.pairs = reinterpret_cast<const bpst::PairDev*>(ws + b.off_pairs);
+    a.phases = reinterpret_cast<const bpst::PhaseDesc*>(ws + b.off_phases);
+    a.tiles = reinterpret_cast<const int*>(ws + b.off_tiles);
+    a.npairs = b.n;
+    a.nphases = b.nphases;
+    a.L = b.L;
+    a.lambda = p->lambda;
+    // min(T, D) differs per pair only when T exceeds some pair's D; the clamp value is
+    // min(lambda * T, 32767) either way unless T >= D, where the clamp never binds
+    const long long lt = (long long)p->lambda * p->trunc;
+    a.capv = (int)(lt < 32767 ? lt : 32767);
+    a.K = p->converge_iters;
+    a.mode = p->skip_mode;
+    a.order = order;
+    a.barrier = reinterpret_cast<unsigned*>(ws);
+    a.error = reinterpret_cast<int*>(ws + 8);
+    a.timeout_ticks = ticks * 10;  // 10 s
+    return a;
+}
+
+int32_t enqueue_batch(const BatchPlan& b, const bp_batch_params* p, char* ws, int bpc, int order, int cus,
+                      long long ticks, hipStream_t st)
+{
+    const bpst::BatchArgs a = batch_args(b, p, ws, order, ticks);
+    HIP_TRY(bpst::launch_batch_reset(reinterpret_cast<unsigned*>(ws), reinterpret_cast<int*>(ws + 8), st));
+    HIP_TRY(bpst::launch_ncc_batched(reinterpret_cast<const bpst::NccPair*>(ws + b.off_ncc),
+                                     reinterpret_cast<const int*>(ws + b.off_ncc_tiles), b.n, b.ncc_total, b.max_d,
+                                     p->window, p->cost_scale, p->cost_trunc, st));
+    int blocks = bpc * cus;
+    if (order == 1) blocks = std::max(bpst::kXcds, blocks / bpst::kXcds * bpst::kXcds);
+    HIP_TRY(bpst::launch_batch_solve(a, blocks, b.lds, st));
+    return BP_OK;
+}
+
+}  // namespace
+
+BP_API size_t bp_batch_workspace_bytes(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params)
+{
+    BatchPlan b;
+    if (plan_batch(pairs, n, params, &b, false) != BP_OK) return 0;
+    return b.total;
+}
+
+BP_API int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params,
+                                void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!ctx) return fail(BP_E_INVAL, "a batched solve needs a context");
+    BatchPlan b;
+    int32_t rc = plan_batch(pairs, n, params, &b, true);
+    if (rc != BP_OK) return rc;
+    if (!workspace || workspace_bytes < b.total)
+        return fail(BP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, b.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(BP_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t st = (hipStream_t)stream;
+    int cus = 0, max_bpc = 0;
+    long long ticks = 0;
+    rc = device_limits(params->skip_mode, b.lds, &cus, &max_bpc, &ticks);
+    if (rc != BP_OK) return rc;
+    int bpc = std::min(2, max_bpc), order = 0;
+    const std::vector<int32_t> sig = batch_signature(pairs, n, params);
+    for (const auto& t : ctx->tuned)
+        if (t.sig == sig) {
+            bpc = std::min(t.bpc, max_bpc);
+            order = t.order;
+        }
+    std::vector<char> img;
+    fill_tables(b, pairs, ws, &img);
+    rc = upload_tables(ctx, img, ws, st);
+    if (rc != BP_OK) return rc;
+    if (ctx->graphs && st != nullptr) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(st, &cs));
+        if (cs == hipStreamCaptureStatusNone) {
+            // graph key: the table image (pointers and shapes), the workspace and the launch shape
+            std::vector<char> key(img);
+            const char* extra = reinterpret_cast<const char*>(&ws);
+            key.insert(key.end(), extra, extra + sizeof(ws));
+            key.insert(key.end(), reinterpret_cast<const char*>(params),
+                       reinterpret_cast<const char*>(params) + sizeof(*params));
+            const int shape[2] = {bpc, order};
+            key.insert(key.end(), reinterpret_cast<const char*>(shape), reinterpret_cast<const char*>(shape) + 8);
+            for (auto& e : ctx->batch_graphs)
+                if (e.first == key) {
+                    HIP_TRY(hipGraphLaunch(e.second, st));
+                    ctx->graph_hits++;
+                    return ok();
+                }
+            if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                const int32_t r2 = enqueue_batch(b, params, ws, bpc, order, cus, ticks, st);
+                hipGraph_t g = nullptr;
+                const hipError_t ee = hipStreamEndCapture(st, &g);
+                hipGraphExec_t ex = nullptr;
+                const bool good = r2 == BP_OK && ee == hipSuccess && g &&
+                                  hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+                if (g) (void)hipGraphDestroy(g);
+                if (good) {
+                    if (ctx->batch_graphs.size() >= kMaxGraphs) {
+                        (void)hipGraphExecDestroy(ctx->batch_graphs.front().second);
+                        ctx->batch_graphs.erase(ctx->batch_graphs.begin());
+                    }
+                    ctx->batch_graphs.emplace_back(std::move(key), ex);
+                    ctx->graph_captures++;
+                    HIP_TRY(hipGraphLaunch(ex, st));
+                    return ok();
+                }
+            }
+            (void)hipGetLastError();
+            ctx->graph_fallbacks++;
+        }
+    }
+    rc = enqueue_batch(b, params, ws, bpc, order, cus, ticks, st);
+    if (rc != BP_OK) return rc;
+    return ok();
+}
+
+BP_API int32_t bp_batch_status(const void* workspace, void* stream, int32_t* status)
+{
+    if (!workspace || !status) return fail(BP_E_INVAL, "workspace/status is NULL");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    int32_t e = 0;
+    HIP_TRY(hipMemcpy(&e, static_cast<const char*>(workspace) + 8, sizeof e, hipMemcpyDeviceToHost));
+    *status = e;
+    return ok();
+}
+
+BP_API int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, int32_t n,
+                                   const bp_batch_params* params, void* workspace, size_t workspace_bytes,
+                                   void* stream, bp_batch_tuning* out)
+{
+    if (!ctx || !out) return fail(BP_E_INVAL, "ctx/out is NULL");
+    BatchPlan b;
+    int32_t rc = plan_batch(pairs, n, params, &b, true);
+    if (rc != BP_OK) return rc;
+    if (!workspace || workspace_bytes < b.total)
+        return fail(BP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, b.total);
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t st = (hipStream_t)stream;
+    int cus = 0, max_bpc = 0;
+    long long ticks = 0;
+    rc = device_limits(params->skip_mode, b.lds, &cus, &max_bpc, &ticks);
+    if (rc != BP_OK) return rc;
+    std::vector<char> img;
+    fill_tables(b, pairs, ws, &img);
+    rc = upload_tables(ctx, img, ws, st);
+    if (rc != BP_OK) return rc;
+    std::memset(out, 0, sizeof *out);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int k = 0;
+    for (int bpc = 1; bpc <= max_bpc && k < 16; bpc = (bpc < 4 ? bpc + 1 : bpc * 2))
+        for (int order = 0; order < 2 && k < 16; ++order) {
+            out->blocks_per_cu[k] = bpc;
+            out->order[k] = order;
+            float best = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches and code
+                const bpst::BatchArgs a = batch_args(b, params, ws, order, ticks);
+                HIP_TRY(bpst::launch_batch_reset(a.barrier, a.error, st));
+                int blocks = bpc * cus;
+                if (order == 1) blocks = std::max(bpst::kXcds, blocks / bpst::kXcds * bpst::kXcds);
+                HIP_TRY(hipEventRecord(e0, st));
+                HIP_TRY(bpst::launch_batch_solve(a, blocks, b.lds, st));
+                HIP_TRY(hipEventRecord(e1, st));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                best = std::min(best, ms);
+            }
+            int32_t err = 0;
+            HIP_TRY(hipMemcpy(&err, ws + 8, sizeof err, hipMemcpyDeviceToHost));
+            out->ms[k] = err ? 1e30f : best;
+            ++k;
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    out->n_candidates = k;
+    int bi = 0;
+    for (int i = 1; i < k; ++i)
+        if (out->ms[i] < out->ms[bi]) bi = i;
+    out->best = bi;
+    const std::vector<int32_t> sig = batch_signature(pairs, n, params);
+    bool found = false;
+    for (auto& t : ctx->tuned)
+        if (t.sig == sig) {
+            t.bpc = out->blocks_per_cu[bi];
+            t.order = out->order[bi];
+            found = true;
+        }
+    if (!found) ctx->tuned.push_back({sig, out->blocks_per_cu[bi], out->order[bi]});
+    // leave the workspace holding a complete solve of the batch
+    rc = enqueue_batch(b, params, ws, out->blocks_per_cu[bi], out->order[bi], cus, ticks, st);
+    if (rc != BP_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
     return ok();
 }

@@ -66,6 +66,58 @@ struct PyramidArgs {
     int L, D;
 };
 
+// ---- batched solve ----
+struct NccPair {
+    const uint8_t* left;
+    const uint8_t* right;
+    int16_t* cost;
+    int W, H, D, pad_;
+};
+
+// One pair of a batch as the persistent kernel sees it.
+struct PairDev {
+    const int16_t* cost;      // caller's finest cost [H][W][D]
+    int16_t* disparity;       // caller's output [H][W]
+    int16_t* c[kMaxScales];   // internal cost of every scale
+    int16_t* m[2];            // message buffers (even scales in 0, odd in 1)
+    uint8_t* sa;
+    uint8_t* sb;
+    Level lv[kMaxScales];
+    long long vol[kMaxScales];
+    int D, G, vec, pad_;      // vec: the caller's cost allows 16-byte loads
+};
+
+enum PhaseType { kPhPyramid = 0, kPhInit = 1, kPhHalfstep = 2, kPhWta = 3 };
+
+// One phase of the batched solve; all pairs run it before any pair starts the next.
+struct PhaseDesc {
+    int type, level, t, source;
+    int table;  // offset in BatchArgs::tiles of this phase's prefix sums (npairs + 1 ints)
+};
+
+struct BatchArgs {
+    const PairDev* pairs;
+    const PhaseDesc* phases;
+    const int* tiles;
+    int npairs, nphases, L;
+    int lambda, capv, K, mode;
+    int order;                // 0: tiles dealt round-robin to workgroups; 1: one contiguous chunk per XCD
+    unsigned* barrier;        // [0] arrivals, [1] generation
+    int* error;               // set when a grid barrier times out
+    long long timeout_ticks;  // of the wall clock
+};
+
+constexpr int kXcds = 8;
+constexpr int kThreadsPerTile = 256;  // workgroup size of every pixel kernel: a tile is 256 / G pixels
+
+int ncc_tiles(int W, int H);
+hipError_t launch_ncc_batched(const NccPair* pairs, const int* tile_start, int n, int total_tiles, int max_d, int win,
+                              int scale, int trunc, hipStream_t st);
+hipError_t launch_batch_reset(unsigned* barrier, int* error, hipStream_t st);
+// Largest co-resident grid of the persistent kernel for `lds` bytes of LDS per workgroup.
+hipError_t batch_max_blocks_per_cu(int mode, size_t lds, int* blocks);
+hipError_t launch_batch_solve(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
+
 // Launchers (return hipError_t of the launch).
 // launch_pyramid_tree: re-layout of the finest scale plus every coarser scale in one launch;
 // sets *done = false (and launches nothing) when the block of one coarsest pixel does not

@@ -35,15 +35,12 @@ __device__ bool le_times_sqrt(long long B, long long A, unsigned long long P)
     return B >= 0 ? false : (b2 >= a2p);
 }
 
-__global__ __launch_bounds__(kThreads) void k_ncc(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R,
-                                                   int W, int H, int D, int win, int scale, int trunc,
-                                                   float margin, int16_t* __restrict__ cost,
-                                                   float* __restrict__ ncc_out)
+// One tile: image row y, columns x0 .. x0 + kTileX - 1 (clipped), every disparity.
+__device__ void ncc_tile(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R, int W, int H, int D, int win,
+                         int scale, int trunc, float margin, int16_t* __restrict__ cost,
+                         float* __restrict__ ncc_out, int y, int x0, unsigned* smem)
 {
-    extern __shared__ unsigned smem[];
     const int r = win >> 1;
-    const int y = blockIdx.y;
-    const int x0 = blockIdx.x * kTileX;
     const int nI = kTileX + 2 * r;          // left columns  x0-r .. x0+kTileX-1+r
     const int nJ = kTileX + 2 * r + D - 1;  // right columns x0-r-(D-1) .. x0+kTileX-1+r
     const int uI0 = x0 - r, uJ0 = x0 - r - (D - 1);
@@ -153,19 +150,67 @@ __global__ __launch_bounds__(kThreads) void k_ncc(const uint8_t* __restrict__ L,
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_ncc(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R,
+                                                   int W, int H, int D, int win, int scale, int trunc,
+                                                   float margin, int16_t* __restrict__ cost,
+                                                   float* __restrict__ ncc_out)
+{
+    extern __shared__ unsigned smem[];
+    ncc_tile(L, R, W, H, D, win, scale, trunc, margin, cost, ncc_out, blockIdx.y, blockIdx.x * kTileX, smem);
+}
+
+// Every tile of every pair of a batch in one launch; tile_start[p] is the first tile of
+// pair p (prefix sums, tile_start[n] = total), a pair's tiles run row-major over
+// (row, column tile).
+__global__ __launch_bounds__(kThreads) void k_ncc_batched(const NccPair* __restrict__ pairs, const int* tile_start,
+                                                           int n, int win, int scale, int trunc, float margin)
+{
+    extern __shared__ unsigned smem[];
+    const int tile = blockIdx.x;
+    int lo = 0, hi = n;  // find p with tile_start[p] <= tile < tile_start[p + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_start[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    const NccPair P = pairs[lo];
+    const int local = tile - tile_start[lo];
+    const int tx = (P.W + kTileX - 1) / kTileX;
+    const int y = local / tx, x0 = (local - y * tx) * kTileX;
+    ncc_tile(P.left, P.right, P.W, P.H, P.D, win, scale, trunc, margin, P.cost, nullptr, y, x0, smem);
+}
+
+size_t ncc_lds_bytes(int D, int win)
+{
+    const int r = win >> 1;
+    const int nI = kTileX + 2 * r, nJ = kTileX + 2 * r + D - 1;
+    return (size_t)(nI + nJ) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 + (size_t)2 * kTileX * 4 +
+           (size_t)2 * (kTileX + D - 1) * 4 + (size_t)nI * D * 4;
+}
+
+float ncc_margin(int scale) { return 1e-4f + 2e-6f * (float)(2 * scale + 1); }
+
 }  // namespace
+
+int ncc_tiles(int W, int H) { return H * ((W + kTileX - 1) / kTileX); }
 
 hipError_t launch_ncc(const uint8_t* L, const uint8_t* R, int W, int H, int D, int win, int scale, int trunc,
                       int16_t* cost, float* ncc, hipStream_t st)
 {
-    const int r = win >> 1;
-    if (r > kMaxR) return hipErrorInvalidValue;
-    const int nI = kTileX + 2 * r, nJ = kTileX + 2 * r + D - 1;
-    const size_t lds = (size_t)(nI + nJ) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 + (size_t)2 * kTileX * 4 +
-                       (size_t)2 * (kTileX + D - 1) * 4 + (size_t)nI * D * 4;
+    if ((win >> 1) > kMaxR) return hipErrorInvalidValue;
     dim3 grid((unsigned)((W + kTileX - 1) / kTileX), (unsigned)H);
-    const float margin = 1e-4f + 2e-6f * (float)(2 * scale + 1);
-    hipLaunchKernelGGL(k_ncc, grid, dim3(kThreads), lds, st, L, R, W, H, D, win, scale, trunc, margin, cost, ncc);
+    hipLaunchKernelGGL(k_ncc, grid, dim3(kThreads), ncc_lds_bytes(D, win), st, L, R, W, H, D, win, scale, trunc,
+                       ncc_margin(scale), cost, ncc);
+    return hipGetLastError();
+}
+
+hipError_t launch_ncc_batched(const NccPair* pairs, const int* tile_start, int n, int total_tiles, int max_d, int win,
+                              int scale, int trunc, hipStream_t st)
+{
+    if ((win >> 1) > kMaxR) return hipErrorInvalidValue;
+    if (total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ncc_batched, dim3((unsigned)total_tiles), dim3(kThreads), ncc_lds_bytes(max_d, win), st,
+                       pairs, tile_start, n, win, scale, trunc, ncc_margin(scale));
     return hipGetLastError();
 }
 

@@ -1,0 +1,116 @@
+"""GPU parity of the batched persistent solve.
+
+Every pair of a batch must come out bit-identical to the CPU oracle (small pairs) and to
+its own solo GPU solve (larger pairs); reordering the batch or changing the tuned launch
+shape must not change any pair's result.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1709_06509_amd import bpstereo as B
+from paper_1709_06509_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def small_pairs():
+    shapes = [(40, 32, 16), (64, 48, 32), (33, 21, 64), (48, 40, 8), (17, 29, 16), (70, 22, 5), (24, 24, 24)]
+    out = []
+    for i, (W, H, D) in enumerate(shapes):
+        p = synth.make_pair(W, H, D, (3, 5), False, 0, False, seed=500 + i)
+        out.append((p["left"], p["right"], D))
+    return out
+
+
+@pytest.mark.parametrize("skip", [0, 1, 2])
+def test_batch_matches_oracle(skip):
+    pairs = small_pairs()
+    params = B.make_batch_params(5, 3, [6, 5, 4], 64, 4, skip_mode=skip)
+    say(f"batch of {len(pairs)} small pairs, skip={skip}")
+    batch = B.Batch([gpu(l) for l, _, _ in pairs], [gpu(r) for _, r, _ in pairs], [D for _, _, D in pairs], params)
+    ctx = B.Context()
+    batch.solve(ctx)
+    assert batch.status() == 0
+    for i, (l, r, D) in enumerate(pairs):
+        c = oracle.cost_volume(l, r, D, 5)
+        assert np.array_equal(host(batch.costs[i]), c), f"pair {i} cost"
+        d, _, _ = oracle.bp_solve(c, 3, [6, 5, 4], 64, 4, skip, 2, want_msgs=False)
+        assert np.array_equal(host(batch.disps[i]), d), f"pair {i} disparity"
+
+
+def batch_of_generator_pairs(n, seed0):
+    pairs = [synth.batch_pair(i, seed0) for i in range(n)]
+    return [gpu(p["left"]) for p in pairs], [gpu(p["right"]) for p in pairs], [p["num_disp"] for p in pairs]
+
+
+def solo(left, right, D, w):
+    cost = B.stereo_cost_volume(left, right, D, w["window"])
+    d, _, _ = B.bp_hierarchical_solve(cost, w["num_scales"], w["iters"], w["lam"], w["trunc"], w["skip"])
+    return cost, d
+
+
+def test_batch_matches_solo_solves_and_permutation():
+    w = dict(synth.BATCH)
+    lefts, rights, Ds = batch_of_generator_pairs(12, w["seed0"])
+    say("batch of 12 generator pairs vs solo solves")
+    params = B.make_batch_params(w["window"], w["num_scales"], w["iters"], w["lam"], w["trunc"], w["skip"])
+    batch = B.Batch(lefts, rights, Ds, params)
+    ctx = B.Context()
+    batch.solve(ctx)
+    assert batch.status() == 0
+    for i in range(len(lefts)):
+        c, d = solo(lefts[i], rights[i], Ds[i], w)
+        assert torch.equal(batch.costs[i], c), f"pair {i} cost"
+        assert torch.equal(batch.disps[i], d), f"pair {i} disparity"
+    perm = [5, 0, 11, 3, 7, 1, 9, 2, 10, 4, 8, 6]
+    say("permuted batch")
+    b2 = B.Batch([lefts[j] for j in perm], [rights[j] for j in perm], [Ds[j] for j in perm], params)
+    b2.solve(ctx)
+    assert b2.status() == 0
+    for k, j in enumerate(perm):
+        assert torch.equal(b2.disps[k], batch.disps[j])
+
+
+def test_batch_autotune_and_graph_replay():
+    w = dict(synth.BATCH)
+    lefts, rights, Ds = batch_of_generator_pairs(8, 2000)
+    params = B.make_batch_params(w["window"], w["num_scales"], w["iters"], w["lam"], w["trunc"], 1)
+    batch = B.Batch(lefts, rights, Ds, params)
+    ctx = B.Context()
+    batch.solve(ctx)
+    ref = [d.clone() for d in batch.disps]
+    say("autotune 8 pairs")
+    tune = batch.autotune(ctx)
+    assert tune["candidates"] and all(c["ms"] < 1e29 for c in tune["candidates"])
+    assert all(torch.equal(a, b) for a, b in zip(batch.disps, ref))
+    ctx.set_graphs(True)
+    s = torch.cuda.Stream()
+    say("graph replays of the batch")
+    with torch.cuda.stream(s):
+        for rep in range(3):
+            for d in batch.disps:
+                d.fill_(-1)
+            batch.solve(ctx, stream=s)
+            torch.cuda.synchronize()
+            assert batch.status(stream=s) == 0
+            assert all(torch.equal(a, b) for a, b in zip(batch.disps, ref)), f"replay {rep}"
+    counts = ctx.graph_counts()
+    assert counts["captures"] == 1 and counts["replays"] == 2
