@@ -27,7 +27,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="production", choices=["production", "tiny", "large"])
+    ap.add_argument("--workload", default="production", choices=["production", "tiny", "large", "batched"])
+    ap.add_argument("--batch-pairs", type=int, default=256, help="pairs of the batched workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-checker sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-checker leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -76,11 +77,91 @@ def cpu_baseline(w, seconds):
                       f"solve, skip={w['skip']} + energy), single-threaded, {el:.1f} s"}
 
 
+def plain_counts(W, H, levels, iters):
+    """Pixel and directed-message updates of plain BP on a W x H pair (no skipping): half-step t
+    updates the pixels of one colour and sends one message along every 4-edge."""
+    pix = msg = 0
+    for l in range(levels):
+        w, h = W, H
+        for _ in range(l):
+            w, h = (w + 1) // 2, (h + 1) // 2
+        edges = (w - 1) * h + w * (h - 1)
+        n0 = (w * h + 1) // 2
+        for t in range(iters[l]):
+            pix += n0 if t % 2 == 0 else w * h - n0
+            msg += edges
+    return pix, msg
+
+
+def run_batched(args):
+    import torch
+
+    from paper_1709_06509_amd import bpstereo as B
+    from paper_1709_06509_amd import synth
+
+    w = dict(synth.BATCH)
+    n = args.batch_pairs
+    dev = torch.device("cuda:0")
+    pairs = [synth.batch_pair(i, w["seed0"]) for i in range(n)]
+    lefts = [torch.from_numpy(p["left"]).to(dev) for p in pairs]
+    rights = [torch.from_numpy(p["right"]).to(dev) for p in pairs]
+    Ds = [p["num_disp"] for p in pairs]
+    L, iters = w["num_scales"], [w["iters"]] * w["num_scales"]
+    params = B.make_batch_params(w["window"], L, iters, w["lam"], w["trunc"], w["skip"], 2, w["cost_scale"],
+                                 w["cost_trunc"])
+    batch = B.Batch(lefts, rights, Ds, params)
+    ctx = B.Context()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch.solve(ctx, stream)
+        tune = batch.autotune(ctx, stream)
+        ctx.set_graphs(True)
+        for _ in range(max(1, args.warmup // 10)):
+            batch.solve(ctx, stream)
+        torch.cuda.synchronize()
+        steps = max(1, args.steps // 20)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch.solve(ctx, stream)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        status = batch.status(stream)
+    best = tune["candidates"][tune["best"]]
+    msgs = byts = 0
+    for p, D in zip(pairs, Ds):
+        H, W = p["left"].shape
+        pix, m = plain_counts(W, H, L, iters)
+        msgs += m
+        byts += 18 * D * pix
+    per_batch = elapsed / steps
+    achieved = byts / (best["ms"] / 1e3) / 1e9
+    return {
+        "metric": METRIC, "value": n / per_batch, "unit": "pairs/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": per_batch * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int16", "data": "synthetic",
+        "config": {"workload": f"batched: {n} pairs, W 160..640, H 128..480 (step 16), D in {{16,32,64}}, "
+                               f"{w['window']}x{w['window']} NCC, {L} scales x {w['iters']} half-steps, skip={w['skip']}, "
+                               f"seeds {w['seed0']}..{w['seed0'] + n - 1}", "pairs_per_step": n},
+        "gmsg_updates_per_s": msgs / per_batch / 1e9,
+        "batch_status": status,
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_batch_phase (one launch per phase" if best["schedule"] == 1 else
+                                f"k_batch_solve (one persistent launch, {best['blocks_per_cu']} workgroups/CU") +
+                               "; half-step bytes only, time of the whole solve part)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "avg_launch_us": best["ms"] * 1e3, "algorithmic_bytes_per_launch": byts},
+        "autotune": tune,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args)))
+        return
     import numpy as np
     import torch
 

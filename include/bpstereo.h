@@ -220,21 +220,28 @@ int32_t bp_batch_status(const void* workspace, void* stream, int32_t* status);
 /* Launch shapes tried by the autotuner, with their measured time. */
 typedef struct {
     int32_t n_candidates;
-    int32_t blocks_per_cu[16]; /* resident workgroups per compute unit */
+    int32_t schedule[16];      /* 0: one persistent launch; 1: one launch per phase (no grid barrier) */
+    int32_t blocks_per_cu[16]; /* persistent launch: resident workgroups per compute unit */
     int32_t order[16];         /* 0: tiles dealt round-robin; 1: one contiguous eighth per XCD */
     float ms[16];              /* device time of the persistent launch */
     int32_t best;              /* index of the fastest */
 } bp_batch_tuning;
 
 /*
- * Autotune the persistent launch for this batch: times every candidate shape (workgroups
- * per compute unit x tile order) on the real batch with HIP events, keeps the fastest in
- * ctx for later bp_solve_batched calls with the same pair shapes and parameters, and
- * reports the table in *out [host].  Synchronises the stream.  Results do not depend on the
- * shape chosen.
+ * Autotune the batched solve: times every candidate schedule on the real batch with HIP
+ * events (the one-launch-per-phase schedule, and the persistent launch at each number of
+ * workgroups per compute unit and tile order), keeps the fastest in ctx for later
+ * bp_solve_batched calls with the same pair shapes and parameters, and reports the table in
+ * *out [host].  Synchronises the stream.  Results do not depend on the schedule.
+ * Without tuning (or a forced shape) a batch runs as one persistent launch.
  */
 int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params,
                             void* workspace, size_t workspace_bytes, void* stream, bp_batch_tuning* out);
+
+/* Force the schedule of later batched solves on ctx (overrides tuning): schedule 0 with
+   blocks_per_cu >= 1 (capped at the resident maximum) and order 0/1, or schedule 1;
+   schedule -1 returns to the tuned or default choice. */
+int32_t bp_context_set_batch_schedule(bp_context* ctx, int32_t schedule, int32_t blocks_per_cu, int32_t order);
 
 /* Message of the last failed call on this thread ("" if none); valid until the next call. */
 const char* bp_last_error(void);

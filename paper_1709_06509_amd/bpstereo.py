@@ -266,7 +266,7 @@ class BatchParams(ctypes.Structure):
 
 
 class BatchTuning(ctypes.Structure):
-    _fields_ = [("n_candidates", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32 * 16),
+    _fields_ = [("n_candidates", ctypes.c_int32), ("schedule", ctypes.c_int32 * 16), ("blocks_per_cu", ctypes.c_int32 * 16),
                 ("order", ctypes.c_int32 * 16), ("ms", ctypes.c_float * 16), ("best", ctypes.c_int32)]
 
 
@@ -283,6 +283,8 @@ def _batch_sigs(lib):
     lib.bp_autotune_batched.argtypes = [_vp, ctypes.POINTER(PairDesc), _i32, ctypes.POINTER(BatchParams), _vp,
                                         ctypes.c_size_t, _vp, ctypes.POINTER(BatchTuning)]
     lib.bp_autotune_batched.restype = ctypes.c_int32
+    lib.bp_context_set_batch_schedule.argtypes = [_vp, _i32, _i32, _i32]
+    lib.bp_context_set_batch_schedule.restype = ctypes.c_int32
     lib._batch_ready = True
 
 
@@ -342,5 +344,13 @@ class Batch:
         _check(_load().bp_autotune_batched(ctx.handle, self.descs, len(self.descs), ctypes.byref(self.params),
                                            ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                            _stream(stream), ctypes.byref(t)))
-        return {"candidates": [{"blocks_per_cu": t.blocks_per_cu[i], "order": t.order[i], "ms": t.ms[i]}
+        return {"candidates": [{"schedule": t.schedule[i], "blocks_per_cu": t.blocks_per_cu[i], "order": t.order[i],
+                                "ms": t.ms[i]}
                                for i in range(t.n_candidates)], "best": t.best}
+
+
+def set_batch_schedule(ctx, schedule, blocks_per_cu=1, order=0):
+    """Force the schedule of later batched solves on ctx (-1: back to tuned/default)."""
+    lib = _load()
+    _batch_sigs(lib)
+    _check(lib.bp_context_set_batch_schedule(ctx.handle, schedule, blocks_per_cu, order))

@@ -133,11 +133,24 @@ struct bp_context {
     int staging_next = 0;
     struct Tuned {
         std::vector<int32_t> sig;
-        int bpc, order;
+        int bpc, order, sched;
     };
     std::vector<Tuned> tuned;
+    int forced_sched = -1, forced_bpc = 1, forced_order = 0;
     std::vector<std::pair<std::vector<char>, hipGraphExec_t>> batch_graphs;
 };
+
+BP_API int32_t bp_context_set_batch_schedule(bp_context* ctx, int32_t schedule, int32_t blocks_per_cu, int32_t order)
+{
+    if (!ctx) return fail(BP_E_INVAL, "ctx is NULL");
+    if (schedule < -1 || schedule > 1 || (schedule == 0 && (blocks_per_cu < 1 || order < 0 || order > 1)))
+        return fail(BP_E_INVAL, "schedule must be -1, 0 (with blocks_per_cu >= 1, order 0/1) or 1");
+    ctx->forced_sched = schedule;
+    ctx->forced_bpc = blocks_per_cu;
+    ctx->forced_order = order;
+    g_last_error.clear();
+    return BP_OK;
+}
 
 namespace {
 constexpr size_t kMaxGraphs = 32;
@@ -473,10 +486,11 @@ BP_API int32_t bp_energy(const int16_t* cost, const int16_t* disparity, int32_t 
 // ---------------------------------------------------------------------------------------
 namespace {
 
-constexpr size_t kBatchHeader = 256;  // barrier[2] (u32) at 0, error flag (i32) at 8
+constexpr size_t kBatchHeader = 256;    // barrier words (u32) at 0, error flag (i32) at kBatchErrorOff
+constexpr size_t kBatchErrorOff = 64;
 
 struct BatchPlan {
-    int n = 0, L = 0, nphases = 0, ncc_total = 0, max_d = 0;
+    int n = 0, L = 0, nphases = 0, ncc_total = 0, max_d = 0, gmax = 1;
     size_t off_ncc = 0, off_pairs = 0, off_phases = 0, off_tiles = 0, off_ncc_tiles = 0;
     size_t table_end = 0, total = 0, lds = 0;
     std::vector<size_t> pair_off;
@@ -532,6 +546,7 @@ int32_t plan_batch(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* 
             return fail(BP_E_UNSUPPORTED, "pair %d: D=%d with %d scales exceeds the pyramid's LDS", i, d.num_disp, b.L);
         b.lds = std::max(b.lds, tree_lds_bytes(b.L, b.plans[i].G));
         b.max_d = std::max(b.max_d, d.num_disp);
+        b.gmax = std::max(b.gmax, b.plans[i].G);
     }
     // phase sequence (the same as a single solve without a warm start)
     b.phases.push_back({bpst::kPhPyramid, 0, 0, 0, 0});
@@ -647,7 +662,7 @@ std::vector<int32_t> batch_signature(const bp_pair_desc* pairs, int32_t n, const
     return s;
 }
 
-int32_t device_limits(int mode, size_t lds, int* cus, int* max_bpc, long long* ticks_per_s)
+int32_t device_limits(int mode, int gmax, size_t lds, int* cus, int* max_bpc, long long* ticks_per_s)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -655,7 +670,7 @@ int32_t device_limits(int mode, size_t lds, int* cus, int* max_bpc, long long* t
     int khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     *ticks_per_s = (long long)(khz > 0 ? khz : 100000) * 1000LL;
-    HIP_TRY(bpst::batch_max_blocks_per_cu(mode, lds, max_bpc));
+    HIP_TRY(bpst::batch_max_blocks_per_cu(mode, gmax, lds, max_bpc));
     if (*max_bpc < 1) return fail(BP_E_UNSUPPORTED, "the persistent kernel cannot be resident");
     return BP_OK;
 }
@@ -697,24 +712,41 @@ bpst::BatchArgs batch_args(const BatchPlan& b, const bp_batch_params* p, char* w
     a.K = p->converge_iters;
     a.mode = p->skip_mode;
     a.order = order;
+    a.gmax = b.gmax;
     a.barrier = reinterpret_cast<unsigned*>(ws);
-    a.error = reinterpret_cast<int*>(ws + 8);
+    a.error = reinterpret_cast<int*>(ws + kBatchErrorOff);
     a.timeout_ticks = ticks * 10;  // 10 s
     return a;
 }
 
-int32_t enqueue_batch(const BatchPlan& b, const bp_batch_params* p, char* ws, int bpc, int order, int cus,
-                      long long ticks, hipStream_t st)
+// The solve part of a batch: schedule 0 is one persistent launch of bpc workgroups per
+// compute unit; schedule 1 is one launch per phase.
+int32_t enqueue_batch_solve(const BatchPlan& b, const bp_batch_params* p, char* ws, int sched, int bpc, int order,
+                            int cus, long long ticks, hipStream_t st)
 {
     const bpst::BatchArgs a = batch_args(b, p, ws, order, ticks);
-    HIP_TRY(bpst::launch_batch_reset(reinterpret_cast<unsigned*>(ws), reinterpret_cast<int*>(ws + 8), st));
-    HIP_TRY(bpst::launch_ncc_batched(reinterpret_cast<const bpst::NccPair*>(ws + b.off_ncc),
-                                     reinterpret_cast<const int*>(ws + b.off_ncc_tiles), b.n, b.ncc_total, b.max_d,
-                                     p->window, p->cost_scale, p->cost_trunc, st));
+    HIP_TRY(bpst::launch_batch_reset(a.barrier, a.error, st));
+    if (sched == 1) {
+        for (int ph = 0; ph < b.nphases; ++ph) {
+            const bpst::PhaseDesc& d = b.phases[ph];
+            HIP_TRY(bpst::launch_batch_phase(a, ph, d.type, d.source, b.tiles[(size_t)ph * (b.n + 1) + b.n],
+                                             b.lds, st));
+        }
+        return BP_OK;
+    }
     int blocks = bpc * cus;
     if (order == 1) blocks = std::max(bpst::kXcds, blocks / bpst::kXcds * bpst::kXcds);
     HIP_TRY(bpst::launch_batch_solve(a, blocks, b.lds, st));
     return BP_OK;
+}
+
+int32_t enqueue_batch(const BatchPlan& b, const bp_batch_params* p, char* ws, int sched, int bpc, int order, int cus,
+                      long long ticks, hipStream_t st)
+{
+    HIP_TRY(bpst::launch_ncc_batched(reinterpret_cast<const bpst::NccPair*>(ws + b.off_ncc),
+                                     reinterpret_cast<const int*>(ws + b.off_ncc_tiles), b.n, b.ncc_total, b.max_d,
+                                     p->window, p->cost_scale, p->cost_trunc, st));
+    return enqueue_batch_solve(b, p, ws, sched, bpc, order, cus, ticks, st);
 }
 
 }  // namespace
@@ -741,15 +773,21 @@ BP_API int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int3
     hipStream_t st = (hipStream_t)stream;
     int cus = 0, max_bpc = 0;
     long long ticks = 0;
-    rc = device_limits(params->skip_mode, b.lds, &cus, &max_bpc, &ticks);
+    rc = device_limits(params->skip_mode, b.gmax, b.lds, &cus, &max_bpc, &ticks);
     if (rc != BP_OK) return rc;
-    int bpc = std::min(2, max_bpc), order = 0;
+    int bpc = std::min(2, max_bpc), order = 0, sched = 0;
     const std::vector<int32_t> sig = batch_signature(pairs, n, params);
     for (const auto& t : ctx->tuned)
         if (t.sig == sig) {
             bpc = std::min(t.bpc, max_bpc);
             order = t.order;
+            sched = t.sched;
         }
+    if (ctx->forced_sched >= 0) {
+        sched = ctx->forced_sched;
+        bpc = std::min(ctx->forced_bpc, max_bpc);
+        order = ctx->forced_order;
+    }
     std::vector<char> img;
     fill_tables(b, pairs, ws, &img);
     rc = upload_tables(ctx, img, ws, st);
@@ -764,8 +802,8 @@ BP_API int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int3
             key.insert(key.end(), extra, extra + sizeof(ws));
             key.insert(key.end(), reinterpret_cast<const char*>(params),
                        reinterpret_cast<const char*>(params) + sizeof(*params));
-            const int shape[2] = {bpc, order};
-            key.insert(key.end(), reinterpret_cast<const char*>(shape), reinterpret_cast<const char*>(shape) + 8);
+            const int shape[3] = {bpc, order, sched};
+            key.insert(key.end(), reinterpret_cast<const char*>(shape), reinterpret_cast<const char*>(shape) + 12);
             for (auto& e : ctx->batch_graphs)
                 if (e.first == key) {
                     HIP_TRY(hipGraphLaunch(e.second, st));
@@ -773,7 +811,7 @@ BP_API int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int3
                     return ok();
                 }
             if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-                const int32_t r2 = enqueue_batch(b, params, ws, bpc, order, cus, ticks, st);
+                const int32_t r2 = enqueue_batch(b, params, ws, sched, bpc, order, cus, ticks, st);
                 hipGraph_t g = nullptr;
                 const hipError_t ee = hipStreamEndCapture(st, &g);
                 hipGraphExec_t ex = nullptr;
@@ -795,7 +833,7 @@ BP_API int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int3
             ctx->graph_fallbacks++;
         }
     }
-    rc = enqueue_batch(b, params, ws, bpc, order, cus, ticks, st);
+    rc = enqueue_batch(b, params, ws, sched, bpc, order, cus, ticks, st);
     if (rc != BP_OK) return rc;
     return ok();
 }
@@ -805,7 +843,7 @@ BP_API int32_t bp_batch_status(const void* workspace, void* stream, int32_t* sta
     if (!workspace || !status) return fail(BP_E_INVAL, "workspace/status is NULL");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     int32_t e = 0;
-    HIP_TRY(hipMemcpy(&e, static_cast<const char*>(workspace) + 8, sizeof e, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&e, static_cast<const char*>(workspace) + kBatchErrorOff, sizeof e, hipMemcpyDeviceToHost));
     *status = e;
     return ok();
 }
@@ -824,7 +862,7 @@ BP_API int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, i
     hipStream_t st = (hipStream_t)stream;
     int cus = 0, max_bpc = 0;
     long long ticks = 0;
-    rc = device_limits(params->skip_mode, b.lds, &cus, &max_bpc, &ticks);
+    rc = device_limits(params->skip_mode, b.gmax, b.lds, &cus, &max_bpc, &ticks);
     if (rc != BP_OK) return rc;
     std::vector<char> img;
     fill_tables(b, pairs, ws, &img);
@@ -834,30 +872,35 @@ BP_API int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, i
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    // candidates: the per-phase schedule, then the persistent launch at each shape
+    struct Cand {
+        int sched, bpc, order;
+    };
+    std::vector<Cand> cands{{1, 0, 0}};
+    for (int bpc = 1; bpc <= max_bpc; bpc = (bpc < 4 ? bpc + 1 : bpc * 2))
+        for (int order = 0; order < 2; ++order) cands.push_back({0, bpc, order});
     int k = 0;
-    for (int bpc = 1; bpc <= max_bpc && k < 16; bpc = (bpc < 4 ? bpc + 1 : bpc * 2))
-        for (int order = 0; order < 2 && k < 16; ++order) {
-            out->blocks_per_cu[k] = bpc;
-            out->order[k] = order;
-            float best = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches and code
-                const bpst::BatchArgs a = batch_args(b, params, ws, order, ticks);
-                HIP_TRY(bpst::launch_batch_reset(a.barrier, a.error, st));
-                int blocks = bpc * cus;
-                if (order == 1) blocks = std::max(bpst::kXcds, blocks / bpst::kXcds * bpst::kXcds);
-                HIP_TRY(hipEventRecord(e0, st));
-                HIP_TRY(bpst::launch_batch_solve(a, blocks, b.lds, st));
-                HIP_TRY(hipEventRecord(e1, st));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                best = std::min(best, ms);
-            }
-            int32_t err = 0;
-            HIP_TRY(hipMemcpy(&err, ws + 8, sizeof err, hipMemcpyDeviceToHost));
-            out->ms[k] = err ? 1e30f : best;
-            ++k;
+    for (const Cand& c : cands) {
+        if (k >= 16) break;
+        out->schedule[k] = c.sched;
+        out->blocks_per_cu[k] = c.bpc;
+        out->order[k] = c.order;
+        float best = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches and code
+            HIP_TRY(hipEventRecord(e0, st));
+            rc = enqueue_batch_solve(b, params, ws, c.sched, c.bpc, c.order, cus, ticks, st);
+            if (rc != BP_OK) return rc;
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
         }
+        int32_t err = 0;
+        HIP_TRY(hipMemcpy(&err, ws + kBatchErrorOff, sizeof err, hipMemcpyDeviceToHost));
+        out->ms[k] = err ? 1e30f : best;
+        ++k;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     out->n_candidates = k;
@@ -871,11 +914,12 @@ BP_API int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, i
         if (t.sig == sig) {
             t.bpc = out->blocks_per_cu[bi];
             t.order = out->order[bi];
+            t.sched = out->schedule[bi];
             found = true;
         }
-    if (!found) ctx->tuned.push_back({sig, out->blocks_per_cu[bi], out->order[bi]});
+    if (!found) ctx->tuned.push_back({sig, out->blocks_per_cu[bi], out->order[bi], out->schedule[bi]});
     // leave the workspace holding a complete solve of the batch
-    rc = enqueue_batch(b, params, ws, out->blocks_per_cu[bi], out->order[bi], cus, ticks, st);
+    rc = enqueue_batch(b, params, ws, out->schedule[bi], out->blocks_per_cu[bi], out->order[bi], cus, ticks, st);
     if (rc != BP_OK) return rc;
     HIP_TRY(hipStreamSynchronize(st));
     return ok();

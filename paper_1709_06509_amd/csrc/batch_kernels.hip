@@ -17,13 +17,14 @@
 namespace bpst {
 namespace {
 
+// barrier words: [0..7] arrivals per XCD group, [8] group arrivals, [9] generation
+constexpr int kBarGroup = 8, kBarGen = 9, kBarWords = 10;
+constexpr int kLdsPairs = 1024;  // pair tables up to this size are searched in LDS
+
 __global__ void k_batch_reset(unsigned* barrier, int* error)
 {
-    if (threadIdx.x == 0) {
-        barrier[0] = 0u;
-        barrier[1] = 0u;
-        *error = 0;
-    }
+    if (threadIdx.x < kBarWords) barrier[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) *error = 0;
 }
 
 __device__ __forceinline__ bool error_raised(const BatchArgs& a)
@@ -32,21 +33,32 @@ __device__ __forceinline__ bool error_raised(const BatchArgs& a)
 }
 
 // Grid-wide barrier: release this workgroup's writes, count in, wait for the generation
-// to advance, acquire everyone's writes.  Returns false (for the whole workgroup) on error.
+// to advance, acquire everyone's writes.  Arrivals are counted in two levels: workgroups
+// b with equal b % 8 (the workgroups of one XCD) share a counter, and the last arrival of
+// each group counts in at the group counter, so no single address takes every atomic.
+// Returns false (for the whole workgroup) on error.
 __device__ __forceinline__ bool grid_barrier(const BatchArgs& a, int* s_ok)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        unsigned* count = a.barrier;
-        unsigned* gen = a.barrier + 1;
+        unsigned* gen = a.barrier + kBarGen;
         const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
-        const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        const unsigned x = blockIdx.x % kXcds;
+        const unsigned nx = (gridDim.x - x + kXcds - 1) / kXcds;              // workgroups in group x
+        const unsigned ngroups = gridDim.x < (unsigned)kXcds ? gridDim.x : (unsigned)kXcds;
+        bool last = false;
+        if (__hip_atomic_fetch_add(a.barrier + x, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == nx - 1) {
+            __hip_atomic_store(a.barrier + x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_fetch_add(a.barrier + kBarGroup, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+                ngroups - 1) {
+                __hip_atomic_store(a.barrier + kBarGroup, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                last = true;
+            }
+        }
+        if (!last) {
             const long long t0 = (long long)wall_clock64();
             while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 if (error_raised(a)) { ok = 0; break; }
@@ -65,27 +77,24 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs& a, int* s_ok)
     return *s_ok != 0;
 }
 
-template <int G, int MODE>
-__device__ __forceinline__ void run_tile(const BatchArgs& a, const PhaseDesc& ph, const PairDev& Q, int lt, int* lds)
+// One tile of a phase whose type (and half-step message source) is known at compile time.
+template <int G, int MODE, int TYPE, int SRC>
+__device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& ph, const PairDev& Q, int lt,
+                                           int* lds)
 {
     constexpr int kPix = kThreads / G;  // pixels per tile
     const int lane = threadIdx.x & (G - 1);
     const long long gi = (long long)lt * kPix + threadIdx.x / G;
     const int l = ph.level;
-    switch (ph.type) {
-    case kPhPyramid: {
+    if (TYPE == kPhPyramid) {
         const int Wc = Q.lv[a.L - 1].W;
         if (Q.vec) pyramid_tree_block<G, true>(Q.cost, Q.c, Q.lv, a.L, Q.D, lt % Wc, lt / Wc, lds);
         else pyramid_tree_block<G, false>(Q.cost, Q.c, Q.lv, a.L, Q.D, lt % Wc, lt / Wc, lds);
-        break;
-    }
-    case kPhInit: {
+    } else if (TYPE == kPhInit) {
         const bool top = l == a.L - 1;
         init_pixel<G>(top ? nullptr : Q.m[(l + 1) & 1], Q.lv[top ? l : l + 1], top ? 0 : Q.vol[l + 1], Q.m[l & 1],
                       Q.lv[l], Q.vol[l], Q.sa, Q.sb, a.mode, gi, lane);
-        break;
-    }
-    case kPhHalfstep: {
+    } else if (TYPE == kPhHalfstep) {
         HalfstepArgs h{};
         h.cost = Q.c[l];
         h.msgs = Q.m[l & 1];
@@ -107,66 +116,148 @@ __device__ __forceinline__ void run_tile(const BatchArgs& a, const PhaseDesc& ph
         h.t = ph.t;
         h.K = a.K;
         h.mode = MODE;
-        if (ph.source == kSrcParent) halfstep_pixel<G, MODE, kSrcParent>(h, (int)gi, lane);
-        else if (ph.source == kSrcZero) halfstep_pixel<G, MODE, kSrcZero>(h, (int)gi, lane);
-        else halfstep_pixel<G, MODE, kSrcOwn>(h, (int)gi, lane);
-        break;
-    }
-    case kPhWta:
+        halfstep_pixel<G, MODE, SRC>(h, (int)gi, lane);
+    } else {
         wta_pixel<G>(Q.c[0], Q.m[0], Q.vol[0], Q.lv[0], Q.D, Q.disparity, gi, lane);
-        break;
     }
 }
 
-// Tile i of this workgroup within a phase of `total` tiles, or -1 when it has no more.
-__device__ __forceinline__ int tile_of(const BatchArgs& a, int i, int total)
+// One tile of any phase (type and source read at run time).
+template <int G, int MODE>
+__device__ __forceinline__ void run_tile(const BatchArgs& a, const PhaseDesc& ph, const PairDev& Q, int lt, int* lds)
 {
-    if (a.order == 0) {
-        const long long t = (long long)blockIdx.x + (long long)i * gridDim.x;
-        return t < total ? (int)t : -1;
+    switch (ph.type) {
+    case kPhPyramid: run_tile_t<G, MODE, kPhPyramid, kSrcOwn>(a, ph, Q, lt, lds); break;
+    case kPhInit: run_tile_t<G, MODE, kPhInit, kSrcOwn>(a, ph, Q, lt, lds); break;
+    case kPhHalfstep:
+        if (ph.source == kSrcParent) run_tile_t<G, MODE, kPhHalfstep, kSrcParent>(a, ph, Q, lt, lds);
+        else if (ph.source == kSrcZero) run_tile_t<G, MODE, kPhHalfstep, kSrcZero>(a, ph, Q, lt, lds);
+        else run_tile_t<G, MODE, kPhHalfstep, kSrcOwn>(a, ph, Q, lt, lds);
+        break;
+    default: run_tile_t<G, MODE, kPhWta, kSrcOwn>(a, ph, Q, lt, lds); break;
     }
-    // workgroup b runs on XCD b % 8: give every XCD one contiguous eighth of the tiles
-    const int per = (int)(gridDim.x / kXcds);
-    const int x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
-    const int lo = (int)((long long)total * x / kXcds), hi = (int)((long long)total * (x + 1) / kXcds);
-    const long long t = (long long)lo + j + (long long)i * per;
-    return t < hi ? (int)t : -1;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_batch_solve(BatchArgs a)
+// Each workgroup takes one contiguous chunk of a phase's tiles (mostly one pair, neighbouring
+// rows).  Order 0: chunk = workgroup index.  Order 1: the workgroups of one XCD (b % 8) take
+// adjacent chunks, so neighbouring rows share that XCD's L2.
+__device__ __forceinline__ void chunk_of(const BatchArgs& a, int total, int* lo, int* hi)
+{
+    const int nb = (int)gridDim.x;
+    int c = (int)blockIdx.x;
+    if (a.order == 1 && nb % kXcds == 0) c = (int)(blockIdx.x % kXcds) * (nb / kXcds) + (int)(blockIdx.x / kXcds);
+    *lo = (int)((long long)total * c / nb);
+    *hi = (int)((long long)total * (c + 1) / nb);
+}
+
+// Pair p with ts[p] <= tile < ts[p + 1].
+__device__ __forceinline__ int pair_of(const int* ts, int n, int tile)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ts[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int MODE, int GMAX>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_solve(BatchArgs a)
 {
     extern __shared__ int lds[];
     __shared__ int s_ok;
+    __shared__ int s_ts[kLdsPairs + 1];
+    const bool in_lds = a.npairs <= kLdsPairs;
     for (int p = 0; p < a.nphases; ++p) {
         const PhaseDesc ph = a.phases[p];
-        const int* ts = a.tiles + ph.table;
-        const int total = ts[a.npairs];
-        for (int i = 0;; ++i) {
-            const int tile = tile_of(a, i, total);
-            if (tile < 0) break;
-            int lo = 0, hi = a.npairs;  // ts[lo] <= tile < ts[lo + 1]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (ts[mid] <= tile) lo = mid;
-                else hi = mid;
-            }
-            const PairDev& Q = a.pairs[lo];
-            const int lt = tile - ts[lo];
+        const int* gts = a.tiles + ph.table;
+        if (in_lds) {
+            for (int i = threadIdx.x; i <= a.npairs; i += blockDim.x) s_ts[i] = gts[i];
+            __syncthreads();
+        }
+        const int* ts = in_lds ? s_ts : gts;
+        int lo, hi;
+        chunk_of(a, ts[a.npairs], &lo, &hi);
+        int q = lo < hi ? pair_of(ts, a.npairs, lo) : 0;
+        for (int tile = lo; tile < hi; ++tile) {
+            while (tile >= ts[q + 1]) ++q;
+            const PairDev& Q = a.pairs[q];
+            const int lt = tile - ts[q];
             switch (Q.G) {
             case 1: run_tile<1, MODE>(a, ph, Q, lt, lds); break;
             case 2: run_tile<2, MODE>(a, ph, Q, lt, lds); break;
             case 4: run_tile<4, MODE>(a, ph, Q, lt, lds); break;
             case 8: run_tile<8, MODE>(a, ph, Q, lt, lds); break;
-            case 16: run_tile<16, MODE>(a, ph, Q, lt, lds); break;
-            default: run_tile<32, MODE>(a, ph, Q, lt, lds); break;
+            case 16: if (GMAX >= 16) run_tile<16, MODE>(a, ph, Q, lt, lds); break;
+            default: if (GMAX >= 32) run_tile<32, MODE>(a, ph, Q, lt, lds); break;
             }
         }
         if (!grid_barrier(a, &s_ok)) return;
     }
 }
 
+// The other schedule: one launch per phase, one workgroup per tile of every pair.  The
+// kernel boundary orders the phases, so no grid barrier is needed.
+template <int MODE, int GMAX, int TYPE, int SRC>
+__global__ __launch_bounds__(kThreads) void k_batch_phase(BatchArgs a, int phase)
+{
+    extern __shared__ int lds[];
+    const PhaseDesc ph = a.phases[phase];
+    const int* ts = a.tiles + ph.table;
+    const int tile = blockIdx.x;
+    const int q = pair_of(ts, a.npairs, tile);
+    const PairDev& Q = a.pairs[q];
+    const int lt = tile - ts[q];
+    switch (Q.G) {
+    case 1: run_tile_t<1, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
+    case 2: run_tile_t<2, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
+    case 4: run_tile_t<4, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
+    case 8: run_tile_t<8, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
+    case 16: if (GMAX >= 16) run_tile_t<16, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
+    default: if (GMAX >= 32) run_tile_t<32, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
+    }
+}
+
+template <int MODE, int GMAX>
+static void launch_phase_m(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, hipStream_t st)
+{
+    const dim3 g((unsigned)tiles), b(kThreads);
+    switch (type) {
+    case kPhPyramid: hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhPyramid, kSrcOwn>), g, b, lds, st, a, phase); break;
+    case kPhInit: hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhInit, kSrcOwn>), g, b, 0, st, a, phase); break;
+    case kPhHalfstep:
+        if (src == kSrcParent)
+            hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcParent>), g, b, 0, st, a, phase);
+        else if (src == kSrcZero)
+            hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcZero>), g, b, 0, st, a, phase);
+        else
+            hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcOwn>), g, b, 0, st, a, phase);
+        break;
+    default: hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhWta, kSrcOwn>), g, b, 0, st, a, phase); break;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_batch_phase(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, hipStream_t st)
+{
+    if (tiles <= 0) return hipSuccess;
+    if (a.gmax <= 8) {
+        switch (a.mode) {
+        case 0: launch_phase_m<0, 8>(a, phase, type, src, tiles, lds, st); break;
+        case 1: launch_phase_m<1, 8>(a, phase, type, src, tiles, lds, st); break;
+        default: launch_phase_m<2, 8>(a, phase, type, src, tiles, lds, st); break;
+        }
+    } else {
+        switch (a.mode) {
+        case 0: launch_phase_m<0, 32>(a, phase, type, src, tiles, lds, st); break;
+        case 1: launch_phase_m<1, 32>(a, phase, type, src, tiles, lds, st); break;
+        default: launch_phase_m<2, 32>(a, phase, type, src, tiles, lds, st); break;
+        }
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_batch_reset(unsigned* barrier, int* error, hipStream_t st)
 {
@@ -174,25 +265,38 @@ hipError_t launch_batch_reset(unsigned* barrier, int* error, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t batch_max_blocks_per_cu(int mode, size_t lds, int* blocks)
+template <int GMAX>
+static hipError_t max_blocks_g(int mode, size_t lds, int* blocks)
+{
+    switch (mode) {
+    case 0: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch_solve<0, GMAX>, kThreads, lds);
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch_solve<1, GMAX>, kThreads, lds);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch_solve<2, GMAX>, kThreads, lds);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_max_blocks_per_cu(int mode, int gmax, size_t lds, int* blocks)
 {
     *blocks = 0;
-    switch (mode) {
-    case 0: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch_solve<0>, kThreads, lds);
-    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch_solve<1>, kThreads, lds);
-    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch_solve<2>, kThreads, lds);
-    default: return hipErrorInvalidValue;
+    return gmax <= 8 ? max_blocks_g<8>(mode, lds, blocks) : max_blocks_g<32>(mode, lds, blocks);
+}
+
+template <int GMAX>
+static void launch_g(const BatchArgs& a, int blocks, size_t lds, hipStream_t st)
+{
+    switch (a.mode) {
+    case 0: hipLaunchKernelGGL((k_batch_solve<0, GMAX>), dim3(blocks), dim3(kThreads), lds, st, a); break;
+    case 1: hipLaunchKernelGGL((k_batch_solve<1, GMAX>), dim3(blocks), dim3(kThreads), lds, st, a); break;
+    default: hipLaunchKernelGGL((k_batch_solve<2, GMAX>), dim3(blocks), dim3(kThreads), lds, st, a); break;
     }
 }
 
 hipError_t launch_batch_solve(const BatchArgs& a, int blocks, size_t lds, hipStream_t st)
 {
-    switch (a.mode) {
-    case 0: hipLaunchKernelGGL(k_batch_solve<0>, dim3(blocks), dim3(kThreads), lds, st, a); break;
-    case 1: hipLaunchKernelGGL(k_batch_solve<1>, dim3(blocks), dim3(kThreads), lds, st, a); break;
-    case 2: hipLaunchKernelGGL(k_batch_solve<2>, dim3(blocks), dim3(kThreads), lds, st, a); break;
-    default: return hipErrorInvalidValue;
-    }
+    if (a.mode < 0 || a.mode > 2) return hipErrorInvalidValue;
+    if (a.gmax <= 8) launch_g<8>(a, blocks, lds, st);
+    else launch_g<32>(a, blocks, lds, st);
     return hipGetLastError();
 }
 

@@ -33,6 +33,13 @@ __device__ __forceinline__ int4 pack8(const int o[8])
     return v;
 }
 
+// Label j of a packed vector of 8 non-negative int16 values.
+__device__ __forceinline__ int msg_at(const int4 v, int j)
+{
+    const int w = (j >> 1) == 0 ? v.x : (j >> 1) == 1 ? v.y : (j >> 1) == 2 ? v.z : v.w;
+    return (j & 1) ? (int)((unsigned)w >> 16) : (w & 0xffff);
+}
+
 __device__ __forceinline__ long long slot_of(int x, int y, int Wh)
 {
     return (long long)(2 * y + ((x + y) & 1)) * Wh + (x >> 1);
@@ -282,25 +289,24 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
     bool act = valid;
     if (MODE == 2 || (MODE == 1 && a.t >= 2)) act = act && a.state_a[slot] != 0;
     const int d0 = lane * 8;
-    int Hs[8], m[4][8];
+    // incoming messages stay packed (two int16 per register, values in [0, 32767])
+    int Hs[8];
+    int4 mp[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) m[k][j] = 0;
+    for (int k = 0; k < 4; ++k) mp[k] = make_int4(0, 0, 0, 0);
     if (act) {
         unpack8(*reinterpret_cast<const int4*>(a.cost + slot * Dp + d0), Hs);
         if (SRC == kSrcOwn) {
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (has[k]) unpack8(*reinterpret_cast<const int4*>(a.msgs + k * a.vol + slot * Dp + d0), m[k]);
+                if (has[k]) mp[k] = *reinterpret_cast<const int4*>(a.msgs + k * a.vol + slot * Dp + d0);
         } else if (SRC == kSrcParent) {
             const int px = x >> 1, py = y >> 1;
             const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
             const long long ps = (long long)(2 * py + ((px + py) & 1)) * a.plv.Wh + (px >> 1);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (has[k] && phas[k])
-                    unpack8(*reinterpret_cast<const int4*>(a.pmsgs + k * a.pvol + ps * Dp + d0), m[k]);
+                if (has[k] && phas[k]) mp[k] = *reinterpret_cast<const int4*>(a.pmsgs + k * a.pvol + ps * Dp + d0);
         }
     } else {
 #pragma unroll
@@ -308,7 +314,8 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-        Hs[j] = (d0 + j < a.D) ? Hs[j] + m[0][j] + m[1][j] + m[2][j] + m[3][j] : kBig;
+        Hs[j] = (d0 + j < a.D) ? Hs[j] + msg_at(mp[0], j) + msg_at(mp[1], j) + msg_at(mp[2], j) + msg_at(mp[3], j)
+                               : kBig;
     if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;
     const bool check = (MODE == 2) || (MODE == 1 && a.t >= 2);
     bool all_eq = true;
@@ -316,7 +323,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
     for (int k = 0; k < 4; ++k) {
         int h[8], o[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) h[j] = Hs[j] - m[k][j];
+        for (int j = 0; j < 8; ++j) h[j] = Hs[j] - msg_at(mp[k], j);
         transform<G>(h, a.lambda, a.capv, lane, o);
         bool store = act && has[k];
         int16_t* dst = a.msgs + (k ^ 1) * a.vol + nb[k] * Dp + d0;

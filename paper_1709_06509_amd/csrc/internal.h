@@ -101,8 +101,9 @@ struct BatchArgs {
     const int* tiles;
     int npairs, nphases, L;
     int lambda, capv, K, mode;
-    int order;                // 0: tiles dealt round-robin to workgroups; 1: one contiguous chunk per XCD
-    unsigned* barrier;        // [0] arrivals, [1] generation
+    int order;                // 0: chunk = workgroup index; 1: the workgroups of one XCD take adjacent chunks
+    int gmax;                 // largest lanes-per-pixel among the pairs (selects a leaner kernel when <= 8)
+    unsigned* barrier;        // 10 words: per-XCD-group arrivals, group arrivals, generation
     int* error;               // set when a grid barrier times out
     long long timeout_ticks;  // of the wall clock
 };
@@ -115,8 +116,10 @@ hipError_t launch_ncc_batched(const NccPair* pairs, const int* tile_start, int n
                               int scale, int trunc, hipStream_t st);
 hipError_t launch_batch_reset(unsigned* barrier, int* error, hipStream_t st);
 // Largest co-resident grid of the persistent kernel for `lds` bytes of LDS per workgroup.
-hipError_t batch_max_blocks_per_cu(int mode, size_t lds, int* blocks);
+hipError_t batch_max_blocks_per_cu(int mode, int gmax, size_t lds, int* blocks);
 hipError_t launch_batch_solve(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
+// One phase of the batch as its own launch: `tiles` workgroups, one per tile.
+hipError_t launch_batch_phase(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, hipStream_t st);
 
 // Launchers (return hipError_t of the launch).
 // launch_pyramid_tree: re-layout of the finest scale plus every coarser scale in one launch;

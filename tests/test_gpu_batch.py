@@ -114,3 +114,28 @@ def test_batch_autotune_and_graph_replay():
             assert all(torch.equal(a, b) for a, b in zip(batch.disps, ref)), f"replay {rep}"
     counts = ctx.graph_counts()
     assert counts["captures"] == 1 and counts["replays"] == 2
+
+
+@pytest.mark.parametrize("skip", [0, 1])
+def test_every_schedule_gives_the_same_result(skip):
+    w = dict(synth.BATCH)
+    lefts, rights, Ds = batch_of_generator_pairs(10, 3000)
+    params = B.make_batch_params(w["window"], w["num_scales"], w["iters"], w["lam"], w["trunc"], skip)
+    batch = B.Batch(lefts, rights, Ds, params)
+    ctx = B.Context()
+    ref = None
+    for sched, bpc, order in [(1, 1, 0), (0, 1, 0), (0, 1, 1), (0, 2, 0), (0, 3, 1)]:
+        say(f"schedule {sched} bpc {bpc} order {order} skip {skip}")
+        B.set_batch_schedule(ctx, sched, bpc, order)
+        for d in batch.disps:
+            d.fill_(-1)
+        batch.solve(ctx)
+        assert batch.status() == 0
+        got = [d.clone() for d in batch.disps]
+        if ref is None:
+            ref = got
+            for i in range(len(lefts)):
+                c, d = solo(lefts[i], rights[i], Ds[i], dict(w, skip=skip))
+                assert torch.equal(batch.costs[i], c) and torch.equal(got[i], d), f"pair {i}"
+        else:
+            assert all(torch.equal(a, b) for a, b in zip(got, ref))
