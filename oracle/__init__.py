@@ -76,6 +76,18 @@ def _load():
         lib.oracle_message_at.restype = ctypes.c_int32
         lib.oracle_wta_at.argtypes = [_i16p, _i16p] + [_i32] * 5
         lib.oracle_wta_at.restype = ctypes.c_int32
+        _u16p = ctypes.POINTER(ctypes.c_uint16)
+        _f32p = ctypes.POINTER(ctypes.c_float)
+        lib.oracle_bf16.argtypes = [ctypes.c_float]
+        lib.oracle_bf16.restype = ctypes.c_uint16
+        lib.oracle_warm_input.argtypes = [_u8p, _u8p, _i32, _i32, _i32, _i16p, _i32, _i32, _u16p]
+        lib.oracle_conv3x3.argtypes = [_f64p, _i32, _i32, _i32, _f64p, _f64p, _i32, _f64p]
+        lib.oracle_conv3x3_backward.argtypes = [_f64p, _i32, _i32, _i32, _f64p, _i32, _f64p, _f64p, _f64p, _f64p]
+        lib.oracle_warm_messages.argtypes = [_f32p, _i32, _i32, _i32, _i32, _i16p]
+        lib.oracle_warm_l1.argtypes = [_f32p, _i16p, _i32, _i32, _i32, _i32, _f64p]
+        lib.oracle_warm_l1.restype = ctypes.c_double
+        lib.oracle_adam.argtypes = [_f64p, _f64p, _f64p, _f64p, ctypes.c_int64, _i32, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double]
         lib.oracle_bp_energy.argtypes = [_i16p, _i16p, _i32, _i32, _i32, _i32, _i32]
         lib.oracle_bp_energy.restype = ctypes.c_int64
         _lib = lib
@@ -221,3 +233,87 @@ def wta_at(cost, msgs, x, y):
     cost, msgs = _c(cost, np.int16), _c(msgs, np.int16)
     H, W, D = cost.shape
     return int(_load().oracle_wta_at(_p(cost, _i16p), _p(msgs, _i16p), W, H, D, x, y))
+
+
+# ---------------------------------------------------------------- learned warm start
+_f32 = np.float32
+
+
+def bf16(a):
+    """bf16 bit patterns (uint16) of float32 values, round to nearest even."""
+    a = np.ascontiguousarray(a, dtype=np.float32).ravel()
+    lib = _load()
+    out = np.array([lib.oracle_bf16(float(v)) for v in a], dtype=np.uint16)
+    return out
+
+
+def bf16_value(bits):
+    """float32 values of bf16 bit patterns."""
+    b = np.ascontiguousarray(bits, dtype=np.uint16)
+    return (b.astype(np.uint32) << 16).view(np.float32)
+
+
+def warm_input(left, right, s, coarse, cin_p):
+    """CNN input [Hs, Ws, cin_p] (bf16 bits) at scale s from the views and the scale-(s+1) cost."""
+    left, right, coarse = _c(left, np.uint8), _c(right, np.uint8), _c(coarse, np.int16)
+    H, W = left.shape
+    D = coarse.shape[2]
+    Ws, Hs = W, H
+    for _ in range(s):
+        Ws, Hs = (Ws + 1) // 2, (Hs + 1) // 2
+    out = np.empty((Hs, Ws, cin_p), np.uint16)
+    _load().oracle_warm_input(_p(left, _u8p), _p(right, _u8p), W, H, s, _p(coarse, _i16p), D, cin_p,
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)))
+    return out
+
+
+def conv3x3(x, w, b):
+    """x [H, W, Cin] float64, w [Cout, 9, Cin], b [Cout] -> z [H, W, Cout] (zero padding)."""
+    x = _c(x, np.float64)
+    w = _c(w, np.float64)
+    H, W, Cin = x.shape
+    Cout = w.shape[0]
+    b = _c(b, np.float64) if b is not None else None
+    z = np.empty((H, W, Cout), np.float64)
+    _load().oracle_conv3x3(_p(x, _f64p), H, W, Cin, _p(w, _f64p), _p(b, _f64p) if b is not None else None, Cout,
+                           _p(z, _f64p))
+    return z
+
+
+def conv3x3_backward(x, w, dz, want_dx=True):
+    x, w, dz = _c(x, np.float64), _c(w, np.float64), _c(dz, np.float64)
+    H, W, Cin = x.shape
+    Cout = w.shape[0]
+    dx = np.empty_like(x) if want_dx else None
+    dw = np.empty_like(w)
+    db = np.empty(Cout, np.float64)
+    _load().oracle_conv3x3_backward(_p(x, _f64p), H, W, Cin, _p(w, _f64p), Cout, _p(dz, _f64p),
+                                    _p(dx, _f64p) if want_dx else None, _p(dw, _f64p), _p(db, _f64p))
+    return dx, dw, db
+
+
+def warm_messages(y, D, lam_t):
+    """Initial messages [4, Hs, Ws, D] int16 from the CNN output y [Hs, Ws, 4D] float32."""
+    y = _c(y, np.float32)
+    Hs, Ws, _ = y.shape
+    out = np.empty((4, Hs, Ws, D), np.int16)
+    _load().oracle_warm_messages(y.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), Ws, Hs, D, lam_t,
+                                 _p(out, _i16p))
+    return out
+
+
+def warm_l1(y, label, lam_t, want_grad=True):
+    y, label = _c(y, np.float32), _c(label, np.int16)
+    Hs, Ws, C = y.shape
+    D = C // 4
+    dy = np.empty((Hs, Ws, C), np.float64) if want_grad else None
+    loss = _load().oracle_warm_l1(y.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _p(label, _i16p), Ws, Hs, D,
+                                  lam_t, _p(dy, _f64p) if want_grad else None)
+    return loss, dy
+
+
+def adam(w, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays."""
+    for a in (w, m, v, g):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _load().oracle_adam(_p(w, _f64p), _p(m, _f64p), _p(v, _f64p), _p(g, _f64p), w.size, step, lr, b1, b2, eps)

@@ -484,3 +484,180 @@ int32_t oracle_wta_at(const int16_t* cost, const int16_t* msgs, int32_t W, int32
     }
     return bd;
 }
+
+/*
+ * ---- learned warm start: the small CNN that predicts initial messages ----
+ * Not in the paper: a coarse-scale message initialiser (a learned replacement for the
+ * coarsest scale of the hierarchy).  Readings: input at scale s = L-2 is the two views
+ * box-averaged over 2^s x 2^s blocks and scaled to [0, 1], plus the coarsest-scale cost
+ * (scale s+1) repeated over its 2x2 children and scaled by 1/1024, all rounded to bf16;
+ * the network is 3x3 convolutions with zero padding; its output y is turned into
+ * messages by round(y * lambda*T) clamped to [0, lambda*T], minus the minimum over d.
+ */
+
+/* bf16 (round to nearest even) of a float, and back. */
+uint16_t oracle_bf16(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+float oracle_bf16_value(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+/* Input of the CNN at scale s: [Hs][Ws][cin_p] bf16, channels 0 = left, 1 = right, 2.. = cost. */
+void oracle_warm_input(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t s,
+                       const int16_t* coarse, int32_t D, int32_t cin_p, uint16_t* out)
+{
+    int Ws = W, Hs = H;
+    for (int i = 0; i < s; ++i) { Ws = (Ws + 1) / 2; Hs = (Hs + 1) / 2; }
+    const int Wc = (Ws + 1) / 2;
+    const int B = 1 << s;
+    for (int Y = 0; Y < Hs; ++Y)
+        for (int X = 0; X < Ws; ++X) {
+            long sl = 0, sr = 0, cnt = 0;
+            for (int y = Y * B; y < (Y + 1) * B && y < H; ++y)
+                for (int x = X * B; x < (X + 1) * B && x < W; ++x) {
+                    sl += L[(size_t)y * W + x];
+                    sr += R[(size_t)y * W + x];
+                    ++cnt;
+                }
+            uint16_t* o = out + ((size_t)Y * Ws + X) * cin_p;
+            o[0] = oracle_bf16((float)sl / ((float)cnt * 255.0f));
+            o[1] = oracle_bf16((float)sr / ((float)cnt * 255.0f));
+            const int16_t* c = coarse + ((size_t)(Y >> 1) * Wc + (X >> 1)) * D;
+            for (int d = 0; d < D; ++d) o[2 + d] = oracle_bf16((float)c[d] / 1024.0f);
+            for (int ch = 2 + D; ch < cin_p; ++ch) o[ch] = 0;
+        }
+}
+
+/* z[y][x][co] = b[co] + sum_{dy,dx,ci} in[y+dy-1][x+dx-1][ci] * w[co][3dy+dx][ci], zero padding. */
+void oracle_conv3x3(const double* in, int32_t H, int32_t W, int32_t Cin, const double* w, const double* b,
+                    int32_t Cout, double* z)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int co = 0; co < Cout; ++co) {
+                double acc = b ? b[co] : 0.0;
+                for (int dy = 0; dy < 3; ++dy)
+                    for (int dx = 0; dx < 3; ++dx) {
+                        int yy = y + dy - 1, xx = x + dx - 1;
+                        if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                        const double* iv = in + ((size_t)yy * W + xx) * Cin;
+                        const double* wv = w + ((size_t)co * 9 + dy * 3 + dx) * Cin;
+                        for (int ci = 0; ci < Cin; ++ci) acc += iv[ci] * wv[ci];
+                    }
+                z[((size_t)y * W + x) * Cout + co] = acc;
+            }
+}
+
+/* Gradients of the same convolution given dz = dLoss/dz: din (nullable), dw, db. */
+void oracle_conv3x3_backward(const double* in, int32_t H, int32_t W, int32_t Cin, const double* w, int32_t Cout,
+                             const double* dz, double* din, double* dw, double* db)
+{
+    if (din) memset(din, 0, sizeof(double) * (size_t)H * W * Cin);
+    memset(dw, 0, sizeof(double) * (size_t)Cout * 9 * Cin);
+    memset(db, 0, sizeof(double) * (size_t)Cout);
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int co = 0; co < Cout; ++co) {
+                const double g = dz[((size_t)y * W + x) * Cout + co];
+                db[co] += g;
+                for (int dy = 0; dy < 3; ++dy)
+                    for (int dx = 0; dx < 3; ++dx) {
+                        int yy = y + dy - 1, xx = x + dx - 1;
+                        if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                        const double* iv = in + ((size_t)yy * W + xx) * Cin;
+                        const double* wv = w + ((size_t)co * 9 + dy * 3 + dx) * Cin;
+                        double* dwv = dw + ((size_t)co * 9 + dy * 3 + dx) * Cin;
+                        double* div = din ? din + ((size_t)yy * W + xx) * Cin : NULL;
+                        for (int ci = 0; ci < Cin; ++ci) {
+                            dwv[ci] += g * iv[ci];
+                            if (div) div[ci] += g * wv[ci];
+                        }
+                    }
+            }
+}
+
+/* Messages from the CNN output y [Hs][Ws][4D] (channel k*D + d): round(y*lamT) clamped to
+   [0, lamT], minus its minimum over d; zero where the pixel has no neighbour on side k. */
+void oracle_warm_messages(const float* y, int32_t Ws, int32_t Hs, int32_t D, int32_t lamT, int16_t* out)
+{
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
+    for (int k = 0; k < 4; ++k)
+        for (int Y = 0; Y < Hs; ++Y)
+            for (int X = 0; X < Ws; ++X) {
+                int qx, qy;
+                int16_t* o = out + (((size_t)k * Hs + Y) * Ws + X) * D;
+                if (!neighbour(k, X, Y, Ws, Hs, &qx, &qy)) {
+                    for (int d = 0; d < D; ++d) o[d] = 0;
+                    continue;
+                }
+                int32_t mn = INT32_MAX;
+                for (int d = 0; d < D; ++d) {
+                    float p = y[((size_t)Y * Ws + X) * 4 * D + k * D + d] * (float)lamT;
+                    float r = nearbyintf(p);
+                    int32_t v = r < 0.0f ? 0 : (r > (float)lamT ? lamT : (int32_t)r);
+                    q[d] = v;
+                    if (v < mn) mn = v;
+                }
+                for (int d = 0; d < D; ++d) o[d] = (int16_t)(q[d] - mn);
+            }
+    free(q);
+}
+
+/* Mean L1 distance between y*lamT and the label messages over the slots that have a
+   neighbour; dy (nullable) = its gradient with respect to y. */
+double oracle_warm_l1(const float* y, const int16_t* label, int32_t Ws, int32_t Hs, int32_t D, int32_t lamT,
+                      double* dy)
+{
+    long n = 0;
+    double s = 0.0;
+    for (int k = 0; k < 4; ++k)
+        for (int Y = 0; Y < Hs; ++Y)
+            for (int X = 0; X < Ws; ++X) {
+                int qx, qy;
+                if (!neighbour(k, X, Y, Ws, Hs, &qx, &qy)) continue;
+                n += D;
+                for (int d = 0; d < D; ++d) {
+                    double r = (double)y[((size_t)Y * Ws + X) * 4 * D + k * D + d] * lamT -
+                               label[(((size_t)k * Hs + Y) * Ws + X) * D + d];
+                    s += fabs(r);
+                }
+            }
+    if (dy) {
+        for (size_t i = 0; i < (size_t)Hs * Ws * 4 * D; ++i) dy[i] = 0.0;
+        for (int k = 0; k < 4; ++k)
+            for (int Y = 0; Y < Hs; ++Y)
+                for (int X = 0; X < Ws; ++X) {
+                    int qx, qy;
+                    if (!neighbour(k, X, Y, Ws, Hs, &qx, &qy)) continue;
+                    for (int d = 0; d < D; ++d) {
+                        size_t i = ((size_t)Y * Ws + X) * 4 * D + k * D + d;
+                        double r = (double)y[i] * lamT - label[(((size_t)k * Hs + Y) * Ws + X) * D + d];
+                        dy[i] = (r > 0 ? 1.0 : (r < 0 ? -1.0 : 0.0)) * lamT / (double)n;
+                    }
+                }
+    }
+    return n ? s / (double)n : 0.0;
+}
+
+/* One Adam step (bias-corrected), step counted from 1. */
+void oracle_adam(double* w, double* m, double* v, const double* g, int64_t n, int32_t step, double lr, double b1,
+                 double b2, double eps)
+{
+    const double c1 = 1.0 - pow(b1, step), c2 = 1.0 - pow(b2, step);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        w[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}

@@ -77,6 +77,21 @@ int32_t oracle_message_at(const int16_t* cost, const int16_t* msgs, int32_t widt
 int32_t oracle_wta_at(const int16_t* cost, const int16_t* msgs, int32_t width, int32_t height, int32_t num_disp,
                       int32_t x, int32_t y);
 
+/* learned warm start (test infrastructure for the CNN kernels) */
+uint16_t oracle_bf16(float f);
+float oracle_bf16_value(uint16_t b);
+void oracle_warm_input(const uint8_t* left, const uint8_t* right, int32_t width, int32_t height, int32_t s,
+                       const int16_t* coarse, int32_t num_disp, int32_t cin_p, uint16_t* out);
+void oracle_conv3x3(const double* in, int32_t H, int32_t W, int32_t Cin, const double* w, const double* b,
+                    int32_t Cout, double* z);
+void oracle_conv3x3_backward(const double* in, int32_t H, int32_t W, int32_t Cin, const double* w, int32_t Cout,
+                             const double* dz, double* din, double* dw, double* db);
+void oracle_warm_messages(const float* y, int32_t Ws, int32_t Hs, int32_t D, int32_t lamT, int16_t* out);
+double oracle_warm_l1(const float* y, const int16_t* label, int32_t Ws, int32_t Hs, int32_t D, int32_t lamT,
+                      double* dy);
+void oracle_adam(double* w, double* m, double* v, const double* g, int64_t n, int32_t step, double lr, double b1,
+                 double b2, double eps);
+
 int64_t oracle_bp_energy(const int16_t* cost, const int16_t* disparity, int32_t width, int32_t height,
                          int32_t num_disp, int32_t lambda, int32_t trunc);
 
