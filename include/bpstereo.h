@@ -243,6 +243,108 @@ int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, int32_t 
    schedule -1 returns to the tuned or default choice. */
 int32_t bp_context_set_batch_schedule(bp_context* ctx, int32_t schedule, int32_t blocks_per_cu, int32_t order);
 
+/* ---------------------------------------------------------------------------------------
+ * Learned warm start.  A small CNN predicts the initial messages of scale s = L-2; the
+ * solve then skips scale L-1 and starts at s from them (bp_params.warm_msgs).  The plain,
+ * zero-initialised hierarchy stays the fallback and judge.  This is not from the paper: it
+ * replaces the coarsest scale of its hierarchy ("GPU Implementation") by a learned guess.
+ *
+ * Network (D disparity levels): six 3x3 convolutions with zero padding, stride 1:
+ * (2 + D) -> 32, ReLU; four times 32 -> 32, ReLU; 32 -> 4D, linear.  Weights and activations
+ * are bf16 (round to nearest even), accumulation fp32 on MFMA, biases fp32.
+ * Tensors are NHWC: [H][W][C_p] with C_p the channel count padded (layer inputs to a multiple
+ * of 16, layer outputs to a multiple of 32); padded channels hold 0.
+ * Parameters: one fp32 vector, per layer the weights [Cout_p][9][Cin_p] (tap 3*dy + dx,
+ * dy/dx in 0..2 for offsets -1..1) followed by the bias [Cout_p]; the bf16 copy used by the
+ * kernels has the same layout.
+ * ------------------------------------------------------------------------------------- */
+
+/* Length of the parameter vector for D = num_disp (1..256), or -1. */
+int64_t bp_cnn_param_count(int32_t num_disp);
+/* Layer 0..5: dims[0..4] [host] = cin, cin_p, cout, cout_p, relu; offsets[0..1] [host] =
+   offsets of its weights and bias in the parameter vector. */
+int32_t bp_cnn_layer(int32_t num_disp, int32_t layer, int32_t* dims, int64_t* offsets);
+/* Bytes of the workspace bp_cnn_forward/bp_cnn_backward use at scale size Ws x Hs (<= 4096 each). */
+size_t bp_cnn_workspace_bytes(int32_t Ws, int32_t Hs, int32_t num_disp);
+
+/*
+ * One 3x3 convolution: out[p][co] = b[co] + sum_{tap, ci} in[p + tap offset][ci] * w[co][tap][ci]
+ * (zero outside the image); then ReLU if relu, or multiplied by (mask[p][co] > 0) if mask is
+ * non-NULL; written as bf16 (out_bf16) and/or fp32 before rounding (out_f32), both [P][cout_p]
+ * with 0 in channels >= cout.  in [device] bf16 [H][W][cin_p] (cin_p % 16 == 0); w [device] bf16
+ * [cout_p][9][cin_p] (cout_p % 32 == 0); bias [device] fp32 [cout_p] or NULL; mask [device] bf16
+ * [P][cout_p] or NULL.
+ */
+int32_t bp_conv3x3_forward(const uint16_t* in, int32_t H, int32_t W, int32_t cin_p, const uint16_t* weights,
+                           const float* bias, int32_t cout, int32_t cout_p, int32_t relu, const uint16_t* mask,
+                           uint16_t* out_bf16, float* out_f32, void* stream);
+/*
+ * Gradient of a 3x3 convolution with respect to its input: for the output gradient g [device]
+ * bf16 [P][cout_p] and the layer's weights [cout_p][9][cin_p], computes
+ * d[p][ci] = sum_{tap, co} g[p - tap offset][co] * w[co][tap][ci], multiplied by (mask[p][ci] > 0)
+ * when mask (the layer input after its ReLU) is non-NULL.  flip_scratch [device] bf16,
+ * cin_p * 9 * cout_p elements.  cin_p and cout_p multiples of 32.
+ */
+int32_t bp_conv3x3_data_grad(const uint16_t* g, int32_t H, int32_t W, int32_t cout_p, const uint16_t* weights,
+                             int32_t cin, int32_t cin_p, const uint16_t* mask, uint16_t* flip_scratch,
+                             uint16_t* out_bf16, float* out_f32, void* stream);
+size_t bp_conv3x3_wgrad_workspace_bytes(int32_t H, int32_t W, int32_t cin_p, int32_t cout_p);
+/*
+ * Gradient of a 3x3 convolution with respect to its weights and bias:
+ * dw[co][tap][ci] = sum_p g[p][co] * in[p + tap offset][ci], db[co] = sum_p g[p][co]; fp32,
+ * summed in a fixed order (deterministic).  dw [device] fp32 [cout_p][9][cin_p]; db [cout_p].
+ */
+int32_t bp_conv3x3_weight_grad(const uint16_t* in, const uint16_t* g, int32_t H, int32_t W, int32_t cin_p,
+                               int32_t cout_p, void* workspace, size_t workspace_bytes, float* dw, float* db,
+                               void* stream);
+
+/*
+ * Forward pass: input [device] bf16 [Hs][Ws][cin_p of layer 0]; params [device] fp32 (biases
+ * are read from it); weights_bf16 [device]; y [device] fp32 [Hs][Ws][cout_p of layer 5], the
+ * last layer's output.  The workspace keeps every layer's activation for bp_cnn_backward.
+ */
+int32_t bp_cnn_forward(const uint16_t* input, int32_t Ws, int32_t Hs, int32_t num_disp, const float* params,
+                       const uint16_t* weights_bf16, void* workspace, size_t workspace_bytes, float* y, void* stream);
+/*
+ * Backward pass after bp_cnn_forward on the same input and workspace.  Loss = mean over the
+ * slots that have a neighbour of |y * lam_t - label| (label [device] int16 [4][Hs][Ws][D],
+ * the target messages); its gradient flows back through the network in bf16 with fp32
+ * accumulation.  grads [device] fp32, the parameter layout (overwritten); loss [device] fp32.
+ */
+int32_t bp_cnn_backward(const uint16_t* input, int32_t Ws, int32_t Hs, int32_t num_disp, const uint16_t* weights_bf16,
+                        void* workspace, size_t workspace_bytes, const float* y, const int16_t* label, int32_t lam_t,
+                        float* grads, float* loss, void* stream);
+/* One Adam step (bias-corrected, step >= 1) on fp32 params with moments m, v [device]; also
+   refreshes the bf16 copy. */
+int32_t bp_adam_step(float* params, float* m, float* v, const float* grads, uint16_t* weights_bf16, int64_t n,
+                     int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
+/* bf16 copy of the fp32 parameters (round to nearest even). */
+int32_t bp_cnn_to_bf16(const float* params, int64_t n, uint16_t* weights_bf16, void* stream);
+
+/*
+ * Network input at scale s = L-2 for a pair: channel 0/1 = left/right view averaged over
+ * each 2^s x 2^s block / 255, channels 2..D+1 = the coarsest scale's cost of the pixel's
+ * parent / 1024, bf16.  cost [device] int16 [H][W][D] (finest); params as for the solve
+ * (num_scales >= 2); workspace: a solve workspace (bp_workspace_bytes), whose cost pyramid
+ * this call fills.  input [device] bf16 [Hs][Ws][cin_p of layer 0].
+ */
+int32_t bp_warmstart_input(const uint8_t* left, const uint8_t* right, const int16_t* cost, int32_t width,
+                           int32_t height, const bp_params* params, void* workspace, size_t workspace_bytes,
+                           uint16_t* input, void* stream);
+/*
+ * Initial messages from the network output y [device] fp32 [Hs][Ws][cout_p of layer 5]
+ * (channel k*D + d): with c = min(lambda * min(trunc, D), 32767), round-to-nearest-even(y * c)
+ * clamped to [0, c], minus its minimum over d; zero where the pixel has no neighbour on side k.
+ * msgs [device] int16 [4][Hs][Ws][D], ready for bp_params.warm_msgs.
+ */
+int32_t bp_warmstart_messages(const float* y, int32_t Ws, int32_t Hs, int32_t num_disp, int32_t lambda, int32_t trunc,
+                              int16_t* msgs, void* stream);
+
+/* Scale `level` (0..num_scales-1) of the solve's cost pyramid, in the caller's layout
+   out [device] int16 [H_level][W_level][D]; workspace: a solve workspace. */
+int32_t bp_pyramid_level(const int16_t* cost, int32_t width, int32_t height, const bp_params* params, int32_t level,
+                         void* workspace, size_t workspace_bytes, int16_t* out, void* stream);
+
 /* Message of the last failed call on this thread ("" if none); valid until the next call. */
 const char* bp_last_error(void);
 

@@ -48,7 +48,7 @@ def build_synth():
 
 def build_hip():
     os.makedirs(BUILD_DIR, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip"))) + [os.path.join(HERE, "csrc", "api.cpp")]
+    srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip"))) + sorted(glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
     objs, cmds = [], []
     for s in srcs:
         o = os.path.join(BUILD_DIR, os.path.basename(s) + ".o")

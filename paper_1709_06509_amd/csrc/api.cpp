@@ -37,6 +37,19 @@ int32_t ok()
     return BP_OK;
 }
 
+}  // namespace
+
+namespace bpst {
+int32_t report(int32_t code, const char* msg)
+{
+    if (code == BP_OK) g_last_error.clear();
+    else g_last_error = msg ? msg : "";
+    return code;
+}
+}  // namespace bpst
+
+namespace {
+
 #define HIP_TRY(expr)                                                                      \
     do {                                                                                   \
         hipError_t e_ = (expr);                                                            \
@@ -922,5 +935,82 @@ BP_API int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, i
     rc = enqueue_batch(b, params, ws, out->schedule[bi], out->blocks_per_cu[bi], out->order[bi], cus, ticks, st);
     if (rc != BP_OK) return rc;
     HIP_TRY(hipStreamSynchronize(st));
+    return ok();
+}
+
+// ---------------------------------------------------------------------------------------
+// Pieces of the solve used by the learned warm start
+// ---------------------------------------------------------------------------------------
+namespace {
+// Enqueue the cost pyramid of a solve into its workspace (the internal cost of every scale).
+int32_t enqueue_pyramid(const Plan& pl, const int16_t* cost, char* ws, hipStream_t st)
+{
+    int16_t* C[bpst::kMaxScales];
+    for (int l = 0; l < pl.L; ++l) C[l] = reinterpret_cast<int16_t*>(ws + pl.off_cost[l]);
+    bpst::PyramidArgs pa{};
+    for (int l = 0; l < pl.L; ++l) {
+        pa.c[l] = C[l];
+        pa.lv[l] = pl.lv[l];
+    }
+    pa.L = pl.L;
+    pa.D = pl.D;
+    bool done = false;
+    HIP_TRY(bpst::launch_pyramid_tree(cost, pa, pl.G, &done, st));
+    if (!done) {
+        HIP_TRY(bpst::launch_prep_level0(cost, C[0], pl.lv[0], pl.D, pl.G, st));
+        for (int l = 0; l + 1 < pl.L; ++l)
+            HIP_TRY(bpst::launch_pyramid(C[l], pl.lv[l], C[l + 1], pl.lv[l + 1], pl.D, pl.G, st));
+    }
+    return BP_OK;
+}
+
+int32_t check_solve_args(int32_t W, int32_t H, const bp_params* p, void* ws, size_t wsb, Plan* pl)
+{
+    std::string why;
+    if (!params_valid(W, H, p, &why)) return fail(BP_E_INVAL, "%s", why.c_str());
+    *pl = make_plan(W, H, p);
+    if (!ws || wsb < pl->total) return fail(BP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", wsb, pl->total);
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0)
+        return fail(BP_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    return BP_OK;
+}
+}  // namespace
+
+BP_API int32_t bp_pyramid_level(const int16_t* cost, int32_t width, int32_t height, const bp_params* params,
+                                int32_t level, void* workspace, size_t workspace_bytes, int16_t* out, void* stream)
+{
+    Plan pl;
+    int32_t rc = check_solve_args(width, height, params, workspace, workspace_bytes, &pl);
+    if (rc != BP_OK) return rc;
+    if (!cost || !out) return fail(BP_E_INVAL, "cost/out is NULL");
+    if (level < 0 || level >= pl.L) return fail(BP_E_INVAL, "level must be in 0..num_scales-1");
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = static_cast<char*>(workspace);
+    rc = enqueue_pyramid(pl, cost, ws, st);
+    if (rc != BP_OK) return rc;
+    // export scale `level` from the internal layout (its message buffers are free scratch here)
+    HIP_TRY(bpst::launch_export_cost(reinterpret_cast<const int16_t*>(ws + pl.off_cost[level]), pl.lv[level], pl.D,
+                                     pl.G, out, st));
+    return ok();
+}
+
+BP_API int32_t bp_warmstart_input(const uint8_t* left, const uint8_t* right, const int16_t* cost, int32_t width,
+                                  int32_t height, const bp_params* params, void* workspace, size_t workspace_bytes,
+                                  uint16_t* input, void* stream)
+{
+    Plan pl;
+    int32_t rc = check_solve_args(width, height, params, workspace, workspace_bytes, &pl);
+    if (rc != BP_OK) return rc;
+    if (!left || !right || !cost || !input) return fail(BP_E_INVAL, "a pointer is NULL");
+    if (pl.L < 2) return fail(BP_E_INVAL, "the warm start needs num_scales >= 2");
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = static_cast<char*>(workspace);
+    rc = enqueue_pyramid(pl, cost, ws, st);
+    if (rc != BP_OK) return rc;
+    const int s = pl.L - 2;
+    const int cin_p = (2 + pl.D + 15) / 16 * 16;
+    HIP_TRY(bpst::launch_warm_input(left, right, width, height, s,
+                                    reinterpret_cast<const int16_t*>(ws + pl.off_cost[pl.L - 1]), pl.lv[pl.L - 1],
+                                    pl.Dp, pl.D, pl.lv[s].W, pl.lv[s].H, cin_p, input, st));
     return ok();
 }

@@ -175,6 +175,25 @@ __global__ __launch_bounds__(kThreads) void k_export(const int16_t* __restrict__
     }
 }
 
+// A scale's internal cost back to the caller's layout [H][W][D].
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_export_cost(const int16_t* __restrict__ c, Level lv, int D,
+                                                           int16_t* __restrict__ out)
+{
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const long long gi = t / G;
+    const int lane = (int)(t & (G - 1));
+    if (gi >= lv.slots()) return;
+    ColourPix p = any_pixel(gi, lv);
+    if (!p.valid) return;
+    const int d0 = lane * 8;
+    int v[8];
+    unpack8(*reinterpret_cast<const int4*>(c + gi * (8 * G) + d0), v);
+    int16_t* dst = out + ((long long)p.y * lv.W + p.x) * D + d0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) if (d0 + j < D) dst[j] = (int16_t)v[j];
+}
+
 constexpr int kEnergyBlocks = 1024;
 
 __global__ __launch_bounds__(kThreads) void k_energy_partial(const int16_t* __restrict__ cost,
@@ -369,6 +388,13 @@ hipError_t launch_export(const int16_t* msgs, long long vol, Level lv, int D, in
 {
     const unsigned g = grid_for(lv.slots(), G);
     BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_export<GG>), dim3(g), dim3(kThreads), 0, st, msgs, vol, lv, D, out));
+    return hipGetLastError();
+}
+
+hipError_t launch_export_cost(const int16_t* c, Level lv, int D, int G, int16_t* out, hipStream_t st)
+{
+    const unsigned g = grid_for(lv.slots(), G);
+    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_export_cost<GG>), dim3(g), dim3(kThreads), 0, st, c, lv, D, out));
     return hipGetLastError();
 }
 

@@ -1,0 +1,385 @@
+// Learned warm start: a small CNN (3x3 convolutions, bf16 weights and activations, fp32
+// accumulation on MFMA) that predicts the initial messages of the second-coarsest scale.
+//
+// Activations are NHWC bf16 [H][W][C_p] with C_p a multiple of 16 (padded channels hold 0);
+// weights are bf16 [Cout_p][9][Cin_p] (tap t = 3*dy + dx).  A convolution is an implicit
+// GEMM: D[pixel][co] = sum over (tap, ci) of A[pixel][(tap, ci)] * B[(tap, ci)][co], run on
+// v_mfma_f32_16x16x16_bf16 with the K dimension walked 16 channels of one tap at a time.
+// Operand layout of that instruction (64 lanes): A[i][k] sits in lane i + 16*(k/4), element
+// k%4; B[k][j] in lane j + 16*(k/4), element k%4; D[i][j] in lane j + 16*(i/4), element i%4.
+//
+// Reductions over pixels (weight and bias gradients, the loss) are split into fixed pixel
+// chunks whose partial sums are added in chunk order, so results are deterministic.
+#include "internal.h"
+
+namespace bpst {
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kCT = 256;  // threads per workgroup
+
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ v4s load4(const uint16_t* p)
+{
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    v4s r;
+    r[0] = (short)(u.x & 0xffff);
+    r[1] = (short)(u.x >> 16);
+    r[2] = (short)(u.y & 0xffff);
+    r[3] = (short)(u.y >> 16);
+    return r;
+}
+
+// Forward convolution (also the data gradient, with flipped weights and a ReLU mask).
+// One workgroup: 64 pixels x 32 output channels; wave w owns pixels 16w..16w+15.
+//   out_bf16 [P][Cout_p] = bf16( act(acc + bias) ) where act = ReLU if relu, or
+//                         acc * (mask[p][co] > 0) if mask (the ReLU derivative)
+//   out_f32  [P][Cout_p] = the same value before bf16 rounding (nullable)
+__global__ __launch_bounds__(kCT) void k_conv_fwd(const uint16_t* __restrict__ in, int H, int W, int cin_p,
+                                                  const uint16_t* __restrict__ w, const float* __restrict__ bias,
+                                                  int cout, int cout_p, int relu, const uint16_t* __restrict__ mask,
+                                                  uint16_t* __restrict__ out_bf16, float* __restrict__ out_f32)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int P = H * W;
+    const int p = blockIdx.x * 64 + wave * 16 + (lane & 15);  // this lane's A row (pixel)
+    const int py = p / W, px = p - py * W;
+    const int kq = (lane >> 4) * 4;
+    const int co0 = blockIdx.y * 32;
+    v4f acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    for (int tap = 0; tap < 9; ++tap) {
+        const int ys = py + tap / 3 - 1, xs = px + tap % 3 - 1;
+        const bool ok = p < P && ys >= 0 && ys < H && xs >= 0 && xs < W;
+        const uint16_t* arow = in + ((long long)ys * W + xs) * cin_p + kq;
+        const uint16_t* b0 = w + ((long long)(co0 + (lane & 15)) * 9 + tap) * cin_p + kq;
+        const uint16_t* b1 = w + ((long long)(co0 + 16 + (lane & 15)) * 9 + tap) * cin_p + kq;
+        for (int c0 = 0; c0 < cin_p; c0 += 16) {
+            v4s a = {0, 0, 0, 0};
+            if (ok) a = load4(arow + c0);
+            const v4s bb0 = load4(b0 + c0), bb1 = load4(b1 + c0);
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb0, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb1, acc[1], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int co = co0 + 16 * t + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = blockIdx.x * 64 + wave * 16 + (lane >> 4) * 4 + i;
+            if (q >= P) continue;
+            float v = 0.f;
+            if (co < cout) {
+                v = acc[t][i] + (bias ? bias[co] : 0.f);
+                if (relu) v = fmaxf(v, 0.f);
+                if (mask && from_bf16(mask[(long long)q * cout_p + co]) <= 0.f) v = 0.f;
+            }
+            if (out_bf16) out_bf16[(long long)q * cout_p + co] = to_bf16(v);
+            if (out_f32) out_f32[(long long)q * cout_p + co] = v;
+        }
+    }
+}
+
+// w' [Cin_p][9][Cout_p] with w'[ci][8 - t][co] = w[co][t][ci]: the data gradient of a 3x3
+// convolution with zero padding is the convolution of the output gradient with w'.
+__global__ void k_flip(const uint16_t* __restrict__ w, int cin_p, int cout_p, uint16_t* __restrict__ wf)
+{
+    const long long n = (long long)cout_p * 9 * cin_p;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int ci = (int)(i % cin_p);
+        const int t = (int)((i / cin_p) % 9);
+        const int co = (int)(i / ((long long)cin_p * 9));
+        wf[((long long)ci * 9 + (8 - t)) * cout_p + co] = w[i];
+    }
+}
+
+// Weight gradient partials: dW[co][t][ci] = sum_p g[p][co] * in[p + tap offset][ci] over pixel
+// chunk s; one workgroup per (chunk, tap, 32 output channels, 16 input channels).  The four
+// waves take interleaved 16-pixel steps and are summed in a fixed order at the end.
+__global__ __launch_bounds__(kCT) void k_conv_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ g,
+                                                    int H, int W, int cin_p, int cout_p, int chunk,
+                                                    float* __restrict__ part)
+{
+    __shared__ float red[4][32][16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int s = blockIdx.x, tap = blockIdx.y % 9;
+    const int co0 = (blockIdx.y / 9) * 32, ci0 = blockIdx.z * 16;
+    const int P = H * W;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int pbeg = s * chunk, pend = min(P, pbeg + chunk);
+    v4f acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    const int kq = (lane >> 4) * 4;
+    for (int p0 = pbeg + wave * 16; p0 < pend; p0 += 64) {
+        // A[co][k = pixel], B[k = pixel][ci]
+        v4s a0, a1, b;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int p = p0 + kq + v;
+            short ga0 = 0, ga1 = 0, bx = 0;
+            if (p < pend) {
+                ga0 = (short)g[(long long)p * cout_p + co0 + (lane & 15)];
+                ga1 = (short)g[(long long)p * cout_p + co0 + 16 + (lane & 15)];
+                const int py = p / W, px = p - py * W;
+                const int ys = py + dy, xs = px + dx;
+                if (ys >= 0 && ys < H && xs >= 0 && xs < W)
+                    bx = (short)in[((long long)ys * W + xs) * cin_p + ci0 + (lane & 15)];
+            }
+            a0[v] = ga0;
+            a1[v] = ga1;
+            b[v] = bx;
+        }
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b, acc[1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[wave][16 * t + (lane >> 4) * 4 + i][lane & 15] = acc[t][i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 32 * 16; e += kCT) {
+        const int r = e / 16, c = e % 16;
+        const float v = ((red[0][r][c] + red[1][r][c]) + red[2][r][c]) + red[3][r][c];
+        part[(((long long)s * cout_p + co0 + r) * 9 + tap) * cin_p + ci0 + c] = v;
+    }
+}
+
+// Bias gradient partials: sum over pixel chunk s of g[p][co].
+__global__ void k_bgrad(const uint16_t* __restrict__ g, int P, int cout_p, int chunk, float* __restrict__ part)
+{
+    const int s = blockIdx.x;
+    for (int co = threadIdx.x; co < cout_p; co += blockDim.x) {
+        float acc = 0.f;
+        for (int p = s * chunk; p < min(P, (s + 1) * chunk); ++p) acc += from_bf16(g[(long long)p * cout_p + co]);
+        part[(long long)s * cout_p + co] = acc;
+    }
+}
+
+// out[i] = sum over s (in order) of part[s][i]
+__global__ void k_reduce_chunks(const float* __restrict__ part, int S, long long n, float* __restrict__ out)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int s = 0; s < S; ++s) acc += part[(long long)s * n + i];
+        out[i] = acc;
+    }
+}
+
+// Mean L1 loss of y*lamT against the label messages over the slots with a neighbour, and its
+// gradient with respect to y (bf16, the last layer's output gradient) into g [P][cout_p].
+__global__ void k_l1(const float* __restrict__ y, const int16_t* __restrict__ label, int H, int W, int D, int cout_p,
+                     float lam_t, float inv_n, uint16_t* __restrict__ g, float* __restrict__ part)
+{
+    __shared__ float red[kCT];
+    const int P = H * W;
+    float acc = 0.f;
+    for (long long i = (long long)blockIdx.x * kCT + threadIdx.x; i < (long long)P * cout_p;
+         i += (long long)gridDim.x * kCT) {
+        const int c = (int)(i % cout_p);
+        const int p = (int)(i / cout_p);
+        float grad = 0.f;
+        if (c < 4 * D) {
+            const int k = c / D, d = c - k * D;
+            const int py = p / W, px = p - py * W;
+            const bool has = k == 0 ? px > 0 : k == 1 ? px < W - 1 : k == 2 ? py > 0 : py < H - 1;
+            if (has) {
+                // fused: r is y*lam_t - label rounded once, so its sign is the exact one
+                const float r = fmaf(y[i], lam_t, -(float)label[(((long long)k * H + py) * W + px) * D + d]);
+                acc += fabsf(r);
+                grad = (r > 0.f ? lam_t : (r < 0.f ? -lam_t : 0.f)) * inv_n;
+            }
+        }
+        g[i] = to_bf16(grad);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kCT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] * inv_n;
+}
+
+__global__ void k_sum_ordered(const float* __restrict__ part, int n, float* __restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = (float)s;
+    }
+}
+
+__global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ g,
+                       uint16_t* __restrict__ w16, long long n, float lr, float b1, float b2, float eps, float c1,
+                       float c2)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        w[i] = wi;
+        w16[i] = to_bf16(wi);
+    }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ x, long long n, uint16_t* __restrict__ out)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = to_bf16(x[i]);
+}
+
+// CNN input at scale s: views box-averaged over 2^s x 2^s blocks / 255, and the coarsest
+// cost (internal layout of scale s+1, Dp labels) of the pixel's parent / 1024; bf16.
+__global__ void k_warm_input(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R, int W, int H, int s,
+                             const int16_t* __restrict__ coarse, Level lc, int Dp, int D, int Ws, int Hs, int cin_p,
+                             uint16_t* __restrict__ out)
+{
+    const long long n = (long long)Ws * Hs;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int Y = (int)(i / Ws), X = (int)(i - (long long)Y * Ws);
+        const int B = 1 << s;
+        int sl = 0, sr = 0, cnt = 0;
+        for (int y = Y * B; y < (Y + 1) * B && y < H; ++y)
+            for (int x = X * B; x < (X + 1) * B && x < W; ++x) {
+                sl += L[(long long)y * W + x];
+                sr += R[(long long)y * W + x];
+                ++cnt;
+            }
+        uint16_t* o = out + i * cin_p;
+        o[0] = to_bf16((float)sl / ((float)cnt * 255.0f));
+        o[1] = to_bf16((float)sr / ((float)cnt * 255.0f));
+        const int cx = X >> 1, cy = Y >> 1;
+        const int16_t* c = coarse + ((long long)(2 * cy + ((cx + cy) & 1)) * lc.Wh + (cx >> 1)) * Dp;
+        for (int d = 0; d < D; ++d) o[2 + d] = to_bf16((float)c[d] / 1024.0f);
+        for (int ch = 2 + D; ch < cin_p; ++ch) o[ch] = 0;
+    }
+}
+
+// Messages [4][Hs][Ws][D] from the CNN output y [Hs][Ws][ystride] (channel k*D + d).
+__global__ void k_warm_messages(const float* __restrict__ y, int Ws, int Hs, int D, int ystride, int lam_t,
+                                int16_t* __restrict__ out)
+{
+    const long long n = 4LL * Ws * Hs;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(i / ((long long)Ws * Hs));
+        const long long pix = i - (long long)k * Ws * Hs;
+        const int Y = (int)(pix / Ws), X = (int)(pix - (long long)Y * Ws);
+        const bool has = k == 0 ? X > 0 : k == 1 ? X < Ws - 1 : k == 2 ? Y > 0 : Y < Hs - 1;
+        int16_t* o = out + i * D;
+        if (!has) {
+            for (int d = 0; d < D; ++d) o[d] = 0;
+            continue;
+        }
+        const float* yy = y + pix * ystride + k * D;
+        int mn = 0x7fffffff;
+        for (int d = 0; d < D; ++d) {
+            const float r = rintf(yy[d] * (float)lam_t);
+            const int q = r < 0.f ? 0 : (r > (float)lam_t ? lam_t : (int)r);
+            mn = min(mn, q);
+        }
+        for (int d = 0; d < D; ++d) {
+            const float r = rintf(yy[d] * (float)lam_t);
+            const int q = r < 0.f ? 0 : (r > (float)lam_t ? lam_t : (int)r);
+            o[d] = (int16_t)(q - mn);
+        }
+    }
+}
+
+inline unsigned blocks_for(long long n, int t = kCT, long long cap = 8192)
+{
+    long long b = (n + t - 1) / t;
+    return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+hipError_t launch_conv_fwd(const uint16_t* in, int H, int W, int cin_p, const uint16_t* w, const float* bias, int cout,
+                           int cout_p, int relu, const uint16_t* mask, uint16_t* out_bf16, float* out_f32, hipStream_t st)
+{
+    const dim3 grid((unsigned)((H * W + 63) / 64), (unsigned)(cout_p / 32));
+    hipLaunchKernelGGL(k_conv_fwd, grid, dim3(kCT), 0, st, in, H, W, cin_p, w, bias, cout, cout_p, relu, mask, out_bf16,
+                       out_f32);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip(const uint16_t* w, int cin_p, int cout_p, uint16_t* wf, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flip, dim3(blocks_for((long long)cout_p * 9 * cin_p)), dim3(kCT), 0, st, w, cin_p, cout_p, wf);
+    return hipGetLastError();
+}
+
+int wgrad_chunks(int P, int chunk) { return (P + chunk - 1) / chunk; }
+
+hipError_t launch_conv_wgrad(const uint16_t* in, const uint16_t* g, int H, int W, int cin_p, int cout_p, int chunk,
+                             float* part_w, float* part_b, float* dw, float* db, hipStream_t st)
+{
+    const int P = H * W, S = wgrad_chunks(P, chunk);
+    hipLaunchKernelGGL(k_conv_wgrad, dim3((unsigned)S, (unsigned)(9 * (cout_p / 32)), (unsigned)(cin_p / 16)),
+                       dim3(kCT), 0, st, in, g, H, W, cin_p, cout_p, chunk, part_w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long nw = (long long)cout_p * 9 * cin_p;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(blocks_for(nw)), dim3(kCT), 0, st, part_w, S, nw, dw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bgrad, dim3((unsigned)S), dim3(kCT), 0, st, g, P, cout_p, chunk, part_b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(blocks_for(cout_p)), dim3(kCT), 0, st, part_b, S, (long long)cout_p, db);
+    return hipGetLastError();
+}
+
+int l1_blocks(int P, int cout_p) { return (int)blocks_for((long long)P * cout_p, kCT, 1024); }
+
+hipError_t launch_l1(const float* y, const int16_t* label, int H, int W, int D, int cout_p, float lam_t, float inv_n,
+                     uint16_t* g, float* part, float* loss, hipStream_t st)
+{
+    const int nb = l1_blocks(H * W, cout_p);
+    hipLaunchKernelGGL(k_l1, dim3((unsigned)nb), dim3(kCT), 0, st, y, label, H, W, D, cout_p, lam_t, inv_n, g, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, st, part, nb, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* w, float* m, float* v, const float* g, uint16_t* w16, long long n, int step, float lr,
+                       float b1, float b2, float eps, hipStream_t st)
+{
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(kCT), 0, st, w, m, v, g, w16, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float* x, long long n, uint16_t* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(n)), dim3(kCT), 0, st, x, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_input(const uint8_t* L, const uint8_t* R, int W, int H, int s, const int16_t* coarse, Level lc,
+                             int Dp, int D, int Ws, int Hs, int cin_p, uint16_t* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_warm_input, dim3(blocks_for((long long)Ws * Hs)), dim3(kCT), 0, st, L, R, W, H, s, coarse, lc,
+                       Dp, D, Ws, Hs, cin_p, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_messages(const float* y, int Ws, int Hs, int D, int ystride, int lam_t, int16_t* out,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(k_warm_messages, dim3(blocks_for(4LL * Ws * Hs)), dim3(kCT), 0, st, y, Ws, Hs, D, ystride, lam_t,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace bpst

@@ -111,6 +111,30 @@ struct BatchArgs {
 constexpr int kXcds = 8;
 constexpr int kThreadsPerTile = 256;  // workgroup size of every pixel kernel: a tile is 256 / G pixels
 
+hipError_t launch_export_cost(const int16_t* c, Level lv, int D, int G, int16_t* out, hipStream_t st);
+
+// Sets the calling thread's last-error message (cleared for BP_OK); returns code.
+int32_t report(int32_t code, const char* msg);
+
+// ---- learned warm start (cnn_kernels.hip) ----
+hipError_t launch_conv_fwd(const uint16_t* in, int H, int W, int cin_p, const uint16_t* w, const float* bias, int cout,
+                           int cout_p, int relu, const uint16_t* mask, uint16_t* out_bf16, float* out_f32,
+                           hipStream_t st);
+hipError_t launch_flip(const uint16_t* w, int cin_p, int cout_p, uint16_t* wf, hipStream_t st);
+int wgrad_chunks(int P, int chunk);
+hipError_t launch_conv_wgrad(const uint16_t* in, const uint16_t* g, int H, int W, int cin_p, int cout_p, int chunk,
+                             float* part_w, float* part_b, float* dw, float* db, hipStream_t st);
+int l1_blocks(int P, int cout_p);
+hipError_t launch_l1(const float* y, const int16_t* label, int H, int W, int D, int cout_p, float lam_t, float inv_n,
+                     uint16_t* g, float* part, float* loss, hipStream_t st);
+hipError_t launch_adam(float* w, float* m, float* v, const float* g, uint16_t* w16, long long n, int step, float lr,
+                       float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_to_bf16(const float* x, long long n, uint16_t* out, hipStream_t st);
+hipError_t launch_warm_input(const uint8_t* L, const uint8_t* R, int W, int H, int s, const int16_t* coarse, Level lc,
+                             int Dp, int D, int Ws, int Hs, int cin_p, uint16_t* out, hipStream_t st);
+hipError_t launch_warm_messages(const float* y, int Ws, int Hs, int D, int ystride, int lam_t, int16_t* out,
+                                hipStream_t st);
+
 int ncc_tiles(int W, int H);
 hipError_t launch_ncc_batched(const NccPair* pairs, const int* tile_start, int n, int total_tiles, int max_d, int win,
                               int scale, int trunc, hipStream_t st);
