@@ -302,3 +302,27 @@ def test_warm_solve_matches_oracle_end_to_end():
     cost = host(sample.cost)
     ref, _, _ = oracle.bp_solve(cost, 3, [4, 4, 0], 64, 4, warm_msgs=host(msgs), want_msgs=False)
     assert np.array_equal(host(d), ref)
+
+
+def test_trained_network_gain_over_no_network():
+    """What training buys, on held-out pairs: the network's messages are far closer to plain
+    BP's converged scale-(L-2) messages than the zero start the hierarchy would otherwise
+    give there, and a solve started from them passes the 0.5 % energy judge."""
+    from paper_1709_06509_amd import warmstart_train as T
+    cfg = dict(T.DEFAULT, num_disp=16, num_scales=3, iters=8, train_size=(128, 96), eval_size=(128, 96))
+    say("training gain")
+    tr = T.Trainer(cfg, seed=5)
+    T.train(tr, cfg, [cfg["train_seed0"] + i for i in range(400)], log=say)
+    held = [T.Sample(T.gen_pair(cfg["train_size"], 300000 + i, cfg), cfg) for i in range(8)]
+    losses = [tr.heldout_loss(s) for s in held]
+    net, zero = float(np.mean([l[0] for l in losses])), float(np.mean([l[1] for l in losses]))
+    ratios = []
+    for s in held:
+        ep = T.energy(s.cost, T.solve_plain(s, cfg), cfg)
+        ew = T.energy(s.cost, T.solve_warm(s, cfg, tr.predict(s), (8, 8)), cfg)
+        ez = T.energy(s.cost, T.solve_warm(s, cfg, torch.zeros_like(s.label), (8, 8)), cfg)
+        ratios.append((ew / ep, ez / ep))
+    say(f"held-out L1: network {net:.2f}, zero start {zero:.2f}; energy / plain: warm "
+        f"{np.mean([r[0] for r in ratios]):.5f}, zero start {np.mean([r[1] for r in ratios]):.5f}")
+    assert net < 0.5 * zero
+    assert all(r[0] <= 1.005 for r in ratios)
