@@ -20,6 +20,33 @@ sys.path.insert(0, ROOT)
 
 METRIC = "stereo pairs/s and Gmsg-updates/s at equal energy vs plain BP; % HBM peak"
 HBM_PEAK_GBS = 8000.0
+# sources that define the half-step kernel; measured traffic counts only while they are unchanged
+HALFSTEP_SOURCES = ["paper_1709_06509_amd/csrc/bp_device.h", "paper_1709_06509_amd/csrc/bp_kernels.hip",
+                    "paper_1709_06509_amd/csrc/internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "halfstep_traffic.json")
+
+
+def halfstep_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in HALFSTEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per half-step launch from the profiler's counters (profiles/halfstep_traffic.json),
+    or None when there is no record for the workload or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    w = rec.get("workloads", {}).get(workload)
+    if not w or rec.get("source_sha256") != halfstep_source_hash():
+        return None
+    return w["traffic_bytes_per_launch"]
 
 
 def parse():
@@ -278,7 +305,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "launches_per_step": n_launch,
