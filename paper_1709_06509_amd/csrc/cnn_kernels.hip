@@ -40,35 +40,79 @@ __device__ __forceinline__ v4s load4(const uint16_t* p)
     return r;
 }
 
+__device__ __forceinline__ v4s lds_load4(const uint16_t* p)
+{
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    v4s r;
+    r[0] = (short)(u.x & 0xffff);
+    r[1] = (short)(u.x >> 16);
+    r[2] = (short)(u.y & 0xffff);
+    r[3] = (short)(u.y >> 16);
+    return r;
+}
+
+// Weights of one workgroup's 32 output channels in LDS: row co holds [9][cin_p] plus 4
+// elements of padding, so the 16 rows one MFMA operand reads fall in different banks.
+constexpr int kLdsMaxCin = 112;
+__host__ __device__ constexpr int wrow(int cin_p) { return 9 * cin_p + 4; }
+
 // Forward convolution (also the data gradient, with flipped weights and a ReLU mask).
 // One workgroup: 64 pixels x 32 output channels; wave w owns pixels 16w..16w+15.
 //   out_bf16 [P][Cout_p] = bf16( act(acc + bias) ) where act = ReLU if relu, or
 //                         acc * (mask[p][co] > 0) if mask (the ReLU derivative)
 //   out_f32  [P][Cout_p] = the same value before bf16 rounding (nullable)
+// CS = cin_p / 16 when it is at most kLdsMaxCin / 16: the loops are unrolled (every load of a
+// tap is in flight together) and the weights come from LDS; CS = 0: any cin_p, weights read
+// from global memory.
+template <int CS>
 __global__ __launch_bounds__(kCT) void k_conv_fwd(const uint16_t* __restrict__ in, int H, int W, int cin_p,
                                                   const uint16_t* __restrict__ w, const float* __restrict__ bias,
                                                   int cout, int cout_p, int relu, const uint16_t* __restrict__ mask,
                                                   uint16_t* __restrict__ out_bf16, float* __restrict__ out_f32)
 {
+    extern __shared__ uint16_t wl[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int P = H * W;
     const int p = blockIdx.x * 64 + wave * 16 + (lane & 15);  // this lane's A row (pixel)
     const int py = p / W, px = p - py * W;
     const int kq = (lane >> 4) * 4;
     const int co0 = blockIdx.y * 32;
+    const int nc = CS ? CS : cin_p / 16;
+    const int rs = CS ? wrow(16 * CS) : 9 * cin_p;  // element stride between output channels
+    const uint16_t* wb;
+    if (CS) {
+        // stage [32][9][cin_p] (contiguous in global memory) into padded LDS rows, 8 B at a time
+        const uint16_t* src = w + (long long)co0 * 9 * cin_p;
+        const int per = 9 * cin_p / 4;  // 8-byte pieces per row
+        for (int e = threadIdx.x; e < 32 * per; e += kCT) {
+            const int r = e / per, q = e - r * per;
+            *reinterpret_cast<uint2*>(wl + r * rs + 4 * q) = *reinterpret_cast<const uint2*>(src + (long long)r * 9 * cin_p + 4 * q);
+        }
+        __syncthreads();
+        wb = wl;
+    } else {
+        wb = w + (long long)co0 * 9 * cin_p;
+    }
+    const uint16_t* b0 = wb + (long long)(lane & 15) * rs + kq;
+    const uint16_t* b1 = wb + (long long)(16 + (lane & 15)) * rs + kq;
     v4f acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int ys = py + tap / 3 - 1, xs = px + tap % 3 - 1;
         const bool ok = p < P && ys >= 0 && ys < H && xs >= 0 && xs < W;
-        const uint16_t* arow = in + ((long long)ys * W + xs) * cin_p + kq;
-        const uint16_t* b0 = w + ((long long)(co0 + (lane & 15)) * 9 + tap) * cin_p + kq;
-        const uint16_t* b1 = w + ((long long)(co0 + 16 + (lane & 15)) * 9 + tap) * cin_p + kq;
-        for (int c0 = 0; c0 < cin_p; c0 += 16) {
-            v4s a = {0, 0, 0, 0};
-            if (ok) a = load4(arow + c0);
-            const v4s bb0 = load4(b0 + c0), bb1 = load4(b1 + c0);
-            acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb0, acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb1, acc[1], 0, 0, 0);
+        // out-of-image taps read pixel 0 (always valid) and use zero
+        const uint16_t* arow = in + (ok ? ((long long)ys * W + xs) * cin_p : 0LL) + kq;
+        const int tb = tap * cin_p;
+#pragma unroll
+        for (int c = 0; c < (CS ? CS : 1); ++c) {
+            for (int cc = c; cc < nc; cc += (CS ? nc : 1)) {  // CS: one pass; otherwise the runtime loop
+                v4s a = load4(arow + 16 * cc);
+                if (!ok) a = v4s{0, 0, 0, 0};
+                const v4s bb0 = CS ? lds_load4(b0 + tb + 16 * cc) : load4(b0 + tb + 16 * cc);
+                const v4s bb1 = CS ? lds_load4(b1 + tb + 16 * cc) : load4(b1 + tb + 16 * cc);
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb0, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb1, acc[1], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
@@ -153,15 +197,29 @@ __global__ __launch_bounds__(kCT) void k_conv_wgrad(const uint16_t* __restrict__
     }
 }
 
-// Bias gradient partials: sum over pixel chunk s of g[p][co].
-__global__ void k_bgrad(const uint16_t* __restrict__ g, int P, int cout_p, int chunk, float* __restrict__ part)
+// Bias gradient partials: sum over pixel chunk s of g[p][co].  Workgroup (s, 64 channels):
+// wave w adds the pixels p = w (mod 4) of the chunk with four independent accumulators (so
+// four loads are in flight), then the four waves' sums are added in wave order.
+__global__ __launch_bounds__(kCT) void k_bgrad(const uint16_t* __restrict__ g, int P, int cout_p, int chunk,
+                                               float* __restrict__ part)
 {
-    const int s = blockIdx.x;
-    for (int co = threadIdx.x; co < cout_p; co += blockDim.x) {
-        float acc = 0.f;
-        for (int p = s * chunk; p < min(P, (s + 1) * chunk); ++p) acc += from_bf16(g[(long long)p * cout_p + co]);
-        part[(long long)s * cout_p + co] = acc;
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int s = blockIdx.x, co = blockIdx.y * 64 + lane;
+    const int pbeg = s * chunk, pend = min(P, pbeg + chunk);
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (co < cout_p) {
+        int p = pbeg + wave;
+        for (; p + 12 < pend; p += 16) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] += from_bf16(g[(long long)(p + 4 * j) * cout_p + co]);
+        }
+        for (; p < pend; p += 4) acc[0] += from_bf16(g[(long long)p * cout_p + co]);
     }
+    red[wave][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (wave == 0 && co < cout_p)
+        part[(long long)s * cout_p + co] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // out[i] = sum over s (in order) of part[s][i]
@@ -209,13 +267,20 @@ __global__ void k_l1(const float* __restrict__ y, const int16_t* __restrict__ la
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] * inv_n;
 }
 
-__global__ void k_sum_ordered(const float* __restrict__ part, int n, float* __restrict__ out)
+// *out = sum of part[0..n), in fp64 and in a fixed order: thread t adds t, t + 256, ...,
+// then a fixed halving tree over the threads.  One workgroup of kCT threads.
+__global__ __launch_bounds__(kCT) void k_sum_ordered(const float* __restrict__ part, int n, float* __restrict__ out)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += part[i];
-        *out = (float)s;
+    __shared__ double red[kCT];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kCT) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kCT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out = (float)red[0];
 }
 
 __global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ g,
@@ -241,58 +306,75 @@ __global__ void k_to_bf16(const float* __restrict__ x, long long n, uint16_t* __
 }
 
 // CNN input at scale s: views box-averaged over 2^s x 2^s blocks / 255, and the coarsest
-// cost (internal layout of scale s+1, Dp labels) of the pixel's parent / 1024; bf16.
+// cost (internal layout of scale s+1, Dp labels) of the pixel's parent / 1024; bf16.  One
+// thread per output channel, so writes (and the cost reads) are contiguous.
 __global__ void k_warm_input(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R, int W, int H, int s,
                              const int16_t* __restrict__ coarse, Level lc, int Dp, int D, int Ws, int Hs, int cin_p,
                              uint16_t* __restrict__ out)
 {
-    const long long n = (long long)Ws * Hs;
+    const long long n = (long long)Ws * Hs * cin_p;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int Y = (int)(i / Ws), X = (int)(i - (long long)Y * Ws);
-        const int B = 1 << s;
-        int sl = 0, sr = 0, cnt = 0;
-        for (int y = Y * B; y < (Y + 1) * B && y < H; ++y)
-            for (int x = X * B; x < (X + 1) * B && x < W; ++x) {
-                sl += L[(long long)y * W + x];
-                sr += R[(long long)y * W + x];
-                ++cnt;
-            }
-        uint16_t* o = out + i * cin_p;
-        o[0] = to_bf16((float)sl / ((float)cnt * 255.0f));
-        o[1] = to_bf16((float)sr / ((float)cnt * 255.0f));
-        const int cx = X >> 1, cy = Y >> 1;
-        const int16_t* c = coarse + ((long long)(2 * cy + ((cx + cy) & 1)) * lc.Wh + (cx >> 1)) * Dp;
-        for (int d = 0; d < D; ++d) o[2 + d] = to_bf16((float)c[d] / 1024.0f);
-        for (int ch = 2 + D; ch < cin_p; ++ch) o[ch] = 0;
+        const int ch = (int)(i % cin_p);
+        const long long pix = i / cin_p;
+        const int Y = (int)(pix / Ws), X = (int)(pix - (long long)Y * Ws);
+        float v = 0.f;
+        if (ch < 2) {
+            const uint8_t* img = ch == 0 ? L : R;
+            const int B = 1 << s;
+            int sum = 0, cnt = 0;
+            for (int y = Y * B; y < (Y + 1) * B && y < H; ++y)
+                for (int x = X * B; x < (X + 1) * B && x < W; ++x) {
+                    sum += img[(long long)y * W + x];
+                    ++cnt;
+                }
+            v = (float)sum / ((float)cnt * 255.0f);
+        } else if (ch < 2 + D) {
+            const int cx = X >> 1, cy = Y >> 1;
+            v = (float)coarse[((long long)(2 * cy + ((cx + cy) & 1)) * lc.Wh + (cx >> 1)) * Dp + (ch - 2)] / 1024.0f;
+        }
+        out[i] = to_bf16(v);
     }
 }
 
-// Messages [4][Hs][Ws][D] from the CNN output y [Hs][Ws][ystride] (channel k*D + d).
-__global__ void k_warm_messages(const float* __restrict__ y, int Ws, int Hs, int D, int ystride, int lam_t,
-                                int16_t* __restrict__ out)
+// Messages [4][Hs][Ws][D] from the CNN output y [Hs][Ws][ystride] (channel k*D + d).  One
+// message (side k of one pixel) per group of GS lanes (GS = D rounded up to a power of two,
+// at most 64); lane j of a group takes the labels j, j + GS, ..., so reads and writes are
+// contiguous, and the group's minimum comes from a butterfly of lane exchanges.
+template <int GS>
+__global__ __launch_bounds__(kCT) void k_warm_messages(const float* __restrict__ y, int Ws, int Hs, int D, int ystride,
+                                                       int lam_t, int16_t* __restrict__ out)
 {
+    constexpr int kMaxPer = GS < 64 ? 1 : 4;  // labels per lane (D <= GS below 64, D <= 256)
     const long long n = 4LL * Ws * Hs;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int j = threadIdx.x & (GS - 1);
+    const long long first = ((long long)blockIdx.x * kCT + threadIdx.x) / GS;
+    const long long step = (long long)gridDim.x * (kCT / GS);
+    for (long long i = first; i < n; i += step) {  // uniform per group: GS divides 64
         const int k = (int)(i / ((long long)Ws * Hs));
         const long long pix = i - (long long)k * Ws * Hs;
         const int Y = (int)(pix / Ws), X = (int)(pix - (long long)Y * Ws);
         const bool has = k == 0 ? X > 0 : k == 1 ? X < Ws - 1 : k == 2 ? Y > 0 : Y < Hs - 1;
         int16_t* o = out + i * D;
-        if (!has) {
-            for (int d = 0; d < D; ++d) o[d] = 0;
-            continue;
-        }
         const float* yy = y + pix * ystride + k * D;
+        int q[kMaxPer];
         int mn = 0x7fffffff;
-        for (int d = 0; d < D; ++d) {
-            const float r = rintf(yy[d] * (float)lam_t);
-            const int q = r < 0.f ? 0 : (r > (float)lam_t ? lam_t : (int)r);
-            mn = min(mn, q);
+#pragma unroll
+        for (int t = 0; t < kMaxPer; ++t) {
+            const int d = j + t * GS;
+            q[t] = 0;
+            if (d < D && has) {
+                const float r = rintf(yy[d] * (float)lam_t);
+                q[t] = r < 0.f ? 0 : (r > (float)lam_t ? lam_t : (int)r);
+                mn = min(mn, q[t]);
+            }
         }
-        for (int d = 0; d < D; ++d) {
-            const float r = rintf(yy[d] * (float)lam_t);
-            const int q = r < 0.f ? 0 : (r > (float)lam_t ? lam_t : (int)r);
-            o[d] = (int16_t)(q - mn);
+#pragma unroll
+        for (int w = 1; w < GS; w <<= 1) mn = min(mn, __shfl_xor(mn, w, GS));
+        if (!has) mn = 0;
+#pragma unroll
+        for (int t = 0; t < kMaxPer; ++t) {
+            const int d = j + t * GS;
+            if (d < D) o[d] = (int16_t)(q[t] - mn);
         }
     }
 }
@@ -309,8 +391,16 @@ hipError_t launch_conv_fwd(const uint16_t* in, int H, int W, int cin_p, const ui
                            int cout_p, int relu, const uint16_t* mask, uint16_t* out_bf16, float* out_f32, hipStream_t st)
 {
     const dim3 grid((unsigned)((H * W + 63) / 64), (unsigned)(cout_p / 32));
-    hipLaunchKernelGGL(k_conv_fwd, grid, dim3(kCT), 0, st, in, H, W, cin_p, w, bias, cout, cout_p, relu, mask, out_bf16,
-                       out_f32);
+    const int cs = cin_p <= kLdsMaxCin ? cin_p / 16 : 0;
+    const size_t lds = cs ? (size_t)32 * wrow(cin_p) * sizeof(uint16_t) : 0;
+#define BPST_CONV(CSV) \
+    case CSV: hipLaunchKernelGGL(k_conv_fwd<CSV>, grid, dim3(kCT), lds, st, in, H, W, cin_p, w, bias, cout, cout_p, relu, \
+                                 mask, out_bf16, out_f32); break;
+    switch (cs) {
+        BPST_CONV(0) BPST_CONV(1) BPST_CONV(2) BPST_CONV(3) BPST_CONV(4) BPST_CONV(5) BPST_CONV(6) BPST_CONV(7)
+        default: return hipErrorInvalidValue;
+    }
+#undef BPST_CONV
     return hipGetLastError();
 }
 
@@ -333,7 +423,8 @@ hipError_t launch_conv_wgrad(const uint16_t* in, const uint16_t* g, int H, int W
     const long long nw = (long long)cout_p * 9 * cin_p;
     hipLaunchKernelGGL(k_reduce_chunks, dim3(blocks_for(nw)), dim3(kCT), 0, st, part_w, S, nw, dw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bgrad, dim3((unsigned)S), dim3(kCT), 0, st, g, P, cout_p, chunk, part_b);
+    hipLaunchKernelGGL(k_bgrad, dim3((unsigned)S, (unsigned)((cout_p + 63) / 64)), dim3(kCT), 0, st, g, P, cout_p,
+                       chunk, part_b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_chunks, dim3(blocks_for(cout_p)), dim3(kCT), 0, st, part_b, S, (long long)cout_p, db);
     return hipGetLastError();
@@ -348,7 +439,7 @@ hipError_t launch_l1(const float* y, const int16_t* label, int H, int W, int D, 
     hipLaunchKernelGGL(k_l1, dim3((unsigned)nb), dim3(kCT), 0, st, y, label, H, W, D, cout_p, lam_t, inv_n, g, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, st, part, nb, loss);
+    hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(kCT), 0, st, part, nb, loss);
     return hipGetLastError();
 }
 
@@ -369,16 +460,25 @@ hipError_t launch_to_bf16(const float* x, long long n, uint16_t* out, hipStream_
 hipError_t launch_warm_input(const uint8_t* L, const uint8_t* R, int W, int H, int s, const int16_t* coarse, Level lc,
                              int Dp, int D, int Ws, int Hs, int cin_p, uint16_t* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_warm_input, dim3(blocks_for((long long)Ws * Hs)), dim3(kCT), 0, st, L, R, W, H, s, coarse, lc,
-                       Dp, D, Ws, Hs, cin_p, out);
+    hipLaunchKernelGGL(k_warm_input, dim3(blocks_for((long long)Ws * Hs * cin_p)), dim3(kCT), 0, st, L, R, W, H, s,
+                       coarse, lc, Dp, D, Ws, Hs, cin_p, out);
     return hipGetLastError();
 }
 
 hipError_t launch_warm_messages(const float* y, int Ws, int Hs, int D, int ystride, int lam_t, int16_t* out,
                                 hipStream_t st)
 {
-    hipLaunchKernelGGL(k_warm_messages, dim3(blocks_for(4LL * Ws * Hs)), dim3(kCT), 0, st, y, Ws, Hs, D, ystride, lam_t,
-                       out);
+    const long long n = 4LL * Ws * Hs;
+    int gs = 1;
+    while (gs < D && gs < 64) gs <<= 1;
+    const unsigned nb = blocks_for(n * gs);
+#define BPST_WARM(GS) \
+    case GS: hipLaunchKernelGGL(k_warm_messages<GS>, dim3(nb), dim3(kCT), 0, st, y, Ws, Hs, D, ystride, lam_t, out); break;
+    switch (gs) {
+        BPST_WARM(1) BPST_WARM(2) BPST_WARM(4) BPST_WARM(8) BPST_WARM(16) BPST_WARM(32) BPST_WARM(64)
+        default: return hipErrorInvalidValue;
+    }
+#undef BPST_WARM
     return hipGetLastError();
 }
 
