@@ -35,12 +35,15 @@ __device__ bool le_times_sqrt(long long B, long long A, unsigned long long P)
     return B >= 0 ? false : (b2 >= a2p);
 }
 
-// One tile: image row y, columns x0 .. x0 + kTileX - 1 (clipped), every disparity.
-__device__ void ncc_tile(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R, int W, int H, int D, int win,
-                         int scale, int trunc, float margin, int16_t* __restrict__ cost,
-                         float* __restrict__ ncc_out, int y, int x0, unsigned* smem)
+// One tile: image row y, columns x0 .. x0 + kTileX - 1 (clipped), every disparity.  WIN is
+// the window size (odd, <= 13), known at compile time so every window loop unrolls.
+// Element loops walk (column, disparity) pairs with an incremental index, not a division.
+template <int WIN>
+__device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R, int W, int H,
+                                         int D, int scale, int trunc, float margin, int16_t* __restrict__ cost,
+                                         float* __restrict__ ncc_out, int y, int x0, unsigned* smem)
 {
-    const int r = win >> 1;
+    constexpr int r = WIN >> 1;
     const int nI = kTileX + 2 * r;          // left columns  x0-r .. x0+kTileX-1+r
     const int nJ = kTileX + 2 * r + D - 1;  // right columns x0-r-(D-1) .. x0+kTileX-1+r
     const int uI0 = x0 - r, uJ0 = x0 - r - (D - 1);
@@ -63,14 +66,15 @@ __device__ void ncc_tile(const uint8_t* __restrict__ L, const uint8_t* __restric
         const int u = left ? uI0 + c : uJ0 + (c - nI);
         const int xx = clampi(u, 0, W - 1);
         unsigned w4[4] = {0u, 0u, 0u, 0u};
-        for (int j = 0; j < win; ++j) {
+#pragma unroll
+        for (int j = 0; j < WIN; ++j) {
             const unsigned v = img[(long long)clampi(y - r + j, 0, H - 1) * W + xx];
             w4[j >> 2] |= v << (8 * (j & 3));
         }
         const uint4 pk = make_uint4(w4[0], w4[1], w4[2], w4[3]);
         unsigned s = 0, ss = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < (WIN + 3) / 4; ++k) {
             s = __builtin_amdgcn_udot4(w4[k], 0x01010101u, s, false);
             ss = __builtin_amdgcn_udot4(w4[k], w4[k], ss, false);
         }
@@ -82,88 +86,102 @@ __device__ void ncc_tile(const uint8_t* __restrict__ L, const uint8_t* __restric
     // 2. horizontal window sums of the left columns and the right columns
     for (int i = threadIdx.x; i < kTileX; i += kThreads) {
         int s = 0, ss = 0;
-        for (int k = 0; k < win; ++k) { s += cI[i + k]; ss += cII[i + k]; }
+#pragma unroll
+        for (int k = 0; k < WIN; ++k) { s += cI[i + k]; ss += cII[i + k]; }
         SI[i] = s; SII[i] = ss;
     }
     for (int i = threadIdx.x; i < kTileX + D - 1; i += kThreads) {
         int s = 0, ss = 0;
-        for (int k = 0; k < win; ++k) { s += cJ[i + k]; ss += cJJ[i + k]; }
+#pragma unroll
+        for (int k = 0; k < WIN; ++k) { s += cJ[i + k]; ss += cJJ[i + k]; }
         SJ[i] = s; SJJ[i] = ss;
     }
     // 3. column products V[u][d] = sum over the window rows of left(u) * right(u - d)
-    for (int e = threadIdx.x; e < nI * D; e += kThreads) {
-        const int u = e / D, d = e - u * D;
-        const uint4 a = colI[u];
-        const uint4 b = colJ[u - d + (D - 1)];  // right column uI0 + u - d
-        unsigned s = __builtin_amdgcn_udot4(a.x, b.x, 0u, false);
-        s = __builtin_amdgcn_udot4(a.y, b.y, s, false);
-        s = __builtin_amdgcn_udot4(a.z, b.z, s, false);
-        s = __builtin_amdgcn_udot4(a.w, b.w, s, false);
-        V[e] = (int)s;
+    const int du = kThreads / D, dd = kThreads - du * D;  // step of (u, d) per kThreads elements
+    {
+        int u = threadIdx.x / D, d = threadIdx.x - u * D;
+        for (int e = threadIdx.x; e < nI * D; e += kThreads) {
+            const uint4 a = colI[u];
+            const uint4 b = colJ[u - d + (D - 1)];  // right column uI0 + u - d
+            unsigned s = __builtin_amdgcn_udot4(a.x, b.x, 0u, false);
+            if (WIN > 4) s = __builtin_amdgcn_udot4(a.y, b.y, s, false);
+            if (WIN > 8) s = __builtin_amdgcn_udot4(a.z, b.z, s, false);
+            if (WIN > 12) s = __builtin_amdgcn_udot4(a.w, b.w, s, false);
+            V[e] = (int)s;
+            u += du;
+            d += dd;
+            if (d >= D) { d -= D; ++u; }
+        }
     }
     __syncthreads();
 
     // 4. finish every (x, d) of the tile; consecutive threads write consecutive d
-    const long long n = (long long)win * win;
+    constexpr int n = WIN * WIN;
     const int tileW = min(kTileX, W - x0);
+    int i = threadIdx.x / D, d = threadIdx.x - i * D;
     for (int e = threadIdx.x; e < tileW * D; e += kThreads) {
-        const int i = e / D, d = e - i * D;
         const int x = x0 + i;
         const long long o = ((long long)y * W + x) * D + d;
         if (x - d < 0) {
             cost[o] = (int16_t)trunc;
             if (ncc_out) ncc_out[o] = -2.0f;
-            continue;
-        }
-        int sij = 0;
-        for (int k = 0; k < win; ++k) sij += V[(i + k) * D + d];
-        // window <= 13: every product and difference below fits in int32
-        const int si = SI[i], sii = SII[i];
-        const int sj = SJ[i - d + (D - 1)], sjj = SJJ[i - d + (D - 1)];
-        const int num = (int)n * sij - si * sj;
-        const int vi = (int)n * sii - si * si;
-        const int vj = (int)n * sjj - sj * sj;
-        long long k;
-        float nv;
-        if (vi == 0 || vj == 0) {
-            k = scale;
-            nv = 0.0f;
         } else {
-            // fp32 estimate: relative error of c below ~4e-7, so |error of v| < 3.1e-7 * scale;
-            // within `margin` (>= 2e-6 * scale) of a boundary the exact test decides
-            const float c = (float)num * rsqrtf((float)vi * (float)vj);
-            nv = c;
-            const float v = (float)scale * (1.0f - c) + 0.5f;
-            k = (long long)floorf(v);
-            const float fr = v - (float)k;
-            if (fr < margin || fr > 1.0f - margin) {
-                const unsigned long long P = (unsigned long long)vi * (unsigned long long)vj;
-                const long long B = 2LL * scale * num;
-                while (!le_times_sqrt(B, 2LL * scale - 2 * k + 1, P)) --k;
-                while (le_times_sqrt(B, 2LL * scale - 2 * (k + 1) + 1, P)) ++k;
+            int sij = 0;
+            const int* vp = V + i * D + d;
+#pragma unroll
+            for (int k = 0; k < WIN; ++k) sij += vp[k * D];
+            // window <= 13: every product and difference below fits in int32
+            const int si = SI[i], sii = SII[i];
+            const int sj = SJ[i - d + (D - 1)], sjj = SJJ[i - d + (D - 1)];
+            const int num = n * sij - si * sj;
+            const int vi = n * sii - si * si;
+            const int vj = n * sjj - sj * sj;
+            long long k;
+            float nv;
+            if (vi == 0 || vj == 0) {
+                k = scale;
+                nv = 0.0f;
+            } else {
+                // fp32 estimate: relative error of c below ~4e-7, so |error of v| < 3.1e-7 * scale;
+                // within `margin` (>= 2e-6 * scale) of a boundary the exact test decides
+                const float c = (float)num * rsqrtf((float)vi * (float)vj);
+                nv = c;
+                const float v = (float)scale * (1.0f - c) + 0.5f;
+                k = (long long)floorf(v);
+                const float fr = v - (float)k;
+                if (fr < margin || fr > 1.0f - margin) {
+                    const unsigned long long P = (unsigned long long)vi * (unsigned long long)vj;
+                    const long long B = 2LL * scale * num;
+                    while (!le_times_sqrt(B, 2LL * scale - 2 * k + 1, P)) --k;
+                    while (le_times_sqrt(B, 2LL * scale - 2 * (k + 1) + 1, P)) ++k;
+                }
             }
+            if (k < 0) k = 0;
+            if (k > trunc) k = trunc;
+            cost[o] = (int16_t)k;
+            if (ncc_out) ncc_out[o] = nv;
         }
-        if (k < 0) k = 0;
-        if (k > trunc) k = trunc;
-        cost[o] = (int16_t)k;
-        if (ncc_out) ncc_out[o] = nv;
+        i += du;
+        d += dd;
+        if (d >= D) { d -= D; ++i; }
     }
 }
 
+template <int WIN>
 __global__ __launch_bounds__(kThreads) void k_ncc(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R,
-                                                   int W, int H, int D, int win, int scale, int trunc,
-                                                   float margin, int16_t* __restrict__ cost,
-                                                   float* __restrict__ ncc_out)
+                                                   int W, int H, int D, int scale, int trunc, float margin,
+                                                   int16_t* __restrict__ cost, float* __restrict__ ncc_out)
 {
     extern __shared__ unsigned smem[];
-    ncc_tile(L, R, W, H, D, win, scale, trunc, margin, cost, ncc_out, blockIdx.y, blockIdx.x * kTileX, smem);
+    ncc_tile<WIN>(L, R, W, H, D, scale, trunc, margin, cost, ncc_out, blockIdx.y, blockIdx.x * kTileX, smem);
 }
 
 // Every tile of every pair of a batch in one launch; tile_start[p] is the first tile of
 // pair p (prefix sums, tile_start[n] = total), a pair's tiles run row-major over
 // (row, column tile).
+template <int WIN>
 __global__ __launch_bounds__(kThreads) void k_ncc_batched(const NccPair* __restrict__ pairs, const int* tile_start,
-                                                           int n, int win, int scale, int trunc, float margin)
+                                                           int n, int scale, int trunc, float margin)
 {
     extern __shared__ unsigned smem[];
     const int tile = blockIdx.x;
@@ -177,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_ncc_batched(const NccPair* __restr
     const int local = tile - tile_start[lo];
     const int tx = (P.W + kTileX - 1) / kTileX;
     const int y = local / tx, x0 = (local - y * tx) * kTileX;
-    ncc_tile(P.left, P.right, P.W, P.H, P.D, win, scale, trunc, margin, P.cost, nullptr, y, x0, smem);
+    ncc_tile<WIN>(P.left, P.right, P.W, P.H, P.D, scale, trunc, margin, P.cost, nullptr, y, x0, smem);
 }
 
 size_t ncc_lds_bytes(int D, int win)
@@ -199,8 +217,15 @@ hipError_t launch_ncc(const uint8_t* L, const uint8_t* R, int W, int H, int D, i
 {
     if ((win >> 1) > kMaxR) return hipErrorInvalidValue;
     dim3 grid((unsigned)((W + kTileX - 1) / kTileX), (unsigned)H);
-    hipLaunchKernelGGL(k_ncc, grid, dim3(kThreads), ncc_lds_bytes(D, win), st, L, R, W, H, D, win, scale, trunc,
-                       ncc_margin(scale), cost, ncc);
+    const size_t lds = ncc_lds_bytes(D, win);
+    const float m = ncc_margin(scale);
+#define BPST_NCC(WV) \
+    case WV: hipLaunchKernelGGL(k_ncc<WV>, grid, dim3(kThreads), lds, st, L, R, W, H, D, scale, trunc, m, cost, ncc); break;
+    switch (win) {
+        BPST_NCC(1) BPST_NCC(3) BPST_NCC(5) BPST_NCC(7) BPST_NCC(9) BPST_NCC(11) BPST_NCC(13)
+        default: return hipErrorInvalidValue;
+    }
+#undef BPST_NCC
     return hipGetLastError();
 }
 
@@ -209,8 +234,17 @@ hipError_t launch_ncc_batched(const NccPair* pairs, const int* tile_start, int n
 {
     if ((win >> 1) > kMaxR) return hipErrorInvalidValue;
     if (total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ncc_batched, dim3((unsigned)total_tiles), dim3(kThreads), ncc_lds_bytes(max_d, win), st,
-                       pairs, tile_start, n, win, scale, trunc, ncc_margin(scale));
+    const size_t lds = ncc_lds_bytes(max_d, win);
+    const float m = ncc_margin(scale);
+    const dim3 grid((unsigned)total_tiles);
+#define BPST_NCCB(WV) \
+    case WV: hipLaunchKernelGGL(k_ncc_batched<WV>, grid, dim3(kThreads), lds, st, pairs, tile_start, n, scale, trunc, m); \
+        break;
+    switch (win) {
+        BPST_NCCB(1) BPST_NCCB(3) BPST_NCCB(5) BPST_NCCB(7) BPST_NCCB(9) BPST_NCCB(11) BPST_NCCB(13)
+        default: return hipErrorInvalidValue;
+    }
+#undef BPST_NCCB
     return hipGetLastError();
 }
 
