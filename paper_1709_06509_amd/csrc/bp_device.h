@@ -312,12 +312,22 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
 #pragma unroll
         for (int j = 0; j < 8; ++j) Hs[j] = 0;
     }
+    const bool check = (MODE == 2) || (MODE == 1 && a.t >= 2);
+    // the outgoing messages this update may overwrite, loaded together with the incoming
+    // ones (nothing else writes them during the half-step), so the four compare-and-store
+    // steps below do not each wait for a load
+    int4 op[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        op[k] = make_int4(0, 0, 0, 0);
+        if (check && act && has[k])
+            op[k] = *reinterpret_cast<const int4*>(a.msgs + (k ^ 1) * a.vol + nb[k] * Dp + d0);
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j)
         Hs[j] = (d0 + j < a.D) ? Hs[j] + msg_at(mp[0], j) + msg_at(mp[1], j) + msg_at(mp[2], j) + msg_at(mp[3], j)
                                : kBig;
     if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;
-    const bool check = (MODE == 2) || (MODE == 1 && a.t >= 2);
     bool all_eq = true;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -328,11 +338,9 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
         bool store = act && has[k];
         int16_t* dst = a.msgs + (k ^ 1) * a.vol + nb[k] * Dp + d0;
         if (check) {
-            int old[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (store) unpack8(*reinterpret_cast<const int4*>(dst), old);
             int e = 1;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) if (d0 + j < a.D && old[j] != o[j]) e = 0;
+            for (int j = 0; j < 8; ++j) if (d0 + j < a.D && msg_at(op[k], j) != o[j]) e = 0;
             e = group_min<G>(e);
             if (store && !e) all_eq = false;
             if (e) store = false;
