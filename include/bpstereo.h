@@ -88,6 +88,15 @@ int32_t bp_context_set_timing(bp_context* ctx, int32_t on);
 int32_t bp_context_take_timing(bp_context* ctx, bp_timing* out);
 
 /*
+ * Several consecutive half-steps of a scale in one launch, from LDS: a workgroup loads an
+ * interior tile plus a halo as wide as the number of half-steps, runs them, and writes back
+ * the interior, which is then bit-identical to one launch per half-step.  It saves launch
+ * latency on small scales.  mode 0: never; 1: wherever a tile fits (D <= 64, no counters,
+ * skip modes 0 and 1); 2 (default, also without a context): on scales whose cost and
+ * messages take at most 48 MB.  Results never depend on the mode.
+ */
+int32_t bp_context_set_fused(bp_context* ctx, int32_t mode);
+/*
  * When `on` is non-zero, bp_hierarchical_solve on this context records its launch
  * sequence into a HIP graph the first time it sees a given set of arguments (shape,
  * parameters and every pointer) and replays that graph on later identical calls.  Applies

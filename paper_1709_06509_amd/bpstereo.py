@@ -70,6 +70,7 @@ def _load():
         lib.bp_context_destroy.argtypes = [_vp]
         lib.bp_context_set_timing.argtypes = [_vp, _i32]
         lib.bp_context_set_graphs.argtypes = [_vp, _i32]
+        lib.bp_context_set_fused.argtypes = [_vp, _i32]
         lib.bp_context_graph_counts.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
         lib.bp_context_take_timing.argtypes = [_vp, ctypes.POINTER(BPTiming)]
         lib.stereo_luma.argtypes = [_vp, _i32, _i32, _vp, _vp]
@@ -82,7 +83,7 @@ def _load():
         lib.bp_energy_workspace_bytes.restype = ctypes.c_size_t
         lib.bp_energy.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t, _vp]
         for name in ("bp_context_create", "bp_context_destroy", "bp_context_set_timing", "bp_context_take_timing",
-                     "bp_context_set_graphs", "bp_context_graph_counts",
+                     "bp_context_set_graphs", "bp_context_set_fused", "bp_context_graph_counts",
                      "stereo_luma", "stereo_cost_volume", "bp_hierarchical_solve", "bp_energy"):
             getattr(lib, name).restype = ctypes.c_int32
         _lib = lib
@@ -129,6 +130,10 @@ class Context:
 
     def set_graphs(self, on=True):
         _check(_load().bp_context_set_graphs(self.handle, 1 if on else 0))
+
+    def set_fused(self, mode):
+        """Half-steps per launch on small scales: 0 one each, 1 several wherever they fit, 2 by size."""
+        _check(_load().bp_context_set_fused(self.handle, int(mode)))
 
     def graph_counts(self):
         c = (ctypes.c_int64 * 3)()

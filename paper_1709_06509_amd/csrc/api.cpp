@@ -128,6 +128,7 @@ struct SolveKey {
     bp_params params;
     const void *cost, *workspace, *disparity, *final_msgs;
     size_t workspace_bytes;
+    int32_t fused;
 };
 
 struct bp_context {
@@ -136,6 +137,7 @@ struct bp_context {
     size_t used = 0;
     long long pixels_max = 0;
     bool graphs = false;
+    int fused = 2;  // several half-steps per launch on small scales: 0 never, 1 wherever it fits, 2 by size
     std::vector<std::pair<SolveKey, hipGraphExec_t>> cache;  // oldest first
     long long graph_hits = 0, graph_captures = 0, graph_fallbacks = 0;
     // batched solve: pinned staging for the per-batch tables (two, each guarded by the event
@@ -167,9 +169,10 @@ BP_API int32_t bp_context_set_batch_schedule(bp_context* ctx, int32_t schedule, 
 
 namespace {
 constexpr size_t kMaxGraphs = 32;
+constexpr int kFusedMaxSteps = 5;  // half-steps (and halo pixels) per fused launch when forced
 
 SolveKey make_key(int32_t W, int32_t H, const bp_params* p, const void* cost, const void* ws, size_t wsb,
-                  const void* disp, const void* msgs)
+                  const void* disp, const void* msgs, int32_t fused)
 {
     SolveKey k;
     std::memset(&k, 0, sizeof k);  // padding too: keys are compared bytewise
@@ -188,6 +191,7 @@ SolveKey make_key(int32_t W, int32_t H, const bp_params* p, const void* cost, co
     k.workspace_bytes = wsb;
     k.disparity = disp;
     k.final_msgs = msgs;
+    k.fused = fused;
     return k;
 }
 }  // namespace
@@ -200,6 +204,7 @@ BP_API int32_t bp_context_create(bp_context** out)
     bp_context* c = new (std::nothrow) bp_context();
     if (!c) return fail(BP_E_NOMEM, "cannot allocate a context");
     *out = c;
+    bpst::fused_prepare();
     return ok();
 }
 
@@ -220,6 +225,14 @@ BP_API int32_t bp_context_destroy(bp_context* ctx)
         if (ctx->staging[i]) (void)hipHostFree(ctx->staging[i]);
     }
     delete ctx;
+    return ok();
+}
+
+BP_API int32_t bp_context_set_fused(bp_context* ctx, int32_t mode)
+{
+    if (!ctx) return fail(BP_E_INVAL, "ctx is NULL");
+    if (mode < 0 || mode > 2) return fail(BP_E_INVAL, "mode must be 0, 1 or 2");
+    ctx->fused = mode;
     return ok();
 }
 
@@ -337,6 +350,32 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         // colour-0 slots would never be written), a warm start, or the exact dirty-skip,
         // whose change test compares against the initial messages.
         const bool fuse = iters >= 2 && mode != 2 && !(l == start && params->warm_msgs);
+        // Several half-steps per launch from LDS (fused_kernels.hip): no counters, freeze
+        // rule or plain, and (by default) only where a half-step moves little enough memory
+        // that one launch per half-step would be bound by launch latency.
+        int ftw = 0, fth = 0, fsteps = 0;
+        long long frmax = 0;
+        const int fmode = ctx ? ctx->fused : 2;
+        if (fmode != 0 && !count && mode != 2 && iters >= 1 && pl.G <= 8) {
+            if (fmode == 2) {
+                if (!bpst::fused_geometry(pl.lv[l], pl.G, iters, &fsteps, &ftw, &fth, &frmax)) fsteps = 0;
+            } else {
+                const int chunks = (iters + kFusedMaxSteps - 1) / kFusedMaxSteps;
+                fsteps = (iters + chunks - 1) / chunks;
+                if (!bpst::fused_geometry_max(pl.lv[l], pl.G, fsteps, &ftw, &fth, &frmax)) fsteps = 0;
+            }
+            {
+                // test hook: smaller interior tiles, so that small images are cut into many
+                const char* forced = getenv("BPSTEREO_FUSED_TILE");
+                int fw = 0, fh = 0;
+                if (fsteps > 0 && forced && sscanf(forced, "%dx%d", &fw, &fh) == 2 && fw >= 1 && fh >= 1 &&
+                    fw <= ftw && fh <= fth) {
+                    ftw = fw;
+                    fth = fh;
+                    frmax = (long long)(fw + 2 * fsteps) * (fh + 2 * fsteps);
+                }
+            }
+        }
         int source = bpst::kSrcOwn;
         if (fuse) {
             source = (l == start) ? bpst::kSrcZero : bpst::kSrcParent;
@@ -370,7 +409,54 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         a.count = count ? 1 : 0;
         a.stats = stats;
         a.level = l;
-        for (int t = 0; t < iters; ++t) {
+        if (fsteps > 0) {
+            // the fused kernel reads the parent's (or zero) messages itself at t = 0, as the
+            // first half-step does; where an init kernel ran, it reads its own volumes
+            bpst::FusedArgs f{};
+            f.cost = C[l];
+            f.msgs = msgs;
+            f.vol = pl.vol[l];
+            f.pmsgs = a.pmsgs;
+            f.pvol = a.pvol;
+            f.plv = a.plv;
+            f.state_a = sa;
+            f.state_b = sb;
+            f.lv = pl.lv[l];
+            f.D = pl.D;
+            f.G = pl.G;
+            f.lambda = params->lambda;
+            f.capv = capv;
+            f.K = params->converge_iters;
+            f.mode = mode;
+            f.TW = ftw;
+            f.TH = fth;
+            f.tiles_x = (pl.lv[l].W + ftw - 1) / ftw;
+            f.rmax = frmax;
+            for (int t0 = 0; t0 < iters; t0 += fsteps) {
+                f.t0 = t0;
+                f.nsteps = iters - t0 < fsteps ? iters - t0 : fsteps;
+                f.halo = f.nsteps;  // a shorter last chunk keeps the tile: its smaller halo fits the LDS
+                f.source = t0 == 0 ? source : bpst::kSrcOwn;
+                f.keep_state = t0 + f.nsteps < iters ? 1 : 0;
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (ctx && ctx->timing) {
+                    if (ctx->used == ctx->events.size()) {
+                        hipEvent_t x, y;
+                        HIP_TRY(hipEventCreate(&x));
+                        HIP_TRY(hipEventCreate(&y));
+                        ctx->events.emplace_back(x, y);
+                    }
+                    e0 = ctx->events[ctx->used].first;
+                    e1 = ctx->events[ctx->used].second;
+                    ctx->used++;
+                    ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh * f.nsteps;
+                    HIP_TRY(hipEventRecord(e0, st));
+                }
+                HIP_TRY(bpst::launch_fused(f, st));
+                if (e1) HIP_TRY(hipEventRecord(e1, st));
+            }
+        }
+        for (int t = 0; t < (fsteps > 0 ? 0 : iters); ++t) {
             a.t = t;
             a.colour = t & 1;
             a.source = (t == 0) ? source : bpst::kSrcOwn;
@@ -418,7 +504,7 @@ BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32
         HIP_TRY(hipStreamIsCapturing(st, &cs));
         if (cs == hipStreamCaptureStatusNone) {
             const SolveKey key = make_key(width, height, params, cost, workspace, workspace_bytes, disparity,
-                                          final_msgs_or_null);
+                                          final_msgs_or_null, ctx->fused);
             for (auto& e : ctx->cache)
                 if (std::memcmp(&e.first, &key, sizeof key) == 0) {
                     HIP_TRY(hipGraphLaunch(e.second, st));

@@ -45,12 +45,70 @@ __device__ __forceinline__ long long slot_of(int x, int y, int Wh)
     return (long long)(2 * y + ((x + y) & 1)) * Wh + (x >> 1);
 }
 
-template <int G>
+// Lane exchanges inside an aligned group of G lanes.  Groups of 2 or 4 lie inside one quad,
+// where a DPP quad permutation (a VALU operand modifier, no LDS round trip) moves the
+// value; wider groups use the LDS permute behind __shfl_*.  Quad permutation codes:
+// lane i of a quad reads lane sel_i, code = sel0 | sel1 << 2 | sel2 << 4 | sel3 << 6.
+template <int G, int O>
+__device__ __forceinline__ int lanes_xor(int v)
+{
+    if constexpr (G == 2 || (G == 4 && O == 1)) return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (G == 4 && O == 2) return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);
+    else return __shfl_xor(v, O, G);
+}
+
+// value of lane - O of the group (meaningful for lanes >= O)
+template <int G, int O>
+__device__ __forceinline__ int lanes_up(int v)
+{
+    if constexpr (G == 2) return __builtin_amdgcn_update_dpp(v, v, 0xA0, 0xF, 0xF, false);          // 0,0,2,2
+    else if constexpr (G == 4 && O == 1) return __builtin_amdgcn_update_dpp(v, v, 0x90, 0xF, 0xF, false);  // 0,0,1,2
+    else if constexpr (G == 4 && O == 2) return __builtin_amdgcn_update_dpp(v, v, 0x44, 0xF, 0xF, false);  // 0,1,0,1
+    else return __shfl_up(v, O, G);
+}
+
+// value of lane + O of the group (meaningful for lanes < G - O)
+template <int G, int O>
+__device__ __forceinline__ int lanes_down(int v)
+{
+    if constexpr (G == 2) return __builtin_amdgcn_update_dpp(v, v, 0xF5, 0xF, 0xF, false);          // 1,1,3,3
+    else if constexpr (G == 4 && O == 1) return __builtin_amdgcn_update_dpp(v, v, 0xF9, 0xF, 0xF, false);  // 1,2,3,3
+    else if constexpr (G == 4 && O == 2) return __builtin_amdgcn_update_dpp(v, v, 0xEE, 0xF, 0xF, false);  // 2,3,2,3
+    else return __shfl_down(v, O, G);
+}
+
+template <int G, int O = 1>
 __device__ __forceinline__ int group_min(int v)
 {
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) v = min(v, __shfl_xor(v, o, G));
-    return v;
+    if constexpr (O < G) return group_min<G, 2 * O>(min(v, lanes_xor<G, O>(v)));
+    else return v;
+}
+
+// Inclusive min-scan over the group, towards higher lanes: c(lane) = min over j <= lane of
+// (c_j + step * (lane - j)).
+template <int G, int O = 1>
+__device__ __forceinline__ int scan_up(int c, int step, int lane)
+{
+    if constexpr (O < G) {
+        const int t = lanes_up<G, O>(c);
+        if (lane >= O) c = min(c, t + step * O);
+        return scan_up<G, 2 * O>(c, step, lane);
+    } else {
+        return c;
+    }
+}
+
+// The same towards lower lanes.
+template <int G, int O = 1>
+__device__ __forceinline__ int scan_down(int c, int step, int lane)
+{
+    if constexpr (O < G) {
+        const int t = lanes_down<G, O>(c);
+        if (lane + O < G) c = min(c, t + step * O);
+        return scan_down<G, 2 * O>(c, step, lane);
+    } else {
+        return c;
+    }
 }
 
 // Min-sum message with truncated-linear jump cost, normalised:
@@ -72,14 +130,9 @@ __device__ __forceinline__ void transform(const int h[8], int lam, int capv, int
 #pragma unroll
     for (int j = 1; j < 8; ++j) last = min(h[j], last + lam);
     int cin = kScanId;
-    if (G > 1) {
-        int c = last;
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) {
-            int t = __shfl_up(c, o, G);
-            if (lane >= o) c = min(c, t + 8 * lam * o);
-        }
-        cin = __shfl_up(c, 1, G);
+    if constexpr (G > 1) {
+        const int c = scan_up<G>(last, 8 * lam, lane);
+        cin = lanes_up<G, 1>(c);
         if (lane == 0) cin = kScanId;
     }
     f[0] = min(h[0], cin + lam);
@@ -90,14 +143,9 @@ __device__ __forceinline__ void transform(const int h[8], int lam, int capv, int
 #pragma unroll
     for (int j = 6; j >= 0; --j) first = min(f[j], first + lam);
     int cb = kScanId;
-    if (G > 1) {
-        int c = first;
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) {
-            int t = __shfl_down(c, o, G);
-            if (lane + o < G) c = min(c, t + 8 * lam * o);
-        }
-        cb = __shfl_down(c, 1, G);
+    if constexpr (G > 1) {
+        const int c = scan_down<G>(first, 8 * lam, lane);
+        cb = lanes_down<G, 1>(c);
         if (lane == G - 1) cb = kScanId;
     }
     f[7] = min(f[7], cb + lam);

@@ -1,0 +1,375 @@
+// Several consecutive half-steps of one scale in one launch, for scales small enough that a
+// launch per half-step is bound by launch latency rather than by memory.
+//
+// The scale is cut into interior tiles.  A workgroup loads its tile plus a halo of h
+// pixels on every side (clipped to the image) into LDS: the cost and the four incoming
+// message volumes of every region pixel (and the freeze state).  It then runs h
+// half-steps on the region with a workgroup barrier between them, and writes back the
+// interior pixels only.  Half-step t reads, for every updated pixel, values that were
+// final after half-step t-1 on the pixel and its four neighbours, so the set of region
+// pixels whose values are exact shrinks by at most one pixel per half-step from the
+// region's cut edges (image borders are exact: nothing lies beyond them).  After h
+// half-steps the interior is exact, and equal bit for bit to h launches of k_halfstep.
+//
+// Per-pixel arithmetic is the same as the per-launch kernel (transform, freeze rule);
+// only the storage differs: LDS holds the region row-major, [pixel][Dp] per volume.
+#include <vector>
+
+#include "bp_device.h"
+
+namespace bpst {
+namespace {
+
+constexpr int kFusedThreads = 1024;
+
+struct Region {
+    int rx0, ry0, RW, RH;  // region origin and size (clipped to the image)
+    int ix0, iy0, IW, IH;  // interior origin and size
+};
+
+__device__ __forceinline__ Region region_of(const FusedArgs& a)
+{
+    Region g;
+    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    g.ix0 = tx * a.TW;
+    g.iy0 = ty * a.TH;
+    const int ix1 = min(g.ix0 + a.TW, a.lv.W), iy1 = min(g.iy0 + a.TH, a.lv.H);
+    g.IW = ix1 - g.ix0;
+    g.IH = iy1 - g.iy0;
+    g.rx0 = max(g.ix0 - a.halo, 0);
+    g.ry0 = max(g.iy0 - a.halo, 0);
+    g.RW = min(ix1 + a.halo, a.lv.W) - g.rx0;
+    g.RH = min(iy1 + a.halo, a.lv.H) - g.ry0;
+    return g;
+}
+
+template <int G, int MODE>
+__global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
+{
+    constexpr int Dp = 8 * G;
+    extern __shared__ int4 lds4[];
+    const Region g = region_of(a);
+    const int W = a.lv.W, H = a.lv.H, Wh = a.lv.Wh;
+    const long long cap = a.rmax;  // region pixels the LDS was sized for
+    int16_t* lc = reinterpret_cast<int16_t*>(lds4);
+    int16_t* lm = lc + cap * Dp;   // volume k at lm + k * cap * Dp
+    uint8_t* lsa = reinterpret_cast<uint8_t*>(lm + 4 * cap * Dp);
+    uint8_t* lsb = lsa + cap;
+    const int R = g.RW * g.RH;
+
+    // 1. load the region: cost, incoming messages (own, parent's or zero), freeze state
+    for (int e = threadIdx.x; e < R * G; e += blockDim.x) {
+        const int r = e / G, lane = e - r * G;
+        const int ry = r / g.RW, rx = r - ry * g.RW;
+        const int x = g.rx0 + rx, y = g.ry0 + ry;
+        const long long slot = slot_of(x, y, Wh);
+        const int d0 = lane * 8;
+        *reinterpret_cast<int4*>(lc + (long long)r * Dp + d0) =
+            *reinterpret_cast<const int4*>(a.cost + slot * Dp + d0);
+        const bool has[4] = {x > 0, x < W - 1, y > 0, y < H - 1};
+        int4 m[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m[k] = make_int4(0, 0, 0, 0);
+        if (a.source == kSrcOwn) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (has[k]) m[k] = *reinterpret_cast<const int4*>(a.msgs + k * a.vol + slot * Dp + d0);
+        } else if (a.source == kSrcParent) {
+            const int px = x >> 1, py = y >> 1;
+            const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
+            const long long ps = slot_of(px, py, a.plv.Wh);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (has[k] && phas[k]) m[k] = *reinterpret_cast<const int4*>(a.pmsgs + k * a.pvol + ps * Dp + d0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) *reinterpret_cast<int4*>(lm + k * cap * Dp + (long long)r * Dp + d0) = m[k];
+        if (MODE == 1 && lane == 0) {
+            lsa[r] = a.t0 >= 2 ? a.state_a[slot] : (uint8_t)1;
+            lsb[r] = a.t0 >= 2 ? a.state_b[slot] : (uint8_t)0;
+        }
+    }
+    __syncthreads();
+
+    // 2. the half-steps, one colour each.  Thread e handles lane e % G of pixel e / G of the
+    //    colour's row-major list (RWc a row), and every blockDim.x / G pixels after it; the
+    //    (row, index) pair advances by a fixed step instead of being divided out each time.
+    const int RWc = (g.RW + 1) >> 1;  // pixels of one colour in a region row (at most)
+    const int npix = g.RH * RWc;
+    const int lane = threadIdx.x & (G - 1);
+    const int d0 = lane * 8;
+    const int pstep = blockDim.x / G, step_ry = pstep / RWc, step_i = pstep - step_ry * RWc;
+    const int p_first = threadIdx.x / G;
+    const int ry_first = p_first / RWc, i_first = p_first - ry_first * RWc;
+    for (int s = 0; s < a.nsteps; ++s) {
+        const int t = a.t0 + s, colour = t & 1;
+        const bool check = MODE == 1 && t >= 2;
+        int ry = ry_first, i = i_first;
+        for (int p = p_first; p < npix; p += pstep) {
+            const int y = g.ry0 + ry;
+            const int rx = 2 * i + ((colour ^ (g.rx0 + y)) & 1);
+            const int x = g.rx0 + rx;
+            const bool valid = rx < g.RW;
+            const int r = ry * g.RW + rx;
+            const bool has[4] = {x > 0, x < W - 1, y > 0, y < H - 1};
+            const bool inreg[4] = {rx > 0, rx < g.RW - 1, ry > 0, ry < g.RH - 1};
+            const int nbr[4] = {r - 1, r + 1, r - g.RW, r + g.RW};
+            // every LDS read is issued unconditionally from a valid address and masked after,
+            // so the loads of a pixel overlap instead of waiting on each other's branches
+            const long long rr = valid ? r : 0;
+            const int4 c4 = *reinterpret_cast<const int4*>(lc + rr * Dp + d0);
+            int4 mp[4], op[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool tk = valid && has[k] && inreg[k];
+                mp[k] = *reinterpret_cast<const int4*>(lm + k * cap * Dp + rr * Dp + d0);
+                op[k] = *reinterpret_cast<const int4*>(lm + (k ^ 1) * cap * Dp + (tk ? (long long)nbr[k] : rr) * Dp + d0);
+                if (!has[k]) mp[k] = make_int4(0, 0, 0, 0);
+                if (!(check && tk)) op[k] = make_int4(0, 0, 0, 0);
+            }
+            const bool act = valid && (!check || lsa[rr] != 0);
+            int Hs[8];
+            unpack8(c4, Hs);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                Hs[j] = (d0 + j < a.D) ? Hs[j] + msg_at(mp[0], j) + msg_at(mp[1], j) + msg_at(mp[2], j) +
+                                             msg_at(mp[3], j)
+                                       : kBig;
+            bool all_eq = true;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int h[8], o[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) h[j] = Hs[j] - msg_at(mp[k], j);
+                transform<G>(h, a.lambda, a.capv, lane, o);
+                bool store = act && has[k] && inreg[k];
+                if (check) {
+                    // a receiver outside the region is not held: its compare is skipped, which
+                    // only affects pixels on the region's cut edge (never exact past step 0)
+                    int eq = 1;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) if (d0 + j < a.D && msg_at(op[k], j) != o[j]) eq = 0;
+                    eq = group_min<G>(eq);
+                    if (store && !eq) all_eq = false;
+                    if (eq) store = false;
+                }
+                if (store)
+                    *reinterpret_cast<int4*>(lm + (k ^ 1) * cap * Dp + (long long)nbr[k] * Dp + d0) = pack8(o);
+            }
+            if (MODE == 1 && act && lane == 0) {
+                if (t < 2) {
+                    lsa[r] = 1;
+                    lsb[r] = 0;
+                } else {
+                    const int st = all_eq ? (int)lsb[r] + 1 : 0;
+                    lsb[r] = (uint8_t)st;
+                    if (2 * st >= a.K) lsa[r] = 0;
+                }
+            }
+            i += step_i;
+            ry += step_ry;
+            if (i >= RWc) {
+                i -= RWc;
+                ++ry;
+            }
+        }
+        __syncthreads();
+    }
+
+    // 3. write back the interior: incoming messages on existing sides, and the state when
+    //    later half-steps of this scale follow
+    for (int e = threadIdx.x; e < g.IW * g.IH * G; e += blockDim.x) {
+        const int q = e / G, lane = e - q * G;
+        const int iy = q / g.IW, ix = q - iy * g.IW;
+        const int x = g.ix0 + ix, y = g.iy0 + iy;
+        const int r = (y - g.ry0) * g.RW + (x - g.rx0);
+        const long long slot = slot_of(x, y, Wh);
+        const int d0 = lane * 8;
+        const bool has[4] = {x > 0, x < W - 1, y > 0, y < H - 1};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (has[k])
+                *reinterpret_cast<int4*>(a.msgs + k * a.vol + slot * Dp + d0) =
+                    *reinterpret_cast<const int4*>(lm + k * cap * Dp + (long long)r * Dp + d0);
+        if (MODE == 1 && lane == 0 && a.keep_state) {
+            a.state_a[slot] = lsa[r];
+            a.state_b[slot] = lsb[r];
+        }
+    }
+}
+
+}  // namespace
+
+size_t fused_lds_bytes(int G, long long rmax)
+{
+    const long long Dp = 8LL * G;
+    return (size_t)(5 * rmax * Dp * 2 + 2 * rmax + 15) / 16 * 16;
+}
+
+int fused_threads(int G, long long rmax)
+{
+    const long long lanes = (rmax + 1) / 2 * G;  // one colour of the region, G lanes a pixel
+    long long t = (lanes + 63) / 64 * 64;
+    return (int)(t < 64 ? 64 : (t > kFusedThreads ? kFusedThreads : t));
+}
+
+// Estimated device time (us) of `iters` half-steps on scale lv: one launch per half-step,
+// or fused launches of `steps` half-steps on TW x TH interior tiles.  The constants are
+// measured on MI355X: a small launch costs about 4.5 us and a streaming one moves about
+// 5 TB/s; a fused launch costs about 4 us plus its region loads and interior stores at
+// 5 TB/s, and each of its half-steps about 0.9 us per 256 lanes a compute unit updates.
+double per_launch_us(const Level& lv, int G, int iters)
+{
+    const double bytes = (double)lv.slots() / 2 * 8 * G * 2 * 9;  // one colour: cost, 4 in, 4 out
+    const double t = bytes / 5.0e6;
+    return iters * (t > 4.5 ? t : 4.5);
+}
+
+double fused_us(const Level& lv, int G, int iters, int steps, int TW, int TH)
+{
+    const int h = steps;
+    const double rw = (double)(TW + 2 * h < lv.W ? TW + 2 * h : lv.W);
+    const double rh = (double)(TH + 2 * h < lv.H ? TH + 2 * h : lv.H);
+    const long long tiles = (long long)((lv.W + TW - 1) / TW) * ((lv.H + TH - 1) / TH);
+    const long long lds = (long long)fused_lds_bytes(G, (long long)(TW + 2 * h) * (TH + 2 * h));
+    long long per_cu = kFusedLdsBytes / (lds > 0 ? lds : 1);
+    const long long threads = fused_threads(G, (long long)(TW + 2 * h) * (TH + 2 * h));
+    const long long by_threads = 2048 / threads;
+    if (per_cu > by_threads) per_cu = by_threads;
+    if (per_cu < 1) per_cu = 1;
+    const long long resident = 256 * per_cu;
+    const double rounds = (double)((tiles + resident - 1) / resident);
+    const long long in_round = tiles < resident ? tiles : resident;
+    const double lanes_per_cu = (double)((in_round + 255) / 256) * (rw * rh / 2.0) * G;  // on a busy CU
+    const double pass = 0.9 * (lanes_per_cu > 256.0 ? lanes_per_cu / 256.0 : 1.0);
+    const double dp2 = 8.0 * G * 2;
+    const double traffic = ((double)tiles * rw * rh * dp2 * 5 + (double)lv.W * lv.H * dp2 * 4) / 5.0e6;
+    const int launches = (iters + steps - 1) / steps;
+    return launches * (rounds * (4.0 + steps * pass) + traffic);
+}
+
+namespace {
+bool fused_search(const Level& lv, int G, int iters, int* steps, int* TW, int* TH, long long* rmax);
+}
+
+bool fused_geometry(const Level& lv, int G, int iters, int* steps, int* TW, int* TH, long long* rmax)
+{
+    // the search is memoised per (scale size, lanes, half-steps): solves repeat shapes
+    struct Entry {
+        int W, H, G, iters, ok, steps, TW, TH;
+        long long rmax;
+    };
+    thread_local std::vector<Entry> memo;
+    for (const Entry& e : memo)
+        if (e.W == lv.W && e.H == lv.H && e.G == G && e.iters == iters) {
+            *steps = e.steps;
+            *TW = e.TW;
+            *TH = e.TH;
+            *rmax = e.rmax;
+            return e.ok != 0;
+        }
+    Entry e{lv.W, lv.H, G, iters, 0, 0, 0, 0, 0};
+    e.ok = fused_search(lv, G, iters, &e.steps, &e.TW, &e.TH, &e.rmax) ? 1 : 0;
+    if (memo.size() > 256) memo.clear();
+    memo.push_back(e);
+    *steps = e.steps;
+    *TW = e.TW;
+    *TH = e.TH;
+    *rmax = e.rmax;
+    return e.ok != 0;
+}
+
+namespace {
+bool fused_search(const Level& lv, int G, int iters, int* steps, int* TW, int* TH, long long* rmax)
+{
+    const long long per = 5LL * 8 * G * 2 + 2;                       // LDS bytes per region pixel
+    const long long cap = (long long)(kFusedLdsBytes - 16) / per;   // room for the 16-byte rounding
+    double best = per_launch_us(lv, G, iters);
+    bool found = false;
+    for (int h = 1; h <= iters && h <= 12; ++h) {
+        const int chunks = (iters + h - 1) / h;
+        const int hs = (iters + chunks - 1) / chunks;  // equal chunks: the last is not shorter by much
+        if (hs != h) continue;
+        for (int tw = 2; tw <= lv.W + 1 && tw <= 256; tw += (tw < 16 ? 1 : 4)) {
+            for (int th = 2; th <= lv.H + 1 && th <= 256; th += (th < 16 ? 1 : 4)) {
+                const int ew = tw < lv.W ? tw : lv.W, eh = th < lv.H ? th : lv.H;
+                if ((long long)(ew + 2 * h) * (eh + 2 * h) > cap) break;
+                const double t = fused_us(lv, G, iters, h, ew, eh);
+                if (t < best) {
+                    best = t;
+                    found = true;
+                    *steps = h;
+                    *TW = ew;
+                    *TH = eh;
+                    *rmax = (long long)(ew + 2 * h) * (eh + 2 * h);
+                }
+                if (th >= lv.H) break;
+            }
+            if (tw >= lv.W) break;
+        }
+    }
+    return found;
+}
+}  // namespace
+
+// Any tile: the widest interior whose region fits (used when fused launches are forced).
+bool fused_geometry_max(const Level& lv, int G, int steps, int* TW, int* TH, long long* rmax)
+{
+    const long long per = 5LL * 8 * G * 2 + 2;
+    const long long cap = (long long)(kFusedLdsBytes - 16) / per;
+    const int h = steps;
+    long long best_tiles = -1;
+    for (int tw = 1; tw <= lv.W; ++tw) {
+        if ((long long)(tw + 2 * h) * (1 + 2 * h) > cap) break;
+        int th = (int)(cap / (tw + 2 * h)) - 2 * h;
+        if (th > lv.H) th = lv.H;
+        if (th < 1) break;
+        const long long tiles = (long long)((lv.W + tw - 1) / tw) * ((lv.H + th - 1) / th);
+        if (best_tiles < 0 || tiles < best_tiles) {
+            best_tiles = tiles;
+            *TW = tw;
+            *TH = th;
+            *rmax = (long long)(tw + 2 * h) * (th + 2 * h);
+        }
+    }
+    return best_tiles > 0;
+}
+
+template <int G, int MODE>
+void set_lds_attr()
+{
+    (void)hipFuncSetAttribute((const void*)k_fused<G, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kFusedLdsBytes);
+}
+
+void fused_prepare()
+{
+    static bool done = false;
+    if (done) return;
+    set_lds_attr<1, 0>(); set_lds_attr<1, 1>(); set_lds_attr<2, 0>(); set_lds_attr<2, 1>();
+    set_lds_attr<4, 0>(); set_lds_attr<4, 1>(); set_lds_attr<8, 0>(); set_lds_attr<8, 1>();
+    (void)hipGetLastError();
+    done = true;
+}
+
+hipError_t launch_fused(const FusedArgs& a, hipStream_t st)
+{
+    const int tiles = a.tiles_x * ((a.lv.H + a.TH - 1) / a.TH);
+    const size_t lds = fused_lds_bytes(a.G, a.rmax);
+    if (lds > (size_t)kFusedLdsBytes || a.halo != a.nsteps || a.nsteps < 1) return hipErrorInvalidValue;
+    fused_prepare();
+    const dim3 grid((unsigned)tiles), block((unsigned)fused_threads(a.G, a.rmax));
+#define BPST_FUSED_G(GG)                                                                        \
+    case GG:                                                                                    \
+        if (a.mode == 1) hipLaunchKernelGGL((k_fused<GG, 1>), grid, block, lds, st, a);         \
+        else hipLaunchKernelGGL((k_fused<GG, 0>), grid, block, lds, st, a);                     \
+        break;
+    switch (a.G) {
+        BPST_FUSED_G(1) BPST_FUSED_G(2) BPST_FUSED_G(4) BPST_FUSED_G(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef BPST_FUSED_G
+    return hipGetLastError();
+}
+
+}  // namespace bpst

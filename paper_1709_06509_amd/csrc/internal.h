@@ -108,6 +108,35 @@ struct BatchArgs {
     long long timeout_ticks;  // of the wall clock
 };
 
+// Several half-steps of one scale in one launch (fused_kernels.hip).
+struct FusedArgs {
+    const int16_t* cost;     // this scale's cost, colour-split, Dp labels
+    int16_t* msgs;           // 4 volumes
+    long long vol;
+    const int16_t* pmsgs;    // parent scale's volumes (source kSrcParent)
+    long long pvol;
+    Level plv;
+    uint8_t* state_a;        // freeze rule: active, stable count
+    uint8_t* state_b;
+    Level lv;
+    int D, G, lambda, capv, K, mode;
+    int source;              // incoming messages at t0: kSrcOwn, kSrcParent or kSrcZero
+    int t0, nsteps;          // half-steps t0 .. t0 + nsteps - 1
+    int TW, TH, halo, tiles_x;
+    long long rmax;          // region pixels the LDS holds: (TW + 2 halo) (TH + 2 halo)
+    int keep_state;          // write the freeze state back (later half-steps of the scale follow)
+};
+constexpr int kFusedLdsBytes = 160 * 1024;
+// Half-steps per fused launch and interior tile for `iters` half-steps on scale lv, chosen
+// by a cost model; false if one launch per half-step is estimated to be faster.
+bool fused_geometry(const Level& lv, int G, int iters, int* steps, int* TW, int* TH, long long* rmax);
+// The widest interior tile whose region (halo = steps) fits the LDS.
+bool fused_geometry_max(const Level& lv, int G, int steps, int* TW, int* TH, long long* rmax);
+size_t fused_lds_bytes(int G, long long rmax);
+hipError_t launch_fused(const FusedArgs& a, hipStream_t st);
+// Lets the fused kernels use the whole LDS; called once outside graph capture (errors ignored).
+void fused_prepare();
+
 constexpr int kXcds = 8;
 constexpr int kThreadsPerTile = 256;  // workgroup size of every pixel kernel: a tile is 256 / G pixels
 
