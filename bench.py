@@ -22,7 +22,8 @@ METRIC = "stereo pairs/s and Gmsg-updates/s at equal energy vs plain BP; % HBM p
 HBM_PEAK_GBS = 8000.0
 # sources that define the half-step kernel; measured traffic counts only while they are unchanged
 HALFSTEP_SOURCES = ["paper_1709_06509_amd/csrc/bp_device.h", "paper_1709_06509_amd/csrc/bp_kernels.hip",
-                    "paper_1709_06509_amd/csrc/internal.h"]
+                    "paper_1709_06509_amd/csrc/fused_kernels.hip", "paper_1709_06509_amd/csrc/internal.h",
+                    "paper_1709_06509_amd/csrc/api.cpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "halfstep_traffic.json")
 
 
@@ -300,7 +301,8 @@ def main():
         "msg_updates_per_pair_plain": st_plain["msg_updates"],
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_halfstep (message update, all scales)",
+            "kernel": "message-update launches of all scales: k_halfstep (one half-step) and k_fused (several "
+                      "half-steps of a small scale from LDS)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -311,7 +313,7 @@ def main():
             "launches_per_step": n_launch,
         },
         "halfstep_ms_per_step_eager": timing["halfstep_ms"] / max(1, n_timed),
-        "timing_note": "value: graph replays of the whole step; roofline: the same step launched eagerly with HIP events around each half-step",
+        "timing_note": "value: graph replays of the whole step; roofline: the same step launched eagerly with HIP events around each message-update launch",
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
