@@ -154,7 +154,20 @@ def run_batched(args):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         status = batch.status(stream)
-    best = tune["candidates"][tune["best"]]
+        best = tune["candidates"][tune["best"]]
+        timing = None
+        if best["schedule"] == 1:
+            # the dominant kernel's own time: the same batch launched eagerly, a HIP event pair
+            # on the launch stream around every half-step phase
+            ctx.set_graphs(False)
+            ctx.set_timing(True)
+            n_timed = 3
+            for _ in range(n_timed):
+                batch.solve(ctx, stream)
+            torch.cuda.synchronize()
+            timing = ctx.take_timing()
+            timing["solves"] = n_timed
+            ctx.set_timing(False)
     msgs = byts = 0
     for p, D in zip(pairs, Ds):
         H, W = p["left"].shape
@@ -162,7 +175,16 @@ def run_batched(args):
         msgs += m
         byts += 18 * D * pix
     per_batch = elapsed / steps
-    achieved = byts / (best["ms"] / 1e3) / 1e9
+    if timing and timing["halfstep_launches"]:
+        launches = timing["halfstep_launches"] // timing["solves"]
+        avg_launch_s = timing["halfstep_ms"] / 1e3 / timing["halfstep_launches"]
+        per_launch = byts / launches
+        kernel = "k_batch_phase, half-step phases (one launch per phase, every pair's tiles)"
+    else:
+        launches, avg_launch_s, per_launch = 1, best["ms"] / 1e3, byts
+        kernel = (f"k_batch_solve (one persistent launch, {best['blocks_per_cu']} workgroups/CU; "
+                  "half-step bytes over the whole solve part)")
+    achieved = per_launch / avg_launch_s / 1e9
     return {
         "metric": METRIC, "value": n / per_batch, "unit": "pairs/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": per_batch * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -172,12 +194,10 @@ def run_batched(args):
                                f"seeds {w['seed0']}..{w['seed0'] + n - 1}", "pairs_per_step": n},
         "gmsg_updates_per_s": msgs / per_batch / 1e9,
         "batch_status": status,
-        "roofline": {"bound": "hbm",
-                     "kernel": ("k_batch_phase (one launch per phase" if best["schedule"] == 1 else
-                                f"k_batch_solve (one persistent launch, {best['blocks_per_cu']} workgroups/CU") +
-                               "; half-step bytes only, time of the whole solve part)",
+        "roofline": {"bound": "hbm", "kernel": kernel,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_us": best["ms"] * 1e3, "algorithmic_bytes_per_launch": byts},
+                     "traffic": None, "avg_launch_us": avg_launch_s * 1e6, "algorithmic_bytes_per_launch": per_launch,
+                     "launches_per_step": launches},
         "autotune": tune,
     }
 

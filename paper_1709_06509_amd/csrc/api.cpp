@@ -357,7 +357,13 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         long long frmax = 0;
         const int fmode = ctx ? ctx->fused : 2;
         if (fmode != 0 && !count && mode != 2 && iters >= 1 && pl.G <= 8) {
-            if (fmode == 2) {
+            // test and tuning hook: a fixed number of half-steps per fused launch
+            const char* fs = getenv("BPSTEREO_FUSED_STEPS");
+            const int forced_steps = fs ? atoi(fs) : 0;
+            if (forced_steps > 0) {
+                fsteps = forced_steps < iters ? forced_steps : iters;
+                if (!bpst::fused_geometry_max(pl.lv[l], pl.G, fsteps, &ftw, &fth, &frmax)) fsteps = 0;
+            } else if (fmode == 2) {
                 if (!bpst::fused_geometry(pl.lv[l], pl.G, iters, &fsteps, &ftw, &fth, &frmax)) fsteps = 0;
             } else {
                 const int chunks = (iters + kFusedMaxSteps - 1) / kFusedMaxSteps;
@@ -820,16 +826,39 @@ bpst::BatchArgs batch_args(const BatchPlan& b, const bp_batch_params* p, char* w
 
 // The solve part of a batch: schedule 0 is one persistent launch of bpc workgroups per
 // compute unit; schedule 1 is one launch per phase.
-int32_t enqueue_batch_solve(const BatchPlan& b, const bp_batch_params* p, char* ws, int sched, int bpc, int order,
-                            int cus, long long ticks, hipStream_t st)
+// Event pair for one timed launch on ctx (timing mode).
+int32_t timing_events(bp_context* ctx, hipEvent_t* e0, hipEvent_t* e1)
+{
+    if (ctx->used == ctx->events.size()) {
+        hipEvent_t x, y;
+        HIP_TRY(hipEventCreate(&x));
+        HIP_TRY(hipEventCreate(&y));
+        ctx->events.emplace_back(x, y);
+    }
+    *e0 = ctx->events[ctx->used].first;
+    *e1 = ctx->events[ctx->used].second;
+    ctx->used++;
+    return BP_OK;
+}
+
+int32_t enqueue_batch_solve(bp_context* ctx, const BatchPlan& b, const bp_batch_params* p, char* ws, int sched, int bpc,
+                            int order, int cus, long long ticks, hipStream_t st)
 {
     const bpst::BatchArgs a = batch_args(b, p, ws, order, ticks);
     HIP_TRY(bpst::launch_batch_reset(a.barrier, a.error, st));
     if (sched == 1) {
         for (int ph = 0; ph < b.nphases; ++ph) {
             const bpst::PhaseDesc& d = b.phases[ph];
+            // timing mode: an event pair around every half-step phase
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (ctx && ctx->timing && d.type == bpst::kPhHalfstep) {
+                const int32_t rc = timing_events(ctx, &e0, &e1);
+                if (rc != BP_OK) return rc;
+                HIP_TRY(hipEventRecord(e0, st));
+            }
             HIP_TRY(bpst::launch_batch_phase(a, ph, d.type, d.source, b.tiles[(size_t)ph * (b.n + 1) + b.n],
                                              b.lds, st));
+            if (e1) HIP_TRY(hipEventRecord(e1, st));
         }
         return BP_OK;
     }
@@ -839,13 +868,13 @@ int32_t enqueue_batch_solve(const BatchPlan& b, const bp_batch_params* p, char* 
     return BP_OK;
 }
 
-int32_t enqueue_batch(const BatchPlan& b, const bp_batch_params* p, char* ws, int sched, int bpc, int order, int cus,
-                      long long ticks, hipStream_t st)
+int32_t enqueue_batch(bp_context* ctx, const BatchPlan& b, const bp_batch_params* p, char* ws, int sched, int bpc,
+                      int order, int cus, long long ticks, hipStream_t st)
 {
     HIP_TRY(bpst::launch_ncc_batched(reinterpret_cast<const bpst::NccPair*>(ws + b.off_ncc),
                                      reinterpret_cast<const int*>(ws + b.off_ncc_tiles), b.n, b.ncc_total, b.max_d,
                                      p->window, p->cost_scale, p->cost_trunc, st));
-    return enqueue_batch_solve(b, p, ws, sched, bpc, order, cus, ticks, st);
+    return enqueue_batch_solve(ctx, b, p, ws, sched, bpc, order, cus, ticks, st);
 }
 
 }  // namespace
@@ -891,7 +920,7 @@ BP_API int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int3
     fill_tables(b, pairs, ws, &img);
     rc = upload_tables(ctx, img, ws, st);
     if (rc != BP_OK) return rc;
-    if (ctx->graphs && st != nullptr) {
+    if (ctx->graphs && !ctx->timing && st != nullptr) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         HIP_TRY(hipStreamIsCapturing(st, &cs));
         if (cs == hipStreamCaptureStatusNone) {
@@ -910,7 +939,7 @@ BP_API int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int3
                     return ok();
                 }
             if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-                const int32_t r2 = enqueue_batch(b, params, ws, sched, bpc, order, cus, ticks, st);
+                const int32_t r2 = enqueue_batch(nullptr, b, params, ws, sched, bpc, order, cus, ticks, st);
                 hipGraph_t g = nullptr;
                 const hipError_t ee = hipStreamEndCapture(st, &g);
                 hipGraphExec_t ex = nullptr;
@@ -932,7 +961,7 @@ BP_API int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int3
             ctx->graph_fallbacks++;
         }
     }
-    rc = enqueue_batch(b, params, ws, sched, bpc, order, cus, ticks, st);
+    rc = enqueue_batch(ctx, b, params, ws, sched, bpc, order, cus, ticks, st);
     if (rc != BP_OK) return rc;
     return ok();
 }
@@ -987,7 +1016,7 @@ BP_API int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, i
         float best = 1e30f;
         for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches and code
             HIP_TRY(hipEventRecord(e0, st));
-            rc = enqueue_batch_solve(b, params, ws, c.sched, c.bpc, c.order, cus, ticks, st);
+            rc = enqueue_batch_solve(nullptr, b, params, ws, c.sched, c.bpc, c.order, cus, ticks, st);
             if (rc != BP_OK) return rc;
             HIP_TRY(hipEventRecord(e1, st));
             HIP_TRY(hipEventSynchronize(e1));
@@ -1018,7 +1047,8 @@ BP_API int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, i
         }
     if (!found) ctx->tuned.push_back({sig, out->blocks_per_cu[bi], out->order[bi], out->schedule[bi]});
     // leave the workspace holding a complete solve of the batch
-    rc = enqueue_batch(b, params, ws, out->schedule[bi], out->blocks_per_cu[bi], out->order[bi], cus, ticks, st);
+    rc = enqueue_batch(nullptr, b, params, ws, out->schedule[bi], out->blocks_per_cu[bi], out->order[bi], cus, ticks,
+                       st);
     if (rc != BP_OK) return rc;
     HIP_TRY(hipStreamSynchronize(st));
     return ok();
