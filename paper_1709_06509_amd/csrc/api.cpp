@@ -693,7 +693,7 @@ int32_t plan_batch(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* 
     long long acc = 0;
     for (int i = 0; i < n; ++i) {
         b.ncc_tiles[i] = (int)acc;
-        acc += bpst::ncc_tiles(pairs[i].width, pairs[i].height);
+        acc += bpst::ncc_tiles(pairs[i].width, pairs[i].height, pairs[i].num_disp);
     }
     b.ncc_tiles[n] = (int)acc;
     b.ncc_total = (int)acc;

@@ -164,7 +164,7 @@ hipError_t launch_warm_input(const uint8_t* L, const uint8_t* R, int W, int H, i
 hipError_t launch_warm_messages(const float* y, int Ws, int Hs, int D, int ystride, int lam_t, int16_t* out,
                                 hipStream_t st);
 
-int ncc_tiles(int W, int H);
+int ncc_tiles(int W, int H, int D);
 hipError_t launch_ncc_batched(const NccPair* pairs, const int* tile_start, int n, int total_tiles, int max_d, int win,
                               int scale, int trunc, hipStream_t st);
 hipError_t launch_batch_reset(unsigned* barrier, int* error, hipStream_t st);

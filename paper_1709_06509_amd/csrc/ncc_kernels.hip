@@ -1,6 +1,6 @@
 // Correlation volume: zero-mean NCC of window x window patches, quantised to an int16 cost.
 //
-// One workgroup produces one image row y and a tile of kTileX columns for every
+// One workgroup produces one image row y and a tile of TX columns for every
 // disparity.  The window rows y-r..y+r of both views are staged in LDS as packed byte
 // columns (4 dwords = up to 16 rows), so every window sum is a handful of 4-way byte
 // dot products (v_dot4_u32_u8), all in exact integer arithmetic:
@@ -17,7 +17,8 @@
 namespace bpst {
 namespace {
 
-constexpr int kTileX = 32;
+// Columns per workgroup: about 2048 outputs a workgroup, at least 32 columns.
+__host__ __device__ inline int ncc_tile_x(int D) { return D <= 16 ? 128 : (D <= 32 ? 64 : 32); }
 constexpr int kThreads = 256;
 constexpr int kMaxR = 6;  // window <= 13 rows: fits 4 packed dwords per column
 
@@ -35,7 +36,7 @@ __device__ bool le_times_sqrt(long long B, long long A, unsigned long long P)
     return B >= 0 ? false : (b2 >= a2p);
 }
 
-// One tile: image row y, columns x0 .. x0 + kTileX - 1 (clipped), every disparity.  WIN is
+// One tile: image row y, columns x0 .. x0 + TX - 1 (clipped), every disparity.  WIN is
 // the window size (odd, <= 13), known at compile time so every window loop unrolls.
 // Element loops walk (column, disparity) pairs with an incremental index, not a division.
 template <int WIN>
@@ -44,8 +45,9 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
                                          float* __restrict__ ncc_out, int y, int x0, unsigned* smem)
 {
     constexpr int r = WIN >> 1;
-    const int nI = kTileX + 2 * r;          // left columns  x0-r .. x0+kTileX-1+r
-    const int nJ = kTileX + 2 * r + D - 1;  // right columns x0-r-(D-1) .. x0+kTileX-1+r
+    const int TX = ncc_tile_x(D);
+    const int nI = TX + 2 * r;          // left columns  x0-r .. x0+TX-1+r
+    const int nJ = TX + 2 * r + D - 1;  // right columns x0-r-(D-1) .. x0+TX-1+r
     const int uI0 = x0 - r, uJ0 = x0 - r - (D - 1);
     uint4* colI = reinterpret_cast<uint4*>(smem);
     uint4* colJ = colI + nI;
@@ -53,11 +55,11 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
     int* cII = cI + nI;
     int* cJ = cII + nI;
     int* cJJ = cJ + nJ;
-    int* SI = cJJ + nJ;                            // window sums, kTileX of them
-    int* SII = SI + kTileX;
-    int* SJ = SII + kTileX;                        // kTileX + D - 1 of them, for u = x0-(D-1) ..
-    int* SJJ = SJ + kTileX + D - 1;
-    int* V = SJJ + kTileX + D - 1;                 // [nI][D]
+    int* SI = cJJ + nJ;                            // window sums, TX of them
+    int* SII = SI + TX;
+    int* SJ = SII + TX;                            // TX + D - 1 of them, for u = x0-(D-1) ..
+    int* SJJ = SJ + TX + D - 1;
+    int* V = SJJ + TX + D - 1;                     // [nI][D]
 
     // 1. packed byte columns of the window rows (clamped), zero beyond the window
     for (int c = threadIdx.x; c < nI + nJ; c += kThreads) {
@@ -84,13 +86,13 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
     __syncthreads();
 
     // 2. horizontal window sums of the left columns and the right columns
-    for (int i = threadIdx.x; i < kTileX; i += kThreads) {
+    for (int i = threadIdx.x; i < TX; i += kThreads) {
         int s = 0, ss = 0;
 #pragma unroll
         for (int k = 0; k < WIN; ++k) { s += cI[i + k]; ss += cII[i + k]; }
         SI[i] = s; SII[i] = ss;
     }
-    for (int i = threadIdx.x; i < kTileX + D - 1; i += kThreads) {
+    for (int i = threadIdx.x; i < TX + D - 1; i += kThreads) {
         int s = 0, ss = 0;
 #pragma unroll
         for (int k = 0; k < WIN; ++k) { s += cJ[i + k]; ss += cJJ[i + k]; }
@@ -115,28 +117,37 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
     }
     __syncthreads();
 
-    // 4. finish every (x, d) of the tile; consecutive threads write consecutive d
+    // 4. finish every (x, d) of the tile.  Thread t takes disparity d = t mod D and a run of
+    //    XR consecutive columns, sliding the horizontal window sum along the run (two LDS
+    //    reads per column instead of WIN); consecutive threads write consecutive d.
     constexpr int n = WIN * WIN;
-    const int tileW = min(kTileX, W - x0);
-    int i = threadIdx.x / D, d = threadIdx.x - i * D;
-    for (int e = threadIdx.x; e < tileW * D; e += kThreads) {
-        const int x = x0 + i;
-        const long long o = ((long long)y * W + x) * D + d;
-        if (x - d < 0) {
-            cost[o] = (int16_t)trunc;
-            if (ncc_out) ncc_out[o] = -2.0f;
-        } else {
-            int sij = 0;
-            const int* vp = V + i * D + d;
+    const int tileW = min(TX, W - x0);
+    const int tpd = D >= kThreads ? 1 : kThreads / D;  // runs per disparity
+    const int XR = (TX + tpd - 1) / tpd;
+    const int d = threadIdx.x % D, run = threadIdx.x / D;
+    if (run < tpd) {
+        const int i0 = run * XR, i1 = min(i0 + XR, tileW);
+        int sij = 0;
+        if (i0 < i1) {
 #pragma unroll
-            for (int k = 0; k < WIN; ++k) sij += vp[k * D];
+            for (int k = 0; k < WIN; ++k) sij += V[(i0 + k) * D + d];
+        }
+        for (int i = i0; i < i1; ++i) {
+            if (i > i0) sij += V[(i + WIN - 1) * D + d] - V[(i - 1) * D + d];
+            const int x = x0 + i;
+            const long long o = ((long long)y * W + x) * D + d;
+            if (x - d < 0) {
+                cost[o] = (int16_t)trunc;
+                if (ncc_out) ncc_out[o] = -2.0f;
+                continue;
+            }
             // window <= 13: every product and difference below fits in int32
             const int si = SI[i], sii = SII[i];
             const int sj = SJ[i - d + (D - 1)], sjj = SJJ[i - d + (D - 1)];
             const int num = n * sij - si * sj;
             const int vi = n * sii - si * si;
             const int vj = n * sjj - sj * sj;
-            long long k;
+            int k;  // |k| <= 2 * scale + 1 < 2^31
             float nv;
             if (vi == 0 || vj == 0) {
                 k = scale;
@@ -147,23 +158,19 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
                 const float c = (float)num * rsqrtf((float)vi * (float)vj);
                 nv = c;
                 const float v = (float)scale * (1.0f - c) + 0.5f;
-                k = (long long)floorf(v);
+                k = (int)floorf(v);
                 const float fr = v - (float)k;
                 if (fr < margin || fr > 1.0f - margin) {
                     const unsigned long long P = (unsigned long long)vi * (unsigned long long)vj;
                     const long long B = 2LL * scale * num;
-                    while (!le_times_sqrt(B, 2LL * scale - 2 * k + 1, P)) --k;
-                    while (le_times_sqrt(B, 2LL * scale - 2 * (k + 1) + 1, P)) ++k;
+                    while (!le_times_sqrt(B, 2LL * scale - 2LL * k + 1, P)) --k;
+                    while (le_times_sqrt(B, 2LL * scale - 2LL * (k + 1) + 1, P)) ++k;
                 }
             }
-            if (k < 0) k = 0;
-            if (k > trunc) k = trunc;
+            k = k < 0 ? 0 : (k > trunc ? trunc : k);
             cost[o] = (int16_t)k;
             if (ncc_out) ncc_out[o] = nv;
         }
-        i += du;
-        d += dd;
-        if (d >= D) { d -= D; ++i; }
     }
 }
 
@@ -173,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_ncc(const uint8_t* __restrict__ L,
                                                    int16_t* __restrict__ cost, float* __restrict__ ncc_out)
 {
     extern __shared__ unsigned smem[];
-    ncc_tile<WIN>(L, R, W, H, D, scale, trunc, margin, cost, ncc_out, blockIdx.y, blockIdx.x * kTileX, smem);
+    ncc_tile<WIN>(L, R, W, H, D, scale, trunc, margin, cost, ncc_out, blockIdx.y, blockIdx.x * ncc_tile_x(D), smem);
 }
 
 // Every tile of every pair of a batch in one launch; tile_start[p] is the first tile of
@@ -193,30 +200,39 @@ __global__ __launch_bounds__(kThreads) void k_ncc_batched(const NccPair* __restr
     }
     const NccPair P = pairs[lo];
     const int local = tile - tile_start[lo];
-    const int tx = (P.W + kTileX - 1) / kTileX;
-    const int y = local / tx, x0 = (local - y * tx) * kTileX;
+    const int TX = ncc_tile_x(P.D);
+    const int tx = (P.W + TX - 1) / TX;
+    const int y = local / tx, x0 = (local - y * tx) * TX;
     ncc_tile<WIN>(P.left, P.right, P.W, P.H, P.D, scale, trunc, margin, P.cost, nullptr, y, x0, smem);
 }
 
 size_t ncc_lds_bytes(int D, int win)
 {
     const int r = win >> 1;
-    const int nI = kTileX + 2 * r, nJ = kTileX + 2 * r + D - 1;
-    return (size_t)(nI + nJ) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 + (size_t)2 * kTileX * 4 +
-           (size_t)2 * (kTileX + D - 1) * 4 + (size_t)nI * D * 4;
+    const int TX = ncc_tile_x(D);
+    const int nI = TX + 2 * r, nJ = TX + 2 * r + D - 1;
+    return (size_t)(nI + nJ) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 + (size_t)2 * TX * 4 +
+           (size_t)2 * (TX + D - 1) * 4 + (size_t)nI * D * 4;
 }
 
 float ncc_margin(int scale) { return 1e-4f + 2e-6f * (float)(2 * scale + 1); }
 
 }  // namespace
 
-int ncc_tiles(int W, int H) { return H * ((W + kTileX - 1) / kTileX); }
+int ncc_tiles(int W, int H, int D) { return H * ((W + ncc_tile_x(D) - 1) / ncc_tile_x(D)); }
+
+size_t ncc_lds_max(int max_d, int win)
+{
+    size_t m = 0;
+    for (int D = 1; D <= max_d; ++D) m = ncc_lds_bytes(D, win) > m ? ncc_lds_bytes(D, win) : m;
+    return m;
+}
 
 hipError_t launch_ncc(const uint8_t* L, const uint8_t* R, int W, int H, int D, int win, int scale, int trunc,
                       int16_t* cost, float* ncc, hipStream_t st)
 {
     if ((win >> 1) > kMaxR) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((W + kTileX - 1) / kTileX), (unsigned)H);
+    dim3 grid((unsigned)((W + ncc_tile_x(D) - 1) / ncc_tile_x(D)), (unsigned)H);
     const size_t lds = ncc_lds_bytes(D, win);
     const float m = ncc_margin(scale);
 #define BPST_NCC(WV) \
@@ -234,7 +250,7 @@ hipError_t launch_ncc_batched(const NccPair* pairs, const int* tile_start, int n
 {
     if ((win >> 1) > kMaxR) return hipErrorInvalidValue;
     if (total_tiles <= 0) return hipSuccess;
-    const size_t lds = ncc_lds_bytes(max_d, win);
+    const size_t lds = ncc_lds_max(max_d, win);  // the tile width, hence the LDS, depends on D
     const float m = ncc_margin(scale);
     const dim3 grid((unsigned)total_tiles);
 #define BPST_NCCB(WV) \
