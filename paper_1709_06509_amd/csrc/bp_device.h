@@ -155,6 +155,114 @@ __device__ __forceinline__ void transform(const int h[8], int lam, int capv, int
     for (int j = 0; j < 8; ++j) out[j] = min(f[j] - hm, capv);
 }
 
+// ---- two messages at once in packed 16-bit halves ----
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_pk(unsigned v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ unsigned pk_bits(u16x2 v) { return __builtin_bit_cast(unsigned, v); }
+__device__ __forceinline__ u16x2 pk_min(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
+__device__ __forceinline__ u16x2 pk_adds(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
+__device__ __forceinline__ u16x2 pk_splat(unsigned v) { return u16x2{(unsigned short)v, (unsigned short)v}; }
+
+template <int G, int O = 1>
+__device__ __forceinline__ u16x2 pk_scan_up(u16x2 c, unsigned step, int lane)
+{
+    if constexpr (O < G) {
+        const u16x2 t = as_pk((unsigned)lanes_up<G, O>((int)pk_bits(c)));
+        if (lane >= O) c = pk_min(c, pk_adds(t, pk_splat(min(step * O, 65535u))));
+        return pk_scan_up<G, 2 * O>(c, step, lane);
+    } else {
+        return c;
+    }
+}
+
+template <int G, int O = 1>
+__device__ __forceinline__ u16x2 pk_scan_down(u16x2 c, unsigned step, int lane)
+{
+    if constexpr (O < G) {
+        const u16x2 t = as_pk((unsigned)lanes_down<G, O>((int)pk_bits(c)));
+        if (lane + O < G) c = pk_min(c, pk_adds(t, pk_splat(min(step * O, 65535u))));
+        return pk_scan_down<G, 2 * O>(c, step, lane);
+    } else {
+        return c;
+    }
+}
+
+// The messages a and b of one pixel (h inputs ha, hb) computed together: label j of a in
+// the low half and of b in the high half of one register, so every min and add of the
+// envelope passes serves both (v_pk_min_u16, v_pk_add_u16 with clamp).  The result is the
+// same as transform() bit for bit: out = min(f - min h, C) with C = capv <= 32767, and the
+// envelope is a min-plus convolution, so shifting h by its minimum first, clipping it at C
+// and saturating every sum at 65535 (>= C) leave min(., C) unchanged; f <= C throughout.
+// Outputs come in memory order (labels 2w, 2w+1 of one message per 32-bit word).
+template <int G>
+__device__ __forceinline__ void transform2(const int ha[8], const int hb[8], int lam, int capv, int lane, int4& outa,
+                                           int4& outb)
+{
+    int ma = min(min(min(ha[0], ha[1]), min(ha[2], ha[3])), min(min(ha[4], ha[5]), min(ha[6], ha[7])));
+    int mb = min(min(min(hb[0], hb[1]), min(hb[2], hb[3])), min(min(hb[4], hb[5]), min(hb[6], hb[7])));
+    ma = group_min<G>(ma);
+    mb = group_min<G>(mb);
+    u16x2 x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        x[j] = as_pk((unsigned)min(ha[j] - ma, capv) | ((unsigned)min(hb[j] - mb, capv) << 16));
+    const u16x2 L = pk_splat(min((unsigned)lam, 65535u));
+    const unsigned step = 8u * (unsigned)lam;  // lam <= 65535: no overflow
+    // forward
+    u16x2 last = x[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) last = pk_min(x[j], pk_adds(last, L));
+    u16x2 cin = pk_splat(0xffffu);  // no carry: 65535 + lam saturates and never wins
+    if constexpr (G > 1) {
+        const u16x2 c = pk_scan_up<G>(last, step, lane);
+        cin = as_pk((unsigned)lanes_up<G, 1>((int)pk_bits(c)));
+        if (lane == 0) cin = pk_splat(0xffffu);
+    }
+    u16x2 f[8];
+    f[0] = pk_min(x[0], pk_adds(cin, L));
+#pragma unroll
+    for (int j = 1; j < 8; ++j) f[j] = pk_min(x[j], pk_adds(f[j - 1], L));
+    // backward
+    u16x2 first = f[7];
+#pragma unroll
+    for (int j = 6; j >= 0; --j) first = pk_min(f[j], pk_adds(first, L));
+    u16x2 cb = pk_splat(0xffffu);
+    if constexpr (G > 1) {
+        const u16x2 c = pk_scan_down<G>(first, step, lane);
+        cb = as_pk((unsigned)lanes_down<G, 1>((int)pk_bits(c)));
+        if (lane == G - 1) cb = pk_splat(0xffffu);
+    }
+    f[7] = pk_min(f[7], pk_adds(cb, L));
+#pragma unroll
+    for (int j = 6; j >= 0; --j) f[j] = pk_min(f[j], pk_adds(f[j + 1], L));
+    // regroup: low halves of labels 2w, 2w+1 -> word w of a; high halves -> word w of b
+    unsigned wa[4], wb[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        wa[w] = __builtin_amdgcn_perm(pk_bits(f[2 * w + 1]), pk_bits(f[2 * w]), 0x05040100u);
+        wb[w] = __builtin_amdgcn_perm(pk_bits(f[2 * w + 1]), pk_bits(f[2 * w]), 0x07060302u);
+    }
+    outa = make_int4((int)wa[0], (int)wa[1], (int)wa[2], (int)wa[3]);
+    outb = make_int4((int)wb[0], (int)wb[1], (int)wb[2], (int)wb[3]);
+}
+
+// Mask of the real labels (d < D) of this lane's four packed words.
+__device__ __forceinline__ int4 label_mask(int d0, int D)
+{
+    unsigned w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        w[i] = (d0 + 2 * i < D ? 0xffffu : 0u) | (d0 + 2 * i + 1 < D ? 0xffff0000u : 0u);
+    return make_int4((int)w[0], (int)w[1], (int)w[2], (int)w[3]);
+}
+
+// Packed words a and b agree on the real labels.
+__device__ __forceinline__ bool same_labels(const int4 a, const int4 b, const int4 m)
+{
+    return (((a.x ^ b.x) & m.x) | ((a.y ^ b.y) & m.y) | ((a.z ^ b.z) & m.z) | ((a.w ^ b.w) & m.w)) == 0;
+}
+
 struct ColourPix {
     int x, y;
     long long slot;
@@ -377,24 +485,29 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
                                : kBig;
     if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;
     bool all_eq = true;
+    const int4 lmask = label_mask(d0, a.D);
+    int4 out[4];
+#pragma unroll
+    for (int k = 0; k < 4; k += 2) {
+        int ha[8], hb[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            ha[j] = Hs[j] - msg_at(mp[k], j);
+            hb[j] = Hs[j] - msg_at(mp[k + 1], j);
+        }
+        transform2<G>(ha, hb, a.lambda, a.capv, lane, out[k], out[k + 1]);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int h[8], o[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) h[j] = Hs[j] - msg_at(mp[k], j);
-        transform<G>(h, a.lambda, a.capv, lane, o);
         bool store = act && has[k];
         int16_t* dst = a.msgs + (k ^ 1) * a.vol + nb[k] * Dp + d0;
         if (check) {
-            int e = 1;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) if (d0 + j < a.D && msg_at(op[k], j) != o[j]) e = 0;
-            e = group_min<G>(e);
+            const int e = group_min<G>(same_labels(op[k], out[k], lmask) ? 1 : 0);
             if (store && !e) all_eq = false;
             if (e) store = false;
             if (MODE == 2 && store && lane == 0) a.state_a[nb[k]] = 1;
         }
-        if (store) *reinterpret_cast<int4*>(dst) = pack8(o);
+        if (store) *reinterpret_cast<int4*>(dst) = out[k];
     }
     if (MODE == 1 && act && lane == 0) {
         if (a.t < 2) {

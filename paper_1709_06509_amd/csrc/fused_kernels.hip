@@ -98,6 +98,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
     const int npix = g.RH * RWc;
     const int lane = threadIdx.x & (G - 1);
     const int d0 = lane * 8;
+    const int4 lmask = label_mask(d0, a.D);
     const int pstep = blockDim.x / G, step_ry = pstep / RWc, step_i = pstep - step_ry * RWc;
     const int p_first = threadIdx.x / G;
     const int ry_first = p_first / RWc, i_first = p_first - ry_first * RWc;
@@ -136,25 +137,28 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
                                              msg_at(mp[3], j)
                                        : kBig;
             bool all_eq = true;
+            int4 out[4];
+#pragma unroll
+            for (int k = 0; k < 4; k += 2) {
+                int ha[8], hb[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    ha[j] = Hs[j] - msg_at(mp[k], j);
+                    hb[j] = Hs[j] - msg_at(mp[k + 1], j);
+                }
+                transform2<G>(ha, hb, a.lambda, a.capv, lane, out[k], out[k + 1]);
+            }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                int h[8], o[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) h[j] = Hs[j] - msg_at(mp[k], j);
-                transform<G>(h, a.lambda, a.capv, lane, o);
                 bool store = act && has[k] && inreg[k];
                 if (check) {
                     // a receiver outside the region is not held: its compare is skipped, which
                     // only affects pixels on the region's cut edge (never exact past step 0)
-                    int eq = 1;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) if (d0 + j < a.D && msg_at(op[k], j) != o[j]) eq = 0;
-                    eq = group_min<G>(eq);
+                    const int eq = group_min<G>(same_labels(op[k], out[k], lmask) ? 1 : 0);
                     if (store && !eq) all_eq = false;
                     if (eq) store = false;
                 }
-                if (store)
-                    *reinterpret_cast<int4*>(lm + (k ^ 1) * cap * Dp + (long long)nbr[k] * Dp + d0) = pack8(o);
+                if (store) *reinterpret_cast<int4*>(lm + (k ^ 1) * cap * Dp + (long long)nbr[k] * Dp + d0) = out[k];
             }
             if (MODE == 1 && act && lane == 0) {
                 if (t < 2) {
