@@ -55,11 +55,15 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
     int* cII = cI + nI;
     int* cJ = cII + nI;
     int* cJJ = cJ + nJ;
-    int* SI = cJJ + nJ;                            // window sums, TX of them
-    int* SII = SI + TX;
-    int* SJ = SII + TX;                            // TX + D - 1 of them, for u = x0-(D-1) ..
-    int* SJJ = SJ + TX + D - 1;
-    int* V = SJJ + TX + D - 1;                     // [nI][D]
+    // per left column x: window sum S_I, n S_II - S_I^2 and its reciprocal square root (0 for a
+    // flat window); the same per right column u = x0-(D-1) ..: TX and TX + D - 1 of each
+    int* SI = cJJ + nJ;
+    int* VI = SI + TX;
+    float* RI = reinterpret_cast<float*>(VI + TX);
+    int* SJ = reinterpret_cast<int*>(RI + TX);
+    int* VJ = SJ + TX + D - 1;
+    float* RJ = reinterpret_cast<float*>(VJ + TX + D - 1);
+    int* V = reinterpret_cast<int*>(RJ + TX + D - 1);  // [nI][D]
 
     // 1. packed byte columns of the window rows (clamped), zero beyond the window
     for (int c = threadIdx.x; c < nI + nJ; c += kThreads) {
@@ -85,18 +89,22 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
     }
     __syncthreads();
 
-    // 2. horizontal window sums of the left columns and the right columns
+    // 2. horizontal window sums of the left columns and the right columns, and their
+    //    variances (window <= 13: n S_II - S_I^2 fits in int32) with reciprocal roots
+    constexpr int n = WIN * WIN;
     for (int i = threadIdx.x; i < TX; i += kThreads) {
         int s = 0, ss = 0;
 #pragma unroll
         for (int k = 0; k < WIN; ++k) { s += cI[i + k]; ss += cII[i + k]; }
-        SI[i] = s; SII[i] = ss;
+        const int v = n * ss - s * s;
+        SI[i] = s; VI[i] = v; RI[i] = v > 0 ? rsqrtf((float)v) : 0.0f;
     }
     for (int i = threadIdx.x; i < TX + D - 1; i += kThreads) {
         int s = 0, ss = 0;
 #pragma unroll
         for (int k = 0; k < WIN; ++k) { s += cJ[i + k]; ss += cJJ[i + k]; }
-        SJ[i] = s; SJJ[i] = ss;
+        const int v = n * ss - s * s;
+        SJ[i] = s; VJ[i] = v; RJ[i] = v > 0 ? rsqrtf((float)v) : 0.0f;
     }
     // 3. column products V[u][d] = sum over the window rows of left(u) * right(u - d)
     const int du = kThreads / D, dd = kThreads - du * D;  // step of (u, d) per kThreads elements
@@ -120,7 +128,6 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
     // 4. finish every (x, d) of the tile.  Thread t takes disparity d = t mod D and a run of
     //    XR consecutive columns, sliding the horizontal window sum along the run (two LDS
     //    reads per column instead of WIN); consecutive threads write consecutive d.
-    constexpr int n = WIN * WIN;
     const int tileW = min(TX, W - x0);
     const int tpd = D >= kThreads ? 1 : kThreads / D;  // runs per disparity
     const int XR = (TX + tpd - 1) / tpd;
@@ -142,20 +149,20 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
                 continue;
             }
             // window <= 13: every product and difference below fits in int32
-            const int si = SI[i], sii = SII[i];
-            const int sj = SJ[i - d + (D - 1)], sjj = SJJ[i - d + (D - 1)];
-            const int num = n * sij - si * sj;
-            const int vi = n * sii - si * si;
-            const int vj = n * sjj - sj * sj;
+            const int u = i - d + (D - 1);
+            const int num = n * sij - SI[i] * SJ[u];
+            const int vi = VI[i], vj = VJ[u];
             int k;  // |k| <= 2 * scale + 1 < 2^31
             float nv;
             if (vi == 0 || vj == 0) {
                 k = scale;
                 nv = 0.0f;
             } else {
-                // fp32 estimate: relative error of c below ~4e-7, so |error of v| < 3.1e-7 * scale;
-                // within `margin` (>= 2e-6 * scale) of a boundary the exact test decides
-                const float c = (float)num * rsqrtf((float)vi * (float)vj);
+                // fp32 estimate: c carries at most about 4 units of rounding (two conversions,
+                // two reciprocal roots of 1 ulp, two products), relative error below 5e-7, so
+                // |error of v| < 5e-7 * scale; within `margin` (>= 4e-6 * scale) of a rounding
+                // boundary the exact test decides
+                const float c = (float)num * (RI[i] * RJ[u]);
                 nv = c;
                 const float v = (float)scale * (1.0f - c) + 0.5f;
                 k = (int)floorf(v);
@@ -211,8 +218,8 @@ size_t ncc_lds_bytes(int D, int win)
     const int r = win >> 1;
     const int TX = ncc_tile_x(D);
     const int nI = TX + 2 * r, nJ = TX + 2 * r + D - 1;
-    return (size_t)(nI + nJ) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 + (size_t)2 * TX * 4 +
-           (size_t)2 * (TX + D - 1) * 4 + (size_t)nI * D * 4;
+    return (size_t)(nI + nJ) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 + (size_t)3 * TX * 4 +
+           (size_t)3 * (TX + D - 1) * 4 + (size_t)nI * D * 4;
 }
 
 float ncc_margin(int scale) { return 1e-4f + 2e-6f * (float)(2 * scale + 1); }
