@@ -118,12 +118,47 @@ __global__ __launch_bounds__(kThreads) void k_import(const int16_t* __restrict__
 }
 
 // One half-step over a whole scale (see halfstep_pixel), with optional per-block counters.
+//
+// Where pixels can be inactive (the freeze rule from its third half-step on, the exact
+// skip always), a workgroup first compacts its tile: each wave forms the 64-bit mask of its
+// active pixels with a ballot, each active pixel takes its rank from mbcnt plus the counts
+// of the waves before it, and the active pixels are packed onto the first lanes.  Waves
+// left without work leave at once (a tile with no active pixel loads nothing), the others
+// update only active pixels.  Updates of one colour are independent, so the order does not
+// change any result.
 template <int G, int MODE, int SRC, bool COUNT>
 __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
 {
-    const int t = blockIdx.x * kThreads + threadIdx.x;
-    const int lane = t & (G - 1);
-    const PixOut r = halfstep_pixel<G, MODE, SRC>(a, t / G, lane);
+    constexpr int kPix = kThreads / G;  // pixels of one tile
+    const int lane = threadIdx.x & (G - 1);
+    int gi = blockIdx.x * kPix + threadIdx.x / G;
+    if (MODE == 2 || (MODE == 1 && a.t >= 2)) {
+        __shared__ int list[kPix];
+        __shared__ int wcount[kThreads / 64];
+        const long long npix = (long long)a.lv.H * a.lv.Wh;
+        bool active = false;
+        if (lane == 0 && gi < npix) {
+            const int y = gi / a.lv.Wh, xi = gi - y * a.lv.Wh;
+            const int x = 2 * xi + ((a.colour ^ y) & 1);
+            active = x < a.lv.W && a.state_a[(long long)(2 * y + a.colour) * a.lv.Wh + xi] != 0;
+        }
+        const unsigned long long m = __ballot(active);
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) wcount[wave] = __popcll(m);
+        __syncthreads();
+        int base = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            base += w < wave ? wcount[w] : 0;
+            total += wcount[w];
+        }
+        if (active) list[base + rank] = threadIdx.x / G;
+        __syncthreads();
+        if (!COUNT && (threadIdx.x & ~63) >= total * G) return;  // the whole wave has no pixel
+        gi = threadIdx.x < total * G ? blockIdx.x * kPix + list[threadIdx.x / G] : (int)npix;  // npix: no pixel
+    }
+    const PixOut r = halfstep_pixel<G, MODE, SRC>(a, gi, lane);
     if (COUNT) {
         __shared__ int cnt[2];
         if (threadIdx.x == 0) { cnt[0] = 0; cnt[1] = 0; }

@@ -243,3 +243,20 @@ def test_graph_forced_failure_falls_back(monkeypatch):
         torch.cuda.synchronize()
     assert np.array_equal(host(d), ref)
     assert ctx.graph_counts()["fallbacks"] == 1
+
+
+@pytest.mark.parametrize("skip", [1, 2])
+def test_compacted_halfsteps_without_counters(skip):
+    """The freeze rule and the exact skip compact active pixels per tile; without counters idle
+    waves leave early.  One launch per half-step (fused launches off) against the oracle."""
+    ctx = B.Context()
+    ctx.set_fused(0)
+    for (H, W, D, L, iters) in [(61, 83, 16, 3, [9, 8, 7]), (40, 57, 24, 2, [12, 10]), (33, 35, 64, 2, [8, 6])]:
+        say(f"compacted skip={skip} {W}x{H} D={D} L={L} iters={iters}")
+        p = synth.make_pair(W, H, D, (3, 5), True, 0, False, seed=300 + W)
+        cost = oracle.cost_volume(p["left"], p["right"], D, 5)
+        d, m, _ = B.bp_hierarchical_solve(gpu(cost), L, iters, 64, 4, skip, 2, want_msgs=True, ctx=ctx)
+        rd, rm, _ = oracle.bp_solve(cost, L, iters, 64, 4, skip, 2)
+        assert np.array_equal(host(m), rm), "messages differ"
+        assert np.array_equal(host(d), rd), "disparities differ"
+    ctx.close()
