@@ -51,10 +51,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
     const Region g = region_of(a);
     const int W = a.lv.W, H = a.lv.H, Wh = a.lv.Wh;
     const long long cap = a.rmax;  // region pixels the LDS was sized for
-    int16_t* lc = reinterpret_cast<int16_t*>(lds4);
+    int* wsum = reinterpret_cast<int*>(lds4);           // per-wave counts (kFusedThreads / 64 of 64)
+    int16_t* lc = reinterpret_cast<int16_t*>(lds4 + 16);  // after 256 bytes
     int16_t* lm = lc + cap * Dp;   // volume k at lm + k * cap * Dp
     uint8_t* lsa = reinterpret_cast<uint8_t*>(lm + 4 * cap * Dp);
     uint8_t* lsb = lsa + cap;
+    int* llist = reinterpret_cast<int*>(lsb + ((cap + 3) & ~3LL));  // active pixels of a half-step
     const int R = g.RW * g.RH;
 
     // 1. load the region: cost, incoming messages (own, parent's or zero), freeze state
@@ -102,11 +104,55 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
     const int pstep = blockDim.x / G, step_ry = pstep / RWc, step_i = pstep - step_ry * RWc;
     const int p_first = threadIdx.x / G;
     const int ry_first = p_first / RWc, i_first = p_first - ry_first * RWc;
+    const int wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
     for (int s = 0; s < a.nsteps; ++s) {
         const int t = a.t0 + s, colour = t & 1;
         const bool check = MODE == 1 && t >= 2;
+        // under the freeze rule, list the active pixels of this colour first (a ballot mask
+        // per wave, ranks from mbcnt and the counts of the waves before), so that the update
+        // loop below runs over active pixels only
+        int count = npix;
+        if (check) {
+            int total = 0;
+            int ry = ry_first, i = i_first;
+            for (int p0 = 0; p0 < npix; p0 += pstep) {
+                const int p = p0 + p_first;
+                bool active = false;
+                int code = 0;
+                if (p < npix && lane == 0) {
+                    const int rx = 2 * i + ((colour ^ (g.rx0 + g.ry0 + ry)) & 1);
+                    active = rx < g.RW && lsa[ry * g.RW + rx] != 0;
+                    code = (ry << 16) | i;
+                }
+                const unsigned long long m = __ballot(active);
+                const int rank =
+                    (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                if ((threadIdx.x & 63) == 0) wsum[wave] = __popcll(m);
+                __syncthreads();
+                int base = 0, sum = 0;
+                for (int w = 0; w < nwaves; ++w) {
+                    base += w < wave ? wsum[w] : 0;
+                    sum += wsum[w];
+                }
+                if (active) llist[total + base + rank] = code;
+                total += sum;
+                __syncthreads();
+                i += step_i;
+                ry += step_ry;
+                if (i >= RWc) {
+                    i -= RWc;
+                    ++ry;
+                }
+            }
+            count = total;
+        }
         int ry = ry_first, i = i_first;
-        for (int p = p_first; p < npix; p += pstep) {
+        for (int p = p_first; p < count; p += pstep) {
+            if (check) {
+                const int code = llist[p];
+                ry = code >> 16;
+                i = code & 0xffff;
+            }
             const int y = g.ry0 + ry;
             const int rx = 2 * i + ((colour ^ (g.rx0 + y)) & 1);
             const int x = g.rx0 + rx;
@@ -207,7 +253,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
 size_t fused_lds_bytes(int G, long long rmax)
 {
     const long long Dp = 8LL * G;
-    return (size_t)(5 * rmax * Dp * 2 + 2 * rmax + 15) / 16 * 16;
+    // cost and 4 volumes, two state bytes (padded to 4) and an int of the active list per pixel
+    return (size_t)(256 + 5 * rmax * Dp * 2 + ((2 * rmax + 3) & ~3LL) + 4 * rmax + 15) / 16 * 16;
 }
 
 int fused_threads(int G, long long rmax)
@@ -286,8 +333,8 @@ bool fused_geometry(const Level& lv, int G, int iters, int* steps, int* TW, int*
 namespace {
 bool fused_search(const Level& lv, int G, int iters, int* steps, int* TW, int* TH, long long* rmax)
 {
-    const long long per = 5LL * 8 * G * 2 + 2;                       // LDS bytes per region pixel
-    const long long cap = (long long)(kFusedLdsBytes - 16) / per;   // room for the 16-byte rounding
+    const long long per = 5LL * 8 * G * 2 + 6;                       // LDS bytes per region pixel
+    const long long cap = (long long)(kFusedLdsBytes - 256 - 32) / per;  // wave counts, alignment
     double best = per_launch_us(lv, G, iters);
     bool found = false;
     for (int h = 1; h <= iters && h <= 12; ++h) {
@@ -319,8 +366,8 @@ bool fused_search(const Level& lv, int G, int iters, int* steps, int* TW, int* T
 // Any tile: the widest interior whose region fits (used when fused launches are forced).
 bool fused_geometry_max(const Level& lv, int G, int steps, int* TW, int* TH, long long* rmax)
 {
-    const long long per = 5LL * 8 * G * 2 + 2;
-    const long long cap = (long long)(kFusedLdsBytes - 16) / per;
+    const long long per = 5LL * 8 * G * 2 + 6;
+    const long long cap = (long long)(kFusedLdsBytes - 256 - 32) / per;
     const int h = steps;
     long long best_tiles = -1;
     for (int tw = 1; tw <= lv.W; ++tw) {
