@@ -295,6 +295,7 @@ def main():
     avg_launch_s = timing["halfstep_ms"] / 1000.0 / max(1, timing["halfstep_launches"])
     bytes_per_launch = hs_bytes / max(1, n_launch)
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    traffic = measured_traffic(args.workload)  # profiler-measured HBM bytes per launch, or None
     out = {
         "metric": METRIC,
         "value": pairs_per_s,
@@ -327,7 +328,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload),
+            "traffic": traffic,
+            "traffic_gbs": traffic / avg_launch_s / 1e9 if traffic and avg_launch_s > 0 else None,
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "launches_per_step": n_launch,

@@ -348,8 +348,12 @@ def main():
     ap.add_argument("--resume", default=None, help="checkpoint file to continue from")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--ckpt-every", type=int, default=5000)
+    ap.add_argument("--long-factor", type=int, default=DEFAULT["long_factor"],
+                    help="labels: plain BP's scale-(L-2) messages after this many times the half-steps per scale "
+                         "(1: exactly plain BP's own messages there)")
     args = ap.parse_args()
     cfg = dict(DEFAULT)
+    cfg["long_factor"] = args.long_factor
     os.makedirs(args.out, exist_ok=True)
 
     def log(msg):
@@ -386,6 +390,7 @@ def main():
     log(f"schedule {schedule}")
     res = evaluate(pipes, cfg, args.eval_pairs, schedule, log)
     res.update({"train_pairs": args.train_pairs, "steps": trainer.step, "train_seconds": t_train,
+                "label_long_factor": cfg["long_factor"],
                 "heldout_l1_network": l_net, "heldout_l1_zero": l_zero, "loss_curve": losses,
                 "schedule_table": table})
     with open(os.path.join(args.out, "result.json"), "w") as f:
