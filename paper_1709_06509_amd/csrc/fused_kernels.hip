@@ -13,6 +13,7 @@
 //
 // Per-pixel arithmetic is the same as the per-launch kernel (transform, freeze rule);
 // only the storage differs: LDS holds the region row-major, [pixel][Dp] per volume.
+#include <mutex>
 #include <vector>
 
 #include "bp_device.h"
@@ -395,12 +396,21 @@ void set_lds_attr()
 
 void fused_prepare()
 {
-    static bool done = false;
-    if (done) return;
+    // once per device (the attribute belongs to the device's copy of each kernel)
+    static std::mutex mu;
+    static std::vector<bool> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        return;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if ((size_t)dev < done.size() && done[dev]) return;
     set_lds_attr<1, 0>(); set_lds_attr<1, 1>(); set_lds_attr<2, 0>(); set_lds_attr<2, 1>();
     set_lds_attr<4, 0>(); set_lds_attr<4, 1>(); set_lds_attr<8, 0>(); set_lds_attr<8, 1>();
     (void)hipGetLastError();
-    done = true;
+    if ((size_t)dev >= done.size()) done.resize(dev + 1, false);
+    done[dev] = true;
 }
 
 hipError_t launch_fused(const FusedArgs& a, hipStream_t st)
