@@ -619,10 +619,10 @@ bp_params pair_params(const bp_pair_desc& d, const bp_batch_params* p)
     return q;
 }
 
+// LDS of a pyramid workgroup of the batched solve (kThreadsPerTile lanes).
 size_t tree_lds_bytes(int L, int G)
 {
-    const long long s1 = 1LL << (L - 2), s2 = s1 / 2;
-    return (size_t)(s1 * s1 + s2 * s2) * 8 * G * sizeof(int);
+    return (size_t)bpst::tree_blocks(L, G, bpst::kThreadsPerTile) * bpst::tree_block_lds(L, G);
 }
 
 // Validates the batch and lays out its workspace; returns 0 or a BP_E_* code.
@@ -647,7 +647,7 @@ int32_t plan_batch(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* 
         if (check_ptrs && (!d.left || !d.right || !d.cost || !d.disparity))
             return fail(BP_E_INVAL, "pair %d: a pointer is NULL", i);
         b.plans[i] = make_plan(d.width, d.height, &q);
-        if (tree_lds_bytes(b.L, b.plans[i].G) > 64 * 1024)
+        if (bpst::tree_block_lds(b.L, b.plans[i].G) > 64 * 1024)
             return fail(BP_E_UNSUPPORTED, "pair %d: D=%d with %d scales exceeds the pyramid's LDS", i, d.num_disp, b.L);
         b.lds = std::max(b.lds, tree_lds_bytes(b.L, b.plans[i].G));
         b.max_d = std::max(b.max_d, d.num_disp);
@@ -679,7 +679,11 @@ int32_t plan_batch(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* 
             const bpst::Level& lv = pl.lv[d.level];
             long long nt = 0;
             switch (d.type) {
-            case bpst::kPhPyramid: nt = (long long)pl.lv[b.L - 1].W * pl.lv[b.L - 1].H; break;
+            case bpst::kPhPyramid: {
+                const long long nb = bpst::tree_blocks(b.L, pl.G, bpst::kThreadsPerTile);
+                nt = ((long long)pl.lv[b.L - 1].W * pl.lv[b.L - 1].H + nb - 1) / nb;
+                break;
+            }
             case bpst::kPhInit:
             case bpst::kPhWta: nt = (lv.slots() + px - 1) / px; break;
             case bpst::kPhHalfstep: nt = ((long long)lv.H * lv.Wh + px - 1) / px; break;

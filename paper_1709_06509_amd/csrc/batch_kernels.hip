@@ -87,9 +87,9 @@ __device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& 
     const long long gi = (long long)lt * kPix + threadIdx.x / G;
     const int l = ph.level;
     if (TYPE == kPhPyramid) {
-        const int Wc = Q.lv[a.L - 1].W;
-        if (Q.vec) pyramid_tree_block<G, true>(Q.cost, Q.c, Q.lv, a.L, Q.D, lt % Wc, lt / Wc, lds);
-        else pyramid_tree_block<G, false>(Q.cost, Q.c, Q.lv, a.L, Q.D, lt % Wc, lt / Wc, lds);
+        const int c0 = lt * tree_blocks(a.L, G, kThreads);
+        if (Q.vec) pyramid_tree_block<G, true>(Q.cost, Q.c, Q.lv, a.L, Q.D, c0, lds);
+        else pyramid_tree_block<G, false>(Q.cost, Q.c, Q.lv, a.L, Q.D, c0, lds);
     } else if (TYPE == kPhInit) {
         const bool top = l == a.L - 1;
         init_pixel<G>(top ? nullptr : Q.m[(l + 1) & 1], Q.lv[top ? l : l + 1], top ? 0 : Q.vol[l + 1], Q.m[l & 1],

@@ -317,24 +317,33 @@ struct PixOut {
     bool has[4];  // it has a neighbour on side k
 };
 
-// The whole cost pyramid in one launch.  One workgroup per pixel (X, Y) of the coarsest
-// scale: it re-lays the finest costs of the block of pixels under (X, Y) into the internal
-// layout and builds every coarser scale of that block, handing each scale to the next in
+// The whole cost pyramid in one launch.  A block is the set of pixels under one pixel
+// (X, Y) of the coarsest scale: its lanes re-lay the block's finest costs into the internal
+// layout and build every coarser scale of the block, handing each scale to the next in
 // LDS.  Scale sizes halve with ceil, so the block's pixels at scale l are exactly
-// [X s_l, (X+1) s_l) x [Y s_l, (Y+1) s_l) clipped to the scale, s_l = 2^(L-1-l).
+// [X s_l, (X+1) s_l) x [Y s_l, (Y+1) s_l) clipped to the scale, s_l = 2^(L-1-l).  A
+// workgroup takes coarsest pixels c0, c0 + 1, ... (row-major), tree_blocks() of them, each
+// with its own lanes and LDS slice; all blocks meet the same barriers.  A coarsest index
+// past the last pixel has Y >= the coarsest height, so every pixel of its block is out of
+// range on every scale and it only takes part in the barriers.
 template <int G, bool VEC>
 __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ user, int16_t* const* cs,
-                                                   const Level* lvs, int L, int D, int X, int Y, int* lds)
+                                                   const Level* lvs, int L, int D, int c0, int* lds)
 {
     constexpr int Dp = 8 * G;
-    const int s1 = 1 << (L - 2);
-    int* cur = lds;                 // scale l-1 of the block, [s_{l-1}^2][Dp]
-    int* nxt = lds + s1 * s1 * Dp;  // scale l
+    const int s1 = 1 << (L - 2), s2 = s1 / 2;
+    const int p1 = s1 * s1 * G;
+    const int nt = p1 < (int)blockDim.x ? p1 : (int)blockDim.x;  // lanes per block
+    const int sub = (int)threadIdx.x / nt, tid = (int)threadIdx.x % nt;
+    const int Wc = lvs[L - 1].W;
+    const int X = (c0 + sub) % Wc, Y = (c0 + sub) / Wc;
+    int* cur = lds + sub * (s1 * s1 + s2 * s2) * Dp;  // scale l-1 of the block, [s_{l-1}^2][Dp]
+    int* nxt = cur + s1 * s1 * Dp;                    // scale l
     // scale 1 from the caller's finest costs; also writes the internal finest layout
     {
         const Level l0 = lvs[0], l1 = lvs[1];
         const int tasks = s1 * s1 * G;
-        for (int task = threadIdx.x; task < tasks; task += blockDim.x) {
+        for (int task = tid; task < tasks; task += nt) {
             const int p = task / G, lane = task & (G - 1), d0 = lane * 8;
             const int px = X * s1 + (p % s1), py = Y * s1 + (p / s1);
             const bool valid = px < l1.W && py < l1.H;
@@ -379,7 +388,7 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
         const Level lf = lvs[l - 1], lc = lvs[l];
         const int sl = 1 << (L - 1 - l), sf = 2 * sl;
         const int tasks = sl * sl * G;
-        for (int task = threadIdx.x; task < tasks; task += blockDim.x) {
+        for (int task = tid; task < tasks; task += nt) {
             const int p = task / G, lane = task & (G - 1), d0 = lane * 8;
             const int qx = p % sl, qy = p / sl;
             const int px = X * sl + qx, py = Y * sl + qy;

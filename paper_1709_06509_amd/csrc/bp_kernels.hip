@@ -75,7 +75,7 @@ template <int G, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_pyramid_tree(const int16_t* __restrict__ user, PyramidArgs a)
 {
     extern __shared__ int lds[];
-    pyramid_tree_block<G, VEC>(user, a.c, a.lv, a.L, a.D, blockIdx.x, blockIdx.y, lds);
+    pyramid_tree_block<G, VEC>(user, a.c, a.lv, a.L, a.D, (int)blockIdx.x * tree_blocks(a.L, G, blockDim.x), lds);
 }
 
 // Start a scale: copy each pixel's parent messages (zero for a missing neighbour or for
@@ -342,13 +342,19 @@ hipError_t launch_pyramid_tree(const int16_t* user, const PyramidArgs& a, int G,
 {
     *done = false;
     if (a.L < 2) return hipSuccess;
-    const long long s1 = 1LL << (a.L - 2), s2 = s1 / 2;
-    const size_t lds = (size_t)(s1 * s1 + s2 * s2) * 8 * G * sizeof(int);
-    if (lds > 64 * 1024) return hipSuccess;
+    if (tree_block_lds(a.L, G) > 64 * 1024) return hipSuccess;
     const bool vec = (a.D % 8 == 0) && ((reinterpret_cast<uintptr_t>(user) & 15) == 0);
-    const long long tasks = s1 * s1 * G;
-    const unsigned threads = (unsigned)(tasks >= kThreads ? kThreads : ((tasks + 63) / 64) * 64);
-    const dim3 grid((unsigned)a.lv[a.L - 1].W, (unsigned)a.lv[a.L - 1].H);
+    // Workgroup width: whole waves, at least one block's lanes up to kThreads; then
+    // narrower (fewer blocks per workgroup) while the grid would not give every CU two.
+    const long long coarsest = (long long)a.lv[a.L - 1].W * a.lv[a.L - 1].H;
+    const long long p1 = (1LL << (2 * (a.L - 2))) * G;
+    long long threads = kThreads;
+    while (threads > 64 && threads / 2 >= p1 &&
+           (coarsest + tree_blocks(a.L, G, (int)threads) - 1) / tree_blocks(a.L, G, (int)threads) < 512)
+        threads /= 2;
+    const int nb = tree_blocks(a.L, G, (int)threads);
+    const size_t lds = (size_t)nb * tree_block_lds(a.L, G);
+    const dim3 grid((unsigned)((coarsest + nb - 1) / nb));
     if (vec) {
         BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_pyramid_tree<GG, true>), grid, dim3(threads), lds, st, user, a));
     } else {

@@ -60,6 +60,22 @@ struct HalfstepArgs {
     int level;
 };
 
+// Coarsest pixels that one workgroup of `threads` lanes takes in the one-launch cost
+// pyramid.  The block under one coarsest pixel needs s1^2 G lanes on scale 1
+// (s1 = 2^(L-2)); blocks smaller than the workgroup are packed side by side.
+__host__ __device__ inline int tree_blocks(int L, int G, int threads)
+{
+    const int p1 = (1 << (2 * (L - 2))) * G;
+    return p1 >= threads ? 1 : threads / p1;
+}
+
+// LDS of one block of the cost pyramid: scales 1 and 2 of the block, int per label.
+inline size_t tree_block_lds(int L, int G)
+{
+    const long long s1 = 1LL << (L - 2), s2 = s1 / 2;
+    return (size_t)(s1 * s1 + s2 * s2) * 8 * G * sizeof(int);
+}
+
 struct PyramidArgs {
     int16_t* c[kMaxScales];  // internal cost of every scale
     Level lv[kMaxScales];
