@@ -58,7 +58,8 @@ typedef struct {
     int32_t converge_iters;  /* K for skip_mode 1, in half-steps: even, 2..64               */
     const int16_t* warm_msgs; /* [device] nullable: [4][H_s][W_s][D] initial messages at
                                  scale s = L-2 (needs L >= 2); the solve then skips scale
-                                 L-1 and starts at s.  Slots without a neighbour are ignored. */
+                                 L-1 and starts at s.  Values 0..32767 (messages are never
+                                 negative).  Slots without a neighbour are ignored.       */
 } bp_params;
 
 /* Counters of one solve, returned [host]. */
@@ -229,10 +230,12 @@ int32_t bp_batch_status(const void* workspace, void* stream, int32_t* status);
 /* Launch shapes tried by the autotuner, with their measured time. */
 typedef struct {
     int32_t n_candidates;
-    int32_t schedule[16];      /* 0: one persistent launch; 1: one launch per phase (no grid barrier) */
+    int32_t schedule[16];      /* 0: one persistent launch; 1: one launch per phase (no grid barrier);
+                                  2: as 1, the half-steps with packed 16-bit message sums (offered
+                                  when lambda * trunc <= 16383; results are identical) */
     int32_t blocks_per_cu[16]; /* persistent launch: resident workgroups per compute unit */
     int32_t order[16];         /* 0: tiles dealt round-robin; 1: one contiguous eighth per XCD */
-    float ms[16];              /* device time of the persistent launch */
+    float ms[16];              /* device time of the candidate's solve */
     int32_t best;              /* index of the fastest */
 } bp_batch_tuning;
 
@@ -248,8 +251,9 @@ int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, int32_t 
                             void* workspace, size_t workspace_bytes, void* stream, bp_batch_tuning* out);
 
 /* Force the schedule of later batched solves on ctx (overrides tuning): schedule 0 with
-   blocks_per_cu >= 1 (capped at the resident maximum) and order 0/1, or schedule 1;
-   schedule -1 returns to the tuned or default choice. */
+   blocks_per_cu >= 1 (capped at the resident maximum) and order 0/1, or schedule 1 or 2
+   (2 runs as 1 when lambda * trunc > 16383); schedule -1 returns to the tuned or default
+   choice. */
 int32_t bp_context_set_batch_schedule(bp_context* ctx, int32_t schedule, int32_t blocks_per_cu, int32_t order);
 
 /* ---------------------------------------------------------------------------------------

@@ -158,8 +158,8 @@ struct bp_context {
 BP_API int32_t bp_context_set_batch_schedule(bp_context* ctx, int32_t schedule, int32_t blocks_per_cu, int32_t order)
 {
     if (!ctx) return fail(BP_E_INVAL, "ctx is NULL");
-    if (schedule < -1 || schedule > 1 || (schedule == 0 && (blocks_per_cu < 1 || order < 0 || order > 1)))
-        return fail(BP_E_INVAL, "schedule must be -1, 0 (with blocks_per_cu >= 1, order 0/1) or 1");
+    if (schedule < -1 || schedule > 2 || (schedule == 0 && (blocks_per_cu < 1 || order < 0 || order > 1)))
+        return fail(BP_E_INVAL, "schedule must be -1, 0 (with blocks_per_cu >= 1, order 0/1), 1 or 2");
     ctx->forced_sched = schedule;
     ctx->forced_bpc = blocks_per_cu;
     ctx->forced_order = order;
@@ -342,6 +342,17 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
     }
 
     const int start = params->warm_msgs ? pl.L - 2 : pl.L - 1;
+    // Half-step t of scale l may use packed 16-bit sums (bp_device.h, the narrow path) when
+    // every incoming message it reads is a transform output, in [0, capv], and capv is small
+    // enough.  Raw warm messages (any value up to 32767) are read by the warm scale's first
+    // half-step, and reach finer scales when the warm scale runs fewer than two half-steps
+    // (then some slots are never rewritten).
+    auto narrow_ok = [&](int l, int t) {
+        if (capv > bpst::kNarrowCap) return false;
+        if (!params->warm_msgs) return true;
+        if (l == start) return t > 0;
+        return params->iters[start] >= 2;
+    };
     for (int l = start; l >= 0; --l) {
         int16_t* msgs = M[l & 1];
         const int iters = params->iters[l];
@@ -444,6 +455,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                 f.halo = f.nsteps;  // a shorter last chunk keeps the tile: its smaller halo fits the LDS
                 f.source = t0 == 0 ? source : bpst::kSrcOwn;
                 f.keep_state = t0 + f.nsteps < iters ? 1 : 0;
+                f.narrow = narrow_ok(l, t0) && bpst::fused_narrow_pays(pl.G, frmax) ? 1 : 0;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (ctx && ctx->timing) {
                     if (ctx->used == ctx->events.size()) {
@@ -466,6 +478,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
             a.t = t;
             a.colour = t & 1;
             a.source = (t == 0) ? source : bpst::kSrcOwn;
+            a.narrow = narrow_ok(l, t) && !count && pl.G <= bpst::kNarrowMaxG ? 1 : 0;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (ctx && ctx->timing) {
                 if (ctx->used == ctx->events.size()) {
@@ -804,7 +817,8 @@ int32_t upload_tables(bp_context* ctx, const std::vector<char>& img, char* ws, h
     return BP_OK;
 }
 
-bpst::BatchArgs batch_args(const BatchPlan& b, const bp_batch_params* p, char* ws, int order, long long ticks)
+bpst::BatchArgs batch_args(const BatchPlan& b, const bp_batch_params* p, char* ws, int order, long long ticks,
+                           bool narrow)
 {
     bpst::BatchArgs a{};
     a.pairs = reinterpret_cast<const bpst::PairDev*>(ws + b.off_pairs);
@@ -818,6 +832,7 @@ bpst::BatchArgs batch_args(const BatchPlan& b, const bp_batch_params* p, char* w
     // min(lambda * T, 32767) either way unless T >= D, where the clamp never binds
     const long long lt = (long long)p->lambda * p->trunc;
     a.capv = (int)(lt < 32767 ? lt : 32767);
+    a.narrow = narrow && a.capv <= bpst::kNarrowCap ? 1 : 0;
     a.K = p->converge_iters;
     a.mode = p->skip_mode;
     a.order = order;
@@ -848,9 +863,10 @@ int32_t timing_events(bp_context* ctx, hipEvent_t* e0, hipEvent_t* e1)
 int32_t enqueue_batch_solve(bp_context* ctx, const BatchPlan& b, const bp_batch_params* p, char* ws, int sched, int bpc,
                             int order, int cus, long long ticks, hipStream_t st)
 {
-    const bpst::BatchArgs a = batch_args(b, p, ws, order, ticks);
+    // schedules: 0 one persistent launch, 1 one launch per phase, 2 the same on the narrow path
+    const bpst::BatchArgs a = batch_args(b, p, ws, order, ticks, sched == 2);
     HIP_TRY(bpst::launch_batch_reset(a.barrier, a.error, st));
-    if (sched == 1) {
+    if (sched == 1 || sched == 2) {
         for (int ph = 0; ph < b.nphases; ++ph) {
             const bpst::PhaseDesc& d = b.phases[ph];
             // timing mode: an event pair around every half-step phase
@@ -1009,6 +1025,7 @@ BP_API int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, i
         int sched, bpc, order;
     };
     std::vector<Cand> cands{{1, 0, 0}};
+    if ((long long)params->lambda * params->trunc <= bpst::kNarrowCap) cands.push_back({2, 0, 0});
     for (int bpc = 1; bpc <= max_bpc; bpc = (bpc < 4 ? bpc + 1 : bpc * 2))
         for (int order = 0; order < 2; ++order) cands.push_back({0, bpc, order});
     int k = 0;
@@ -1105,6 +1122,14 @@ BP_API int32_t bp_pyramid_level(const int16_t* cost, int32_t width, int32_t heig
     if (!cost || !out) return fail(BP_E_INVAL, "cost/out is NULL");
     if (level < 0 || level >= pl.L) return fail(BP_E_INVAL, "level must be in 0..num_scales-1");
     hipStream_t st = (hipStream_t)stream;
+    if (level == 0) {
+        // the finest scale is the caller's cost itself (internally it is kept shifted by each
+        // pixel's minimum)
+        if (out != cost)
+            HIP_TRY(hipMemcpyAsync(out, cost, (size_t)width * height * params->num_disp * sizeof(int16_t),
+                                   hipMemcpyDeviceToDevice, st));
+        return ok();
+    }
     char* ws = static_cast<char*>(workspace);
     rc = enqueue_pyramid(pl, cost, ws, st);
     if (rc != BP_OK) return rc;

@@ -116,6 +116,12 @@ __device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& 
         h.t = ph.t;
         h.K = a.K;
         h.mode = MODE;
+        if constexpr (G <= kNarrowMaxG) {
+            if (a.narrow) {
+                halfstep_pixel<G, MODE, SRC, true>(h, (int)gi, lane);
+                return;
+            }
+        }
         halfstep_pixel<G, MODE, SRC>(h, (int)gi, lane);
     } else {
         wta_pixel<G>(Q.c[0], Q.m[0], Q.vol[0], Q.lv[0], Q.D, Q.disparity, gi, lane);

@@ -33,6 +33,22 @@ __device__ __forceinline__ int4 pack8(const int o[8])
     return v;
 }
 
+// The same for the internal costs and messages, which are never negative: zero-extended
+// (the finest scale's internal cost uses the whole u16 range).
+__device__ __forceinline__ void unpack8u(const int4 v, int o[8])
+{
+    o[0] = v.x & 0xffff; o[1] = (int)((unsigned)v.x >> 16);
+    o[2] = v.y & 0xffff; o[3] = (int)((unsigned)v.y >> 16);
+    o[4] = v.z & 0xffff; o[5] = (int)((unsigned)v.z >> 16);
+    o[6] = v.w & 0xffff; o[7] = (int)((unsigned)v.w >> 16);
+}
+
+__device__ __forceinline__ int4 pack8u(const unsigned o[8])
+{
+    return make_int4((int)((o[0] & 0xffffu) | (o[1] << 16)), (int)((o[2] & 0xffffu) | (o[3] << 16)),
+                     (int)((o[4] & 0xffffu) | (o[5] << 16)), (int)((o[6] & 0xffffu) | (o[7] << 16)));
+}
+
 // Label j of a packed vector of 8 non-negative int16 values.
 __device__ __forceinline__ int msg_at(const int4 v, int j)
 {
@@ -247,6 +263,148 @@ __device__ __forceinline__ void transform2(const int ha[8], const int hb[8], int
     outb = make_int4((int)wb[0], (int)wb[1], (int)wb[2], (int)wb[3]);
 }
 
+// ---- the narrow path: whole message sums in packed 16-bit ----
+//
+// Every scale's internal cost is min-normalised per pixel (min over d = 0): the finest
+// scale holds cost - min_d cost as u16 (0..65535), coarser scales the pyramid's values
+// (0..32767).  Incoming messages are transform outputs in [0, C], C = capv.  Then the sums
+// h_k = cost + (the three other incoming messages) can be formed with saturating 16-bit
+// adds when C <= 16383, and every message is still exact: the minimum of h_k is at most
+// 3C (take the label where the cost is 0), far below 65535, so it is never a saturated
+// value; a label whose sum saturated has h - min h >= 65535 - 3C >= C, so it clips to C
+// exactly as its true value would.  The message is then the envelope of
+// x = min(h - min h, C), as in transform2.
+//
+// Lane mapping: a pixel keeps its G lanes.  With G = 1 the one lane computes both packed
+// pairs (messages 0 and 1, messages 2 and 3) over its 8 labels.  With G >= 2 the pixel's
+// lanes are split between the pairs: lanes [0, G/2) compute messages 0 and 1 and lanes
+// [G/2, G) messages 2 and 3, each lane over 16 consecutive labels (two 16-byte vectors),
+// label group g = lane % (G/2).  Each lane thus runs one envelope chain per pass over its
+// labels, and a pixel of D <= 16 needs no lane exchange at all.
+
+// Vectors per lane, pair and first label of a lane on the narrow path.
+template <int G>
+struct NarrowLane {
+    static constexpr int NV = G == 1 ? 1 : 2;  // 16-byte vectors of labels per lane
+    static constexpr int GL = G == 1 ? 1 : G / 2;  // lanes of one pair
+    int q;   // the lane's pair (G >= 2): messages 2q, 2q + 1
+    int g;   // label group inside the pair
+    int d0;  // first label
+    __device__ __forceinline__ explicit NarrowLane(int lane)
+    {
+        q = G == 1 ? 0 : lane / GL;
+        g = G == 1 ? 0 : lane % GL;
+        d0 = G == 1 ? 0 : 16 * g;
+    }
+};
+
+// Minimum of n packed values as a tree (independent mins issue back to back; a linear
+// chain of dependent packed ops costs a wait state each).
+template <int N>
+__device__ __forceinline__ u16x2 pk_min_tree(const u16x2* v)
+{
+    if constexpr (N == 1) return v[0];
+    else return pk_min(pk_min_tree<N / 2>(v), pk_min_tree<N - N / 2>(v + N / 2));
+}
+
+__device__ __forceinline__ unsigned word_of(const int4 v, int u)
+{
+    return (unsigned)(u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w);
+}
+
+// Messages a and b (one packed pair) of one pixel over a lane's NV vectors of labels,
+// GL lanes per pair: h_a = cost + m1 + m2 + mb, h_b = cost + m1 + m2 + ma, where ma, mb are
+// the pair's own incoming messages and m1, m2 the other pair's.  Outputs in memory order.
+template <int GL, int NV>
+__device__ __forceinline__ void narrow_pair(const int4 (&c)[NV], const int4 (&ma)[NV], const int4 (&mb)[NV],
+                                            const int4 (&m1)[NV], const int4 (&m2)[NV], int D, int d0, bool pad,
+                                            unsigned lam, unsigned capv, int g, int4 (&outa)[NV], int4 (&outb)[NV])
+{
+    constexpr int NJ = 8 * NV;
+    u16x2 x[NJ];  // label j of a in the low half, of b in the high half
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const u16x2 o = pk_adds(as_pk(word_of(c[v], u)), pk_adds(as_pk(word_of(m1[v], u)), as_pk(word_of(m2[v], u))));
+            const unsigned ha = pk_bits(pk_adds(o, as_pk(word_of(mb[v], u))));
+            const unsigned hb = pk_bits(pk_adds(o, as_pk(word_of(ma[v], u))));
+            x[8 * v + 2 * u] = as_pk(__builtin_amdgcn_perm(hb, ha, 0x05040100u));
+            x[8 * v + 2 * u + 1] = as_pk(__builtin_amdgcn_perm(hb, ha, 0x07060302u));
+        }
+    }
+    if (pad) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) x[j] = as_pk(pk_bits(x[j]) | (d0 + j < D ? 0u : 0xffffffffu));
+    }
+    u16x2 mn = pk_min_tree<NJ>(x);
+    if constexpr (GL > 1) {
+        mn = pk_min(mn, as_pk((unsigned)lanes_xor<GL, 1>((int)pk_bits(mn))));
+        if constexpr (GL > 2) mn = pk_min(mn, as_pk((unsigned)lanes_xor<GL, 2>((int)pk_bits(mn))));
+        if constexpr (GL > 4) mn = pk_min(mn, as_pk((unsigned)lanes_xor<GL, 4>((int)pk_bits(mn))));
+        if constexpr (GL > 8) mn = pk_min(mn, as_pk((unsigned)lanes_xor<GL, 8>((int)pk_bits(mn))));
+    }
+    const u16x2 C = pk_splat(capv), L = pk_splat(min(lam, 65535u));
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) x[j] = pk_min(x[j] - mn, C);  // x >= mn: no wrap
+    // forward pass, with the carry from the pair's lanes before this one
+    if constexpr (GL > 1) {
+        u16x2 last = x[0];
+#pragma unroll
+        for (int j = 1; j < NJ; ++j) last = pk_min(x[j], pk_adds(last, L));
+        const u16x2 cs = pk_scan_up<GL>(last, (unsigned)NJ * lam, g);
+        u16x2 cin = as_pk((unsigned)lanes_up<GL, 1>((int)pk_bits(cs)));
+        if (g == 0) cin = pk_splat(0xffffu);  // no carry: 65535 + lam saturates and never wins
+        x[0] = pk_min(x[0], pk_adds(cin, L));
+    }
+#pragma unroll
+    for (int j = 1; j < NJ; ++j) x[j] = pk_min(x[j], pk_adds(x[j - 1], L));
+    // backward pass
+    if constexpr (GL > 1) {
+        u16x2 first = x[NJ - 1];
+#pragma unroll
+        for (int j = NJ - 2; j >= 0; --j) first = pk_min(x[j], pk_adds(first, L));
+        const u16x2 cs = pk_scan_down<GL>(first, (unsigned)NJ * lam, g);
+        u16x2 cb = as_pk((unsigned)lanes_down<GL, 1>((int)pk_bits(cs)));
+        if (g == GL - 1) cb = pk_splat(0xffffu);
+        x[NJ - 1] = pk_min(x[NJ - 1], pk_adds(cb, L));
+    }
+#pragma unroll
+    for (int j = NJ - 2; j >= 0; --j) x[j] = pk_min(x[j], pk_adds(x[j + 1], L));
+    // back to memory order: word u of message a = low halves of labels 2u, 2u+1
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        unsigned wa[4], wb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = 8 * v + 2 * u;
+            wa[u] = __builtin_amdgcn_perm(pk_bits(x[j + 1]), pk_bits(x[j]), 0x05040100u);
+            wb[u] = __builtin_amdgcn_perm(pk_bits(x[j + 1]), pk_bits(x[j]), 0x07060302u);
+        }
+        outa[v] = make_int4((int)wa[0], (int)wa[1], (int)wa[2], (int)wa[3]);
+        outb[v] = make_int4((int)wb[0], (int)wb[1], (int)wb[2], (int)wb[3]);
+    }
+}
+
+// The outgoing messages a lane computes on the narrow path.  c and m are the lane's NV
+// vectors of the cost and of the incoming messages (zero where there is no neighbour), at
+// labels [nl.d0, nl.d0 + 8 NV), the messages in the lane's role order: m[0], m[1] its own
+// pair's (2q, 2q + 1), m[2], m[3] the other pair's.  out[e] is the message 2q + e it sends
+// (with G = 1, q = 0 and all four), in memory order.
+template <int G>
+__device__ __forceinline__ void narrow_update(const NarrowLane<G>& nl, const int4 (&c)[NarrowLane<G>::NV],
+                                              const int4 (&m)[4][NarrowLane<G>::NV], int D, bool pad, unsigned lam,
+                                              unsigned capv, int4 (&out)[4][NarrowLane<G>::NV])
+{
+    constexpr int NV = NarrowLane<G>::NV, GL = NarrowLane<G>::GL;
+    narrow_pair<GL, NV>(c, m[0], m[1], m[2], m[3], D, nl.d0, pad, lam, capv, nl.g, out[0], out[1]);
+    if constexpr (G == 1) narrow_pair<1, NV>(c, m[2], m[3], m[0], m[1], D, nl.d0, pad, lam, capv, 0, out[2], out[3]);
+}
+
+// Message volume of role r for a lane that computes messages 2 and 3 (hi) or 0 and 1: its
+// own pair first, then the other pair.
+__device__ __forceinline__ int role_msg(bool hi, int r) { return hi ? (r + 2) & 3 : r; }
+
 // Mask of the real labels (d < D) of this lane's four packed words.
 __device__ __forceinline__ int4 label_mask(int d0, int D)
 {
@@ -311,6 +469,23 @@ __device__ __forceinline__ void init_pixel(const int16_t* __restrict__ parent, L
     }
 }
 
+// The finest scale's internal cost of one pixel (lane's 8 labels of the caller's values v):
+// cost - min_d cost over the real labels, as u16 (always 0..65535); padded labels hold 0.
+// Messages and the winner are unchanged by a per-pixel shift of the cost, and with every
+// scale min-normalised the narrow path's packed sums stay exact.
+template <int G>
+__device__ __forceinline__ int4 finest_internal(const int v[8], int d0, int D)
+{
+    int mn = kBig;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) if (d0 + j < D) mn = min(mn, v[j]);
+    mn = group_min<G>(mn);
+    unsigned o[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o[j] = d0 + j < D ? (unsigned)(v[j] - mn) : 0u;
+    return pack8u(o);
+}
+
 // What a half-step body reports about its pixel, for the counters.
 struct PixOut {
     bool act;     // the pixel was updated
@@ -364,7 +539,8 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
 #pragma unroll
                             for (int j = 0; j < 8; ++j) v[j] = (d0 + j < D) ? (int)src[j] : 0;
                         }
-                        *reinterpret_cast<int4*>(cs[0] + slot_of(x, y, l0.Wh) * Dp + d0) = pack8(v);
+                        *reinterpret_cast<int4*>(cs[0] + slot_of(x, y, l0.Wh) * Dp + d0) =
+                            finest_internal<G>(v, d0, D);
 #pragma unroll
                         for (int j = 0; j < 8; ++j) s[j] += v[j];
                     }
@@ -435,10 +611,19 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
 // Skip mode 1 resets a pixel's state at its first update of the scale (t < 2).
 // Handles pixel gi of the scale's colour-a.colour pixels with lane `lane` of its G lanes;
 // returns whether it was updated and which neighbours it has (for the counters).
-template <int G, int MODE, int SRC>
+template <int G, int MODE, int SRC, bool NARROW = false>
 __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, int lane)
 {
     constexpr int Dp = 8 * G;
+    constexpr int NV = NARROW ? NarrowLane<G>::NV : 1;  // label vectors a lane reads per volume
+    constexpr int GL = NARROW ? NarrowLane<G>::GL : G;  // lanes that share one message
+    constexpr int NK = NARROW && G > 1 ? 2 : 4;         // messages a lane sends
+    const NarrowLane<G> nl(lane);
+    const int d0 = NARROW ? nl.d0 : lane * 8;
+    const int glane = NARROW ? nl.g : lane;
+    // incoming volumes in the lane's role order (identity unless the lane computes the
+    // second pair on the narrow path)
+    const bool hi = NARROW && G > 1 && nl.q != 0;
     const int W = a.lv.W, H = a.lv.H, Wh = a.lv.Wh;
     const bool in = gi < H * Wh;
     const int y = in ? gi / Wh : 0;
@@ -453,71 +638,104 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
                              (long long)(2 * (y + 1) + 1 - a.colour) * Wh + (x >> 1)};
     bool act = valid;
     if (MODE == 2 || (MODE == 1 && a.t >= 2)) act = act && a.state_a[slot] != 0;
-    const int d0 = lane * 8;
-    // incoming messages stay packed (two int16 per register, values in [0, 32767])
-    int Hs[8];
-    int4 mp[4];
+    bool hr[4];
+    long long nbr[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) mp[k] = make_int4(0, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) {
+        hr[r] = hi ? has[(r + 2) & 3] : has[r];
+        nbr[r] = hi ? nb[(r + 2) & 3] : nb[r];
+    }
+    // incoming messages stay packed (two int16 per register, values in [0, 32767])
+    int4 c4[NV], mp[4][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        c4[v] = make_int4(0, 0, 0, 0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) mp[k][v] = make_int4(0, 0, 0, 0);
+    }
     if (act) {
-        unpack8(*reinterpret_cast<const int4*>(a.cost + slot * Dp + d0), Hs);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) c4[v] = *reinterpret_cast<const int4*>(a.cost + slot * Dp + d0 + 8 * v);
         if (SRC == kSrcOwn) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (has[k]) mp[k] = *reinterpret_cast<const int4*>(a.msgs + k * a.vol + slot * Dp + d0);
+            for (int r = 0; r < 4; ++r)
+                if (hr[r])
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+                        mp[r][v] = *reinterpret_cast<const int4*>(a.msgs + role_msg(hi, r) * a.vol + slot * Dp + d0 +
+                                                                  8 * v);
         } else if (SRC == kSrcParent) {
             const int px = x >> 1, py = y >> 1;
             const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
             const long long ps = (long long)(2 * py + ((px + py) & 1)) * a.plv.Wh + (px >> 1);
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (has[k] && phas[k]) mp[k] = *reinterpret_cast<const int4*>(a.pmsgs + k * a.pvol + ps * Dp + d0);
-        }
-    } else {
+            for (int r = 0; r < 4; ++r)
+                if (hr[r] && (hi ? phas[(r + 2) & 3] : phas[r]))
 #pragma unroll
-        for (int j = 0; j < 8; ++j) Hs[j] = 0;
+                    for (int v = 0; v < NV; ++v)
+                        mp[r][v] = *reinterpret_cast<const int4*>(a.pmsgs + role_msg(hi, r) * a.pvol + ps * Dp + d0 +
+                                                                  8 * v);
+        }
     }
     const bool check = (MODE == 2) || (MODE == 1 && a.t >= 2);
-    // the outgoing messages this update may overwrite, loaded together with the incoming
-    // ones (nothing else writes them during the half-step), so the four compare-and-store
-    // steps below do not each wait for a load
-    int4 op[4];
+    // The messages this lane sends: all four, or with the pairs split the two of its pair
+    // (k = 2q + e).  The outgoing values this update may overwrite are loaded together with
+    // the incoming ones (nothing else writes them during the half-step), so the compares
+    // below do not each wait for a load.
+    int4 op[NK][NV];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        op[k] = make_int4(0, 0, 0, 0);
-        if (check && act && has[k])
-            op[k] = *reinterpret_cast<const int4*>(a.msgs + (k ^ 1) * a.vol + nb[k] * Dp + d0);
-    }
+    for (int e = 0; e < NK; ++e)
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-        Hs[j] = (d0 + j < a.D) ? Hs[j] + msg_at(mp[0], j) + msg_at(mp[1], j) + msg_at(mp[2], j) + msg_at(mp[3], j)
-                               : kBig;
+        for (int v = 0; v < NV; ++v) {
+            op[e][v] = make_int4(0, 0, 0, 0);
+            if (check && act && hr[e])
+                op[e][v] = *reinterpret_cast<const int4*>(a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0 +
+                                                          8 * v);
+        }
     if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;
+    int4 out[4][NV];
+    if constexpr (NARROW) {
+        narrow_update<G>(nl, c4, mp, a.D, a.D < Dp, (unsigned)a.lambda, (unsigned)a.capv, out);
+    } else {
+        int Hs[8];
+        unpack8u(c4[0], Hs);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            Hs[j] = (d0 + j < a.D) ? Hs[j] + msg_at(mp[0][0], j) + msg_at(mp[1][0], j) + msg_at(mp[2][0], j) +
+                                         msg_at(mp[3][0], j)
+                                   : kBig;
+#pragma unroll
+        for (int k = 0; k < 4; k += 2) {
+            int ha[8], hb[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                ha[j] = Hs[j] - msg_at(mp[k][0], j);
+                hb[j] = Hs[j] - msg_at(mp[k + 1][0], j);
+            }
+            transform2<G>(ha, hb, a.lambda, a.capv, lane, out[k][0], out[k + 1][0]);
+        }
+    }
     bool all_eq = true;
-    const int4 lmask = label_mask(d0, a.D);
-    int4 out[4];
 #pragma unroll
-    for (int k = 0; k < 4; k += 2) {
-        int ha[8], hb[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            ha[j] = Hs[j] - msg_at(mp[k], j);
-            hb[j] = Hs[j] - msg_at(mp[k + 1], j);
-        }
-        transform2<G>(ha, hb, a.lambda, a.capv, lane, out[k], out[k + 1]);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        bool store = act && has[k];
-        int16_t* dst = a.msgs + (k ^ 1) * a.vol + nb[k] * Dp + d0;
+    for (int e = 0; e < NK; ++e) {
+        bool store = act && hr[e];
+        int16_t* dst = a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0;
         if (check) {
-            const int e = group_min<G>(same_labels(op[k], out[k], lmask) ? 1 : 0);
-            if (store && !e) all_eq = false;
-            if (e) store = false;
-            if (MODE == 2 && store && lane == 0) a.state_a[nb[k]] = 1;
+            bool same = true;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) same = same && same_labels(op[e][v], out[e][v], label_mask(d0 + 8 * v, a.D));
+            const int eq = group_min<GL>(same ? 1 : 0);  // the GL lanes of the message
+            if (store && !eq) all_eq = false;
+            if (eq) store = false;
+            if (MODE == 2 && store && glane == 0) a.state_a[nbr[e]] = 1;
         }
-        if (store) *reinterpret_cast<int4*>(dst) = out[k];
+        if (store) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) *reinterpret_cast<int4*>(dst + 8 * v) = out[e][v];
+        }
     }
+    // the freeze state needs all four messages: combine the pixel's lanes
+    if (NARROW && G > 1 && MODE == 1 && check) all_eq = group_min<G>(all_eq ? 1 : 0) != 0;
     if (MODE == 1 && act && lane == 0) {
         if (a.t < 2) {
             a.state_a[slot] = 1;
@@ -549,12 +767,12 @@ __device__ __forceinline__ void wta_pixel(const int16_t* __restrict__ c0, const 
     const bool has[4] = {p.x > 0, p.x < lv.W - 1, p.y > 0, p.y < lv.H - 1};
     int b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (valid) {
-        unpack8(*reinterpret_cast<const int4*>(c0 + gi * Dp + d0), b);
+        unpack8u(*reinterpret_cast<const int4*>(c0 + gi * Dp + d0), b);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (has[k]) {
                 int v[8];
-                unpack8(*reinterpret_cast<const int4*>(msgs + k * vol + gi * Dp + d0), v);
+                unpack8u(*reinterpret_cast<const int4*>(msgs + k * vol + gi * Dp + d0), v);
 #pragma unroll
                 for (int j = 0; j < 8; ++j) b[j] += v[j];
             }

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_level0(const int16_t* __restr
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = (d0 + j < D) ? (int)src[j] : 0;
     }
-    *reinterpret_cast<int4*>(c0 + gi * (8 * G) + d0) = pack8(v);
+    *reinterpret_cast<int4*>(c0 + gi * (8 * G) + d0) = finest_internal<G>(v, d0, D);
 }
 
 template <int G>
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kThreads) void k_pyramid(const int16_t* __restrict_
                 int x = 2 * p.x + a, y = 2 * p.y + b;
                 if (x < lf.W && y < lf.H) {
                     int v[8];
-                    unpack8(*reinterpret_cast<const int4*>(fine + slot_of(x, y, lf.Wh) * (8 * G) + d0), v);
+                    unpack8u(*reinterpret_cast<const int4*>(fine + slot_of(x, y, lf.Wh) * (8 * G) + d0), v);
 #pragma unroll
                     for (int j = 0; j < 8; ++j) s[j] += v[j];
                 }
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void k_import(const int16_t* __restrict__
 // left without work leave at once (a tile with no active pixel loads nothing), the others
 // update only active pixels.  Updates of one colour are independent, so the order does not
 // change any result.
-template <int G, int MODE, int SRC, bool COUNT>
+template <int G, int MODE, int SRC, bool COUNT, bool NARROW>
 __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
 {
     constexpr int kPix = kThreads / G;  // pixels of one tile
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
         if (!COUNT && (threadIdx.x & ~63) >= total * G) return;  // the whole wave has no pixel
         gi = threadIdx.x < total * G ? blockIdx.x * kPix + list[threadIdx.x / G] : (int)npix;  // npix: no pixel
     }
-    const PixOut r = halfstep_pixel<G, MODE, SRC>(a, gi, lane);
+    const PixOut r = halfstep_pixel<G, MODE, SRC, NARROW>(a, gi, lane);
     if (COUNT) {
         __shared__ int cnt[2];
         if (threadIdx.x == 0) { cnt[0] = 0; cnt[1] = 0; }
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void k_export(const int16_t* __restrict__
     const bool has[4] = {p.x > 0, p.x < lv.W - 1, p.y > 0, p.y < lv.H - 1};
     for (int k = 0; k < 4; ++k) {
         int v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (has[k]) unpack8(*reinterpret_cast<const int4*>(msgs + k * vol + gi * (8 * G) + d0), v);
+        if (has[k]) unpack8u(*reinterpret_cast<const int4*>(msgs + k * vol + gi * (8 * G) + d0), v);
         int16_t* dst = out + (((long long)k * lv.H + p.y) * lv.W + p.x) * D + d0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) if (d0 + j < D) dst[j] = (int16_t)v[j];
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_export_cost(const int16_t* __restr
     if (!p.valid) return;
     const int d0 = lane * 8;
     int v[8];
-    unpack8(*reinterpret_cast<const int4*>(c + gi * (8 * G) + d0), v);
+    unpack8u(*reinterpret_cast<const int4*>(c + gi * (8 * G) + d0), v);
     int16_t* dst = out + ((long long)p.y * lv.W + p.x) * D + d0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) if (d0 + j < D) dst[j] = (int16_t)v[j];
@@ -382,17 +382,25 @@ hipError_t launch_import(const int16_t* warm, int16_t* msgs, Level lv, long long
     return hipGetLastError();
 }
 
-template <int MODE, int SRC, bool COUNT>
+template <int MODE, int SRC, bool COUNT, bool NARROW>
 static hipError_t launch_halfstep_t(const HalfstepArgs& a, unsigned g, hipStream_t st)
 {
-    BPST_DISPATCH_G(a.G, hipLaunchKernelGGL((k_halfstep<GG, MODE, SRC, COUNT>), dim3(g), dim3(kThreads), 0, st, a));
+    // the narrow variant exists for G <= kNarrowMaxG only
+    BPST_DISPATCH_G(a.G, if constexpr (!NARROW || GG <= kNarrowMaxG) hipLaunchKernelGGL(
+                             (k_halfstep<GG, MODE, SRC, COUNT, NARROW>), dim3(g), dim3(kThreads), 0, st, a);
+                         else return hipErrorInvalidValue);
     return hipGetLastError();
 }
 
 template <int MODE, int SRC>
 static hipError_t launch_halfstep_c(const HalfstepArgs& a, unsigned g, hipStream_t st)
 {
-    return a.count ? launch_halfstep_t<MODE, SRC, true>(a, g, st) : launch_halfstep_t<MODE, SRC, false>(a, g, st);
+    if (a.count) return launch_halfstep_t<MODE, SRC, true, false>(a, g, st);  // no narrow counting variant
+    if (a.narrow) {
+        if (a.capv < 0 || a.capv > kNarrowCap) return hipErrorInvalidValue;
+        return launch_halfstep_t<MODE, SRC, false, true>(a, g, st);
+    }
+    return launch_halfstep_t<MODE, SRC, false, false>(a, g, st);
 }
 
 template <int MODE>

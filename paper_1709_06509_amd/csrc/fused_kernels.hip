@@ -44,7 +44,7 @@ __device__ __forceinline__ Region region_of(const FusedArgs& a)
     return g;
 }
 
-template <int G, int MODE>
+template <int G, int MODE, bool NARROW>
 __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
 {
     constexpr int Dp = 8 * G;
@@ -97,11 +97,19 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
     // 2. the half-steps, one colour each.  Thread e handles lane e % G of pixel e / G of the
     //    colour's row-major list (RWc a row), and every blockDim.x / G pixels after it; the
     //    (row, index) pair advances by a fixed step instead of being divided out each time.
+    //    On the narrow path the pixel's lanes split its two message pairs (NarrowLane).
     const int RWc = (g.RW + 1) >> 1;  // pixels of one colour in a region row (at most)
     const int npix = g.RH * RWc;
     const int lane = threadIdx.x & (G - 1);
-    const int d0 = lane * 8;
-    const int4 lmask = label_mask(d0, a.D);
+    constexpr int NV = NARROW ? NarrowLane<G>::NV : 1;  // label vectors a lane reads per volume
+    constexpr int GL = NARROW ? NarrowLane<G>::GL : G;  // lanes that share one message
+    const NarrowLane<G> nl(lane);
+    const int d0 = NARROW ? nl.d0 : lane * 8;
+    const bool hi = NARROW && G > 1 && nl.q != 0;  // the lane computes messages 2 and 3
+    int4 lmask[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) lmask[v] = label_mask(d0 + 8 * v, a.D);
+    const bool pad = a.D < Dp;
     const int pstep = blockDim.x / G, step_ry = pstep / RWc, step_i = pstep - step_ry * RWc;
     const int p_first = threadIdx.x / G;
     const int ry_first = p_first / RWc, i_first = p_first - ry_first * RWc;
@@ -162,51 +170,93 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
             const bool has[4] = {x > 0, x < W - 1, y > 0, y < H - 1};
             const bool inreg[4] = {rx > 0, rx < g.RW - 1, ry > 0, ry < g.RH - 1};
             const int nbr[4] = {r - 1, r + 1, r - g.RW, r + g.RW};
+            // incoming volumes in the lane's role order (identity unless the lane computes the
+            // second pair on the narrow path): own pair first, then the other pair
+            bool hr[4], ir[4];
+            int nr[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                hr[q] = hi ? has[(q + 2) & 3] : has[q];
+                ir[q] = hi ? inreg[(q + 2) & 3] : inreg[q];
+                nr[q] = hi ? nbr[(q + 2) & 3] : nbr[q];
+            }
             // every LDS read is issued unconditionally from a valid address and masked after,
             // so the loads of a pixel overlap instead of waiting on each other's branches
             const long long rr = valid ? r : 0;
-            const int4 c4 = *reinterpret_cast<const int4*>(lc + rr * Dp + d0);
-            int4 mp[4], op[4];
+            int4 c4[NV], mp[4][NV];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const bool tk = valid && has[k] && inreg[k];
-                mp[k] = *reinterpret_cast<const int4*>(lm + k * cap * Dp + rr * Dp + d0);
-                op[k] = *reinterpret_cast<const int4*>(lm + (k ^ 1) * cap * Dp + (tk ? (long long)nbr[k] : rr) * Dp + d0);
-                if (!has[k]) mp[k] = make_int4(0, 0, 0, 0);
-                if (!(check && tk)) op[k] = make_int4(0, 0, 0, 0);
+            for (int v = 0; v < NV; ++v) c4[v] = *reinterpret_cast<const int4*>(lc + rr * Dp + d0 + 8 * v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    mp[q][v] = *reinterpret_cast<const int4*>(lm + role_msg(hi, q) * cap * Dp + rr * Dp + d0 + 8 * v);
+                    if (!hr[q]) mp[q][v] = make_int4(0, 0, 0, 0);
+                }
             }
             const bool act = valid && (!check || lsa[rr] != 0);
-            int Hs[8];
-            unpack8(c4, Hs);
+            int4 out[4][NV];
+            if constexpr (NARROW) {
+                narrow_update<G>(nl, c4, mp, a.D, pad, (unsigned)a.lambda, (unsigned)a.capv, out);
+            } else {
+                int Hs[8];
+                unpack8u(c4[0], Hs);
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                Hs[j] = (d0 + j < a.D) ? Hs[j] + msg_at(mp[0], j) + msg_at(mp[1], j) + msg_at(mp[2], j) +
-                                             msg_at(mp[3], j)
-                                       : kBig;
-            bool all_eq = true;
-            int4 out[4];
+                for (int j = 0; j < 8; ++j)
+                    Hs[j] = (d0 + j < a.D) ? Hs[j] + msg_at(mp[0][0], j) + msg_at(mp[1][0], j) +
+                                                 msg_at(mp[2][0], j) + msg_at(mp[3][0], j)
+                                           : kBig;
 #pragma unroll
-            for (int k = 0; k < 4; k += 2) {
-                int ha[8], hb[8];
+                for (int k = 0; k < 4; k += 2) {
+                    int ha[8], hb[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    ha[j] = Hs[j] - msg_at(mp[k], j);
-                    hb[j] = Hs[j] - msg_at(mp[k + 1], j);
+                    for (int j = 0; j < 8; ++j) {
+                        ha[j] = Hs[j] - msg_at(mp[k][0], j);
+                        hb[j] = Hs[j] - msg_at(mp[k + 1][0], j);
+                    }
+                    transform2<G>(ha, hb, a.lambda, a.capv, lane, out[k][0], out[k + 1][0]);
                 }
-                transform2<G>(ha, hb, a.lambda, a.capv, lane, out[k], out[k + 1]);
             }
+            // The messages this lane sends: all four, or with the pairs split the two of its
+            // pair (k = 2q + e; out[e] holds them).  Under the freeze rule the receivers'
+            // previous values are read here, after the transform, so that they do not hold
+            // registers through it.
+            constexpr int NK = NARROW && G > 1 ? 2 : 4;
+            int4 op[NK][NV];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                bool store = act && has[k] && inreg[k];
+            for (int e = 0; e < NK; ++e) {
+                const bool tk = valid && hr[e] && ir[e];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    op[e][v] = make_int4(0, 0, 0, 0);
+                    if (check)
+                        op[e][v] = *reinterpret_cast<const int4*>(lm + (role_msg(hi, e) ^ 1) * cap * Dp +
+                                                                  (tk ? (long long)nr[e] : rr) * Dp + d0 + 8 * v);
+                }
+            }
+            bool all_eq = true;
+#pragma unroll
+            for (int e = 0; e < NK; ++e) {
+                bool store = act && hr[e] && ir[e];
                 if (check) {
                     // a receiver outside the region is not held: its compare is skipped, which
                     // only affects pixels on the region's cut edge (never exact past step 0)
-                    const int eq = group_min<G>(same_labels(op[k], out[k], lmask) ? 1 : 0);
+                    bool same = true;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) same = same && same_labels(op[e][v], out[e][v], lmask[v]);
+                    const int eq = group_min<GL>(same ? 1 : 0);  // the GL lanes of the message
                     if (store && !eq) all_eq = false;
                     if (eq) store = false;
                 }
-                if (store) *reinterpret_cast<int4*>(lm + (k ^ 1) * cap * Dp + (long long)nbr[k] * Dp + d0) = out[k];
+                if (store) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+                        *reinterpret_cast<int4*>(lm + (role_msg(hi, e) ^ 1) * cap * Dp + (long long)nr[e] * Dp + d0 +
+                                                 8 * v) = out[e][v];
+                }
             }
+            // the freeze state needs all four messages: combine the pixel's lanes
+            if (NARROW && G > 1 && check) all_eq = group_min<G>(all_eq ? 1 : 0) != 0;
             if (MODE == 1 && act && lane == 0) {
                 if (t < 2) {
                     lsa[r] = 1;
@@ -300,6 +350,13 @@ double fused_us(const Level& lv, int G, int iters, int steps, int TW, int TH)
     return launches * (rounds * (4.0 + steps * pass) + traffic);
 }
 
+bool fused_narrow_pays(int G, long long rmax)
+{
+    (void)G;
+    (void)rmax;
+    return true;
+}
+
 namespace {
 bool fused_search(const Level& lv, int G, int iters, int* steps, int* TW, int* TH, long long* rmax);
 }
@@ -390,7 +447,9 @@ bool fused_geometry_max(const Level& lv, int G, int steps, int* TW, int* TH, lon
 template <int G, int MODE>
 void set_lds_attr()
 {
-    (void)hipFuncSetAttribute((const void*)k_fused<G, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_fused<G, MODE, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kFusedLdsBytes);
+    (void)hipFuncSetAttribute((const void*)k_fused<G, MODE, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kFusedLdsBytes);
 }
 
@@ -418,12 +477,18 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t st)
     const int tiles = a.tiles_x * ((a.lv.H + a.TH - 1) / a.TH);
     const size_t lds = fused_lds_bytes(a.G, a.rmax);
     if (lds > (size_t)kFusedLdsBytes || a.halo != a.nsteps || a.nsteps < 1) return hipErrorInvalidValue;
+    if (a.narrow && (a.capv < 0 || a.capv > kNarrowCap)) return hipErrorInvalidValue;
     fused_prepare();
     const dim3 grid((unsigned)tiles), block((unsigned)fused_threads(a.G, a.rmax));
 #define BPST_FUSED_G(GG)                                                                        \
     case GG:                                                                                    \
-        if (a.mode == 1) hipLaunchKernelGGL((k_fused<GG, 1>), grid, block, lds, st, a);         \
-        else hipLaunchKernelGGL((k_fused<GG, 0>), grid, block, lds, st, a);                     \
+        if (a.narrow) {                                                                         \
+            if (a.mode == 1) hipLaunchKernelGGL((k_fused<GG, 1, true>), grid, block, lds, st, a);  \
+            else hipLaunchKernelGGL((k_fused<GG, 0, true>), grid, block, lds, st, a);              \
+        } else {                                                                                \
+            if (a.mode == 1) hipLaunchKernelGGL((k_fused<GG, 1, false>), grid, block, lds, st, a); \
+            else hipLaunchKernelGGL((k_fused<GG, 0, false>), grid, block, lds, st, a);             \
+        }                                                                                       \
         break;
     switch (a.G) {
         BPST_FUSED_G(1) BPST_FUSED_G(2) BPST_FUSED_G(4) BPST_FUSED_G(8)

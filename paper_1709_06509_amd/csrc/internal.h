@@ -56,6 +56,7 @@ struct HalfstepArgs {
     int lambda;
     int capv;                // min(lambda * min(T, D), 32767): clamp of a normalised message
     int colour, t, K, mode, source, count;
+    int narrow;              // packed 16-bit sums (no counters): see the narrow path in bp_device.h
     DevStats* stats;
     int level;
 };
@@ -118,6 +119,7 @@ struct BatchArgs {
     int npairs, nphases, L;
     int lambda, capv, K, mode;
     int order;                // 0: chunk = workgroup index; 1: the workgroups of one XCD take adjacent chunks
+    int narrow;               // half-steps on the narrow path (pairs with G <= kNarrowMaxG; capv <= kNarrowCap)
     int gmax;                 // largest lanes-per-pixel among the pairs (selects a leaner kernel when <= 8)
     unsigned* barrier;        // 10 words: per-XCD-group arrivals, group arrivals, generation
     int* error;               // set when a grid barrier times out
@@ -141,8 +143,20 @@ struct FusedArgs {
     int TW, TH, halo, tiles_x;
     long long rmax;          // region pixels the LDS holds: (TW + 2 halo) (TH + 2 halo)
     int keep_state;          // write the freeze state back (later half-steps of the scale follow)
+    int narrow;              // packed 16-bit sums: incoming messages in [0, capv], capv <= kNarrowCap
 };
 constexpr int kFusedLdsBytes = 160 * 1024;
+// Largest capv for which the packed 16-bit message sums are exact: with every cost
+// min-normalised per pixel, a sum that saturates at 65535 is still at least capv above the
+// minimum (at most 3 capv), so it clips to capv as its true value would.
+constexpr int kNarrowCap = 16383;
+// Widest pixel (lanes) a one-per-half-step launch takes the narrow path for.  Wider pixels
+// are large disparity ranges, whose half-steps stream far more memory than they compute:
+// there the narrow path's doubled vector loads per lane cost more than its arithmetic saves.
+constexpr int kNarrowMaxG = 8;
+// Whether the narrow path is expected to be faster in a fused launch whose region holds
+// rmax pixels (it lowers the work per lane; small regions are bound by other costs).
+bool fused_narrow_pays(int G, long long rmax);
 // Half-steps per fused launch and interior tile for `iters` half-steps on scale lv, chosen
 // by a cost model; false if one launch per half-step is estimated to be faster.
 bool fused_geometry(const Level& lv, int G, int iters, int* steps, int* TW, int* TH, long long* rmax);

@@ -124,7 +124,7 @@ def test_every_schedule_gives_the_same_result(skip):
     batch = B.Batch(lefts, rights, Ds, params)
     ctx = B.Context()
     ref = None
-    for sched, bpc, order in [(1, 1, 0), (0, 1, 0), (0, 1, 1), (0, 2, 0), (0, 3, 1)]:
+    for sched, bpc, order in [(1, 1, 0), (2, 1, 0), (0, 1, 0), (0, 1, 1), (0, 2, 0), (0, 3, 1)]:
         say(f"schedule {sched} bpc {bpc} order {order} skip {skip}")
         B.set_batch_schedule(ctx, sched, bpc, order)
         for d in batch.disps:
@@ -139,3 +139,27 @@ def test_every_schedule_gives_the_same_result(skip):
                 assert torch.equal(batch.costs[i], c) and torch.equal(got[i], d), f"pair {i}"
         else:
             assert all(torch.equal(a, b) for a, b in zip(got, ref))
+
+
+@pytest.mark.parametrize("skip", [0, 1, 2])
+def test_batch_narrow_schedule_matches_oracle(skip):
+    """Schedule 2 (one launch per phase, packed 16-bit message sums where a pair's pixel
+    spans at most 8 lanes) against the oracle, with pairs of every lane width: D = 5 and 8
+    (one lane), 16 and 24 (two, four), 64 (eight) and 128 (sixteen lanes: the int32 path)."""
+    shapes = [(40, 32, 16), (33, 21, 64), (48, 40, 8), (70, 22, 5), (24, 24, 24), (26, 18, 128)]
+    pairs = []
+    for i, (W, H, D) in enumerate(shapes):
+        p = synth.make_pair(W, H, D, (3, 5), False, 0, False, seed=700 + i)
+        pairs.append((p["left"], p["right"], D))
+    params = B.make_batch_params(5, 3, [6, 5, 4], 64, 4, skip_mode=skip)
+    say(f"narrow schedule, batch of {len(pairs)} small pairs, skip={skip}")
+    batch = B.Batch([gpu(l) for l, _, _ in pairs], [gpu(r) for _, r, _ in pairs], [D for _, _, D in pairs], params)
+    ctx = B.Context()
+    B.set_batch_schedule(ctx, 2)
+    batch.solve(ctx)
+    assert batch.status() == 0
+    for i, (l, r, D) in enumerate(pairs):
+        c = oracle.cost_volume(l, r, D, 5)
+        assert np.array_equal(host(batch.costs[i]), c), f"pair {i} cost"
+        d, _, _ = oracle.bp_solve(c, 3, [6, 5, 4], 64, 4, skip, 2, want_msgs=False)
+        assert np.array_equal(host(batch.disps[i]), d), f"pair {i} disparity"

@@ -127,3 +127,49 @@ def test_fused_modes_agree_on_production_pair():
         ctx.close()
     for d, m in outs[1:]:
         assert np.array_equal(d, outs[0][0]) and np.array_equal(m, outs[0][1])
+
+
+# The packed 16-bit message sums (scales above the finest, capv <= 10922): at the limit the
+# sums reach 32767 + 3 * 10922 = 65533, one past it the int32 path runs instead.
+@pytest.mark.parametrize("lam,T", [(10922, 1), (10923, 1), (5461, 2), (64, 4)])
+def test_fused_packed_sums_at_the_limit(lam, T, fused_ctx):
+    os.environ["BPSTEREO_FUSED_TILE"] = "5x4"
+    rng = np.random.default_rng(lam + T)
+    cost = rng.integers(20000, 32768, (27, 35, 16)).astype(np.int16)  # coarse costs saturate
+    say(f"fused packed-sum limit lam={lam} T={T}")
+    for skip in (0, 1):
+        d, m, _ = B.bp_hierarchical_solve(gpu(cost), 4, [6, 6, 6, 6], lam, T, skip, 2, want_msgs=True, ctx=fused_ctx)
+        rd, rm, _ = oracle.bp_solve(cost, 4, [6, 6, 6, 6], lam, T, skip, 2)
+        assert np.array_equal(host(m), rm) and np.array_equal(host(d), rd)
+
+
+@pytest.mark.parametrize("warm_iters", [0, 1, 2])
+def test_fused_warm_values_beyond_capv(warm_iters, fused_ctx):
+    """Warm messages far above capv: the warm scale reads them on the int32 path, and with
+    fewer than two half-steps there they also reach the finer scales, which then stay off the
+    packed path."""
+    os.environ["BPSTEREO_FUSED_TILE"] = "4x4"
+    W, H, D, L = 34, 26, 16, 4
+    cost = cost_of(W, H, D, 91)
+    hs, ws = H, W
+    for _ in range(L - 2):
+        hs, ws = (hs + 1) // 2, (ws + 1) // 2
+    warm = np.random.default_rng(warm_iters).integers(0, 32768, (4, hs, ws, D)).astype(np.int16)
+    iters = [5, 4, warm_iters, 0]
+    say(f"fused warm start, warm-scale half-steps {warm_iters}")
+    for skip in (0, 1):
+        d, m, _ = B.bp_hierarchical_solve(gpu(cost), L, iters, 64, 4, skip, 2, warm_msgs=gpu(warm), want_msgs=True,
+                                          ctx=fused_ctx)
+        rd, rm, _ = oracle.bp_solve(cost, L, iters, 64, 4, skip, 2, warm_msgs=warm)
+        assert np.array_equal(host(m), rm) and np.array_equal(host(d), rd)
+
+
+def test_fused_negative_finest_costs(fused_ctx):
+    os.environ["BPSTEREO_FUSED_TILE"] = "6x5"
+    rng = np.random.default_rng(17)
+    cost = rng.integers(-32768, 32768, (23, 31, 16)).astype(np.int16)
+    say("fused, negative finest costs")
+    for skip in (0, 1):
+        d, m, _ = B.bp_hierarchical_solve(gpu(cost), 3, [6, 6, 6], 64, 4, skip, 2, want_msgs=True, ctx=fused_ctx)
+        rd, rm, _ = oracle.bp_solve(cost, 3, [6, 6, 6], 64, 4, skip, 2)
+        assert np.array_equal(host(m), rm) and np.array_equal(host(d), rd)
