@@ -60,36 +60,61 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
     int* llist = reinterpret_cast<int*>(lsb + ((cap + 3) & ~3LL));  // active pixels of a half-step
     const int R = g.RW * g.RH;
 
-    // 1. load the region: cost, incoming messages (own, parent's or zero), freeze state
-    for (int e = threadIdx.x; e < R * G; e += blockDim.x) {
-        const int r = e / G, lane = e - r * G;
-        const int ry = r / g.RW, rx = r - ry * g.RW;
-        const int x = g.rx0 + rx, y = g.ry0 + ry;
-        const long long slot = slot_of(x, y, Wh);
-        const int d0 = lane * 8;
-        *reinterpret_cast<int4*>(lc + (long long)r * Dp + d0) =
-            *reinterpret_cast<const int4*>(a.cost + slot * Dp + d0);
-        const bool has[4] = {x > 0, x < W - 1, y > 0, y < H - 1};
-        int4 m[4];
+    // 1. load the region: cost, incoming messages (own, parent's or zero), freeze state.  A
+    //    thread takes two elements per round and issues all their global loads before any
+    //    LDS store, so the round costs one memory latency, not two.
+    constexpr int kU = 2;
+    for (int e0 = threadIdx.x; e0 < R * G; e0 += kU * blockDim.x) {
+        int4 cv[kU], mv[kU][4];
+        uint8_t sav[kU], sbv[kU];
+        int rv[kU];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) m[k] = make_int4(0, 0, 0, 0);
-        if (a.source == kSrcOwn) {
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + u * (int)blockDim.x;
+            const bool in = e < R * G;
+            const int ee = in ? e : 0;
+            const int r = ee / G, lane = ee - r * G;
+            const int ry = r / g.RW, rx = r - ry * g.RW;
+            const int x = g.rx0 + rx, y = g.ry0 + ry;
+            const long long slot = slot_of(x, y, Wh);
+            const int d0 = lane * 8;
+            rv[u] = in ? r : -1;
+            cv[u] = in ? *reinterpret_cast<const int4*>(a.cost + slot * Dp + d0) : make_int4(0, 0, 0, 0);
+            const bool has[4] = {x > 0, x < W - 1, y > 0, y < H - 1};
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (has[k]) m[k] = *reinterpret_cast<const int4*>(a.msgs + k * a.vol + slot * Dp + d0);
-        } else if (a.source == kSrcParent) {
-            const int px = x >> 1, py = y >> 1;
-            const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
-            const long long ps = slot_of(px, py, a.plv.Wh);
+            for (int k = 0; k < 4; ++k) mv[u][k] = make_int4(0, 0, 0, 0);
+            if (in && a.source == kSrcOwn) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (has[k] && phas[k]) m[k] = *reinterpret_cast<const int4*>(a.pmsgs + k * a.pvol + ps * Dp + d0);
+                for (int k = 0; k < 4; ++k)
+                    if (has[k]) mv[u][k] = *reinterpret_cast<const int4*>(a.msgs + k * a.vol + slot * Dp + d0);
+            } else if (in && a.source == kSrcParent) {
+                const int px = x >> 1, py = y >> 1;
+                const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
+                const long long ps = slot_of(px, py, a.plv.Wh);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (has[k] && phas[k])
+                        mv[u][k] = *reinterpret_cast<const int4*>(a.pmsgs + k * a.pvol + ps * Dp + d0);
+            }
+            sav[u] = 1;
+            sbv[u] = 0;
+            if (MODE == 1 && in && lane == 0 && a.t0 >= 2) {
+                sav[u] = a.state_a[slot];
+                sbv[u] = a.state_b[slot];
+            }
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) *reinterpret_cast<int4*>(lm + k * cap * Dp + (long long)r * Dp + d0) = m[k];
-        if (MODE == 1 && lane == 0) {
-            lsa[r] = a.t0 >= 2 ? a.state_a[slot] : (uint8_t)1;
-            lsb[r] = a.t0 >= 2 ? a.state_b[slot] : (uint8_t)0;
+        for (int u = 0; u < kU; ++u) {
+            const int r = rv[u];
+            if (r < 0) continue;
+            const int d0 = (e0 + u * (int)blockDim.x - r * G) * 8;
+            *reinterpret_cast<int4*>(lc + (long long)r * Dp + d0) = cv[u];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) *reinterpret_cast<int4*>(lm + k * cap * Dp + (long long)r * Dp + d0) = mv[u][k];
+            if (MODE == 1 && d0 == 0) {
+                lsa[r] = sav[u];
+                lsb[r] = sbv[u];
+            }
         }
     }
     __syncthreads();

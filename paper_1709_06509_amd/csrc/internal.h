@@ -57,6 +57,7 @@ struct HalfstepArgs {
     int capv;                // min(lambda * min(T, D), 32767): clamp of a normalised message
     int colour, t, K, mode, source, count;
     int narrow;              // packed 16-bit sums (no counters): see the narrow path in bp_device.h
+    int spec;                // narrow path: load every pixel's data without waiting for its state
     DevStats* stats;
     int level;
 };
@@ -154,6 +155,8 @@ constexpr int kNarrowCap = 16383;
 // are large disparity ranges, whose half-steps stream far more memory than they compute:
 // there the narrow path's doubled vector loads per lane cost more than its arithmetic saves.
 constexpr int kNarrowMaxG = 8;
+// Estimated device time (us) of `iters` one-per-half-step launches on scale lv.
+double per_launch_us(const Level& lv, int G, int iters);
 // Whether the narrow path is expected to be faster in a fused launch whose region holds
 // rmax pixels (it lowers the work per lane; small regions are bound by other costs).
 bool fused_narrow_pays(int G, long long rmax);

@@ -248,10 +248,13 @@ def test_graph_forced_failure_falls_back(monkeypatch):
 @pytest.mark.parametrize("skip", [1, 2])
 def test_compacted_halfsteps_without_counters(skip):
     """The freeze rule and the exact skip compact active pixels per tile; without counters idle
-    waves leave early.  One launch per half-step (fused launches off) against the oracle."""
+    waves leave early.  One launch per half-step (fused launches off) against the oracle.
+    Small scales load every pixel's data at once instead (latency-bound launches); the two
+    larger images keep compaction on their finest scale."""
     ctx = B.Context()
     ctx.set_fused(0)
-    for (H, W, D, L, iters) in [(61, 83, 16, 3, [9, 8, 7]), (40, 57, 24, 2, [12, 10]), (33, 35, 64, 2, [8, 6])]:
+    for (H, W, D, L, iters) in [(61, 83, 16, 3, [9, 8, 7]), (40, 57, 24, 2, [12, 10]), (33, 35, 64, 2, [8, 6]),
+                                (320, 512, 16, 2, [6, 4]), (160, 256, 64, 2, [5, 3])]:
         say(f"compacted skip={skip} {W}x{H} D={D} L={L} iters={iters}")
         p = synth.make_pair(W, H, D, (3, 5), True, 0, False, seed=300 + W)
         cost = oracle.cost_volume(p["left"], p["right"], D, 5)
