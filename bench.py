@@ -156,7 +156,7 @@ def run_batched(args):
         status = batch.status(stream)
         best = tune["candidates"][tune["best"]]
         timing = None
-        if best["schedule"] == 1:
+        if best["schedule"] in (1, 2):
             # the dominant kernel's own time: the same batch launched eagerly, a HIP event pair
             # on the launch stream around every half-step phase
             ctx.set_graphs(False)
@@ -179,7 +179,8 @@ def run_batched(args):
         launches = timing["halfstep_launches"] // timing["solves"]
         avg_launch_s = timing["halfstep_ms"] / 1e3 / timing["halfstep_launches"]
         per_launch = byts / launches
-        kernel = "k_batch_phase, half-step phases (one launch per phase, every pair's tiles)"
+        kernel = ("k_batch_phase, half-step phases (one launch per phase, every pair's tiles"
+                  + ("; packed sums on scales that fit the caches)" if best["schedule"] == 2 else ")"))
     else:
         launches, avg_launch_s, per_launch = 1, best["ms"] / 1e3, byts
         kernel = (f"k_batch_solve (one persistent launch, {best['blocks_per_cu']} workgroups/CU; "

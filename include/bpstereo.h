@@ -231,8 +231,9 @@ int32_t bp_batch_status(const void* workspace, void* stream, int32_t* status);
 typedef struct {
     int32_t n_candidates;
     int32_t schedule[16];      /* 0: one persistent launch; 1: one launch per phase (no grid barrier);
-                                  2: as 1, the half-steps with packed 16-bit message sums (offered
-                                  when lambda * trunc <= 16383; results are identical) */
+                                  2: as 1, with packed 16-bit message sums in the half-steps of
+                                  scales that fit the caches (offered when lambda * trunc <= 16383;
+                                  results are identical) */
     int32_t blocks_per_cu[16]; /* persistent launch: resident workgroups per compute unit */
     int32_t order[16];         /* 0: tiles dealt round-robin; 1: one contiguous eighth per XCD */
     float ms[16];              /* device time of the candidate's solve */

@@ -479,9 +479,13 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
             a.t = t;
             a.colour = t & 1;
             a.source = (t == 0) ? source : bpst::kSrcOwn;
-            a.narrow = narrow_ok(l, t) && !count && pl.G <= bpst::kNarrowMaxG ? 1 : 0;
-            // where a half-step's traffic is small enough that its launch is bound by latency,
-            // load every pixel's data together with its state instead of compacting first
+            // Scales too large for the caches stream their volumes (nontemporal accesses) on
+            // the int32 path; the narrow path's lower arithmetic pays where memory does not
+            // bound the launch.  Where a half-step's traffic is small enough that its launch is
+            // bound by latency, every pixel loads its data together with its state instead of
+            // compacting first.
+            a.stream = bpst::stream_scale(pl.lv[l], pl.G) ? 1 : 0;
+            a.narrow = narrow_ok(l, t) && !count && pl.G <= bpst::kNarrowMaxG && !a.stream ? 1 : 0;
             a.spec = bpst::per_launch_us(pl.lv[l], pl.G, 1) <= kSpecLatencyUs ? 1 : 0;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (ctx && ctx->timing) {
@@ -670,18 +674,26 @@ int32_t plan_batch(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* 
         b.max_d = std::max(b.max_d, d.num_disp);
         b.gmax = std::max(b.gmax, b.plans[i].G);
     }
+    // half-steps of a scale stream their volumes when all pairs' working sets together exceed
+    // the caches (see stream_scale)
+    int stream[bpst::kMaxScales] = {0};
+    for (int l = 0; l < b.L; ++l) {
+        double bytes = 0;
+        for (int i = 0; i < n; ++i) bytes += 5.0 * (double)b.plans[i].lv[l].slots() * 8 * b.plans[i].G * 2;
+        stream[l] = bytes > bpst::kStreamBytes ? 1 : 0;
+    }
     // phase sequence (the same as a single solve without a warm start)
-    b.phases.push_back({bpst::kPhPyramid, 0, 0, 0, 0});
+    b.phases.push_back({bpst::kPhPyramid, 0, 0, 0, 0, 0});
     for (int l = b.L - 1; l >= 0; --l) {
         const bool fuse = p->iters[l] >= 2 && p->skip_mode != 2;
-        if (!fuse) b.phases.push_back({bpst::kPhInit, l, 0, bpst::kSrcOwn, 0});
+        if (!fuse) b.phases.push_back({bpst::kPhInit, l, 0, bpst::kSrcOwn, 0, 0});
         for (int t = 0; t < p->iters[l]; ++t) {
             int src = bpst::kSrcOwn;
             if (t == 0 && fuse) src = (l == b.L - 1) ? bpst::kSrcZero : bpst::kSrcParent;
-            b.phases.push_back({bpst::kPhHalfstep, l, t, src, 0});
+            b.phases.push_back({bpst::kPhHalfstep, l, t, src, 0, stream[l]});
         }
     }
-    b.phases.push_back({bpst::kPhWta, 0, 0, 0, 0});
+    b.phases.push_back({bpst::kPhWta, 0, 0, 0, 0, 0});
     b.nphases = (int)b.phases.size();
     b.tiles.assign((size_t)b.nphases * (n + 1), 0);
     for (int ph = 0; ph < b.nphases; ++ph) {
@@ -880,8 +892,10 @@ int32_t enqueue_batch_solve(bp_context* ctx, const BatchPlan& b, const bp_batch_
                 if (rc != BP_OK) return rc;
                 HIP_TRY(hipEventRecord(e0, st));
             }
+            // streamed phases stay on the int32 path (the narrow path pays only off the memory bound)
+            const int hv = d.stream ? bpst::kHvStream : (a.narrow ? bpst::kHvNarrow : 0);
             HIP_TRY(bpst::launch_batch_phase(a, ph, d.type, d.source, b.tiles[(size_t)ph * (b.n + 1) + b.n],
-                                             b.lds, st));
+                                             b.lds, hv, st));
             if (e1) HIP_TRY(hipEventRecord(e1, st));
         }
         return BP_OK;

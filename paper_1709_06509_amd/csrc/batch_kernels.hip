@@ -78,7 +78,11 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs& a, int* s_ok)
 }
 
 // One tile of a phase whose type (and half-step message source) is known at compile time.
-template <int G, int MODE, int TYPE, int SRC>
+// HV: the half-step variant, fixed at compile time for one-phase launches (bit 0 narrow
+// path, bit 1 streamed volumes) or -1 to read it from the arguments (persistent launch).
+constexpr int kHvRuntime = -1;
+
+template <int G, int MODE, int TYPE, int SRC, int HV = kHvRuntime>
 __device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& ph, const PairDev& Q, int lt,
                                            int* lds)
 {
@@ -116,13 +120,20 @@ __device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& 
         h.t = ph.t;
         h.K = a.K;
         h.mode = MODE;
-        if constexpr (G <= kNarrowMaxG) {
-            if (a.narrow) {
-                halfstep_pixel<G, MODE, SRC, true>(h, (int)gi, lane);
-                return;
+        if constexpr (HV == kHvRuntime) {
+            if constexpr (G <= kNarrowMaxG) {
+                if (a.narrow && !ph.stream) {
+                    halfstep_pixel<G, MODE, SRC, true>(h, (int)gi, lane);
+                    return;
+                }
             }
+            if (ph.stream) halfstep_pixel<G, MODE, SRC, false, false, true>(h, (int)gi, lane);
+            else halfstep_pixel<G, MODE, SRC>(h, (int)gi, lane);
+        } else {
+            // pixels wider than kNarrowMaxG lanes stay on the int32 path
+            constexpr bool N = (HV & kHvNarrow) != 0 && G <= kNarrowMaxG;
+            halfstep_pixel<G, MODE, SRC, N, false, (HV & kHvStream) != 0>(h, (int)gi, lane);
         }
-        halfstep_pixel<G, MODE, SRC>(h, (int)gi, lane);
     } else {
         wta_pixel<G>(Q.c[0], Q.m[0], Q.vol[0], Q.lv[0], Q.D, Q.disparity, gi, lane);
     }
@@ -205,7 +216,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 
 // The other schedule: one launch per phase, one workgroup per tile of every pair.  The
 // kernel boundary orders the phases, so no grid barrier is needed.
-template <int MODE, int GMAX, int TYPE, int SRC>
+template <int MODE, int GMAX, int TYPE, int SRC, int HV>
 __global__ __launch_bounds__(kThreads) void k_batch_phase(BatchArgs a, int phase)
 {
     extern __shared__ int lds[];
@@ -216,50 +227,65 @@ __global__ __launch_bounds__(kThreads) void k_batch_phase(BatchArgs a, int phase
     const PairDev& Q = a.pairs[q];
     const int lt = tile - ts[q];
     switch (Q.G) {
-    case 1: run_tile_t<1, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
-    case 2: run_tile_t<2, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
-    case 4: run_tile_t<4, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
-    case 8: run_tile_t<8, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
-    case 16: if (GMAX >= 16) run_tile_t<16, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
-    default: if (GMAX >= 32) run_tile_t<32, MODE, TYPE, SRC>(a, ph, Q, lt, lds); break;
+    case 1: run_tile_t<1, MODE, TYPE, SRC, HV>(a, ph, Q, lt, lds); break;
+    case 2: run_tile_t<2, MODE, TYPE, SRC, HV>(a, ph, Q, lt, lds); break;
+    case 4: run_tile_t<4, MODE, TYPE, SRC, HV>(a, ph, Q, lt, lds); break;
+    case 8: run_tile_t<8, MODE, TYPE, SRC, HV>(a, ph, Q, lt, lds); break;
+    case 16: if (GMAX >= 16) run_tile_t<16, MODE, TYPE, SRC, HV>(a, ph, Q, lt, lds); break;
+    default: if (GMAX >= 32) run_tile_t<32, MODE, TYPE, SRC, HV>(a, ph, Q, lt, lds); break;
     }
 }
 
-template <int MODE, int GMAX>
-static void launch_phase_m(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, hipStream_t st)
+template <int MODE, int GMAX, int HV>
+static void launch_phase_v(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, hipStream_t st)
 {
     const dim3 g((unsigned)tiles), b(kThreads);
     switch (type) {
-    case kPhPyramid: hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhPyramid, kSrcOwn>), g, b, lds, st, a, phase); break;
-    case kPhInit: hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhInit, kSrcOwn>), g, b, 0, st, a, phase); break;
+    case kPhPyramid:
+        hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhPyramid, kSrcOwn, 0>), g, b, lds, st, a, phase);
+        break;
+    case kPhInit: hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhInit, kSrcOwn, 0>), g, b, 0, st, a, phase); break;
     case kPhHalfstep:
         if (src == kSrcParent)
-            hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcParent>), g, b, 0, st, a, phase);
+            hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcParent, HV>), g, b, 0, st, a, phase);
         else if (src == kSrcZero)
-            hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcZero>), g, b, 0, st, a, phase);
+            hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcZero, HV>), g, b, 0, st, a, phase);
         else
-            hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcOwn>), g, b, 0, st, a, phase);
+            hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcOwn, HV>), g, b, 0, st, a, phase);
         break;
-    default: hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhWta, kSrcOwn>), g, b, 0, st, a, phase); break;
+    default: hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhWta, kSrcOwn, 0>), g, b, 0, st, a, phase); break;
+    }
+}
+
+// hv: the half-step variant (kHvNarrow | kHvStream bits), fixed per launch
+template <int MODE, int GMAX>
+static void launch_phase_m(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, int hv,
+                           hipStream_t st)
+{
+    switch (hv) {
+    case kHvNarrow: launch_phase_v<MODE, GMAX, kHvNarrow>(a, phase, type, src, tiles, lds, st); break;
+    case kHvStream: launch_phase_v<MODE, GMAX, kHvStream>(a, phase, type, src, tiles, lds, st); break;
+    default: launch_phase_v<MODE, GMAX, 0>(a, phase, type, src, tiles, lds, st); break;
     }
 }
 
 }  // namespace
 
-hipError_t launch_batch_phase(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, hipStream_t st)
+hipError_t launch_batch_phase(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, int hv,
+                              hipStream_t st)
 {
     if (tiles <= 0) return hipSuccess;
     if (a.gmax <= 8) {
         switch (a.mode) {
-        case 0: launch_phase_m<0, 8>(a, phase, type, src, tiles, lds, st); break;
-        case 1: launch_phase_m<1, 8>(a, phase, type, src, tiles, lds, st); break;
-        default: launch_phase_m<2, 8>(a, phase, type, src, tiles, lds, st); break;
+        case 0: launch_phase_m<0, 8>(a, phase, type, src, tiles, lds, hv, st); break;
+        case 1: launch_phase_m<1, 8>(a, phase, type, src, tiles, lds, hv, st); break;
+        default: launch_phase_m<2, 8>(a, phase, type, src, tiles, lds, hv, st); break;
         }
     } else {
         switch (a.mode) {
-        case 0: launch_phase_m<0, 32>(a, phase, type, src, tiles, lds, st); break;
-        case 1: launch_phase_m<1, 32>(a, phase, type, src, tiles, lds, st); break;
-        default: launch_phase_m<2, 32>(a, phase, type, src, tiles, lds, st); break;
+        case 0: launch_phase_m<0, 32>(a, phase, type, src, tiles, lds, hv, st); break;
+        case 1: launch_phase_m<1, 32>(a, phase, type, src, tiles, lds, hv, st); break;
+        default: launch_phase_m<2, 32>(a, phase, type, src, tiles, lds, hv, st); break;
         }
     }
     return hipGetLastError();

@@ -171,6 +171,32 @@ __device__ __forceinline__ void transform(const int h[8], int lam, int capv, int
     for (int j = 0; j < 8; ++j) out[j] = min(f[j] - hm, capv);
 }
 
+// 16-byte loads and stores of a half-step, with the nontemporal hint where the scale's
+// volumes are far larger than the caches (they are streamed once per half-step, and the
+// hint keeps them from evicting anything useful); plain where they stay cache-resident
+// from one half-step to the next.
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+template <bool STREAM>
+__device__ __forceinline__ int4 ld16(const int16_t* p)
+{
+    if constexpr (STREAM) {
+        const v4i_t v = __builtin_nontemporal_load(reinterpret_cast<const v4i_t*>(p));
+        return make_int4(v.x, v.y, v.z, v.w);
+    } else {
+        return *reinterpret_cast<const int4*>(p);
+    }
+}
+template <bool STREAM>
+__device__ __forceinline__ void st16(int16_t* p, const int4 v)
+{
+    if constexpr (STREAM) {
+        const v4i_t w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<v4i_t*>(p));
+    } else {
+        *reinterpret_cast<int4*>(p) = v;
+    }
+}
+
 // ---- two messages at once in packed 16-bit halves ----
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
@@ -614,7 +640,8 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
 // SPEC: load the pixel's data whether or not the freeze state turns out active, so that the
 // state and data loads overlap (for scales small enough that the extra bytes are cheaper
 // than a second memory latency); results are the same.
-template <int G, int MODE, int SRC, bool NARROW = false, bool SPEC = false>
+// STREAM: the scale's volumes are streamed (nontemporal loads and stores, see ld16).
+template <int G, int MODE, int SRC, bool NARROW = false, bool SPEC = false, bool STREAM = false>
 __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, int lane)
 {
     constexpr int Dp = 8 * G;
@@ -659,15 +686,14 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
     }
     if (ld) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) c4[v] = *reinterpret_cast<const int4*>(a.cost + slot * Dp + d0 + 8 * v);
+        for (int v = 0; v < NV; ++v) c4[v] = ld16<STREAM>(a.cost + slot * Dp + d0 + 8 * v);
         if (SRC == kSrcOwn) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 if (hr[r])
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
-                        mp[r][v] = *reinterpret_cast<const int4*>(a.msgs + role_msg(hi, r) * a.vol + slot * Dp + d0 +
-                                                                  8 * v);
+                        mp[r][v] = ld16<STREAM>(a.msgs + role_msg(hi, r) * a.vol + slot * Dp + d0 + 8 * v);
         } else if (SRC == kSrcParent) {
             const int px = x >> 1, py = y >> 1;
             const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
@@ -677,8 +703,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
                 if (hr[r] && (hi ? phas[(r + 2) & 3] : phas[r]))
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
-                        mp[r][v] = *reinterpret_cast<const int4*>(a.pmsgs + role_msg(hi, r) * a.pvol + ps * Dp + d0 +
-                                                                  8 * v);
+                        mp[r][v] = ld16<STREAM>(a.pmsgs + role_msg(hi, r) * a.pvol + ps * Dp + d0 + 8 * v);
         }
     }
     const bool check = (MODE == 2) || (MODE == 1 && a.t >= 2);
@@ -693,8 +718,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
         for (int v = 0; v < NV; ++v) {
             op[e][v] = make_int4(0, 0, 0, 0);
             if (check && ld && hr[e])
-                op[e][v] = *reinterpret_cast<const int4*>(a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0 +
-                                                          8 * v);
+                op[e][v] = ld16<STREAM>(a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0 + 8 * v);
         }
     if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;
     int4 out[4][NV];
@@ -735,7 +759,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
         }
         if (store) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) *reinterpret_cast<int4*>(dst + 8 * v) = out[e][v];
+            for (int v = 0; v < NV; ++v) st16<STREAM>(dst + 8 * v, out[e][v]);
         }
     }
     // the freeze state needs all four messages: combine the pixel's lanes

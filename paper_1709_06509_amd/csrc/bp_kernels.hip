@@ -126,9 +126,14 @@ __global__ __launch_bounds__(kThreads) void k_import(const int16_t* __restrict__
 // left without work leave at once (a tile with no active pixel loads nothing), the others
 // update only active pixels.  Updates of one colour are independent, so the order does not
 // change any result.
-template <int G, int MODE, int SRC, bool COUNT, bool NARROW, bool SPEC>
+// Variant flags of k_halfstep.
+constexpr int kHsCount = 1, kHsNarrow = 2, kHsSpec = 4, kHsStream = 8;
+
+template <int G, int MODE, int SRC, int FL>
 __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
 {
+    constexpr bool COUNT = (FL & kHsCount) != 0, NARROW = (FL & kHsNarrow) != 0, SPEC = (FL & kHsSpec) != 0,
+                   STREAM = (FL & kHsStream) != 0;
     constexpr int kPix = kThreads / G;  // pixels of one tile
     const int lane = threadIdx.x & (G - 1);
     int gi = blockIdx.x * kPix + threadIdx.x / G;
@@ -160,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
         if (!COUNT && (threadIdx.x & ~63) >= total * G) return;  // the whole wave has no pixel
         gi = threadIdx.x < total * G ? blockIdx.x * kPix + list[threadIdx.x / G] : (int)npix;  // npix: no pixel
     }
-    const PixOut r = halfstep_pixel<G, MODE, SRC, NARROW, SPEC>(a, gi, lane);
+    const PixOut r = halfstep_pixel<G, MODE, SRC, NARROW, SPEC, STREAM>(a, gi, lane);
     if (COUNT) {
         __shared__ int cnt[2];
         if (threadIdx.x == 0) { cnt[0] = 0; cnt[1] = 0; }
@@ -384,12 +389,12 @@ hipError_t launch_import(const int16_t* warm, int16_t* msgs, Level lv, long long
     return hipGetLastError();
 }
 
-template <int MODE, int SRC, bool COUNT, bool NARROW, bool SPEC>
+template <int MODE, int SRC, int FL>
 static hipError_t launch_halfstep_t(const HalfstepArgs& a, unsigned g, hipStream_t st)
 {
     // the narrow variants exist for G <= kNarrowMaxG only
-    BPST_DISPATCH_G(a.G, if constexpr (!NARROW || GG <= kNarrowMaxG) hipLaunchKernelGGL(
-                             (k_halfstep<GG, MODE, SRC, COUNT, NARROW, SPEC>), dim3(g), dim3(kThreads), 0, st, a);
+    BPST_DISPATCH_G(a.G, if constexpr ((FL & kHsNarrow) == 0 || GG <= kNarrowMaxG) hipLaunchKernelGGL(
+                             (k_halfstep<GG, MODE, SRC, FL>), dim3(g), dim3(kThreads), 0, st, a);
                          else return hipErrorInvalidValue);
     return hipGetLastError();
 }
@@ -397,14 +402,15 @@ static hipError_t launch_halfstep_t(const HalfstepArgs& a, unsigned g, hipStream
 template <int MODE, int SRC>
 static hipError_t launch_halfstep_c(const HalfstepArgs& a, unsigned g, hipStream_t st)
 {
-    if (a.count) return launch_halfstep_t<MODE, SRC, true, false, false>(a, g, st);  // no narrow counting variant
+    if (a.count) return launch_halfstep_t<MODE, SRC, kHsCount>(a, g, st);  // no narrow counting variant
     if (a.narrow) {
         if (a.capv < 0 || a.capv > kNarrowCap) return hipErrorInvalidValue;
         // speculative loads only matter where pixels can be inactive
-        if (a.spec && (MODE == 2 || MODE == 1)) return launch_halfstep_t<MODE, SRC, false, true, true>(a, g, st);
-        return launch_halfstep_t<MODE, SRC, false, true, false>(a, g, st);
+        if (a.spec && (MODE == 2 || MODE == 1)) return launch_halfstep_t<MODE, SRC, kHsNarrow | kHsSpec>(a, g, st);
+        return launch_halfstep_t<MODE, SRC, kHsNarrow>(a, g, st);
     }
-    return launch_halfstep_t<MODE, SRC, false, false, false>(a, g, st);
+    if (a.stream) return launch_halfstep_t<MODE, SRC, kHsStream>(a, g, st);
+    return launch_halfstep_t<MODE, SRC, 0>(a, g, st);
 }
 
 template <int MODE>

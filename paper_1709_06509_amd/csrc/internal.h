@@ -58,6 +58,7 @@ struct HalfstepArgs {
     int colour, t, K, mode, source, count;
     int narrow;              // packed 16-bit sums (no counters): see the narrow path in bp_device.h
     int spec;                // narrow path: load every pixel's data without waiting for its state
+    int stream;              // nontemporal loads and stores (the scale's volumes exceed the caches)
     DevStats* stats;
     int level;
 };
@@ -110,7 +111,8 @@ enum PhaseType { kPhPyramid = 0, kPhInit = 1, kPhHalfstep = 2, kPhWta = 3 };
 // One phase of the batched solve; all pairs run it before any pair starts the next.
 struct PhaseDesc {
     int type, level, t, source;
-    int table;  // offset in BatchArgs::tiles of this phase's prefix sums (npairs + 1 ints)
+    int table;   // offset in BatchArgs::tiles of this phase's prefix sums (npairs + 1 ints)
+    int stream;  // half-step: the pairs' working sets at this scale together exceed the caches
 };
 
 struct BatchArgs {
@@ -155,6 +157,11 @@ constexpr int kNarrowCap = 16383;
 // are large disparity ranges, whose half-steps stream far more memory than they compute:
 // there the narrow path's doubled vector loads per lane cost more than its arithmetic saves.
 constexpr int kNarrowMaxG = 8;
+// Half-steps whose working set (the cost and the four message volumes) is larger than this
+// stream it with nontemporal loads and stores: it cannot stay in the 256 MB Infinity Cache
+// from one half-step to the next, and plain accesses would only evict what could.
+constexpr double kStreamBytes = 192e6;
+inline bool stream_scale(const Level& lv, int G) { return 5.0 * (double)lv.slots() * 8 * G * 2 > kStreamBytes; }
 // Estimated device time (us) of `iters` one-per-half-step launches on scale lv.
 double per_launch_us(const Level& lv, int G, int iters);
 // Whether the narrow path is expected to be faster in a fused launch whose region holds
@@ -205,7 +212,10 @@ hipError_t launch_batch_reset(unsigned* barrier, int* error, hipStream_t st);
 hipError_t batch_max_blocks_per_cu(int mode, int gmax, size_t lds, int* blocks);
 hipError_t launch_batch_solve(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 // One phase of the batch as its own launch: `tiles` workgroups, one per tile.
-hipError_t launch_batch_phase(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, hipStream_t st);
+// Half-step variant bits of a one-phase launch: the narrow path, streamed volumes.
+constexpr int kHvNarrow = 1, kHvStream = 2;
+hipError_t launch_batch_phase(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, int hv,
+                              hipStream_t st);
 
 // Launchers (return hipError_t of the launch).
 // launch_pyramid_tree: re-layout of the finest scale plus every coarser scale in one launch;

@@ -263,3 +263,17 @@ def test_compacted_halfsteps_without_counters(skip):
         assert np.array_equal(host(m), rm), "messages differ"
         assert np.array_equal(host(d), rd), "disparities differ"
     ctx.close()
+
+
+@pytest.mark.parametrize("H,W,D,skip", [(380, 420, 128, 1), (520, 600, 64, 2)])
+def test_streamed_halfsteps(H, W, D, skip):
+    """A finest scale whose cost and message volumes exceed 192 MB is streamed with
+    nontemporal loads and stores on the int32 path (the freeze rule at D = 128, the exact
+    skip at D = 64); its coarser scale takes the narrow path."""
+    rng = np.random.default_rng(H + W + D + skip)
+    cost = rng.integers(0, 1024, (H, W, D)).astype(np.int16)
+    say(f"streamed half-steps {W}x{H} D={D} skip={skip}")
+    d, m, _ = B.bp_hierarchical_solve(gpu(cost), 2, [2, 2], 64, 4, skip, 2, want_msgs=True)
+    rd, rm, _ = oracle.bp_solve(cost, 2, [2, 2], 64, 4, skip, 2)
+    assert np.array_equal(host(m), rm), "messages differ"
+    assert np.array_equal(host(d), rd), "disparities differ"
