@@ -51,19 +51,16 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
     const int uI0 = x0 - r, uJ0 = x0 - r - (D - 1);
     uint4* colI = reinterpret_cast<uint4*>(smem);
     uint4* colJ = colI + nI;
-    int* cI = reinterpret_cast<int*>(colJ + nJ);   // per-column sums
+    // per left column x: {window sum S_I, n S_II - S_I^2, its reciprocal square root (0 for a
+    // flat window), 0}; the same per right column u = x0-(D-1) ..: TX and TX + D - 1 entries,
+    // one 16-byte read each in the finishing loop
+    int4* QI = reinterpret_cast<int4*>(colJ + nJ);
+    int4* QJ = QI + TX;
+    int* cI = reinterpret_cast<int*>(QJ + TX + D - 1);  // per-column sums
     int* cII = cI + nI;
     int* cJ = cII + nI;
     int* cJJ = cJ + nJ;
-    // per left column x: window sum S_I, n S_II - S_I^2 and its reciprocal square root (0 for a
-    // flat window); the same per right column u = x0-(D-1) ..: TX and TX + D - 1 of each
-    int* SI = cJJ + nJ;
-    int* VI = SI + TX;
-    float* RI = reinterpret_cast<float*>(VI + TX);
-    int* SJ = reinterpret_cast<int*>(RI + TX);
-    int* VJ = SJ + TX + D - 1;
-    float* RJ = reinterpret_cast<float*>(VJ + TX + D - 1);
-    int* V = reinterpret_cast<int*>(RJ + TX + D - 1);  // [nI][D]
+    int* V = cJJ + nJ;  // [nI][D]
 
     // 1. packed byte columns of the window rows (clamped), zero beyond the window
     for (int c = threadIdx.x; c < nI + nJ; c += kThreads) {
@@ -97,14 +94,14 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
 #pragma unroll
         for (int k = 0; k < WIN; ++k) { s += cI[i + k]; ss += cII[i + k]; }
         const int v = n * ss - s * s;
-        SI[i] = s; VI[i] = v; RI[i] = v > 0 ? rsqrtf((float)v) : 0.0f;
+        QI[i] = make_int4(s, v, __float_as_int(v > 0 ? rsqrtf((float)v) : 0.0f), 0);
     }
     for (int i = threadIdx.x; i < TX + D - 1; i += kThreads) {
         int s = 0, ss = 0;
 #pragma unroll
         for (int k = 0; k < WIN; ++k) { s += cJ[i + k]; ss += cJJ[i + k]; }
         const int v = n * ss - s * s;
-        SJ[i] = s; VJ[i] = v; RJ[i] = v > 0 ? rsqrtf((float)v) : 0.0f;
+        QJ[i] = make_int4(s, v, __float_as_int(v > 0 ? rsqrtf((float)v) : 0.0f), 0);
     }
     // 3. column products V[u][d] = sum over the window rows of left(u) * right(u - d)
     const int du = kThreads / D, dd = kThreads - du * D;  // step of (u, d) per kThreads elements
@@ -127,56 +124,54 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
 
     // 4. finish every (x, d) of the tile.  Thread t takes disparity d = t mod D and a run of
     //    XR consecutive columns, sliding the horizontal window sum along the run (two LDS
-    //    reads per column instead of WIN); consecutive threads write consecutive d.
+    //    reads per column instead of WIN); consecutive threads write consecutive d.  The
+    //    loop body has no branch but the exact settle, which the wave takes only when one of
+    //    its lanes lies near a rounding boundary.
     const int tileW = min(TX, W - x0);
     const int tpd = D >= kThreads ? 1 : kThreads / D;  // runs per disparity
     const int XR = (TX + tpd - 1) / tpd;
     const int d = threadIdx.x % D, run = threadIdx.x / D;
     if (run < tpd) {
         const int i0 = run * XR, i1 = min(i0 + XR, tileW);
+        // the window's first WIN - 1 columns; each step adds its last column before use and
+        // drops its first after
         int sij = 0;
         if (i0 < i1) {
 #pragma unroll
-            for (int k = 0; k < WIN; ++k) sij += V[(i0 + k) * D + d];
+            for (int k = 0; k < WIN - 1; ++k) sij += V[(i0 + k) * D + d];
         }
-        for (int i = i0; i < i1; ++i) {
-            if (i > i0) sij += V[(i + WIN - 1) * D + d] - V[(i - 1) * D + d];
+        long long o = ((long long)y * W + x0 + i0) * D + d;
+        const float fscale = (float)scale;
+        for (int i = i0; i < i1; ++i, o += D) {
+            sij += V[(i + WIN - 1) * D + d];
+            const int drop = V[i * D + d];
             const int x = x0 + i;
-            const long long o = ((long long)y * W + x) * D + d;
-            if (x - d < 0) {
-                cost[o] = (int16_t)trunc;
-                if (ncc_out) ncc_out[o] = -2.0f;
-                continue;
-            }
+            const bool outside = x - d < 0;  // no right pixel: the truncation cost
             // window <= 13: every product and difference below fits in int32
-            const int u = i - d + (D - 1);
-            const int num = n * sij - SI[i] * SJ[u];
-            const int vi = VI[i], vj = VJ[u];
-            int k;  // |k| <= 2 * scale + 1 < 2^31
-            float nv;
-            if (vi == 0 || vj == 0) {
-                k = scale;
-                nv = 0.0f;
-            } else {
-                // fp32 estimate: c carries at most about 4 units of rounding (two conversions,
-                // two reciprocal roots of 1 ulp, two products), relative error below 5e-7, so
-                // |error of v| < 5e-7 * scale; within `margin` (>= 4e-6 * scale) of a rounding
-                // boundary the exact test decides
-                const float c = (float)num * (RI[i] * RJ[u]);
-                nv = c;
-                const float v = (float)scale * (1.0f - c) + 0.5f;
-                k = (int)floorf(v);
-                const float fr = v - (float)k;
-                if (fr < margin || fr > 1.0f - margin) {
-                    const unsigned long long P = (unsigned long long)vi * (unsigned long long)vj;
-                    const long long B = 2LL * scale * num;
-                    while (!le_times_sqrt(B, 2LL * scale - 2LL * k + 1, P)) --k;
-                    while (le_times_sqrt(B, 2LL * scale - 2LL * (k + 1) + 1, P)) ++k;
-                }
+            const int u = outside ? 0 : i - d + (D - 1);
+            const int4 qi = QI[i], qj = QJ[u];
+            const int num = n * sij - qi.x * qj.x;
+            const bool flat = qi.y == 0 || qj.y == 0;
+            // fp32 estimate: c carries at most about 4 units of rounding (two conversions,
+            // two reciprocal roots of 1 ulp, two products), relative error below 5e-7, so
+            // |error of v| < 5e-7 * scale; within `margin` (>= 4e-6 * scale) of a rounding
+            // boundary the exact test decides
+            const float c = (float)num * (__int_as_float(qi.z) * __int_as_float(qj.z));
+            const float v = fscale * (1.0f - c) + 0.5f;
+            int k = (int)floorf(v);
+            const float fr = v - (float)k;
+            const bool settle = !outside && !flat && (fr < margin || fr > 1.0f - margin);
+            if (settle) {
+                const unsigned long long P = (unsigned long long)qi.y * (unsigned long long)qj.y;
+                const long long B = 2LL * scale * num;
+                while (!le_times_sqrt(B, 2LL * scale - 2LL * k + 1, P)) --k;
+                while (le_times_sqrt(B, 2LL * scale - 2LL * (k + 1) + 1, P)) ++k;
             }
+            k = flat ? scale : k;
             k = k < 0 ? 0 : (k > trunc ? trunc : k);
-            cost[o] = (int16_t)k;
-            if (ncc_out) ncc_out[o] = nv;
+            cost[o] = (int16_t)(outside ? trunc : k);
+            if (ncc_out) ncc_out[o] = outside ? -2.0f : (flat ? 0.0f : c);
+            sij -= drop;
         }
     }
 }
@@ -218,8 +213,8 @@ size_t ncc_lds_bytes(int D, int win)
     const int r = win >> 1;
     const int TX = ncc_tile_x(D);
     const int nI = TX + 2 * r, nJ = TX + 2 * r + D - 1;
-    return (size_t)(nI + nJ) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 + (size_t)3 * TX * 4 +
-           (size_t)3 * (TX + D - 1) * 4 + (size_t)nI * D * 4;
+    return (size_t)(nI + nJ) * 16 + (size_t)(TX + TX + D - 1) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 +
+           (size_t)nI * D * 4;
 }
 
 float ncc_margin(int scale) { return 1e-4f + 2e-6f * (float)(2 * scale + 1); }
