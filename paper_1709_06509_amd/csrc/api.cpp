@@ -170,7 +170,6 @@ BP_API int32_t bp_context_set_batch_schedule(bp_context* ctx, int32_t schedule, 
 namespace {
 constexpr size_t kMaxGraphs = 32;
 constexpr int kFusedMaxSteps = 5;  // half-steps (and halo pixels) per fused launch when forced
-constexpr double kSpecLatencyUs = 4.5;  // per-launch estimate at or below which a half-step is latency-bound
 
 SolveKey make_key(int32_t W, int32_t H, const bp_params* p, const void* cost, const void* ws, size_t wsb,
                   const void* disp, const void* msgs, int32_t fused)
@@ -481,12 +480,9 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
             a.source = (t == 0) ? source : bpst::kSrcOwn;
             // Scales too large for the caches stream their volumes (nontemporal accesses) on
             // the int32 path; the narrow path's lower arithmetic pays where memory does not
-            // bound the launch.  Where a half-step's traffic is small enough that its launch is
-            // bound by latency, every pixel loads its data together with its state instead of
-            // compacting first.
+            // bound the launch.
             a.stream = bpst::stream_scale(pl.lv[l], pl.G) ? 1 : 0;
             a.narrow = narrow_ok(l, t) && !count && pl.G <= bpst::kNarrowMaxG && !a.stream ? 1 : 0;
-            a.spec = bpst::per_launch_us(pl.lv[l], pl.G, 1) <= kSpecLatencyUs ? 1 : 0;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (ctx && ctx->timing) {
                 if (ctx->used == ctx->events.size()) {

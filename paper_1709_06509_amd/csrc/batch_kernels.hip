@@ -127,12 +127,12 @@ __device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& 
                     return;
                 }
             }
-            if (ph.stream) halfstep_pixel<G, MODE, SRC, false, false, true>(h, (int)gi, lane);
+            if (ph.stream) halfstep_pixel<G, MODE, SRC, false, true>(h, (int)gi, lane);
             else halfstep_pixel<G, MODE, SRC>(h, (int)gi, lane);
         } else {
             // pixels wider than kNarrowMaxG lanes stay on the int32 path
             constexpr bool N = (HV & kHvNarrow) != 0 && G <= kNarrowMaxG;
-            halfstep_pixel<G, MODE, SRC, N, false, (HV & kHvStream) != 0>(h, (int)gi, lane);
+            halfstep_pixel<G, MODE, SRC, N, (HV & kHvStream) != 0>(h, (int)gi, lane);
         }
     } else {
         wta_pixel<G>(Q.c[0], Q.m[0], Q.vol[0], Q.lv[0], Q.D, Q.disparity, gi, lane);

@@ -637,11 +637,8 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
 // Skip mode 1 resets a pixel's state at its first update of the scale (t < 2).
 // Handles pixel gi of the scale's colour-a.colour pixels with lane `lane` of its G lanes;
 // returns whether it was updated and which neighbours it has (for the counters).
-// SPEC: load the pixel's data whether or not the freeze state turns out active, so that the
-// state and data loads overlap (for scales small enough that the extra bytes are cheaper
-// than a second memory latency); results are the same.
 // STREAM: the scale's volumes are streamed (nontemporal loads and stores, see ld16).
-template <int G, int MODE, int SRC, bool NARROW = false, bool SPEC = false, bool STREAM = false>
+template <int G, int MODE, int SRC, bool NARROW = false, bool STREAM = false>
 __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, int lane)
 {
     constexpr int Dp = 8 * G;
@@ -668,7 +665,6 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
                              (long long)(2 * (y + 1) + 1 - a.colour) * Wh + (x >> 1)};
     bool act = valid;
     if (MODE == 2 || (MODE == 1 && a.t >= 2)) act = act && a.state_a[slot] != 0;
-    const bool ld = SPEC ? valid : act;  // loads of the pixel's data
     bool hr[4];
     long long nbr[4];
 #pragma unroll
@@ -684,7 +680,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
 #pragma unroll
         for (int k = 0; k < 4; ++k) mp[k][v] = make_int4(0, 0, 0, 0);
     }
-    if (ld) {
+    if (act) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) c4[v] = ld16<STREAM>(a.cost + slot * Dp + d0 + 8 * v);
         if (SRC == kSrcOwn) {
@@ -717,7 +713,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             op[e][v] = make_int4(0, 0, 0, 0);
-            if (check && ld && hr[e])
+            if (check && act && hr[e])
                 op[e][v] = ld16<STREAM>(a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0 + 8 * v);
         }
     if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;

@@ -127,19 +127,16 @@ __global__ __launch_bounds__(kThreads) void k_import(const int16_t* __restrict__
 // update only active pixels.  Updates of one colour are independent, so the order does not
 // change any result.
 // Variant flags of k_halfstep.
-constexpr int kHsCount = 1, kHsNarrow = 2, kHsSpec = 4, kHsStream = 8;
+constexpr int kHsCount = 1, kHsNarrow = 2, kHsStream = 4;
 
 template <int G, int MODE, int SRC, int FL>
 __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
 {
-    constexpr bool COUNT = (FL & kHsCount) != 0, NARROW = (FL & kHsNarrow) != 0, SPEC = (FL & kHsSpec) != 0,
-                   STREAM = (FL & kHsStream) != 0;
+    constexpr bool COUNT = (FL & kHsCount) != 0, NARROW = (FL & kHsNarrow) != 0, STREAM = (FL & kHsStream) != 0;
     constexpr int kPix = kThreads / G;  // pixels of one tile
     const int lane = threadIdx.x & (G - 1);
     int gi = blockIdx.x * kPix + threadIdx.x / G;
-    // (with SPEC the tile is not compacted: every pixel loads its data at once and the
-    // inactive ones skip their stores)
-    if (!SPEC && (MODE == 2 || (MODE == 1 && a.t >= 2))) {
+    if (MODE == 2 || (MODE == 1 && a.t >= 2)) {
         __shared__ int list[kPix];
         __shared__ int wcount[kThreads / 64];
         const long long npix = (long long)a.lv.H * a.lv.Wh;
@@ -165,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
         if (!COUNT && (threadIdx.x & ~63) >= total * G) return;  // the whole wave has no pixel
         gi = threadIdx.x < total * G ? blockIdx.x * kPix + list[threadIdx.x / G] : (int)npix;  // npix: no pixel
     }
-    const PixOut r = halfstep_pixel<G, MODE, SRC, NARROW, SPEC, STREAM>(a, gi, lane);
+    const PixOut r = halfstep_pixel<G, MODE, SRC, NARROW, STREAM>(a, gi, lane);
     if (COUNT) {
         __shared__ int cnt[2];
         if (threadIdx.x == 0) { cnt[0] = 0; cnt[1] = 0; }
@@ -405,8 +402,6 @@ static hipError_t launch_halfstep_c(const HalfstepArgs& a, unsigned g, hipStream
     if (a.count) return launch_halfstep_t<MODE, SRC, kHsCount>(a, g, st);  // no narrow counting variant
     if (a.narrow) {
         if (a.capv < 0 || a.capv > kNarrowCap) return hipErrorInvalidValue;
-        // speculative loads only matter where pixels can be inactive
-        if (a.spec && (MODE == 2 || MODE == 1)) return launch_halfstep_t<MODE, SRC, kHsNarrow | kHsSpec>(a, g, st);
         return launch_halfstep_t<MODE, SRC, kHsNarrow>(a, g, st);
     }
     if (a.stream) return launch_halfstep_t<MODE, SRC, kHsStream>(a, g, st);

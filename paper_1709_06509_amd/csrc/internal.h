@@ -57,7 +57,6 @@ struct HalfstepArgs {
     int capv;                // min(lambda * min(T, D), 32767): clamp of a normalised message
     int colour, t, K, mode, source, count;
     int narrow;              // packed 16-bit sums (no counters): see the narrow path in bp_device.h
-    int spec;                // narrow path: load every pixel's data without waiting for its state
     int stream;              // nontemporal loads and stores (the scale's volumes exceed the caches)
     DevStats* stats;
     int level;
@@ -162,8 +161,6 @@ constexpr int kNarrowMaxG = 8;
 // from one half-step to the next, and plain accesses would only evict what could.
 constexpr double kStreamBytes = 192e6;
 inline bool stream_scale(const Level& lv, int G) { return 5.0 * (double)lv.slots() * 8 * G * 2 > kStreamBytes; }
-// Estimated device time (us) of `iters` one-per-half-step launches on scale lv.
-double per_launch_us(const Level& lv, int G, int iters);
 // Whether the narrow path is expected to be faster in a fused launch whose region holds
 // rmax pixels (it lowers the work per lane; small regions are bound by other costs).
 bool fused_narrow_pays(int G, long long rmax);

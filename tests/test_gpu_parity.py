@@ -248,9 +248,8 @@ def test_graph_forced_failure_falls_back(monkeypatch):
 @pytest.mark.parametrize("skip", [1, 2])
 def test_compacted_halfsteps_without_counters(skip):
     """The freeze rule and the exact skip compact active pixels per tile; without counters idle
-    waves leave early.  One launch per half-step (fused launches off) against the oracle.
-    Small scales load every pixel's data at once instead (latency-bound launches); the two
-    larger images keep compaction on their finest scale."""
+    waves leave early.  One launch per half-step (fused launches off) against the oracle; the
+    two larger images run many thousand compacted tiles per half-step."""
     ctx = B.Context()
     ctx.set_fused(0)
     for (H, W, D, L, iters) in [(61, 83, 16, 3, [9, 8, 7]), (40, 57, 24, 2, [12, 10]), (33, 35, 64, 2, [8, 6]),
