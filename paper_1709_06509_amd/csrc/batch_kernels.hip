@@ -167,6 +167,23 @@ __device__ __forceinline__ void chunk_of(const BatchArgs& a, int total, int* lo,
     *hi = (int)((long long)total * (c + 1) / nb);
 }
 
+// The same for at most kWavePairs - 1 pairs in one memory round trip instead of a chain of
+// dependent loads: every lane of the wave loads eight of the n + 1 prefix sums, and the
+// number of sums <= tile (they are non-decreasing, so these form a prefix) is one more than
+// the pair.  Each wave computes it on its own, so no barrier is needed.
+constexpr int kWavePairs = 512;
+__device__ __forceinline__ int pair_of_wave(const int* ts, int n, int tile)
+{
+    const int l = (int)(threadIdx.x & 63);
+    int v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = 64 * k + l <= n ? ts[64 * k + l] : 0x7fffffff;
+    int count = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) count += __popcll(__ballot(v[k] <= tile));
+    return count - 1;
+}
+
 // Pair p with ts[p] <= tile < ts[p + 1].
 __device__ __forceinline__ int pair_of(const int* ts, int n, int tile)
 {
@@ -223,7 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_phase(BatchArgs a, int phase
     const PhaseDesc ph = a.phases[phase];
     const int* ts = a.tiles + ph.table;
     const int tile = blockIdx.x;
-    const int q = pair_of(ts, a.npairs, tile);
+    const int q = a.npairs < kWavePairs ? pair_of_wave(ts, a.npairs, tile) : pair_of(ts, a.npairs, tile);
     const PairDev& Q = a.pairs[q];
     const int lt = tile - ts[q];
     switch (Q.G) {
