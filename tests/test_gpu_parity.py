@@ -276,3 +276,46 @@ def test_streamed_halfsteps(H, W, D, skip):
     rd, rm, _ = oracle.bp_solve(cost, 2, [2, 2], 64, 4, skip, 2)
     assert np.array_equal(host(m), rm), "messages differ"
     assert np.array_equal(host(d), rd), "disparities differ"
+
+
+def test_large_workload_sampled():
+    """The 1920x1080 RGB pair, D = 128, 5 scales x 12 half-steps, at full size in the
+    configuration the benchmark times (streamed finest scales).  The oracle cannot run the
+    whole solve at this size, so it checks what it can compute one by one: luma, sampled
+    costs, every outgoing message of sampled pixels of the colour updated last (recomputed
+    from the final message state, which no later half-step changed), sampled winners and
+    the exact energy."""
+    w = synth.WORKLOADS["large"]
+    p = synth.workload_pair("large")
+    D, win, L = w["num_disp"], w["window"], w["num_scales"]
+    iters = [w["iters"]] * L
+    say("large workload 1920x1080 D=128, sampled checks")
+    lg, rg = B.stereo_luma(gpu(p["left"])), B.stereo_luma(gpu(p["right"]))
+    lh, rh = oracle.luma(p["left"]), oracle.luma(p["right"])
+    assert np.array_equal(host(lg), lh) and np.array_equal(host(rg), rh)
+    cost = B.stereo_cost_volume(lg, rg, D, win)
+    d, m, _ = B.bp_hierarchical_solve(cost, L, iters, w["lam"], w["trunc"], w["skip"], want_msgs=True)
+    c, dd, mm = host(cost), host(d), host(m)
+    H, W = lh.shape
+    rng = np.random.default_rng(41)
+    for x, y, k in zip(rng.integers(0, W, 300), rng.integers(0, H, 300), rng.integers(0, D, 300)):
+        assert c[y, x, k] == oracle.cost_at(lh, rh, win, int(x), int(y), int(k)), f"cost at {x},{y},{k}"
+    last = (iters[0] - 1) & 1
+    nb = [(-1, 0), (1, 0), (0, -1), (0, 1)]
+    checked = 0
+    for x, y in zip(rng.integers(0, W, 400), rng.integers(0, H, 400)):
+        x, y = int(x), int(y)
+        if (x + y) & 1 != last:
+            x = x + 1 if x + 1 < W else x - 1
+        for k in range(4):
+            ref = oracle.message_at(c, mm, w["lam"], w["trunc"], x, y, k)
+            if ref is None:
+                continue
+            qx, qy = x + nb[k][0], y + nb[k][1]
+            assert np.array_equal(mm[k ^ 1, qy, qx], ref), f"message {k} of {x},{y}"
+            checked += 1
+    assert checked > 1000
+    for x, y in zip(rng.integers(0, W, 500), rng.integers(0, H, 500)):
+        assert dd[y, x] == oracle.wta_at(c, mm, int(x), int(y)), f"winner at {x},{y}"
+    e = B.bp_energy(cost, d, w["lam"], w["trunc"])
+    assert int(host(e)[0]) == oracle.energy(c, dd, w["lam"], w["trunc"])
