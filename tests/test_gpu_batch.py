@@ -163,3 +163,39 @@ def test_batch_narrow_schedule_matches_oracle(skip):
         assert np.array_equal(host(batch.costs[i]), c), f"pair {i} cost"
         d, _, _ = oracle.bp_solve(c, 3, [6, 5, 4], 64, 4, skip, 2, want_msgs=False)
         assert np.array_equal(host(batch.disps[i]), d), f"pair {i} disparity"
+
+
+def test_full_benchmark_batch():
+    """The 256-pair batch the benchmark times, autotuned and replayed from a graph: sampled
+    pairs equal their solo solves bit for bit (costs and disparities), and the smallest pair
+    equals the oracle."""
+    w = dict(synth.BATCH)
+    n = w["count"]
+    pairs = [synth.batch_pair(i, w["seed0"]) for i in range(n)]
+    L, iters = w["num_scales"], [w["iters"]] * w["num_scales"]
+    params = B.make_batch_params(w["window"], L, iters, w["lam"], w["trunc"], w["skip"], 2, w["cost_scale"],
+                                 w["cost_trunc"])
+    say("full benchmark batch, 256 pairs")
+    batch = B.Batch([gpu(p["left"]) for p in pairs], [gpu(p["right"]) for p in pairs],
+                    [p["num_disp"] for p in pairs], params)
+    ctx = B.Context()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        batch.autotune(ctx, s)
+        ctx.set_graphs(True)
+        for d in batch.disps:
+            d.fill_(-1)
+        batch.solve(ctx, s)
+        batch.solve(ctx, s)  # a replay of the captured graph
+    torch.cuda.synchronize()
+    assert batch.status(stream=s) == 0
+    rng = np.random.default_rng(5)
+    for i in sorted(set(rng.integers(0, n, 8).tolist())):
+        c, d = solo(batch.lefts[i], batch.rights[i], pairs[i]["num_disp"], dict(w, iters=iters))
+        assert torch.equal(batch.costs[i], c) and torch.equal(batch.disps[i], d), f"pair {i}"
+    small = min(range(n), key=lambda i: pairs[i]["left"].size * pairs[i]["num_disp"])
+    p = pairs[small]
+    c = oracle.cost_volume(p["left"], p["right"], p["num_disp"], w["window"])
+    assert np.array_equal(host(batch.costs[small]), c)
+    rd, _, _ = oracle.bp_solve(c, L, iters, w["lam"], w["trunc"], w["skip"], 2, want_msgs=False)
+    assert np.array_equal(host(batch.disps[small]), rd), f"pair {small} vs oracle"
