@@ -393,6 +393,20 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                 }
             }
         }
+        // half-steps t >= fused_from run in fused launches, the others one launch each
+        int fused_from = fsteps > 0 ? 0 : iters;
+        {
+            // tuning hook: under the freeze rule, where one launch per half-step was chosen,
+            // fuse the half-steps from t = k on (when most pixels have frozen)
+            const char* tail = getenv("BPSTEREO_FUSED_TAIL");
+            const int k = tail ? atoi(tail) : 0;
+            if (k >= 2 && k < iters && fsteps == 0 && fmode != 0 && mode == 1 && !count && pl.G <= 8) {
+                const int chunks = (iters - k + kFusedMaxSteps * 2 - 1) / (kFusedMaxSteps * 2);
+                fsteps = (iters - k + chunks - 1) / chunks;
+                if (bpst::fused_geometry_max(pl.lv[l], pl.G, fsteps, &ftw, &fth, &frmax)) fused_from = k;
+                else fsteps = 0;
+            }
+        }
         int source = bpst::kSrcOwn;
         if (fuse) {
             source = (l == start) ? bpst::kSrcZero : bpst::kSrcParent;
@@ -426,55 +440,8 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         a.count = count ? 1 : 0;
         a.stats = stats;
         a.level = l;
-        if (fsteps > 0) {
-            // the fused kernel reads the parent's (or zero) messages itself at t = 0, as the
-            // first half-step does; where an init kernel ran, it reads its own volumes
-            bpst::FusedArgs f{};
-            f.cost = C[l];
-            f.msgs = msgs;
-            f.vol = pl.vol[l];
-            f.pmsgs = a.pmsgs;
-            f.pvol = a.pvol;
-            f.plv = a.plv;
-            f.state_a = sa;
-            f.state_b = sb;
-            f.lv = pl.lv[l];
-            f.D = pl.D;
-            f.G = pl.G;
-            f.lambda = params->lambda;
-            f.capv = capv;
-            f.K = params->converge_iters;
-            f.mode = mode;
-            f.TW = ftw;
-            f.TH = fth;
-            f.tiles_x = (pl.lv[l].W + ftw - 1) / ftw;
-            f.rmax = frmax;
-            for (int t0 = 0; t0 < iters; t0 += fsteps) {
-                f.t0 = t0;
-                f.nsteps = iters - t0 < fsteps ? iters - t0 : fsteps;
-                f.halo = f.nsteps;  // a shorter last chunk keeps the tile: its smaller halo fits the LDS
-                f.source = t0 == 0 ? source : bpst::kSrcOwn;
-                f.keep_state = t0 + f.nsteps < iters ? 1 : 0;
-                f.narrow = narrow_ok(l, t0) && bpst::fused_narrow_pays(pl.G, frmax) ? 1 : 0;
-                hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (ctx && ctx->timing) {
-                    if (ctx->used == ctx->events.size()) {
-                        hipEvent_t x, y;
-                        HIP_TRY(hipEventCreate(&x));
-                        HIP_TRY(hipEventCreate(&y));
-                        ctx->events.emplace_back(x, y);
-                    }
-                    e0 = ctx->events[ctx->used].first;
-                    e1 = ctx->events[ctx->used].second;
-                    ctx->used++;
-                    ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh * f.nsteps;
-                    HIP_TRY(hipEventRecord(e0, st));
-                }
-                HIP_TRY(bpst::launch_fused(f, st));
-                if (e1) HIP_TRY(hipEventRecord(e1, st));
-            }
-        }
-        for (int t = 0; t < (fsteps > 0 ? 0 : iters); ++t) {
+        // one launch per half-step for t < fused_from, then the fused launches
+        for (int t = 0; t < fused_from; ++t) {
             a.t = t;
             a.colour = t & 1;
             a.source = (t == 0) ? source : bpst::kSrcOwn;
@@ -499,6 +466,54 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
             }
             HIP_TRY(bpst::launch_halfstep(a, st));
             if (e1) HIP_TRY(hipEventRecord(e1, st));
+        }
+        if (fsteps > 0) {
+            // the fused kernel reads the parent's (or zero) messages itself at t = 0, as the
+            // first half-step does; where an init kernel ran, it reads its own volumes
+            bpst::FusedArgs f{};
+            f.cost = C[l];
+            f.msgs = msgs;
+            f.vol = pl.vol[l];
+            f.pmsgs = a.pmsgs;
+            f.pvol = a.pvol;
+            f.plv = a.plv;
+            f.state_a = sa;
+            f.state_b = sb;
+            f.lv = pl.lv[l];
+            f.D = pl.D;
+            f.G = pl.G;
+            f.lambda = params->lambda;
+            f.capv = capv;
+            f.K = params->converge_iters;
+            f.mode = mode;
+            f.TW = ftw;
+            f.TH = fth;
+            f.tiles_x = (pl.lv[l].W + ftw - 1) / ftw;
+            f.rmax = frmax;
+            for (int t0 = fused_from; t0 < iters; t0 += fsteps) {
+                f.t0 = t0;
+                f.nsteps = iters - t0 < fsteps ? iters - t0 : fsteps;
+                f.halo = f.nsteps;  // a shorter last chunk keeps the tile: its smaller halo fits the LDS
+                f.source = t0 == 0 ? source : bpst::kSrcOwn;
+                f.keep_state = t0 + f.nsteps < iters ? 1 : 0;
+                f.narrow = narrow_ok(l, t0) && bpst::fused_narrow_pays(pl.G, frmax) ? 1 : 0;
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (ctx && ctx->timing) {
+                    if (ctx->used == ctx->events.size()) {
+                        hipEvent_t x, y;
+                        HIP_TRY(hipEventCreate(&x));
+                        HIP_TRY(hipEventCreate(&y));
+                        ctx->events.emplace_back(x, y);
+                    }
+                    e0 = ctx->events[ctx->used].first;
+                    e1 = ctx->events[ctx->used].second;
+                    ctx->used++;
+                    ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh * f.nsteps;
+                    HIP_TRY(hipEventRecord(e0, st));
+                }
+                HIP_TRY(bpst::launch_fused(f, st));
+                if (e1) HIP_TRY(hipEventRecord(e1, st));
+            }
         }
     }
     HIP_TRY(bpst::launch_wta(C[0], M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, disparity, st));

@@ -60,13 +60,38 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
     int* llist = reinterpret_cast<int*>(lsb + ((cap + 3) & ~3LL));  // active pixels of a half-step
     const int R = g.RW * g.RH;
 
-    // 1. load the region: cost, incoming messages (own, parent's or zero), freeze state.  A
-    //    thread takes two elements per round and issues all their global loads before any
-    //    LDS store, so the round costs one memory latency, not two.
+    // 0. Under the freeze rule, once pixels can be frozen (t0 >= 2): read the region's freeze
+    //    state first.  A frozen pixel stays frozen for the rest of the scale, so a region
+    //    with no active pixel cannot change during these half-steps: the workgroup leaves
+    //    without loading anything else or writing anything back.  (The vote goes through the
+    //    per-wave words of the dynamic LDS: a library reduction would add static LDS, which
+    //    the largest regions have no room for.)
+    const bool have_state = MODE == 1 && a.t0 >= 2;
+    if (have_state) {
+        int any = 0;
+        for (int r = threadIdx.x; r < R; r += blockDim.x) {
+            const int ry = r / g.RW, rx = r - ry * g.RW;
+            const long long slot = slot_of(g.rx0 + rx, g.ry0 + ry, Wh);
+            const uint8_t sa = a.state_a[slot];
+            lsa[r] = sa;
+            lsb[r] = a.state_b[slot];
+            any |= sa != 0;
+        }
+        const unsigned long long vote = __ballot(any != 0);
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = vote != 0ull ? 1 : 0;
+        __syncthreads();
+        int live = 0;
+        for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) live |= wsum[w];
+        if (live == 0) return;  // the same for every thread of the workgroup
+        // wsum is written again only after the barrier that ends the region load
+    }
+
+    // 1. load the region: cost, incoming messages (own, parent's or zero), and (before t0 = 2)
+    //    the initial freeze state.  A thread takes two elements per round and issues all their
+    //    global loads before any LDS store, so the round costs one memory latency, not two.
     constexpr int kU = 2;
     for (int e0 = threadIdx.x; e0 < R * G; e0 += kU * blockDim.x) {
         int4 cv[kU], mv[kU][4];
-        uint8_t sav[kU], sbv[kU];
         int rv[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -96,12 +121,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
                     if (has[k] && phas[k])
                         mv[u][k] = *reinterpret_cast<const int4*>(a.pmsgs + k * a.pvol + ps * Dp + d0);
             }
-            sav[u] = 1;
-            sbv[u] = 0;
-            if (MODE == 1 && in && lane == 0 && a.t0 >= 2) {
-                sav[u] = a.state_a[slot];
-                sbv[u] = a.state_b[slot];
-            }
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -111,9 +130,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
             *reinterpret_cast<int4*>(lc + (long long)r * Dp + d0) = cv[u];
 #pragma unroll
             for (int k = 0; k < 4; ++k) *reinterpret_cast<int4*>(lm + k * cap * Dp + (long long)r * Dp + d0) = mv[u][k];
-            if (MODE == 1 && d0 == 0) {
-                lsa[r] = sav[u];
-                lsb[r] = sbv[u];
+            if (MODE == 1 && !have_state && d0 == 0) {
+                lsa[r] = 1;  // every pixel is active before its third half-step
+                lsb[r] = 0;
             }
         }
     }
@@ -469,13 +488,20 @@ bool fused_geometry_max(const Level& lv, int G, int steps, int* TW, int* TH, lon
     return best_tiles > 0;
 }
 
+// Largest static LDS of the fused kernels (bytes): a launch needs it on top of its dynamic
+// LDS, and the two together must fit the compute unit's 160 KB.
+static size_t g_fused_static_lds = 0;
+
 template <int G, int MODE>
 void set_lds_attr()
 {
-    (void)hipFuncSetAttribute((const void*)k_fused<G, MODE, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kFusedLdsBytes);
-    (void)hipFuncSetAttribute((const void*)k_fused<G, MODE, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kFusedLdsBytes);
+    const void* fns[2] = {(const void*)k_fused<G, MODE, false>, (const void*)k_fused<G, MODE, true>};
+    for (const void* fn : fns) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kFusedLdsBytes);
+        hipFuncAttributes attr{};
+        if (hipFuncGetAttributes(&attr, fn) == hipSuccess && attr.sharedSizeBytes > g_fused_static_lds)
+            g_fused_static_lds = attr.sharedSizeBytes;
+    }
 }
 
 void fused_prepare()
@@ -501,9 +527,10 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t st)
 {
     const int tiles = a.tiles_x * ((a.lv.H + a.TH - 1) / a.TH);
     const size_t lds = fused_lds_bytes(a.G, a.rmax);
-    if (lds > (size_t)kFusedLdsBytes || a.halo != a.nsteps || a.nsteps < 1) return hipErrorInvalidValue;
+    if (a.halo != a.nsteps || a.nsteps < 1) return hipErrorInvalidValue;
     if (a.narrow && (a.capv < 0 || a.capv > kNarrowCap)) return hipErrorInvalidValue;
     fused_prepare();
+    if (lds + g_fused_static_lds > (size_t)kFusedLdsBytes) return hipErrorInvalidValue;
     const dim3 grid((unsigned)tiles), block((unsigned)fused_threads(a.G, a.rmax));
 #define BPST_FUSED_G(GG)                                                                        \
     case GG:                                                                                    \

@@ -173,3 +173,25 @@ def test_fused_negative_finest_costs(fused_ctx):
         d, m, _ = B.bp_hierarchical_solve(gpu(cost), 3, [6, 6, 6], 64, 4, skip, 2, want_msgs=True, ctx=fused_ctx)
         rd, rm, _ = oracle.bp_solve(cost, 3, [6, 6, 6], 64, 4, skip, 2)
         assert np.array_equal(host(m), rm) and np.array_equal(host(d), rd)
+
+
+@pytest.mark.parametrize("tail", ["2", "4", "7"])
+def test_fused_tail_on_production_pair(tail):
+    """Under the freeze rule, the half-steps of a scale from t = k on in fused launches after
+    one launch each before (the tail hook), on the production pair: equal to the oracle."""
+    w = synth.WORKLOADS["production"]
+    p = synth.workload_pair("production")
+    cost = oracle.cost_volume(p["left"], p["right"], w["num_disp"], w["window"])
+    L, iters = w["num_scales"], [w["iters"]] * w["num_scales"]
+    os.environ["BPSTEREO_FUSED_TAIL"] = tail
+    try:
+        ctx = B.Context()
+        say(f"production pair, fused tail from t = {tail}")
+        d, m, _ = B.bp_hierarchical_solve(gpu(cost), L, iters, w["lam"], w["trunc"], w["skip"], 2, want_msgs=True,
+                                          ctx=ctx)
+        dm = (host(d), host(m))
+        ctx.close()
+    finally:
+        os.environ.pop("BPSTEREO_FUSED_TAIL", None)
+    rd, rm, _ = oracle.bp_solve(cost, L, iters, w["lam"], w["trunc"], w["skip"], 2)
+    assert np.array_equal(dm[1], rm) and np.array_equal(dm[0], rd)
