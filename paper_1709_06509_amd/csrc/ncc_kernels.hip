@@ -41,11 +41,11 @@ __device__ bool le_times_sqrt(long long B, long long A, unsigned long long P)
 // Element loops walk (column, disparity) pairs with an incremental index, not a division.
 template <int WIN>
 __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R, int W, int H,
-                                         int D, int scale, int trunc, float margin, int16_t* __restrict__ cost,
-                                         float* __restrict__ ncc_out, int y, int x0, unsigned* smem)
+                                         int D, int TX, int scale, int trunc, float margin,
+                                         int16_t* __restrict__ cost, float* __restrict__ ncc_out, int y, int x0,
+                                         unsigned* smem)
 {
     constexpr int r = WIN >> 1;
-    const int TX = ncc_tile_x(D);
     const int nI = TX + 2 * r;          // left columns  x0-r .. x0+TX-1+r
     const int nJ = TX + 2 * r + D - 1;  // right columns x0-r-(D-1) .. x0+TX-1+r
     const int uI0 = x0 - r, uJ0 = x0 - r - (D - 1);
@@ -178,11 +178,11 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
 
 template <int WIN>
 __global__ __launch_bounds__(kThreads) void k_ncc(const uint8_t* __restrict__ L, const uint8_t* __restrict__ R,
-                                                   int W, int H, int D, int scale, int trunc, float margin,
+                                                   int W, int H, int D, int TX, int scale, int trunc, float margin,
                                                    int16_t* __restrict__ cost, float* __restrict__ ncc_out)
 {
     extern __shared__ unsigned smem[];
-    ncc_tile<WIN>(L, R, W, H, D, scale, trunc, margin, cost, ncc_out, blockIdx.y, blockIdx.x * ncc_tile_x(D), smem);
+    ncc_tile<WIN>(L, R, W, H, D, TX, scale, trunc, margin, cost, ncc_out, blockIdx.y, blockIdx.x * TX, smem);
 }
 
 // Every tile of every pair of a batch in one launch; tile_start[p] is the first tile of
@@ -205,16 +205,25 @@ __global__ __launch_bounds__(kThreads) void k_ncc_batched(const NccPair* __restr
     const int TX = ncc_tile_x(P.D);
     const int tx = (P.W + TX - 1) / TX;
     const int y = local / tx, x0 = (local - y * tx) * TX;
-    ncc_tile<WIN>(P.left, P.right, P.W, P.H, P.D, scale, trunc, margin, P.cost, nullptr, y, x0, smem);
+    ncc_tile<WIN>(P.left, P.right, P.W, P.H, P.D, TX, scale, trunc, margin, P.cost, nullptr, y, x0, smem);
 }
 
-size_t ncc_lds_bytes(int D, int win)
+size_t ncc_lds_bytes(int D, int win, int TX)
 {
     const int r = win >> 1;
-    const int TX = ncc_tile_x(D);
     const int nI = TX + 2 * r, nJ = TX + 2 * r + D - 1;
     return (size_t)(nI + nJ) * 16 + (size_t)(TX + TX + D - 1) * 16 + (size_t)(2 * nI + 2 * nJ) * 4 +
            (size_t)nI * D * 4;
+}
+
+// Tile width of a single image: the batched width, halved (down to 32 columns) while the
+// image would give fewer than 2048 workgroups, so that a small image still spreads over
+// many compute units and each workgroup's serial part stays short.
+int ncc_single_tile_x(int W, int H, int D)
+{
+    int TX = ncc_tile_x(D);
+    while (TX > 32 && (long long)((W + TX - 1) / TX) * H < 2048) TX /= 2;
+    return TX;
 }
 
 float ncc_margin(int scale) { return 1e-4f + 2e-6f * (float)(2 * scale + 1); }
@@ -226,7 +235,7 @@ int ncc_tiles(int W, int H, int D) { return H * ((W + ncc_tile_x(D) - 1) / ncc_t
 size_t ncc_lds_max(int max_d, int win)
 {
     size_t m = 0;
-    for (int D = 1; D <= max_d; ++D) m = ncc_lds_bytes(D, win) > m ? ncc_lds_bytes(D, win) : m;
+    for (int D = 1; D <= max_d; ++D) m = ncc_lds_bytes(D, win, ncc_tile_x(D)) > m ? ncc_lds_bytes(D, win, ncc_tile_x(D)) : m;
     return m;
 }
 
@@ -234,11 +243,13 @@ hipError_t launch_ncc(const uint8_t* L, const uint8_t* R, int W, int H, int D, i
                       int16_t* cost, float* ncc, hipStream_t st)
 {
     if ((win >> 1) > kMaxR) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((W + ncc_tile_x(D) - 1) / ncc_tile_x(D)), (unsigned)H);
-    const size_t lds = ncc_lds_bytes(D, win);
+    const int TX = ncc_single_tile_x(W, H, D);
+    dim3 grid((unsigned)((W + TX - 1) / TX), (unsigned)H);
+    const size_t lds = ncc_lds_bytes(D, win, TX);
     const float m = ncc_margin(scale);
 #define BPST_NCC(WV) \
-    case WV: hipLaunchKernelGGL(k_ncc<WV>, grid, dim3(kThreads), lds, st, L, R, W, H, D, scale, trunc, m, cost, ncc); break;
+    case WV: hipLaunchKernelGGL(k_ncc<WV>, grid, dim3(kThreads), lds, st, L, R, W, H, D, TX, scale, trunc, m, cost, ncc); \
+        break;
     switch (win) {
         BPST_NCC(1) BPST_NCC(3) BPST_NCC(5) BPST_NCC(7) BPST_NCC(9) BPST_NCC(11) BPST_NCC(13)
         default: return hipErrorInvalidValue;
