@@ -393,20 +393,27 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                 }
             }
         }
-        // half-steps t >= fused_from run in fused launches, the others one launch each
-        int fused_from = fsteps > 0 ? 0 : iters;
-        {
-            // tuning hook: under the freeze rule, where one launch per half-step was chosen,
-            // fuse the half-steps from t = k on (when most pixels have frozen)
-            const char* tail = getenv("BPSTEREO_FUSED_TAIL");
-            const int k = tail ? atoi(tail) : 0;
-            if (k >= 2 && k < iters && fsteps == 0 && fmode != 0 && mode == 1 && !count && pl.G <= 8) {
-                const int chunks = (iters - k + kFusedMaxSteps * 2 - 1) / (kFusedMaxSteps * 2);
-                fsteps = (iters - k + chunks - 1) / chunks;
-                if (bpst::fused_geometry_max(pl.lv[l], pl.G, fsteps, &ftw, &fth, &frmax)) fused_from = k;
-                else fsteps = 0;
+        // The scale's half-steps as consecutive segments, each run one launch per half-step
+        // (steps == 0) or in fused launches of `steps` half-steps on its own tile.
+        struct Seg {
+            int t0, t1, steps, tw, th;
+            long long rmax;
+        };
+        std::vector<Seg> segs;
+        const char* tail = getenv("BPSTEREO_FUSED_TAIL");
+        if (tail && atoi(tail) >= 2 && atoi(tail) < iters && fsteps == 0 && fmode != 0 && mode == 1 && !count &&
+            pl.G <= 8) {
+            // tuning hook: one launch per half-step up to t = k, then fused launches
+            const int k = atoi(tail);
+            const int chunks = (iters - k + kFusedMaxSteps * 2 - 1) / (kFusedMaxSteps * 2);
+            const int steps = (iters - k + chunks - 1) / chunks;
+            Seg b{k, iters, steps, 0, 0, 0};
+            if (bpst::fused_geometry_max(pl.lv[l], pl.G, steps, &b.tw, &b.th, &b.rmax)) {
+                segs.push_back({0, k, 0, 0, 0, 0});
+                segs.push_back(b);
             }
         }
+        if (segs.empty()) segs.push_back({0, iters, fsteps, ftw, fth, frmax});
         int source = bpst::kSrcOwn;
         if (fuse) {
             source = (l == start) ? bpst::kSrcZero : bpst::kSrcParent;
@@ -440,63 +447,16 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         a.count = count ? 1 : 0;
         a.stats = stats;
         a.level = l;
-        // one launch per half-step for t < fused_from, then the fused launches
-        for (int t = 0; t < fused_from; ++t) {
-            a.t = t;
-            a.colour = t & 1;
-            a.source = (t == 0) ? source : bpst::kSrcOwn;
-            // Scales too large for the caches stream their volumes (nontemporal accesses) on
-            // the int32 path; the narrow path's lower arithmetic pays where memory does not
-            // bound the launch.
-            a.stream = bpst::stream_scale(pl.lv[l], pl.G) ? 1 : 0;
-            a.narrow = narrow_ok(l, t) && !count && pl.G <= bpst::kNarrowMaxG && !a.stream ? 1 : 0;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (ctx && ctx->timing) {
-                if (ctx->used == ctx->events.size()) {
-                    hipEvent_t x, y;
-                    HIP_TRY(hipEventCreate(&x));
-                    HIP_TRY(hipEventCreate(&y));
-                    ctx->events.emplace_back(x, y);
-                }
-                e0 = ctx->events[ctx->used].first;
-                e1 = ctx->events[ctx->used].second;
-                ctx->used++;
-                ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh;
-                HIP_TRY(hipEventRecord(e0, st));
-            }
-            HIP_TRY(bpst::launch_halfstep(a, st));
-            if (e1) HIP_TRY(hipEventRecord(e1, st));
-        }
-        if (fsteps > 0) {
-            // the fused kernel reads the parent's (or zero) messages itself at t = 0, as the
-            // first half-step does; where an init kernel ran, it reads its own volumes
-            bpst::FusedArgs f{};
-            f.cost = C[l];
-            f.msgs = msgs;
-            f.vol = pl.vol[l];
-            f.pmsgs = a.pmsgs;
-            f.pvol = a.pvol;
-            f.plv = a.plv;
-            f.state_a = sa;
-            f.state_b = sb;
-            f.lv = pl.lv[l];
-            f.D = pl.D;
-            f.G = pl.G;
-            f.lambda = params->lambda;
-            f.capv = capv;
-            f.K = params->converge_iters;
-            f.mode = mode;
-            f.TW = ftw;
-            f.TH = fth;
-            f.tiles_x = (pl.lv[l].W + ftw - 1) / ftw;
-            f.rmax = frmax;
-            for (int t0 = fused_from; t0 < iters; t0 += fsteps) {
-                f.t0 = t0;
-                f.nsteps = iters - t0 < fsteps ? iters - t0 : fsteps;
-                f.halo = f.nsteps;  // a shorter last chunk keeps the tile: its smaller halo fits the LDS
-                f.source = t0 == 0 ? source : bpst::kSrcOwn;
-                f.keep_state = t0 + f.nsteps < iters ? 1 : 0;
-                f.narrow = narrow_ok(l, t0) && bpst::fused_narrow_pays(pl.G, frmax) ? 1 : 0;
+        for (const Seg& sg : segs) {
+            for (int t = sg.t0; sg.steps == 0 && t < sg.t1; ++t) {
+                a.t = t;
+                a.colour = t & 1;
+                a.source = (t == 0) ? source : bpst::kSrcOwn;
+                // Scales too large for the caches stream their volumes (nontemporal accesses) on
+                // the int32 path; the narrow path's lower arithmetic pays where memory does not
+                // bound the launch.
+                a.stream = bpst::stream_scale(pl.lv[l], pl.G) ? 1 : 0;
+                a.narrow = narrow_ok(l, t) && !count && pl.G <= bpst::kNarrowMaxG && !a.stream ? 1 : 0;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (ctx && ctx->timing) {
                     if (ctx->used == ctx->events.size()) {
@@ -508,11 +468,59 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                     e0 = ctx->events[ctx->used].first;
                     e1 = ctx->events[ctx->used].second;
                     ctx->used++;
-                    ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh * f.nsteps;
+                    ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh;
                     HIP_TRY(hipEventRecord(e0, st));
                 }
-                HIP_TRY(bpst::launch_fused(f, st));
+                HIP_TRY(bpst::launch_halfstep(a, st));
                 if (e1) HIP_TRY(hipEventRecord(e1, st));
+            }
+            if (sg.steps > 0) {
+                // the fused kernel reads the parent's (or zero) messages itself at t = 0, as the
+                // first half-step does; where an init kernel ran, it reads its own volumes
+                bpst::FusedArgs f{};
+                f.cost = C[l];
+                f.msgs = msgs;
+                f.vol = pl.vol[l];
+                f.pmsgs = a.pmsgs;
+                f.pvol = a.pvol;
+                f.plv = a.plv;
+                f.state_a = sa;
+                f.state_b = sb;
+                f.lv = pl.lv[l];
+                f.D = pl.D;
+                f.G = pl.G;
+                f.lambda = params->lambda;
+                f.capv = capv;
+                f.K = params->converge_iters;
+                f.mode = mode;
+                f.TW = sg.tw;
+                f.TH = sg.th;
+                f.tiles_x = (pl.lv[l].W + sg.tw - 1) / sg.tw;
+                f.rmax = sg.rmax;
+                for (int t0 = sg.t0; t0 < sg.t1; t0 += sg.steps) {
+                    f.t0 = t0;
+                    f.nsteps = sg.t1 - t0 < sg.steps ? sg.t1 - t0 : sg.steps;
+                    f.halo = f.nsteps;  // a shorter last chunk keeps the tile: its smaller halo fits the LDS
+                    f.source = t0 == 0 ? source : bpst::kSrcOwn;
+                    f.keep_state = t0 + f.nsteps < iters ? 1 : 0;
+                    f.narrow = narrow_ok(l, t0) && bpst::fused_narrow_pays(pl.G, sg.rmax) ? 1 : 0;
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    if (ctx && ctx->timing) {
+                        if (ctx->used == ctx->events.size()) {
+                            hipEvent_t x, y;
+                            HIP_TRY(hipEventCreate(&x));
+                            HIP_TRY(hipEventCreate(&y));
+                            ctx->events.emplace_back(x, y);
+                        }
+                        e0 = ctx->events[ctx->used].first;
+                        e1 = ctx->events[ctx->used].second;
+                        ctx->used++;
+                        ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh * f.nsteps;
+                        HIP_TRY(hipEventRecord(e0, st));
+                    }
+                    HIP_TRY(bpst::launch_fused(f, st));
+                    if (e1) HIP_TRY(hipEventRecord(e1, st));
+                }
             }
         }
     }
