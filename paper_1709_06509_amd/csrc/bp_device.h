@@ -638,8 +638,10 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
 // Handles pixel gi of the scale's colour-a.colour pixels with lane `lane` of its G lanes;
 // returns whether it was updated and which neighbours it has (for the counters).
 // STREAM: the scale's volumes are streamed (nontemporal loads and stores, see ld16).
+// listed: the caller has already read the pixel's freeze state and passes only active
+// pixels (or gi past the end), so the state is not read again.
 template <int G, int MODE, int SRC, bool NARROW = false, bool STREAM = false>
-__device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, int lane)
+__device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, int lane, bool listed = false)
 {
     constexpr int Dp = 8 * G;
     constexpr int NV = NARROW ? NarrowLane<G>::NV : 1;  // label vectors a lane reads per volume
@@ -664,7 +666,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
                              (long long)(2 * (y - 1) + 1 - a.colour) * Wh + (x >> 1),
                              (long long)(2 * (y + 1) + 1 - a.colour) * Wh + (x >> 1)};
     bool act = valid;
-    if (MODE == 2 || (MODE == 1 && a.t >= 2)) act = act && a.state_a[slot] != 0;
+    if (!listed && (MODE == 2 || (MODE == 1 && a.t >= 2))) act = act && a.state_a[slot] != 0;
     bool hr[4];
     long long nbr[4];
 #pragma unroll
@@ -672,6 +674,22 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
         hr[r] = hi ? has[(r + 2) & 3] : has[r];
         nbr[r] = hi ? nb[(r + 2) & 3] : nb[r];
     }
+    const bool check = (MODE == 2) || (MODE == 1 && a.t >= 2);
+    // The messages this lane sends: all four, or with the pairs split the two of its pair
+    // (k = 2q + e).  The outgoing values this update may overwrite, and the pixel's count of
+    // unchanged half-steps, are loaded first, before the incoming messages (nothing else
+    // writes them during the half-step): placed after, the compiler would issue them only
+    // once the incoming sums were formed, a second memory latency in the pixel's path.
+    int sb = MODE == 1 && a.t >= 2 ? (int)a.state_b[act ? slot : 0] : 0;
+    int4 op[NK][NV];
+#pragma unroll
+    for (int e = 0; e < NK; ++e)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            op[e][v] = make_int4(0, 0, 0, 0);
+            if (check && act && hr[e])
+                op[e][v] = ld16<STREAM>(a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0 + 8 * v);
+        }
     // incoming messages stay packed (two int16 per register, values in [0, 32767])
     int4 c4[NV], mp[4][NV];
 #pragma unroll
@@ -702,21 +720,6 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
                         mp[r][v] = ld16<STREAM>(a.pmsgs + role_msg(hi, r) * a.pvol + ps * Dp + d0 + 8 * v);
         }
     }
-    const bool check = (MODE == 2) || (MODE == 1 && a.t >= 2);
-    // The messages this lane sends: all four, or with the pairs split the two of its pair
-    // (k = 2q + e).  The outgoing values this update may overwrite are loaded together with
-    // the incoming ones (nothing else writes them during the half-step), so the compares
-    // below do not each wait for a load.
-    int4 op[NK][NV];
-#pragma unroll
-    for (int e = 0; e < NK; ++e)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            op[e][v] = make_int4(0, 0, 0, 0);
-            if (check && act && hr[e])
-                op[e][v] = ld16<STREAM>(a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0 + 8 * v);
-        }
-    if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;
     int4 out[4][NV];
     if constexpr (NARROW) {
         narrow_update<G>(nl, c4, mp, a.D, a.D < Dp, (unsigned)a.lambda, (unsigned)a.capv, out);
@@ -739,11 +742,13 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
             transform2<G>(ha, hb, a.lambda, a.capv, lane, out[k][0], out[k + 1][0]);
         }
     }
+    // Every decision first, then every store: arithmetic placed after a store made the
+    // compiler wait for the store to complete before it reused the store's registers.
     bool all_eq = true;
+    bool stf[NK];
 #pragma unroll
     for (int e = 0; e < NK; ++e) {
         bool store = act && hr[e];
-        int16_t* dst = a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0;
         if (check) {
             bool same = true;
 #pragma unroll
@@ -751,23 +756,34 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
             const int eq = group_min<GL>(same ? 1 : 0);  // the GL lanes of the message
             if (store && !eq) all_eq = false;
             if (eq) store = false;
-            if (MODE == 2 && store && glane == 0) a.state_a[nbr[e]] = 1;
         }
-        if (store) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) st16<STREAM>(dst + 8 * v, out[e][v]);
-        }
+        stf[e] = store;
     }
     // the freeze state needs all four messages: combine the pixel's lanes
     if (NARROW && G > 1 && MODE == 1 && check) all_eq = group_min<G>(all_eq ? 1 : 0) != 0;
+    int snew = 0;  // the pixel's new count of unchanged half-steps (freeze rule, t >= 2)
+    if (MODE == 1 && a.t >= 2) {
+        // (the empty asm keeps the compiler from forming sb + 1 right at the load, which
+        // would wait for it before the other loads are issued)
+        asm volatile("" : "+v"(sb));
+        snew = all_eq ? sb + 1 : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < NK; ++e)
+        if (stf[e]) {
+            int16_t* dst = a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) st16<STREAM>(dst + 8 * v, out[e][v]);
+            if (MODE == 2 && glane == 0) a.state_a[nbr[e]] = 1;
+        }
+    if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;  // own colour: no neighbour marks it now
     if (MODE == 1 && act && lane == 0) {
         if (a.t < 2) {
             a.state_a[slot] = 1;
             a.state_b[slot] = 0;
         } else {
-            int s = all_eq ? (int)a.state_b[slot] + 1 : 0;
-            a.state_b[slot] = (uint8_t)s;
-            if (2 * s >= a.K) a.state_a[slot] = 0;
+            a.state_b[slot] = (uint8_t)snew;
+            if (2 * snew >= a.K) a.state_a[slot] = 0;
         }
     }
     PixOut r;

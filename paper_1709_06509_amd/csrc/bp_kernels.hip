@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
         if (!COUNT && (threadIdx.x & ~63) >= total * G) return;  // the whole wave has no pixel
         gi = threadIdx.x < total * G ? blockIdx.x * kPix + list[threadIdx.x / G] : (int)npix;  // npix: no pixel
     }
-    const PixOut r = halfstep_pixel<G, MODE, SRC, NARROW, STREAM>(a, gi, lane);
+    const PixOut r = halfstep_pixel<G, MODE, SRC, NARROW, STREAM>(a, gi, lane, MODE == 2 || (MODE == 1 && a.t >= 2));
     if (COUNT) {
         __shared__ int cnt[2];
         if (threadIdx.x == 0) { cnt[0] = 0; cnt[1] = 0; }

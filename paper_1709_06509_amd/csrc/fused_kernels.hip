@@ -224,21 +224,21 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
                 ir[q] = hi ? inreg[(q + 2) & 3] : inreg[q];
                 nr[q] = hi ? nbr[(q + 2) & 3] : nbr[q];
             }
-            // every LDS read is issued unconditionally from a valid address and masked after,
-            // so the loads of a pixel overlap instead of waiting on each other's branches
+            // every LDS read is issued unconditionally from a valid address, so the loads of a
+            // pixel overlap.  No mask is needed for a side with no neighbour: the region load
+            // stored zeros there, and only that neighbour would ever write the slot.  (Zeroing
+            // the loaded value instead made the compiler wait for each load in its own branch.)
             const long long rr = valid ? r : 0;
             int4 c4[NV], mp[4][NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) c4[v] = *reinterpret_cast<const int4*>(lc + rr * Dp + d0 + 8 * v);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
+                for (int v = 0; v < NV; ++v)
                     mp[q][v] = *reinterpret_cast<const int4*>(lm + role_msg(hi, q) * cap * Dp + rr * Dp + d0 + 8 * v);
-                    if (!hr[q]) mp[q][v] = make_int4(0, 0, 0, 0);
-                }
-            }
             const bool act = valid && (!check || lsa[rr] != 0);
+            const int sb = lsb[rr];  // the pixel's count of unchanged half-steps, read with the rest
             int4 out[4][NV];
             if constexpr (NARROW) {
                 narrow_update<G>(nl, c4, mp, a.D, pad, (unsigned)a.lambda, (unsigned)a.capv, out);
@@ -278,7 +278,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
                                                                   (tk ? (long long)nr[e] : rr) * Dp + d0 + 8 * v);
                 }
             }
+            // every decision first, then every store (arithmetic after a store would wait for it)
             bool all_eq = true;
+            bool stf[NK];
 #pragma unroll
             for (int e = 0; e < NK; ++e) {
                 bool store = act && hr[e] && ir[e];
@@ -292,21 +294,24 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
                     if (store && !eq) all_eq = false;
                     if (eq) store = false;
                 }
-                if (store) {
+                stf[e] = store;
+            }
+            // the freeze state needs all four messages: combine the pixel's lanes
+            if (NARROW && G > 1 && check) all_eq = group_min<G>(all_eq ? 1 : 0) != 0;
+            const int st = all_eq ? sb + 1 : 0;
+#pragma unroll
+            for (int e = 0; e < NK; ++e)
+                if (stf[e]) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
                         *reinterpret_cast<int4*>(lm + (role_msg(hi, e) ^ 1) * cap * Dp + (long long)nr[e] * Dp + d0 +
                                                  8 * v) = out[e][v];
                 }
-            }
-            // the freeze state needs all four messages: combine the pixel's lanes
-            if (NARROW && G > 1 && check) all_eq = group_min<G>(all_eq ? 1 : 0) != 0;
             if (MODE == 1 && act && lane == 0) {
                 if (t < 2) {
                     lsa[r] = 1;
                     lsb[r] = 0;
                 } else {
-                    const int st = all_eq ? (int)lsb[r] + 1 : 0;
                     lsb[r] = (uint8_t)st;
                     if (2 * st >= a.K) lsa[r] = 0;
                 }
