@@ -550,26 +550,41 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
             const bool valid = px < l1.W && py < l1.H;
             int s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             if (valid) {
+                // the four children's costs are all loaded (from the pixel itself where a child
+                // lies past the image) before any is used or stored: one memory latency, not four
+                int v[4][8];
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int k = 0; k < 4; ++k) {
+                    const int x = 2 * px + (k & 1), y = 2 * py + (k >> 1);
+                    const bool in = x < l0.W && y < l0.H;
+                    const int16_t* src = user + ((long long)(in ? y : 2 * py) * l0.W + (in ? x : 2 * px)) * D;
+                    if (VEC) {
+                        // a lane past the labels reads label 0's vector and drops it
+                        unpack8(*reinterpret_cast<const int4*>(src + (d0 < D ? d0 : 0)), v[k]);
+                        const int keep = d0 < D ? -1 : 0;
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const int x = 2 * px + c, y = 2 * py + b;
-                        if (x >= l0.W || y >= l0.H) continue;
-                        const int16_t* src = user + ((long long)y * l0.W + x) * D + d0;
-                        int v[8];
-                        if (VEC) {
-                            if (d0 < D) unpack8(*reinterpret_cast<const int4*>(src), v);
-                            else for (int j = 0; j < 8; ++j) v[j] = 0;
-                        } else {
+                        for (int j = 0; j < 8; ++j) v[k][j] &= keep;
+                    } else {
+                        src += d0;
 #pragma unroll
-                            for (int j = 0; j < 8; ++j) v[j] = (d0 + j < D) ? (int)src[j] : 0;
-                        }
-                        *reinterpret_cast<int4*>(cs[0] + slot_of(x, y, l0.Wh) * Dp + d0) =
-                            finest_internal<G>(v, d0, D);
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) s[j] += v[j];
+                        for (int j = 0; j < 8; ++j) v[k][j] = (d0 + j < D) ? (int)src[j] : 0;
                     }
+                }
+                // then every result, then every store (arithmetic after a store waits for it)
+                int4 fin[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int x = 2 * px + (k & 1), y = 2 * py + (k >> 1);
+                    const int keep = x < l0.W && y < l0.H ? -1 : 0;
+                    fin[k] = finest_internal<G>(v[k], d0, D);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) s[j] += v[k][j] & keep;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int x = 2 * px + (k & 1), y = 2 * py + (k >> 1);
+                    if (x < l0.W && y < l0.H) *reinterpret_cast<int4*>(cs[0] + slot_of(x, y, l0.Wh) * Dp + d0) = fin[k];
+                }
             }
             int mn = kBig;
 #pragma unroll
@@ -805,17 +820,23 @@ __device__ __forceinline__ void wta_pixel(const int16_t* __restrict__ c0, const 
     const bool valid = in && p.valid;
     const int d0 = lane * 8;
     const bool has[4] = {p.x > 0, p.x < lv.W - 1, p.y > 0, p.y < lv.H - 1};
-    int b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (valid) {
-        unpack8u(*reinterpret_cast<const int4*>(c0 + gi * Dp + d0), b);
+    // all five vectors are loaded before any is used, from the pixel's own slot (slot 0 for
+    // a lane without a pixel), and masked after: a load under a branch that also sums would
+    // be waited for inside the branch, one memory latency per volume
+    const long long s = valid ? gi : 0;
+    const int4 cv = *reinterpret_cast<const int4*>(c0 + s * Dp + d0);
+    int4 mv[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (has[k]) {
-                int v[8];
-                unpack8u(*reinterpret_cast<const int4*>(msgs + k * vol + gi * Dp + d0), v);
+    for (int k = 0; k < 4; ++k) mv[k] = *reinterpret_cast<const int4*>(msgs + k * vol + s * Dp + d0);
+    int b[8];
+    unpack8u(cv, b);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) b[j] += v[j];
-            }
+    for (int k = 0; k < 4; ++k) {
+        const int keep = valid && has[k] ? -1 : 0;  // a side with no neighbour holds no message
+        int v[8];
+        unpack8u(make_int4(mv[k].x & keep, mv[k].y & keep, mv[k].z & keep, mv[k].w & keep), v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b[j] += v[j];
     }
     // key = belief * 256 + d: the minimum key is the smallest d among the minimal beliefs
     int key = 0x7fffffff;

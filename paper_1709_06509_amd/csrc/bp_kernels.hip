@@ -233,61 +233,96 @@ __global__ __launch_bounds__(kThreads) void k_export_cost(const int16_t* __restr
     for (int j = 0; j < 8; ++j) if (d0 + j < D) dst[j] = (int16_t)v[j];
 }
 
-constexpr int kEnergyBlocks = 1024;
+constexpr int kEnergyBlocks = 1024;  // a multiple of kThreads (the final sum reads kEnergyBlocks / kThreads a lane)
+static_assert(kEnergyBlocks % kThreads == 0, "energy blocks");
 
+// Sum over the workgroup of e, and whether any lane saw an out-of-range disparity: a
+// butterfly inside each wave, then one LDS word per wave (a single barrier).
+__device__ __forceinline__ void block_sum(long long e, int bad, long long* wsum, int* wbad, long long* total,
+                                          int* anybad)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+    const bool wbad_any = __ballot(bad != 0) != 0ull;
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        wsum[wave] = e;
+        wbad[wave] = wbad_any ? 1 : 0;
+    }
+    __syncthreads();
+    long long t = 0;
+    int b = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        t += wsum[w];
+        b |= wbad[w];
+    }
+    *total = t;
+    *anybad = b;
+}
+
+// Energy of a labelling over a grid-stride range of pixels: the data cost of each pixel and
+// the smoothness cost of its right and lower edges.  The three disparities are loaded
+// together, then the cost at the pixel's disparity (which depends on one of them).
 __global__ __launch_bounds__(kThreads) void k_energy_partial(const int16_t* __restrict__ cost,
                                                               const int16_t* __restrict__ disp, int W, int H,
                                                               int D, int lam, int T, long long* part, int* bad)
 {
-    __shared__ long long red[kThreads];
-    __shared__ int anybad;
-    if (threadIdx.x == 0) anybad = 0;
-    __syncthreads();
+    __shared__ long long wsum[kThreads / 64];
+    __shared__ int wbad[kThreads / 64];
     long long e = 0;
     int mybad = 0;
     const long long n = (long long)W * H;
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
         const int y = (int)(i / W), x = (int)(i - (long long)y * W);
+        const bool right = x + 1 < W, down = y + 1 < H;
         const int dp = disp[i];
-        if (dp < 0 || dp >= D) { mybad = 1; continue; }
-        e += cost[i * D + dp];
-        if (x + 1 < W) {
-            int dq = disp[i + 1];
-            if (dq >= 0 && dq < D) e += (long long)lam * min(abs(dp - dq), T);
-        }
-        if (y + 1 < H) {
-            int dq = disp[i + W];
-            if (dq >= 0 && dq < D) e += (long long)lam * min(abs(dp - dq), T);
-        }
+        const int dr = disp[right ? i + 1 : i];
+        const int dd = disp[down ? i + W : i];
+        const bool ok = dp >= 0 && dp < D;
+        const int c = cost[i * D + (ok ? dp : 0)];
+        // selects, not branches: a branch would pull the neighbours' loads in after dp's
+        const int jr = right && dr >= 0 && dr < D ? min(abs(dp - dr), T) : 0;
+        const int jd = down && dd >= 0 && dd < D ? min(abs(dp - dd), T) : 0;
+        e += ok ? (long long)c + (long long)lam * (jr + jd) : 0;
+        mybad |= ok ? 0 : 1;
     }
-    red[threadIdx.x] = e;
-    if (mybad) anybad = 1;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
+    long long t;
+    int b;
+    block_sum(e, mybad, wsum, wbad, &t, &b);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t;
+        bad[blockIdx.x] = b;
     }
-    if (threadIdx.x == 0) { part[blockIdx.x] = red[0]; bad[blockIdx.x] = anybad; }
 }
 
 __global__ __launch_bounds__(kThreads) void k_energy_final(const long long* part, const int* bad, int nb,
                                                             int64_t* out)
 {
-    __shared__ long long red[kThreads];
-    __shared__ int anybad;
-    if (threadIdx.x == 0) anybad = 0;
-    __syncthreads();
+    __shared__ long long wsum[kThreads / 64];
+    __shared__ int wbad[kThreads / 64];
+    // nb <= kEnergyBlocks: a fixed number of loads a lane, all issued before any is used
+    constexpr int kPer = kEnergyBlocks / kThreads;
+    long long pv[kPer];
+    int bv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = (int)threadIdx.x + u * kThreads;
+        pv[u] = part[i < nb ? i : 0];
+        bv[u] = bad[i < nb ? i : 0];
+    }
     long long e = 0;
     int b = 0;
-    for (int i = threadIdx.x; i < nb; i += kThreads) { e += part[i]; b |= bad[i]; }
-    red[threadIdx.x] = e;
-    if (b) anybad = 1;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const bool in = (int)threadIdx.x + u * kThreads < nb;
+        e += in ? pv[u] : 0;
+        b |= in ? bv[u] : 0;
     }
-    if (threadIdx.x == 0) *out = anybad ? (int64_t)(-9223372036854775807LL - 1) : (int64_t)red[0];
+    long long t;
+    int anybad;
+    block_sum(e, b, wsum, wbad, &t, &anybad);
+    if (threadIdx.x == 0) *out = anybad ? (int64_t)(-9223372036854775807LL - 1) : (int64_t)t;
 }
 
 __global__ __launch_bounds__(kThreads) void k_luma(const uint8_t* __restrict__ rgb, long long n, uint8_t* __restrict__ y)

@@ -62,27 +62,46 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
     int* cJJ = cJ + nJ;
     int* V = cJJ + nJ;  // [nI][D]
 
-    // 1. packed byte columns of the window rows (clamped), zero beyond the window
-    for (int c = threadIdx.x; c < nI + nJ; c += kThreads) {
-        const bool left = c < nI;
-        const uint8_t* img = left ? L : R;
-        const int u = left ? uI0 + c : uJ0 + (c - nI);
-        const int xx = clampi(u, 0, W - 1);
-        unsigned w4[4] = {0u, 0u, 0u, 0u};
+    // 1. packed byte columns of the window rows (clamped), zero beyond the window.  A thread
+    //    takes two columns a round and issues all their loads before using any (a lane past
+    //    the last column reads column 0 and drops it): one memory latency a round.
+    constexpr int kU = 2;
+    for (int c0 = threadIdx.x; c0 < nI + nJ; c0 += kU * kThreads) {
+        unsigned bytes[kU][WIN];
 #pragma unroll
-        for (int j = 0; j < WIN; ++j) {
-            const unsigned v = img[(long long)clampi(y - r + j, 0, H - 1) * W + xx];
-            w4[j >> 2] |= v << (8 * (j & 3));
-        }
-        const uint4 pk = make_uint4(w4[0], w4[1], w4[2], w4[3]);
-        unsigned s = 0, ss = 0;
+        for (int q = 0; q < kU; ++q) {
+            const int c = c0 + q * kThreads < nI + nJ ? c0 + q * kThreads : 0;
+            const bool left = c < nI;
+            const uint8_t* img = left ? L : R;
+            const int xx = clampi(left ? uI0 + c : uJ0 + (c - nI), 0, W - 1);
 #pragma unroll
-        for (int k = 0; k < (WIN + 3) / 4; ++k) {
-            s = __builtin_amdgcn_udot4(w4[k], 0x01010101u, s, false);
-            ss = __builtin_amdgcn_udot4(w4[k], w4[k], ss, false);
+            for (int j = 0; j < WIN; ++j) bytes[q][j] = img[(long long)clampi(y - r + j, 0, H - 1) * W + xx];
         }
-        if (left) { colI[c] = pk; cI[c] = (int)s; cII[c] = (int)ss; }
-        else { colJ[c - nI] = pk; cJ[c - nI] = (int)s; cJJ[c - nI] = (int)ss; }
+        // keeps the scheduler from packing the first column, and waiting for it, before the
+        // second column's loads are issued
+        __builtin_amdgcn_sched_barrier(0);
+        unsigned w4[kU][4];
+#pragma unroll
+        for (int q = 0; q < kU; ++q) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w4[q][k] = 0u;
+#pragma unroll
+            for (int j = 0; j < WIN; ++j) w4[q][j >> 2] |= bytes[q][j] << (8 * (j & 3));
+        }
+#pragma unroll
+        for (int q = 0; q < kU; ++q) {
+            const int c = c0 + q * kThreads;
+            if (c >= nI + nJ) continue;
+            const uint4 pk = make_uint4(w4[q][0], w4[q][1], w4[q][2], w4[q][3]);
+            unsigned s = 0, ss = 0;
+#pragma unroll
+            for (int k = 0; k < (WIN + 3) / 4; ++k) {
+                s = __builtin_amdgcn_udot4(w4[q][k], 0x01010101u, s, false);
+                ss = __builtin_amdgcn_udot4(w4[q][k], w4[q][k], ss, false);
+            }
+            if (c < nI) { colI[c] = pk; cI[c] = (int)s; cII[c] = (int)ss; }
+            else { colJ[c - nI] = pk; cJ[c - nI] = (int)s; cJJ[c - nI] = (int)ss; }
+        }
     }
     __syncthreads();
 
