@@ -13,6 +13,7 @@
 //
 // Per-pixel arithmetic is the same as the per-launch kernel (transform, freeze rule);
 // only the storage differs: LDS holds the region row-major, [pixel][Dp] per volume.
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -163,9 +164,13 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
         const bool check = MODE == 1 && t >= 2;
         // under the freeze rule, list the active pixels of this colour first (a ballot mask
         // per wave, ranks from mbcnt and the counts of the waves before), so that the update
-        // loop below runs over active pixels only
+        // loop below runs over active pixels only.  That pays where a compute unit holds more
+        // waves than it has SIMDs (packing the active pixels onto fewer waves shortens the
+        // longest SIMD queue); with a wave per SIMD or fewer it only adds two barriers, and
+        // a wave whose pixels are all frozen skips the update anyway.
+        const bool listed = check && a.compact;
         int count = npix;
-        if (check) {
+        if (listed) {
             int total = 0;
             int ry = ry_first, i = i_first;
             for (int p0 = 0; p0 < npix; p0 += pstep) {
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
         }
         int ry = ry_first, i = i_first;
         for (int p = p_first; p < count; p += pstep) {
-            if (check) {
+            if (listed) {
                 const int code = llist[p];
                 ry = code >> 16;
                 i = code & 0xffff;
@@ -239,6 +244,17 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
                     mp[q][v] = *reinterpret_cast<const int4*>(lm + role_msg(hi, q) * cap * Dp + rr * Dp + d0 + 8 * v);
             const bool act = valid && (!check || lsa[rr] != 0);
             const int sb = lsb[rr];  // the pixel's count of unchanged half-steps, read with the rest
+            if (check && !listed && __ballot(act) == 0ull) {
+                // every pixel of the wave is frozen (wave-uniform: no lane exchange is skipped
+                // by part of a pixel's lanes)
+                i += step_i;
+                ry += step_ry;
+                if (i >= RWc) {
+                    i -= RWc;
+                    ++ry;
+                }
+                continue;
+            }
             int4 out[4][NV];
             if constexpr (NARROW) {
                 narrow_update<G>(nl, c4, mp, a.D, pad, (unsigned)a.lambda, (unsigned)a.capv, out);
@@ -537,17 +553,23 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t st)
     fused_prepare();
     if (lds + g_fused_static_lds > (size_t)kFusedLdsBytes) return hipErrorInvalidValue;
     const dim3 grid((unsigned)tiles), block((unsigned)fused_threads(a.G, a.rmax));
+    // list active pixels only where a compute unit holds more than a wave per SIMD (a
+    // workgroup per compute unit while the tiles fit the 256 units)
+    FusedArgs b = a;
+    b.compact = (long long)((tiles + 255) / 256) * ((block.x + 63) / 64) > 4 ? 1 : 0;
+    const char* fc = getenv("BPSTEREO_FUSED_COMPACT");  // test hook: force the listing on (1) or off (0)
+    if (fc && (fc[0] == '0' || fc[0] == '1') && fc[1] == 0) b.compact = fc[0] - '0';
 #define BPST_FUSED_G(GG)                                                                        \
     case GG:                                                                                    \
         if (a.narrow) {                                                                         \
-            if (a.mode == 1) hipLaunchKernelGGL((k_fused<GG, 1, true>), grid, block, lds, st, a);  \
-            else hipLaunchKernelGGL((k_fused<GG, 0, true>), grid, block, lds, st, a);              \
+            if (a.mode == 1) hipLaunchKernelGGL((k_fused<GG, 1, true>), grid, block, lds, st, b);  \
+            else hipLaunchKernelGGL((k_fused<GG, 0, true>), grid, block, lds, st, b);              \
         } else {                                                                                \
-            if (a.mode == 1) hipLaunchKernelGGL((k_fused<GG, 1, false>), grid, block, lds, st, a); \
-            else hipLaunchKernelGGL((k_fused<GG, 0, false>), grid, block, lds, st, a);             \
+            if (a.mode == 1) hipLaunchKernelGGL((k_fused<GG, 1, false>), grid, block, lds, st, b); \
+            else hipLaunchKernelGGL((k_fused<GG, 0, false>), grid, block, lds, st, b);             \
         }                                                                                       \
         break;
-    switch (a.G) {
+    switch (b.G) {
         BPST_FUSED_G(1) BPST_FUSED_G(2) BPST_FUSED_G(4) BPST_FUSED_G(8)
         default: return hipErrorInvalidValue;
     }

@@ -79,6 +79,29 @@ def test_fused_matches_oracle(case, fused_ctx):
     assert np.array_equal(host(d), rd), "disparities differ"
 
 
+@pytest.mark.parametrize("compact", ["0", "1"])
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[4], CASES[5], CASES[7], CASES[9]])
+def test_fused_listing_forced(case, compact, fused_ctx):
+    """Freeze-rule half-steps in fused launches with the listing of active pixels forced on
+    or off (by default it is used only where a compute unit holds more than a wave per SIMD)."""
+    W, H, D, L, iters, skip, tile = case
+    say(f"fused {W}x{H} D={D} tile={tile}, listing {compact}")
+    if tile:
+        os.environ["BPSTEREO_FUSED_TILE"] = tile
+    else:
+        os.environ.pop("BPSTEREO_FUSED_TILE", None)
+    os.environ["BPSTEREO_FUSED_COMPACT"] = compact
+    try:
+        cost = cost_of(W, H, D, 900 + W + H + D)
+        d, m, _ = B.bp_hierarchical_solve(gpu(cost), L, iters, 64, 4, skip, 2, want_msgs=True, ctx=fused_ctx)
+        torch.cuda.synchronize()
+    finally:
+        os.environ.pop("BPSTEREO_FUSED_COMPACT", None)
+    rd, rm, _ = oracle.bp_solve(cost, L, iters, 64, 4, skip, 2)
+    assert np.array_equal(host(m), rm), "messages differ"
+    assert np.array_equal(host(d), rd), "disparities differ"
+
+
 def test_fused_warm_start_matches_oracle(fused_ctx):
     W, H, D, L = 36, 28, 16, 3
     os.environ["BPSTEREO_FUSED_TILE"] = "5x4"

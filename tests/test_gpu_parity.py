@@ -202,6 +202,9 @@ def test_energy():
         assert e == oracle.energy(cost, disp, 64, 4)
         disp[H // 2, W // 2] = D  # out of range
         assert host(B.bp_energy(gpu(cost), gpu(disp), 64, 4))[0] == -(2**63)
+        disp[H // 2, W // 2] = 0
+        disp[H - 1, W - 1] = -1  # negative, on the pixel with neither a right nor a lower edge
+        assert host(B.bp_energy(gpu(cost), gpu(disp), 64, 4))[0] == -(2**63)
 
 
 def test_energy_shared_workspace_and_graph_replays():
