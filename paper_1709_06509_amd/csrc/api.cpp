@@ -353,6 +353,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         if (l == start) return t > 0;
         return params->iters[start] >= 2;
     };
+    int wta_colour = -1;  // the pixels the WTA launch covers: -1 all, else one colour
     for (int l = start; l >= 0; --l) {
         int16_t* msgs = M[l & 1];
         const int iters = params->iters[l];
@@ -457,6 +458,14 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                 // bound the launch.
                 a.stream = bpst::stream_scale(pl.lv[l], pl.G) ? 1 : 0;
                 a.narrow = narrow_ok(l, t) && !count && pl.G <= bpst::kNarrowMaxG && !a.stream ? 1 : 0;
+                // plain BP's last half-step at the finest scale also writes the winner of the
+                // pixels it updates (their incoming messages are final): the WTA launch then
+                // covers the other colour only
+                a.disp = nullptr;
+                if (l == 0 && mode == 0 && !a.narrow && t == iters - 1) {
+                    a.disp = disparity;
+                    wta_colour = 1 - (t & 1);
+                }
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (ctx && ctx->timing) {
                     if (ctx->used == ctx->events.size()) {
@@ -524,7 +533,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
             }
         }
     }
-    HIP_TRY(bpst::launch_wta(C[0], M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, disparity, st));
+    HIP_TRY(bpst::launch_wta(C[0], M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, wta_colour, disparity, st));
     if (final_msgs_or_null)
         HIP_TRY(bpst::launch_export(M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, final_msgs_or_null, st));
     return BP_OK;

@@ -756,6 +756,16 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
             }
             transform2<G>(ha, hb, a.lambda, a.capv, lane, out[k][0], out[k + 1][0]);
         }
+        if (a.disp) {
+            // the winner from the same sums: after plain BP's last half-step at the finest
+            // scale the updated pixels' incoming messages are final (their neighbours, the
+            // other colour, are not updated again), so Hs is their belief (as in wta_pixel)
+            int key = 0x7fffffff;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) if (d0 + j < a.D) key = min(key, Hs[j] * 256 + d0 + j);
+            key = group_min<G>(key);
+            if (act && lane == 0) a.disp[(long long)y * W + x] = (int16_t)(key & 255);
+        }
     }
     // Every decision first, then every store: arithmetic placed after a store made the
     // compiler wait for the store to complete before it reused the store's registers.

@@ -185,12 +185,19 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
     }
 }
 
+// colour < 0: every slot; otherwise the slots of one colour (index y * Wh + xi)
 template <int G>
 __global__ __launch_bounds__(kThreads) void k_wta(const int16_t* __restrict__ c0, const int16_t* __restrict__ msgs,
-                                                   long long vol, Level lv, int D, int16_t* __restrict__ disp)
+                                                   long long vol, Level lv, int D, int colour,
+                                                   int16_t* __restrict__ disp)
 {
     const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
-    wta_pixel<G>(c0, msgs, vol, lv, D, disp, t / G, (int)(t & (G - 1)));
+    long long gi = t / G;
+    if (colour >= 0) {
+        const long long y = gi / lv.Wh, xi = gi - y * lv.Wh;
+        gi = y < lv.H ? (2 * y + colour) * lv.Wh + xi : lv.slots();  // slots(): no pixel
+    }
+    wta_pixel<G>(c0, msgs, vol, lv, D, disp, gi, (int)(t & (G - 1)));
 }
 
 template <int G>
@@ -465,11 +472,12 @@ hipError_t launch_halfstep(const HalfstepArgs& a, hipStream_t st)
     }
 }
 
-hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G, int16_t* disp,
-                      hipStream_t st)
+hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G, int colour,
+                      int16_t* disp, hipStream_t st)
 {
-    const unsigned g = grid_for(lv.slots(), G);
-    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_wta<GG>), dim3(g), dim3(kThreads), 0, st, c0, msgs, vol, lv, D, disp));
+    const unsigned g = grid_for(colour < 0 ? lv.slots() : (long long)lv.H * lv.Wh, G);
+    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_wta<GG>), dim3(g), dim3(kThreads), 0, st, c0, msgs, vol, lv, D, colour,
+                                          disp));
     return hipGetLastError();
 }
 

@@ -60,6 +60,8 @@ struct HalfstepArgs {
     int stream;              // nontemporal loads and stores (the scale's volumes exceed the caches)
     DevStats* stats;
     int level;
+    int16_t* disp;           // non-null (plain BP, int32 path, last half-step of the finest scale):
+                             // also write each updated pixel's winner-take-all disparity
 };
 
 // Coarsest pixels that one workgroup of `threads` lanes takes in the one-launch cost
@@ -230,7 +232,8 @@ hipError_t launch_init(const int16_t* parent, Level lp, long long pvol, int16_t*
 hipError_t launch_import(const int16_t* warm, int16_t* msgs, Level lv, long long vol, int D, int G,
                          uint8_t* state_a, uint8_t* state_b, int mode, hipStream_t st);
 hipError_t launch_halfstep(const HalfstepArgs& a, hipStream_t st);
-hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G,
+// colour -1: every pixel; 0 or 1: only the pixels with (x + y) & 1 == colour
+hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G, int colour,
                       int16_t* disparity, hipStream_t st);
 hipError_t launch_export(const int16_t* msgs, long long vol, Level lv, int D, int G, int16_t* out,
                          hipStream_t st);

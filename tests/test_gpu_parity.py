@@ -117,6 +117,11 @@ CASES = [
     (14, 14, 16, 3, [8, 8, 8], 0, 4, 0),
     (14, 14, 16, 3, [8, 8, 8], 64, 0, 0),
     (14, 14, 16, 3, [8, 8, 8], 65535, 100, 0),
+    # plain BP on the int32 path: the last finest half-step also writes the winners of the
+    # colour it updates (odd and even half-step counts: either colour)
+    (19, 23, 16, 3, [7, 4, 4], 65535, 100, 0),
+    (21, 17, 40, 2, [6, 5], 1000, 900, 0),
+    (15, 26, 100, 2, [1, 3], 300, 200, 0),
     # deep hierarchies: the one-launch pyramid is too large for LDS here and falls back
     (70, 90, 64, 6, [4, 3, 3, 3, 3, 3], 64, 4, 1),
     (37, 45, 256, 5, [3, 3, 3, 3, 3], 64, 4, 0),
