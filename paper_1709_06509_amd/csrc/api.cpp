@@ -711,17 +711,21 @@ int32_t plan_batch(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* 
         stream[l] = bytes > bpst::kStreamBytes ? 1 : 0;
     }
     // phase sequence (the same as a single solve without a warm start)
-    b.phases.push_back({bpst::kPhPyramid, 0, 0, 0, 0, 0});
+    b.phases.push_back({bpst::kPhPyramid, 0, 0, 0, 0, 0, 0});
     for (int l = b.L - 1; l >= 0; --l) {
         const bool fuse = p->iters[l] >= 2 && p->skip_mode != 2;
-        if (!fuse) b.phases.push_back({bpst::kPhInit, l, 0, bpst::kSrcOwn, 0, 0});
+        if (!fuse) b.phases.push_back({bpst::kPhInit, l, 0, bpst::kSrcOwn, 0, 0, 0});
         for (int t = 0; t < p->iters[l]; ++t) {
             int src = bpst::kSrcOwn;
             if (t == 0 && fuse) src = (l == b.L - 1) ? bpst::kSrcZero : bpst::kSrcParent;
-            b.phases.push_back({bpst::kPhHalfstep, l, t, src, 0, stream[l]});
+            // plain BP's last half-step of the finest scale also writes the winners of the
+            // pixels it updates (their incoming messages are final)
+            const int wta = l == 0 && t == p->iters[0] - 1 && p->skip_mode == 0 ? 1 : 0;
+            b.phases.push_back({bpst::kPhHalfstep, l, t, src, 0, stream[l], wta});
         }
     }
-    b.phases.push_back({bpst::kPhWta, 0, 0, 0, 0, 0});
+    const int wta_colour = p->iters[0] >= 1 && p->skip_mode == 0 ? (p->iters[0] - 1) & 1 : -1;
+    b.phases.push_back({bpst::kPhWta, 0, 0, 0, 0, stream[0], wta_colour});
     b.nphases = (int)b.phases.size();
     b.tiles.assign((size_t)b.nphases * (n + 1), 0);
     for (int ph = 0; ph < b.nphases; ++ph) {

@@ -120,6 +120,7 @@ __device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& 
         h.t = ph.t;
         h.K = a.K;
         h.mode = MODE;
+        if (MODE == 0 && ph.wta) h.disp = Q.disparity;  // written on the int32 path only
         if constexpr (HV == kHvRuntime) {
             if constexpr (G <= kNarrowMaxG) {
                 if (a.narrow && !ph.stream) {
@@ -135,6 +136,13 @@ __device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& 
             halfstep_pixel<G, MODE, SRC, N, (HV & kHvStream) != 0>(h, (int)gi, lane);
         }
     } else {
+        // the colour the last half-step already decided, where it ran on the int32 path (the
+        // same rule as the half-step's own choice above)
+        const bool narrow = G <= kNarrowMaxG && a.narrow && !ph.stream;
+        if (MODE == 0 && ph.wta >= 0 && !narrow && gi < Q.lv[0].slots()) {
+            const long long row = gi / Q.lv[0].Wh;  // 2 y + colour
+            if ((int)(row & 1) == ph.wta) return;
+        }
         wta_pixel<G>(Q.c[0], Q.m[0], Q.vol[0], Q.lv[0], Q.D, Q.disparity, gi, lane);
     }
 }

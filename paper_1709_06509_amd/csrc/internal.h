@@ -113,7 +113,11 @@ enum PhaseType { kPhPyramid = 0, kPhInit = 1, kPhHalfstep = 2, kPhWta = 3 };
 struct PhaseDesc {
     int type, level, t, source;
     int table;   // offset in BatchArgs::tiles of this phase's prefix sums (npairs + 1 ints)
-    int stream;  // half-step: the pairs' working sets at this scale together exceed the caches
+    int stream;  // half-step: the pairs' working sets at this scale together exceed the caches;
+                 // WTA: the same flag of the last half-step of the finest scale
+    int wta;     // half-step: plain BP's last at the finest scale, which also writes the winners
+                 // of the pixels it updates on the int32 path; WTA: the colour of those pixels
+                 // (-1: none), skipped wherever that half-step ran on the int32 path
 };
 
 struct BatchArgs {

@@ -165,6 +165,28 @@ def test_batch_narrow_schedule_matches_oracle(skip):
         assert np.array_equal(host(batch.disps[i]), d), f"pair {i} disparity"
 
 
+@pytest.mark.parametrize("sched", [0, 1, 2])
+def test_batch_plain_odd_finest_halfsteps(sched):
+    """Plain BP with an odd number of finest half-steps: the last one updates the other
+    colour, whose winners it writes itself (int32 path), the WTA phase covering the rest."""
+    shapes = [(40, 32, 16), (33, 21, 64), (70, 22, 5), (26, 18, 128), (31, 17, 100)]
+    pairs = []
+    for i, (W, H, D) in enumerate(shapes):
+        p = synth.make_pair(W, H, D, (3, 5), False, 0, False, seed=900 + i)
+        pairs.append((p["left"], p["right"], D))
+    params = B.make_batch_params(5, 3, [5, 4, 3], 64, 4, skip_mode=0)
+    say(f"plain batch, 5 finest half-steps, schedule {sched}")
+    batch = B.Batch([gpu(l) for l, _, _ in pairs], [gpu(r) for _, r, _ in pairs], [D for _, _, D in pairs], params)
+    ctx = B.Context()
+    B.set_batch_schedule(ctx, sched, 1, 0)
+    batch.solve(ctx)
+    assert batch.status() == 0
+    for i, (l, r, D) in enumerate(pairs):
+        c = oracle.cost_volume(l, r, D, 5)
+        d, _, _ = oracle.bp_solve(c, 3, [5, 4, 3], 64, 4, 0, 2, want_msgs=False)
+        assert np.array_equal(host(batch.disps[i]), d), f"pair {i} disparity"
+
+
 def test_full_benchmark_batch():
     """The 256-pair batch the benchmark times, autotuned and replayed from a graph: sampled
     pairs equal their solo solves bit for bit (costs and disparities), and the smallest pair
