@@ -161,15 +161,22 @@ __device__ __forceinline__ void ncc_tile(const uint8_t* __restrict__ L, const ui
         }
         long long o = ((long long)y * W + x0 + i0) * D + d;
         const float fscale = (float)scale;
-        for (int i = i0; i < i1; ++i, o += D) {
-            sij += V[(i + WIN - 1) * D + d];
-            const int drop = V[i * D + d];
+        // the columns entering and leaving the window advance by a row of V a step (no index
+        // products in the loop)
+        const int* vin = V + (i0 + WIN - 1) * D + d;
+        const int* vout = V + i0 * D + d;
+        for (int i = i0; i < i1; ++i, o += D, vin += D, vout += D) {
             const int x = x0 + i;
             const bool outside = x - d < 0;  // no right pixel: the truncation cost
-            // window <= 13: every product and difference below fits in int32
             const int u = outside ? 0 : i - d + (D - 1);
+            // all four LDS reads first, so that they overlap
             const int4 qi = QI[i], qj = QJ[u];
-            const int num = n * sij - qi.x * qj.x;
+            const int add = *vin, drop = *vout;
+            __builtin_amdgcn_sched_barrier(0);
+            sij += add;
+            // window <= 13: every product and difference below fits in int32, and the factors
+            // (n, S_IJ <= 169 * 255^2, S_I, S_J <= 169 * 255) fit the 24-bit multiplier
+            const int num = (int)(__umul24((unsigned)n, (unsigned)sij) - __umul24((unsigned)qi.x, (unsigned)qj.x));
             const bool flat = qi.y == 0 || qj.y == 0;
             // fp32 estimate: c carries at most about 4 units of rounding (two conversions,
             // two reciprocal roots of 1 ulp, two products), relative error below 5e-7, so
