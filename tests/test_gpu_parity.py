@@ -122,6 +122,7 @@ CASES = [
     (19, 23, 16, 3, [7, 4, 4], 65535, 100, 0),
     (21, 17, 40, 2, [6, 5], 1000, 900, 0),
     (15, 26, 100, 2, [1, 3], 300, 200, 0),
+    (19, 23, 16, 3, [0, 4, 4], 65535, 100, 0),  # no finest half-step: the WTA covers both colours
     # deep hierarchies: the one-launch pyramid is too large for LDS here and falls back
     (70, 90, 64, 6, [4, 3, 3, 3, 3, 3], 64, 4, 1),
     (37, 45, 256, 5, [3, 3, 3, 3, 3], 64, 4, 0),
