@@ -90,10 +90,16 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
     // 1. load the region: cost, incoming messages (own, parent's or zero), and (before t0 = 2)
     //    the initial freeze state.  A thread takes two elements per round and issues all their
     //    global loads before any LDS store, so the round costs one memory latency, not two.
+    //    Every load reads a valid address (the region's first pixel for a lane past the end,
+    //    the pixel's own slot for a missing neighbour) and is masked afterwards: a load under
+    //    a per-lane branch made the compiler wait for the first element's loads before it
+    //    issued the second's.
     constexpr int kU = 2;
     for (int e0 = threadIdx.x; e0 < R * G; e0 += kU * blockDim.x) {
         int4 cv[kU], mv[kU][4];
-        int rv[kU];
+        int rv[kU], keep[kU][4];
+        const int4* pc[kU];
+        const int4* pm[kU][4];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int e = e0 + u * (int)blockDim.x;
@@ -105,23 +111,27 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
             const long long slot = slot_of(x, y, Wh);
             const int d0 = lane * 8;
             rv[u] = in ? r : -1;
-            cv[u] = in ? *reinterpret_cast<const int4*>(a.cost + slot * Dp + d0) : make_int4(0, 0, 0, 0);
+            pc[u] = reinterpret_cast<const int4*>(a.cost + slot * Dp + d0);
             const bool has[4] = {x > 0, x < W - 1, y > 0, y < H - 1};
+            // the source picks the volumes and the slot (no branch); zero messages read this
+            // scale's own volumes and keep nothing
+            const bool parent = a.source == kSrcParent;
+            const int px = x >> 1, py = y >> 1;
+            const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
+            const int16_t* src = parent ? a.pmsgs : a.msgs;
+            const long long vol = parent ? a.pvol : a.vol;
+            const long long sl = parent ? slot_of(px, py, a.plv.Wh) : slot;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) mv[u][k] = make_int4(0, 0, 0, 0);
-            if (in && a.source == kSrcOwn) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (has[k]) mv[u][k] = *reinterpret_cast<const int4*>(a.msgs + k * a.vol + slot * Dp + d0);
-            } else if (in && a.source == kSrcParent) {
-                const int px = x >> 1, py = y >> 1;
-                const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
-                const long long ps = slot_of(px, py, a.plv.Wh);
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (has[k] && phas[k])
-                        mv[u][k] = *reinterpret_cast<const int4*>(a.pmsgs + k * a.pvol + ps * Dp + d0);
+            for (int k = 0; k < 4; ++k) {
+                pm[u][k] = reinterpret_cast<const int4*>(src + k * vol + sl * Dp + d0);
+                keep[u][k] = a.source != kSrcZero && has[k] && (!parent || phas[k]) ? -1 : 0;
             }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            cv[u] = *pc[u];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) mv[u][k] = *pm[u][k];
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -130,7 +140,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
             const int d0 = (e0 + u * (int)blockDim.x - r * G) * 8;
             *reinterpret_cast<int4*>(lc + (long long)r * Dp + d0) = cv[u];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) *reinterpret_cast<int4*>(lm + k * cap * Dp + (long long)r * Dp + d0) = mv[u][k];
+            for (int k = 0; k < 4; ++k) {
+                const int m = keep[u][k];
+                *reinterpret_cast<int4*>(lm + k * cap * Dp + (long long)r * Dp + d0) =
+                    make_int4(mv[u][k].x & m, mv[u][k].y & m, mv[u][k].z & m, mv[u][k].w & m);
+            }
             if (MODE == 1 && !have_state && d0 == 0) {
                 lsa[r] = 1;  // every pixel is active before its third half-step
                 lsb[r] = 0;
