@@ -301,12 +301,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(FusedArgs a)
             for (int e = 0; e < NK; ++e) {
                 const bool tk = valid && hr[e] && ir[e];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    op[e][v] = make_int4(0, 0, 0, 0);
-                    if (check)
-                        op[e][v] = *reinterpret_cast<const int4*>(lm + (role_msg(hi, e) ^ 1) * cap * Dp +
-                                                                  (tk ? (long long)nr[e] : rr) * Dp + d0 + 8 * v);
-                }
+                for (int v = 0; v < NV; ++v)  // (read whether or not compared: a valid address, no branch)
+                    op[e][v] = *reinterpret_cast<const int4*>(lm + (role_msg(hi, e) ^ 1) * cap * Dp +
+                                                              (tk ? (long long)nr[e] : rr) * Dp + d0 + 8 * v);
             }
             // every decision first, then every store (arithmetic after a store would wait for it)
             bool all_eq = true;
