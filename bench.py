@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="production", choices=["production", "tiny", "large", "batched"])
+    ap.add_argument("--workload", default="production", choices=["production", "tiny", "large", "batched", "jacobi"])
     ap.add_argument("--batch-pairs", type=int, default=256, help="pairs of the batched workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-checker sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-checker leg")
@@ -203,6 +203,60 @@ def run_batched(args):
     }
 
 
+def run_jacobi(args):
+    """The Jacobi schedule (two sets of four message volumes) on the large pair's cost
+    volume: 12 iterations of 1920x1080, D = 128, from zero messages."""
+    import torch
+
+    from paper_1709_06509_amd import bpstereo as B
+    from paper_1709_06509_amd import synth
+
+    w = dict(synth.WORKLOADS["large"])
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = synth.workload_pair("large")
+    D, H, W, n = w["num_disp"], w["height"], w["width"], w["iters"]
+    gl, gr = B.stereo_luma(torch.from_numpy(p["left"]).to(dev)), B.stereo_luma(torch.from_numpy(p["right"]).to(dev))
+    cost = B.stereo_cost_volume(gl, gr, D, w["window"])
+    ws = torch.empty(B.bp_jacobi_workspace_bytes(W, H, D), dtype=torch.uint8, device=dev)
+    out = torch.empty((4, H, W, D), dtype=torch.int16, device=dev)
+    stream = torch.cuda.Stream()
+
+    def timed(iterations, reps):
+        with torch.cuda.stream(stream):
+            for _ in range(2):
+                B.bp_jacobi_iterations(cost, w["lam"], w["trunc"], iterations, workspace=ws, out=out, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                B.bp_jacobi_iterations(cost, w["lam"], w["trunc"], iterations, workspace=ws, out=out, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    steps = max(1, args.steps // 20)
+    per_call = timed(n, steps)
+    # one iteration = two half-step launches (one per colour); their time is the difference
+    # between calls of n and 2 iterations, which share the conversions in and out
+    per_iter = (per_call - timed(2, steps)) / (n - 2)
+    msgs = 4 * W * H - 2 * W - 2 * H  # directed messages an iteration recomputes
+    byts = 2 * D * W * H + 4 * D * msgs  # the cost once, every message read once and written once
+    achieved = byts / per_iter / 1e9
+    return {
+        "metric": METRIC, "value": n * msgs / per_call / 1e9, "unit": "Gmsg-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": 2, "ms_per_step": per_call * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int16", "data": "synthetic",
+        "config": {"workload": f"jacobi: {n} Jacobi iterations (two sets of four message volumes) on the "
+                               f"{W}x{H}, D={D} synthetic pair's {w['window']}x{w['window']} NCC cost volume, "
+                               "from zero messages, with the conversions in and out"},
+        "roofline": {"bound": "hbm", "kernel": "k_halfstep<16, 0, 0, 4> (streamed), two launches an iteration",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "avg_launch_us": per_iter / 2 * 1e6, "algorithmic_bytes_per_launch": byts / 2,
+                     "launches_per_step": 2 * n},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -210,6 +264,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         print(json.dumps(run_batched(args)))
+        return
+    if args.workload == "jacobi":
+        print(json.dumps(run_jacobi(args)))
         return
     import numpy as np
     import torch

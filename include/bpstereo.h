@@ -165,6 +165,34 @@ int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32_t widt
                               int16_t* disparity, int16_t* final_msgs_or_null, bp_stats* stats_or_null,
                               void* stream);
 
+/* Bytes of device workspace bp_jacobi_iterations needs (0 if the sizes are invalid). */
+size_t bp_jacobi_workspace_bytes(int32_t width, int32_t height, int32_t num_disp);
+
+/*
+ * Flat min-sum BP on one scale with the Jacobi schedule ("GPU Implementation": the
+ * messages of an iteration are computed from the previous iteration's, held in a second
+ * set of four volumes; the paper keeps eight textures per scale for this).  Iteration i
+ * computes, for every pixel p and neighbour q, the message of "Fast Converging BP" from
+ * C(p) and p's incoming messages of iteration i - 1 (the same rule as a checkerboard
+ * half-step, applied to both colours at once).  Iteration i's messages from the pixels
+ * of colour c equal half-step i - 1 of a checkerboard run started from the same messages
+ * when i - 1 has colour c, which makes this schedule a cross-check of the solve's.
+ *   cost               [device] int16 [H][W][D], any values
+ *   iterations         0..65536
+ *   init_msgs_or_null  [device] int16 [4][H][W][D], values 0..32767, the messages at
+ *                      iteration 0 in the layout of final_msgs (slot k of a pixel holds
+ *                      the message from its neighbour on side k: 0 left, 1 right, 2 up,
+ *                      3 down); slots without a neighbour are ignored; NULL: zeros
+ *   msgs_out           [device] int16 [4][H][W][D] output, the same layout; slots without
+ *                      a neighbour are written as zero
+ *   workspace          [device] at least bp_jacobi_workspace_bytes(...) bytes, 256-byte
+ *                      aligned; its content on entry does not matter
+ */
+int32_t bp_jacobi_iterations(const int16_t* cost, int32_t width, int32_t height, int32_t num_disp,
+                             int32_t lambda, int32_t trunc, int32_t iterations,
+                             const int16_t* init_msgs_or_null, int16_t* msgs_out, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
 /* Bytes of device workspace bp_energy needs (a fixed small amount). */
 size_t bp_energy_workspace_bytes(int32_t width, int32_t height);
 

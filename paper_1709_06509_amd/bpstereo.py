@@ -82,9 +82,14 @@ def _load():
         lib.bp_energy_workspace_bytes.argtypes = [_i32, _i32]
         lib.bp_energy_workspace_bytes.restype = ctypes.c_size_t
         lib.bp_energy.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t, _vp]
+        lib.bp_jacobi_workspace_bytes.argtypes = [_i32, _i32, _i32]
+        lib.bp_jacobi_workspace_bytes.restype = ctypes.c_size_t
+        lib.bp_jacobi_iterations.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.c_size_t,
+                                             _vp]
         for name in ("bp_context_create", "bp_context_destroy", "bp_context_set_timing", "bp_context_take_timing",
                      "bp_context_set_graphs", "bp_context_set_fused", "bp_context_graph_counts",
-                     "stereo_luma", "stereo_cost_volume", "bp_hierarchical_solve", "bp_energy"):
+                     "stereo_luma", "stereo_cost_volume", "bp_hierarchical_solve", "bp_energy",
+                     "bp_jacobi_iterations"):
             getattr(lib, name).restype = ctypes.c_int32
         _lib = lib
     return _lib
@@ -254,6 +259,27 @@ def bp_energy(cost, disparity, lam, trunc, workspace=None, out=None, stream=None
     _check(_load().bp_energy(_dev(cost, torch.int16, 3, "cost"), _dev(disparity, torch.int16, 2, "disparity"), W, H,
                              D, lam, trunc, _dev(out, torch.int64, 1, "energy"),
                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream)))
+    return out
+
+
+def bp_jacobi_workspace_bytes(width, height, num_disp):
+    return int(_load().bp_jacobi_workspace_bytes(width, height, num_disp))
+
+
+def bp_jacobi_iterations(cost, lam, trunc, iterations, init=None, workspace=None, out=None, stream=None):
+    """Flat Jacobi min-sum iterations on one scale: the int16 messages [4, H, W, D] after
+    `iterations` iterations from `init` (zeros if None)."""
+    H, W, D = cost.shape
+    need = bp_jacobi_workspace_bytes(W, H, D)
+    if need == 0:
+        raise ValueError("bad sizes")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=cost.device)
+    out = torch.empty((4, H, W, D), dtype=torch.int16, device=cost.device) if out is None else out
+    ip = None if init is None else _dev(init, torch.int16, 4, "init")
+    _check(_load().bp_jacobi_iterations(_dev(cost, torch.int16, 3, "cost"), W, H, D, lam, trunc, iterations, ip,
+                                        _dev(out, torch.int16, 4, "out"), ctypes.c_void_p(workspace.data_ptr()),
+                                        workspace.numel(), _stream(stream)))
     return out
 
 

@@ -1189,6 +1189,102 @@ BP_API int32_t bp_pyramid_level(const int16_t* cost, int32_t width, int32_t heig
     return ok();
 }
 
+namespace {
+// Workspace of the Jacobi schedule: the internal cost, then two sets of four message volumes.
+struct JacobiPlan {
+    int G, Dp;
+    bpst::Level lv;
+    long long vol;
+    size_t off_cost, off_msgs[2], total;
+};
+
+bool jacobi_valid(int W, int H, int D, std::string* why)
+{
+    if (W < 1 || H < 1 || W > 16384 || H > 16384) return *why = "width/height must be in 1..16384", false;
+    if (D < 1 || D > 256) return *why = "num_disp must be in 1..256", false;
+    return true;
+}
+
+JacobiPlan make_jacobi_plan(int W, int H, int D)
+{
+    JacobiPlan p{};
+    p.G = bpst::lanes_for(D);
+    p.Dp = 8 * p.G;
+    p.lv = bpst::make_level(W, H);
+    p.vol = p.lv.slots() * p.Dp;
+    size_t o = 0;
+    p.off_cost = o;
+    o = align_up(o + (size_t)p.vol * sizeof(int16_t));
+    for (int b = 0; b < 2; ++b) {
+        p.off_msgs[b] = o;
+        o = align_up(o + 4 * (size_t)p.vol * sizeof(int16_t));
+    }
+    p.total = o;
+    return p;
+}
+}  // namespace
+
+BP_API size_t bp_jacobi_workspace_bytes(int32_t width, int32_t height, int32_t num_disp)
+{
+    std::string why;
+    if (!jacobi_valid(width, height, num_disp, &why)) return 0;
+    return make_jacobi_plan(width, height, num_disp).total;
+}
+
+BP_API int32_t bp_jacobi_iterations(const int16_t* cost, int32_t width, int32_t height, int32_t num_disp,
+                                    int32_t lambda, int32_t trunc, int32_t iterations,
+                                    const int16_t* init_msgs_or_null, int16_t* msgs_out, void* workspace,
+                                    size_t workspace_bytes, void* stream)
+{
+    std::string why;
+    if (!jacobi_valid(width, height, num_disp, &why)) return fail(BP_E_INVAL, "%s", why.c_str());
+    if (lambda < 0 || lambda > 65535 || trunc < 0) return fail(BP_E_INVAL, "lambda/trunc out of range");
+    if (iterations < 0 || iterations > 65536) return fail(BP_E_INVAL, "iterations must be in 0..65536");
+    if (!cost || !msgs_out) return fail(BP_E_INVAL, "cost/msgs_out is NULL");
+    const JacobiPlan jp = make_jacobi_plan(width, height, num_disp);
+    if (!workspace || workspace_bytes < jp.total)
+        return fail(BP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, jp.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(BP_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = static_cast<char*>(workspace);
+    int16_t* C = reinterpret_cast<int16_t*>(ws + jp.off_cost);
+    int16_t* M[2] = {reinterpret_cast<int16_t*>(ws + jp.off_msgs[0]), reinterpret_cast<int16_t*>(ws + jp.off_msgs[1])};
+    HIP_TRY(bpst::launch_prep_level0(cost, C, jp.lv, num_disp, jp.G, st));
+    // the initial set: the caller's messages (zero where a pixel has no neighbour), or zeros
+    if (init_msgs_or_null)
+        HIP_TRY(bpst::launch_import(init_msgs_or_null, M[0], jp.lv, jp.vol, num_disp, jp.G, nullptr, nullptr, 0, st));
+    else
+        HIP_TRY(bpst::launch_init(nullptr, jp.lv, 0, M[0], jp.lv, jp.vol, jp.G, nullptr, nullptr, 0, st));
+    const int tq = trunc < num_disp ? trunc : num_disp;
+    bpst::HalfstepArgs a{};
+    a.cost = C;
+    a.vol = jp.vol;
+    a.lv = jp.lv;
+    a.D = num_disp;
+    a.Dp = jp.Dp;
+    a.G = jp.G;
+    a.lambda = lambda;
+    a.capv = lambda * tq < 32767 ? lambda * tq : 32767;
+    a.mode = 0;
+    a.source = bpst::kSrcOwn;
+    a.stream = bpst::stream_scale(jp.lv, jp.G) ? 1 : 0;
+    // Each iteration reads one set and writes the other: both colours send from the same
+    // (previous) messages.  A colour's update writes only the other colour's slots, so the
+    // two launches of an iteration do not read what the other writes.
+    for (int it = 0; it < iterations; ++it) {
+        a.msgs = M[it & 1];
+        a.out = M[(it + 1) & 1];
+        for (int c = 0; c < 2; ++c) {
+            a.colour = c;
+            a.t = c;
+            HIP_TRY(bpst::launch_halfstep(a, st));
+        }
+    }
+    HIP_TRY(bpst::launch_export(M[iterations & 1], jp.vol, jp.lv, num_disp, jp.G, msgs_out, st));
+    return ok();
+}
+
 BP_API int32_t bp_warmstart_input(const uint8_t* left, const uint8_t* right, const int16_t* cost, int32_t width,
                                   int32_t height, const bp_params* params, void* workspace, size_t workspace_bytes,
                                   uint16_t* input, void* stream)

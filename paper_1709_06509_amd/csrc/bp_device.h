@@ -796,7 +796,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
 #pragma unroll
     for (int e = 0; e < NK; ++e)
         if (stf[e]) {
-            int16_t* dst = a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0;
+            int16_t* dst = (a.out ? a.out : a.msgs) + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0;
 #pragma unroll
             for (int v = 0; v < NV; ++v) st16<STREAM>(dst + 8 * v, out[e][v]);
             if (MODE == 2 && glane == 0) a.state_a[nbr[e]] = 1;

@@ -213,11 +213,19 @@ __global__ __launch_bounds__(kThreads) void k_export(const int16_t* __restrict__
     const int d0 = lane * 8;
     const bool has[4] = {p.x > 0, p.x < lv.W - 1, p.y > 0, p.y < lv.H - 1};
     for (int k = 0; k < 4; ++k) {
-        int v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (has[k]) unpack8u(*reinterpret_cast<const int4*>(msgs + k * vol + gi * (8 * G) + d0), v);
         int16_t* dst = out + (((long long)k * lv.H + p.y) * lv.W + p.x) * D + d0;
+        const int4 m = has[k] ? *reinterpret_cast<const int4*>(msgs + k * vol + gi * (8 * G) + d0)
+                              : make_int4(0, 0, 0, 0);
+        if ((D & 7) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+            // whole 16-byte vectors (dst 16-byte aligned): a lane's 8 labels are all real or
+            // all padding
+            if (d0 < D) *reinterpret_cast<int4*>(dst) = m;
+        } else {
+            int v[8];
+            unpack8u(m, v);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) if (d0 + j < D) dst[j] = (int16_t)v[j];
+            for (int j = 0; j < 8; ++j) if (d0 + j < D) dst[j] = (int16_t)v[j];
+        }
     }
 }
 

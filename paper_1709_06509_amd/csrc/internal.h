@@ -62,6 +62,8 @@ struct HalfstepArgs {
     int level;
     int16_t* disp;           // non-null (plain BP, int32 path, last half-step of the finest scale):
                              // also write each updated pixel's winner-take-all disparity
+    int16_t* out;            // non-null: outgoing messages go to these 4 volumes (the Jacobi
+                             // schedule's second set), not in place
 };
 
 // Coarsest pixels that one workgroup of `threads` lanes takes in the one-launch cost

@@ -72,3 +72,24 @@ def test_workspace_grows_with_shape(lib):
     big = L.bp_workspace_bytes(1920, 1080, ctypes.byref(p))
     # cost pyramid (~4/3 of the finest) + two message buffers (finest and next) + state
     assert 5 * 1920 * 1080 * 128 * 2 < big < 8 * 1920 * 1080 * 128 * 2
+
+
+def test_jacobi_host_validation(lib):
+    from paper_1709_06509_amd import bpstereo as B
+
+    L = B.library()
+    need = L.bp_jacobi_workspace_bytes(64, 48, 16)
+    assert need >= 8 * 64 * 48 * 16 * 2  # two sets of four message volumes
+    for bad in [(0, 48, 16), (64, 0, 16), (64, 48, 0), (64, 48, 257), (16385, 4, 4)]:
+        assert L.bp_jacobi_workspace_bytes(*bad) == 0
+    p = ctypes.c_void_p
+    rc = L.bp_jacobi_iterations(p(16), 64, 48, 16, 64, 4, -1, None, p(16), p(256), need, None)
+    assert rc == B.BP_E_INVAL and b"iterations" in L.bp_last_error()
+    rc = L.bp_jacobi_iterations(p(16), 64, 48, 16, -1, 4, 2, None, p(16), p(256), need, None)
+    assert rc == B.BP_E_INVAL
+    rc = L.bp_jacobi_iterations(None, 64, 48, 16, 64, 4, 2, None, p(16), p(256), need, None)
+    assert rc == B.BP_E_INVAL
+    rc = L.bp_jacobi_iterations(p(16), 64, 48, 16, 64, 4, 2, None, p(16), p(256), need - 1, None)
+    assert rc == B.BP_E_WORKSPACE
+    rc = L.bp_jacobi_iterations(p(16), 64, 48, 16, 64, 4, 2, None, p(16), p(255), need, None)
+    assert rc == B.BP_E_WORKSPACE
