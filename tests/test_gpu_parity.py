@@ -358,3 +358,35 @@ def test_large_workload_sampled():
         assert dd[y, x] == oracle.wta_at(c, mm, int(x), int(y)), f"winner at {x},{y}"
     e = B.bp_energy(cost, d, w["lam"], w["trunc"])
     assert int(host(e)[0]) == oracle.energy(c, dd, w["lam"], w["trunc"])
+
+
+def noisy_frame(img, seed, sigma=2.0):
+    """A later frame of a static scene: the same views with fresh sensor noise."""
+    rng = np.random.default_rng(seed)
+    return np.clip(img.astype(np.float64) + rng.normal(0.0, sigma, img.shape), 0, 255).round().astype(np.uint8)
+
+
+@pytest.mark.parametrize("skip", [0, 1])
+def test_live_frames_warm_started_from_previous_messages(skip):
+    """A live sequence: frame 0 solved by the full hierarchy, each later frame by the finest
+    scale alone (num_scales 2, warm messages at scale 0 = the previous frame's final
+    messages, the coarser scale skipped).  GPU and oracle each carry their own messages from
+    frame to frame; they agree bit for bit on every frame."""
+    w = synth.WORKLOADS["tiny"]
+    p = synth.workload_pair("tiny")
+    D, win = w["num_disp"], w["window"]
+    lam, T = w["lam"], w["trunc"]
+    g_msgs = o_msgs = None
+    for f in range(4):
+        left, right = noisy_frame(p["left"], 100 + f), noisy_frame(p["right"], 200 + f)
+        say(f"live frame {f}, skip={skip}")
+        cost = oracle.cost_volume(left, right, D, win)
+        if f == 0:
+            L, iters = w["num_scales"], [w["iters"]] * w["num_scales"]
+        else:
+            L, iters = 2, [4, 0]
+        gd, gm, _ = B.bp_hierarchical_solve(gpu(cost), L, iters, lam, T, skip, 2, warm_msgs=g_msgs, want_msgs=True)
+        od, om, _ = oracle.bp_solve(cost, L, iters, lam, T, skip, 2, warm_msgs=o_msgs)
+        assert np.array_equal(host(gd), od), f"frame {f} disparities"
+        assert np.array_equal(host(gm), om), f"frame {f} messages"
+        g_msgs, o_msgs = gm, om
