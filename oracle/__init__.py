@@ -89,6 +89,8 @@ def _load():
         lib.oracle_adam.argtypes = [_f64p, _f64p, _f64p, _f64p, ctypes.c_int64, _i32, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double]
         lib.oracle_bp_energy.argtypes = [_i16p, _i16p, _i32, _i32, _i32, _i32, _i32]
+        lib.oracle_lr_check.argtypes = [_i16p, _i16p, _i32, _i32, _i32, _i32, _i16p]
+        lib.oracle_lr_check.restype = None
         lib.oracle_bp_energy.restype = ctypes.c_int64
         _lib = lib
     return _lib
@@ -218,6 +220,15 @@ def energy(cost, disparity, lam, trunc):
     cost, disparity = _c(cost, np.int16), _c(disparity, np.int16)
     H, W, D = cost.shape
     return int(_load().oracle_bp_energy(_p(cost, _i16p), _p(disparity, _i16p), W, H, D, lam, trunc))
+
+
+def lr_check(disp_left, disp_right, num_disp, tol):
+    """Left disparities kept where the right view agrees within tol, -1 elsewhere."""
+    dl, dr = _c(disp_left, np.int16), _c(disp_right, np.int16)
+    H, W = dl.shape
+    out = np.empty((H, W), np.int16)
+    _load().oracle_lr_check(_p(dl, _i16p), _p(dr, _i16p), W, H, num_disp, tol, _p(out, _i16p))
+    return out
 
 
 def message_at(cost, msgs, lam, trunc, x, y, k):

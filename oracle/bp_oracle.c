@@ -262,6 +262,24 @@ void oracle_wta(const int16_t* cost, const int16_t* msgs, int32_t W, int32_t H, 
 }
 
 /* ---- O8: E = sum_p C(p, d_p) + lambda * sum_{4-edges} min(|d_p - d_q|, T) ---- */
+/* Left-right consistency, the plain definition: the left pixel (x, y) with disparity d
+   matches the right pixel (x - d, y); it is kept when that pixel's own disparity (right
+   view as reference) is within tol of d. */
+void oracle_lr_check(const int16_t* dl, const int16_t* dr, int32_t W, int32_t H, int32_t D, int32_t tol,
+                     int16_t* out)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const int d = dl[(size_t)y * W + x];
+            int keep = 0;
+            if (d >= 0 && d < D && x - d >= 0) {
+                const int e = dr[(size_t)y * W + (x - d)];
+                keep = abs(e - d) <= tol;
+            }
+            out[(size_t)y * W + x] = (int16_t)(keep ? d : -1);
+        }
+}
+
 int64_t oracle_bp_energy(const int16_t* cost, const int16_t* disp, int32_t W, int32_t H, int32_t D,
                          int32_t lambda, int32_t T)
 {

@@ -92,6 +92,11 @@ double oracle_warm_l1(const float* y, const int16_t* label, int32_t Ws, int32_t 
 void oracle_adam(double* w, double* m, double* v, const double* g, int64_t n, int32_t step, double lr, double b1,
                  double b2, double eps);
 
+/* Left-right consistency: out = disp_left where the right view's disparity at the matched
+   column x - d agrees within tol (and d is in 0..D-1 with x - d >= 0), else -1. */
+void oracle_lr_check(const int16_t* disp_left, const int16_t* disp_right, int32_t width, int32_t height,
+                     int32_t num_disp, int32_t tol, int16_t* out);
+
 int64_t oracle_bp_energy(const int16_t* cost, const int16_t* disparity, int32_t width, int32_t height,
                          int32_t num_disp, int32_t lambda, int32_t trunc);
 

@@ -382,3 +382,28 @@ def test_freeze_rule_timing_on_flat_cost():
     # every scale starts with all pixels active again
     _, _, s = oracle.bp_solve(np.full((8, 8, 3), 9, np.int16), 2, [5, 5], 64, 4, skip_mode=1, want_msgs=False)
     assert s["active"][1][:5].tolist() == [8, 8, 8, 8, 0] and s["active"][0][:5].tolist() == [32, 32, 32, 32, 0]
+
+
+# ---------------------------------------------------------------- left-right consistency
+def test_lr_check_hand_cases():
+    """Hand-worked cases of the left-right check: a left pixel at column x with disparity d
+    matches right column x - d and is kept when the right view's disparity there is within
+    tol of d; matches off the image, out-of-range disparities and disagreements give -1."""
+    # constant disparity 2 seen the same from both views: the first two columns have no match
+    dl = np.full((1, 6), 2, np.int16)
+    assert oracle.lr_check(dl, dl, 4, 0).tolist() == [[-1, -1, 2, 2, 2, 2]]
+    # columns 3..5 see 3 and match right columns 0..2, which see 1: kept only with tol >= 2
+    # (the boundary value counts as agreement); columns 0..2 see 0 and match themselves,
+    # where the right view's 1 is within tol 1
+    dl = np.array([[0, 0, 0, 3, 3, 3]], np.int16)
+    dr = np.array([[1, 1, 1, 0, 0, 0]], np.int16)
+    assert oracle.lr_check(dl, dr, 4, 0).tolist() == [[-1, -1, -1, -1, -1, -1]]
+    assert oracle.lr_check(dl, dr, 4, 1).tolist() == [[0, 0, 0, -1, -1, -1]]
+    assert oracle.lr_check(dl, dr, 4, 2).tolist() == [[0, 0, 0, 3, 3, 3]]
+    # out-of-range disparities never match
+    dl = np.array([[4, -1, 5, 0]], np.int16)
+    assert oracle.lr_check(dl, np.zeros((1, 4), np.int16), 4, 10).tolist() == [[-1, -1, -1, 0]]
+    # two rows are independent: row 1 uses row 1 of the right map
+    dl = np.array([[1, 1, 1], [1, 1, 1]], np.int16)
+    dr = np.array([[1, 1, 1], [3, 3, 3]], np.int16)
+    assert oracle.lr_check(dl, dr, 4, 0).tolist() == [[-1, 1, 1], [-1, -1, -1]]
