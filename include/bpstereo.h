@@ -165,6 +165,19 @@ int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32_t widt
                               int16_t* disparity, int16_t* final_msgs_or_null, bp_stats* stats_or_null,
                               void* stream);
 
+/*
+ * Left-right consistency of two disparity maps (occlusion and mismatch detection): the
+ * left pixel (x, y) with disparity d matches the right pixel (x - d, y), and keeps d when
+ * the right map's disparity there (the right view as reference, matching right column u
+ * with left column u + d) is within tol of it.  A right map comes from the same calls on
+ * both views mirrored left to right and swapped, with the result mirrored back.
+ *   disp_left, disp_right [device] int16 [H][W]
+ *   out        [device] int16 [H][W] output: d where kept, -1 where x - d < 0, d lies
+ *              outside 0..num_disp-1, or the maps disagree by more than tol
+ */
+int32_t bp_lr_check(const int16_t* disp_left, const int16_t* disp_right, int32_t width, int32_t height,
+                    int32_t num_disp, int32_t tol, int16_t* out, void* stream);
+
 /* Bytes of device workspace bp_jacobi_iterations needs (0 if the sizes are invalid). */
 size_t bp_jacobi_workspace_bytes(int32_t width, int32_t height, int32_t num_disp);
 

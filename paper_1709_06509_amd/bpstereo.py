@@ -82,6 +82,7 @@ def _load():
         lib.bp_energy_workspace_bytes.argtypes = [_i32, _i32]
         lib.bp_energy_workspace_bytes.restype = ctypes.c_size_t
         lib.bp_energy.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t, _vp]
+        lib.bp_lr_check.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp]
         lib.bp_jacobi_workspace_bytes.argtypes = [_i32, _i32, _i32]
         lib.bp_jacobi_workspace_bytes.restype = ctypes.c_size_t
         lib.bp_jacobi_iterations.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.c_size_t,
@@ -89,7 +90,7 @@ def _load():
         for name in ("bp_context_create", "bp_context_destroy", "bp_context_set_timing", "bp_context_take_timing",
                      "bp_context_set_graphs", "bp_context_set_fused", "bp_context_graph_counts",
                      "stereo_luma", "stereo_cost_volume", "bp_hierarchical_solve", "bp_energy",
-                     "bp_jacobi_iterations"):
+                     "bp_jacobi_iterations", "bp_lr_check"):
             getattr(lib, name).restype = ctypes.c_int32
         _lib = lib
     return _lib
@@ -259,6 +260,17 @@ def bp_energy(cost, disparity, lam, trunc, workspace=None, out=None, stream=None
     _check(_load().bp_energy(_dev(cost, torch.int16, 3, "cost"), _dev(disparity, torch.int16, 2, "disparity"), W, H,
                              D, lam, trunc, _dev(out, torch.int64, 1, "energy"),
                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream)))
+    return out
+
+
+def bp_lr_check(disp_left, disp_right, num_disp, tol, out=None, stream=None):
+    """Left disparities kept where the right-reference map agrees within tol, -1 elsewhere."""
+    H, W = disp_left.shape
+    if tuple(disp_right.shape) != (H, W):
+        raise ValueError("disp_right must be [H, W] like disp_left")
+    out = torch.empty((H, W), dtype=torch.int16, device=disp_left.device) if out is None else out
+    _check(_load().bp_lr_check(_dev(disp_left, torch.int16, 2, "disp_left"), _dev(disp_right, torch.int16, 2, "disp_right"),
+                               W, H, num_disp, tol, _dev(out, torch.int16, 2, "out"), _stream(stream)))
     return out
 
 

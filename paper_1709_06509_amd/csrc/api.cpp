@@ -285,6 +285,17 @@ BP_API int32_t stereo_luma(const uint8_t* rgb, int32_t width, int32_t height, ui
     return ok();
 }
 
+BP_API int32_t bp_lr_check(const int16_t* disp_left, const int16_t* disp_right, int32_t width, int32_t height,
+                           int32_t num_disp, int32_t tol, int16_t* out, void* stream)
+{
+    if (!disp_left || !disp_right || !out) return fail(BP_E_INVAL, "disp_left/disp_right/out is NULL");
+    if (width < 1 || height < 1 || width > 16384 || height > 16384) return fail(BP_E_INVAL, "bad image size");
+    if (num_disp < 1 || num_disp > 256) return fail(BP_E_INVAL, "num_disp must be in 1..256");
+    if (tol < 0) return fail(BP_E_INVAL, "tol must be >= 0");
+    HIP_TRY(bpst::launch_lr_check(disp_left, disp_right, width, height, num_disp, tol, out, (hipStream_t)stream));
+    return ok();
+}
+
 BP_API int32_t stereo_cost_volume(const uint8_t* left, const uint8_t* right, int32_t width, int32_t height,
                                   int32_t num_disp, int32_t window, int32_t cost_scale, int32_t cost_trunc,
                                   int16_t* cost, float* ncc_or_null, void* stream)

@@ -340,6 +340,23 @@ __global__ __launch_bounds__(kThreads) void k_energy_final(const long long* part
     if (threadIdx.x == 0) *out = anybad ? (int64_t)(-9223372036854775807LL - 1) : (int64_t)t;
 }
 
+// Left-right consistency: the left pixel (x, y) with disparity d matches the right pixel
+// (x - d, y) and keeps d when that pixel's disparity (right view as reference) is within
+// tol of it; otherwise -1.  Every lane loads its left disparity and, from a clamped column,
+// the right one before either is used.
+__global__ __launch_bounds__(kThreads) void k_lr_check(const int16_t* __restrict__ dl, const int16_t* __restrict__ dr,
+                                                        int W, int H, int D, int tol, int16_t* __restrict__ out)
+{
+    const long long n = (long long)W * H;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+        const int y = (int)(i / W), x = (int)(i - (long long)y * W);
+        const int d = dl[i];
+        const bool in = d >= 0 && d < D && x - d >= 0;
+        const int e = dr[(long long)y * W + (in ? x - d : x)];
+        out[i] = (int16_t)(in && abs(e - d) <= tol ? d : -1);
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_luma(const uint8_t* __restrict__ rgb, long long n, uint8_t* __restrict__ y)
 {
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
@@ -518,6 +535,16 @@ hipError_t launch_energy(const int16_t* cost, const int16_t* disp, int W, int H,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kThreads), 0, st, part, bad, (int)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lr_check(const int16_t* dl, const int16_t* dr, int W, int H, int D, int tol, int16_t* out,
+                           hipStream_t st)
+{
+    const long long n = (long long)W * H;
+    long long nb = (n + kThreads - 1) / kThreads;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_lr_check, dim3((unsigned)nb), dim3(kThreads), 0, st, dl, dr, W, H, D, tol, out);
     return hipGetLastError();
 }
 

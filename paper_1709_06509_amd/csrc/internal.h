@@ -246,6 +246,8 @@ hipError_t launch_export(const int16_t* msgs, long long vol, Level lv, int D, in
 hipError_t launch_energy(const int16_t* cost, const int16_t* disp, int W, int H, int D, int lambda,
                          int trunc, int64_t* out, void* ws, hipStream_t st);
 size_t energy_ws_bytes();
+hipError_t launch_lr_check(const int16_t* dl, const int16_t* dr, int W, int H, int D, int tol, int16_t* out,
+                           hipStream_t st);
 hipError_t launch_luma(const uint8_t* rgb, int W, int H, uint8_t* y, hipStream_t st);
 hipError_t launch_ncc(const uint8_t* L, const uint8_t* R, int W, int H, int D, int win, int scale,
                       int trunc, int16_t* cost, float* ncc, hipStream_t st);

@@ -390,3 +390,37 @@ def test_live_frames_warm_started_from_previous_messages(skip):
         assert np.array_equal(host(gd), od), f"frame {f} disparities"
         assert np.array_equal(host(gm), om), f"frame {f} messages"
         g_msgs, o_msgs = gm, om
+
+
+@pytest.mark.parametrize("H,W,D,tol", [(1, 1, 1, 0), (7, 13, 16, 0), (31, 70, 64, 1), (300, 301, 128, 2)])
+def test_lr_check_random_maps(H, W, D, tol):
+    rng = np.random.default_rng(H + W + D)
+    dl = rng.integers(-2, D + 2, (H, W)).astype(np.int16)  # some out of range on purpose
+    dr = np.clip(dl + rng.integers(-3, 4, (H, W)), -1, D).astype(np.int16)
+    say(f"lr check {H}x{W} D={D} tol={tol}")
+    assert np.array_equal(host(B.bp_lr_check(gpu(dl), gpu(dr), D, tol)), oracle.lr_check(dl, dr, D, tol))
+
+
+def test_lr_check_end_to_end():
+    """Left and right disparity maps of the tiny pair (the right map from the mirrored,
+    swapped views, mirrored back), checked on the GPU from the library's maps and by the
+    oracle from its own: the same result, and most pixels consistent."""
+    w = synth.WORKLOADS["tiny"]
+    p = synth.workload_pair("tiny")
+    D, win, L, iters = w["num_disp"], w["window"], w["num_scales"], [w["iters"]] * w["num_scales"]
+    left, right = p["left"], p["right"]
+    mleft, mright = np.ascontiguousarray(right[:, ::-1]), np.ascontiguousarray(left[:, ::-1])
+    say("lr check end to end, tiny pair")
+    gdl, _, _ = B.bp_hierarchical_solve(B.stereo_cost_volume(gpu(left), gpu(right), D, win), L, iters, w["lam"],
+                                        w["trunc"], w["skip"], want_msgs=False)
+    gdr_m, _, _ = B.bp_hierarchical_solve(B.stereo_cost_volume(gpu(mleft), gpu(mright), D, win), L, iters,
+                                          w["lam"], w["trunc"], w["skip"], want_msgs=False)
+    gdr = torch.flip(gdr_m, dims=[1]).contiguous()
+    got = host(B.bp_lr_check(gdl, gdr, D, 1))
+    odl, _, _ = oracle.bp_solve(oracle.cost_volume(left, right, D, win), L, iters, w["lam"], w["trunc"], w["skip"],
+                                want_msgs=False)
+    odr_m, _, _ = oracle.bp_solve(oracle.cost_volume(mleft, mright, D, win), L, iters, w["lam"], w["trunc"],
+                                  w["skip"], want_msgs=False)
+    ref = oracle.lr_check(odl, np.ascontiguousarray(odr_m[:, ::-1]), D, 1)
+    assert np.array_equal(got, ref)
+    assert (ref >= 0).mean() > 0.6
