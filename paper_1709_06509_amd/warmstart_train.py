@@ -346,7 +346,7 @@ def main():
     ap.add_argument("--tune-pairs", type=int, default=24)
     ap.add_argument("--heldout-pairs", type=int, default=32)
     ap.add_argument("--epochs", type=int, default=1)
-    ap.add_argument("--out", default="gpurun_out/warmstart")
+    ap.add_argument("--out", default="warmstart_out")
     ap.add_argument("--resume", default=None, help="checkpoint file to continue from")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--ckpt-every", type=int, default=5000)
