@@ -92,8 +92,22 @@ def _load():
         lib.oracle_lr_check.argtypes = [_i16p, _i16p, _i32, _i32, _i32, _i32, _i16p]
         lib.oracle_lr_check.restype = None
         lib.oracle_bp_energy.restype = ctypes.c_int64
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int32
+        lib.oracle_set_threads.argtypes = [_i32]
+        lib.oracle_set_threads.restype = None
         _lib = lib
     return _lib
+
+
+def threads():
+    """Host threads the oracle's row loops use."""
+    return int(_load().oracle_threads())
+
+
+def set_threads(n):
+    """Use n host threads (n >= 1) in the oracle's row loops; results do not depend on n."""
+    _load().oracle_set_threads(int(n))
 
 
 def _p(a, t):

@@ -18,10 +18,18 @@
  *
  * Plain loops, int64 for integers, IEEE double for the correlation value.  The
  * message is the O(D^2) minimum over all source labels (its definition).
+ *
+ * Loops over image rows may run on several host threads (OpenMP).  That never changes a
+ * result: every output element of the correlation volume, the pyramid and the winner-
+ * take-all is computed on its own, and within one checkerboard half-step the pixels of
+ * the updated colour read only slots that the other colour wrote (each slot has one
+ * writer), so the order in which they are visited does not matter (the schedule reading
+ * above: colour (x+y)&1 == t&1 updates in place).  Integer counters are summed exactly.
  */
 #include "bp_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -122,6 +130,7 @@ int16_t oracle_cost_at(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H,
 void oracle_cost_volume(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t D,
                         int32_t win, int32_t scale, int32_t trunc, int16_t* cost, double* ncc)
 {
+#pragma omp parallel for schedule(dynamic, 1)
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x)
             for (int d = 0; d < D; ++d) {
@@ -135,8 +144,9 @@ void oracle_cost_volume(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H
 void oracle_pyramid_level(const int16_t* c, int32_t W, int32_t H, int32_t D, int16_t* out)
 {
     const int W2 = (W + 1) / 2, H2 = (H + 1) / 2;
-    int64_t* s = (int64_t*)malloc(sizeof(int64_t) * (size_t)D);
-    for (int Y = 0; Y < H2; ++Y)
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int Y = 0; Y < H2; ++Y) {
+        int64_t* s = (int64_t*)malloc(sizeof(int64_t) * (size_t)D);
         for (int X = 0; X < W2; ++X) {
             for (int d = 0; d < D; ++d) s[d] = 0;
             for (int b = 0; b < 2; ++b)
@@ -152,7 +162,8 @@ void oracle_pyramid_level(const int16_t* c, int32_t W, int32_t H, int32_t D, int
                 out[((size_t)Y * W2 + X) * D + d] = (int16_t)(v > 32767 ? 32767 : v);
             }
         }
-    free(s);
+        free(s);
+    }
 }
 
 /*
@@ -234,7 +245,11 @@ static int update_pixel(grid* g, int x, int y, int32_t* H, int32_t* h, int16_t* 
         int same = memcmp(dst, m, sizeof(int16_t) * (size_t)D) == 0;
         if (!same) {
             *all_equal = 0;
-            if (dirty) dirty[(size_t)qy * g->W + qx] = 1;
+            if (dirty) {
+                /* q may be flagged by senders in other rows, on other threads */
+#pragma omp atomic write
+                dirty[(size_t)qy * g->W + qx] = 1;
+            }
         }
         memcpy(dst, m, sizeof(int16_t) * (size_t)D);
         ++sent;
@@ -245,6 +260,7 @@ static int update_pixel(grid* g, int x, int y, int32_t* H, int32_t* h, int16_t* 
 /* ---- O7: winner-take-all on the beliefs, smallest d on ties ---- */
 void oracle_wta(const int16_t* cost, const int16_t* msgs, int32_t W, int32_t H, int32_t D, int16_t* disp)
 {
+#pragma omp parallel for schedule(dynamic, 1)
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
             int64_t best = INT64_MAX;
@@ -261,7 +277,10 @@ void oracle_wta(const int16_t* cost, const int16_t* msgs, int32_t W, int32_t H, 
         }
 }
 
-/* ---- O8: E = sum_p C(p, d_p) + lambda * sum_{4-edges} min(|d_p - d_q|, T) ---- */
+/* Host threads the row loops may use (OpenMP), and a way to set their number. */
+int32_t oracle_threads(void) { return (int32_t)omp_get_max_threads(); }
+void oracle_set_threads(int32_t n) { if (n >= 1) omp_set_num_threads(n); }
+
 /* Left-right consistency, the plain definition: the left pixel (x, y) with disparity d
    matches the right pixel (x - d, y); it is kept when that pixel's own disparity (right
    view as reference) is within tol of d. */
@@ -280,6 +299,7 @@ void oracle_lr_check(const int16_t* dl, const int16_t* dr, int32_t W, int32_t H,
         }
 }
 
+/* ---- O8: E = sum_p C(p, d_p) + lambda * sum_{4-edges} min(|d_p - d_q|, T) ---- */
 int64_t oracle_bp_energy(const int16_t* cost, const int16_t* disp, int32_t W, int32_t H, int32_t D,
                          int32_t lambda, int32_t T)
 {
@@ -318,16 +338,21 @@ int32_t oracle_bp_flat_checkerboard(const int16_t* cost, int32_t W, int32_t H, i
     size_t nm = (size_t)4 * W * H * D;
     memcpy(out, init, nm * sizeof(int16_t));
     grid g = {W, H, D, lambda, T, cost, out};
-    int32_t* Hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
-    int32_t* hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
-    int16_t* mb = (int16_t*)malloc(sizeof(int16_t) * (size_t)D);
-    for (int t = 0; t < halfsteps; ++t)
-        for (int y = 0; y < H; ++y)
-            for (int x = 0; x < W; ++x) {
-                int eq;
-                if (((x + y) & 1) == (t & 1)) update_pixel(&g, x, y, Hb, hb, mb, &eq, NULL);
-            }
-    free(Hb); free(hb); free(mb);
+    for (int t = 0; t < halfsteps; ++t) {
+#pragma omp parallel
+        {
+            int32_t* Hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
+            int32_t* hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
+            int16_t* mb = (int16_t*)malloc(sizeof(int16_t) * (size_t)D);
+#pragma omp for schedule(dynamic, 1)
+            for (int y = 0; y < H; ++y)
+                for (int x = 0; x < W; ++x) {
+                    int eq;
+                    if (((x + y) & 1) == (t & 1)) update_pixel(&g, x, y, Hb, hb, mb, &eq, NULL);
+                }
+            free(Hb); free(hb); free(mb);
+        }
+    }
     return 0;
 }
 
@@ -339,12 +364,15 @@ int32_t oracle_bp_flat_jacobi(const int16_t* cost, int32_t W, int32_t H, int32_t
     size_t nm = (size_t)4 * W * H * D;
     int16_t* prev = (int16_t*)malloc(nm * sizeof(int16_t));
     memcpy(out, init, nm * sizeof(int16_t));
-    int32_t* Hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
-    int32_t* hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
-    int16_t* mb = (int16_t*)malloc(sizeof(int16_t) * (size_t)D);
     for (int it = 0; it < iterations; ++it) {
         memcpy(prev, out, nm * sizeof(int16_t));
         grid src = {W, H, D, lambda, T, cost, prev};
+#pragma omp parallel
+        {
+        int32_t* Hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
+        int32_t* hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
+        int16_t* mb = (int16_t*)malloc(sizeof(int16_t) * (size_t)D);
+#pragma omp for schedule(dynamic, 1)
         for (int y = 0; y < H; ++y)
             for (int x = 0; x < W; ++x) {
                 int qx, qy;
@@ -363,8 +391,10 @@ int32_t oracle_bp_flat_jacobi(const int16_t* cost, int32_t W, int32_t H, int32_t
                     memcpy(out + (((size_t)opposite(k) * H + qy) * W + qx) * D, mb, sizeof(int16_t) * (size_t)D);
                 }
             }
+        free(Hb); free(hb); free(mb);
+        }
     }
-    free(prev); free(Hb); free(hb); free(mb);
+    free(prev);
     return 0;
 }
 
@@ -403,9 +433,6 @@ int32_t oracle_bp_solve(const int16_t* cost, int32_t W, int32_t H, const oracle_
 
     int start = p->warm_msgs ? L - 2 : L - 1;
     int16_t* prev = NULL; /* messages of scale l+1 */
-    int32_t* Hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
-    int32_t* hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
-    int16_t* mb = (int16_t*)malloc(sizeof(int16_t) * (size_t)D);
     for (int l = start; l >= 0; --l) {
         const int w = Ws[l], h = Hs[l];
         size_t npx = (size_t)w * h;
@@ -432,14 +459,24 @@ int32_t oracle_bp_solve(const int16_t* cost, int32_t W, int32_t H, const oracle_
         memset(active, 1, npx);
         memset(dirty, 1, npx);
         for (int t = 0; t < p->iters[l]; ++t) {
-            int count = 0;
+            int64_t count = 0, msgs_sent = 0;
+#pragma omp parallel reduction(+ : count, msgs_sent)
+            {
+            int32_t* Hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
+            int32_t* hb = (int32_t*)malloc(sizeof(int32_t) * (size_t)D);
+            int16_t* mb = (int16_t*)malloc(sizeof(int16_t) * (size_t)D);
+#pragma omp for schedule(dynamic, 1)
             for (int y = 0; y < h; ++y)
                 for (int x = 0; x < w; ++x) {
                     if (((x + y) & 1) != (t & 1)) continue;
                     size_t i = (size_t)y * w + x;
                     if (p->skip_mode == 1 && !active[i]) continue;
                     if (p->skip_mode == 2) {
-                        if (!dirty[i]) continue;
+                        uint8_t was_dirty;
+#pragma omp atomic read
+                        was_dirty = dirty[i];
+                        if (!was_dirty) continue;
+#pragma omp atomic write
                         dirty[i] = 0;
                     }
                     int eq;
@@ -449,9 +486,15 @@ int32_t oracle_bp_solve(const int16_t* cost, int32_t W, int32_t H, const oracle_
                         if (2 * (int)stable[i] >= p->converge_iters) active[i] = 0;
                     }
                     ++count;
-                    if (st) { st->pixel_updates += 1; st->msg_updates += sent; }
+                    msgs_sent += sent;
                 }
-            if (st && t < 64) st->active[l][t] = count;
+            free(Hb); free(hb); free(mb);
+            }
+            if (st) {
+                st->pixel_updates += count;
+                st->msg_updates += msgs_sent;
+                if (t < 64) st->active[l][t] = (int32_t)count;
+            }
         }
         if (st) st->n_halfsteps[l] = p->iters[l];
         free(active); free(stable); free(dirty);
@@ -461,7 +504,6 @@ int32_t oracle_bp_solve(const int16_t* cost, int32_t W, int32_t H, const oracle_
     oracle_wta(cost, prev, W, H, D, disp);
     if (final_msgs) memcpy(final_msgs, prev, sizeof(int16_t) * (size_t)4 * W * H * D);
     free(prev);
-    free(Hb); free(hb); free(mb);
     for (int l = 1; l < L; ++l) free(C[l]);
     return 0;
 }

@@ -97,6 +97,10 @@ void oracle_adam(double* w, double* m, double* v, const double* g, int64_t n, in
 void oracle_lr_check(const int16_t* disp_left, const int16_t* disp_right, int32_t width, int32_t height,
                      int32_t num_disp, int32_t tol, int16_t* out);
 
+/* Host threads that the row loops may use (OpenMP); set their number (n >= 1). */
+int32_t oracle_threads(void);
+void oracle_set_threads(int32_t n);
+
 int64_t oracle_bp_energy(const int16_t* cost, const int16_t* disparity, int32_t width, int32_t height,
                          int32_t num_disp, int32_t lambda, int32_t trunc);
 

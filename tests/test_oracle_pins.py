@@ -407,3 +407,91 @@ def test_lr_check_hand_cases():
     dl = np.array([[1, 1, 1], [1, 1, 1]], np.int16)
     dr = np.array([[1, 1, 1], [3, 3, 3]], np.int16)
     assert oracle.lr_check(dl, dr, 4, 0).tolist() == [[-1, 1, 1], [-1, -1, -1]]
+
+
+# ---------------------------------------------------------------- per-pixel helpers for sampled checks
+SHAPES_AT = [(1, 1, 4), (1, 9, 5), (9, 1, 5), (2, 2, 3), (5, 6, 7), (4, 9, 16)]
+
+
+@pytest.mark.parametrize("H,W,D", SHAPES_AT)
+def test_message_at_equals_checkerboard_half_steps(H, W, D):
+    """message_at recomputes what a half-step stores: from a random message state, one
+    checkerboard half-step of colour 0 and then one of colour 1 write, into each neighbour's
+    slot, exactly the messages message_at gives from the state each half-step started from
+    (receiver's own message excluded, missing neighbours skipped, borders included)."""
+    rng = np.random.default_rng(H * 100 + W * 10 + D)
+    cost = rng.integers(0, 700, (H, W, D)).astype(np.int16)
+    init = rng.integers(0, 300, (4, H, W, D)).astype(np.int16)
+    lam, T = 41, 3
+    s1 = oracle.flat_checkerboard(cost, lam, T, 1, init)
+    s2 = oracle.flat_checkerboard(cost, lam, T, 2, init)
+    nb = [(-1, 0), (1, 0), (0, -1), (0, 1)]
+    checked = 0
+    for colour, before, after in [(0, init, s1), (1, s1, s2)]:
+        for y in range(H):
+            for x in range(W):
+                if (x + y) & 1 != colour:
+                    continue
+                for k in range(4):
+                    qx, qy = x + nb[k][0], y + nb[k][1]
+                    got = oracle.message_at(cost, before, lam, T, x, y, k)
+                    if not (0 <= qx < W and 0 <= qy < H):
+                        assert got is None
+                        continue
+                    assert np.array_equal(got, after[k ^ 1, qy, qx]), (colour, x, y, k)
+                    checked += 1
+    edges = (W - 1) * H + W * (H - 1)
+    assert checked == 2 * edges
+
+
+def test_message_at_on_a_converged_chain_is_the_dp_message():
+    """On a 1 x n chain, BP run to convergence holds the textbook forward/backward messages:
+    the message pixel i sends to its right neighbour is min_d' [alpha_i(d') + V(d', d)]
+    (alpha = forward DP), normalised to minimum 0; to its left neighbour, the backward one."""
+    rng = np.random.default_rng(31)
+    n, D, lam, T = 15, 7, 29, 3
+    C = rng.integers(0, 300, (n, D)).astype(np.int64)
+    cost = C.astype(np.int16)[None]
+    _, msgs, _ = oracle.bp_solve(cost, 1, [2 * n + 6], lam, T)
+    V = np.array([[lam * min(abs(a - b), T) for b in range(D)] for a in range(D)], np.int64)
+    alpha = np.zeros((n, D), np.int64)
+    beta = np.zeros((n, D), np.int64)
+    alpha[0] = C[0]
+    for i in range(1, n):
+        alpha[i] = C[i] + np.min(alpha[i - 1][:, None] + V, axis=0)
+    beta[n - 1] = C[n - 1]
+    for i in range(n - 2, -1, -1):
+        beta[i] = C[i] + np.min(V + beta[i + 1][None, :], axis=1)
+    for i in range(n):
+        if i + 1 < n:
+            fwd = np.min(alpha[i][:, None] + V, axis=0)
+            assert oracle.message_at(cost, msgs, lam, T, i, 0, 1).tolist() == (fwd - fwd.min()).tolist()
+        else:
+            assert oracle.message_at(cost, msgs, lam, T, i, 0, 1) is None
+        if i > 0:
+            bwd = np.min(V + beta[i][None, :], axis=1)
+            assert oracle.message_at(cost, msgs, lam, T, i, 0, 0).tolist() == (bwd - bwd.min()).tolist()
+        else:
+            assert oracle.message_at(cost, msgs, lam, T, i, 0, 0) is None
+
+
+@pytest.mark.parametrize("H,W,D", SHAPES_AT)
+def test_wta_at_equals_wta_everywhere(H, W, D):
+    """wta_at of every pixel equals the whole-image winner-take-all, and both equal the
+    first (smallest-d) minimum of C + the messages from the sides that have a neighbour;
+    slots on the image border hold garbage here and must be ignored."""
+    rng = np.random.default_rng(H * 7 + W * 3 + D)
+    cost = rng.integers(0, 50, (H, W, D)).astype(np.int16)  # small range: many ties
+    msgs = rng.integers(0, 50, (4, H, W, D)).astype(np.int16)
+    full = oracle.wta(cost, msgs)
+    has = np.zeros((4, H, W), bool)
+    has[0, :, 1:] = True
+    has[1, :, :-1] = True
+    has[2, 1:, :] = True
+    has[3, :-1, :] = True
+    belief = cost.astype(np.int64) + (msgs.astype(np.int64) * has[..., None]).sum(0)
+    ref = np.argmin(belief, axis=2)
+    assert np.array_equal(full, ref)
+    for y in range(H):
+        for x in range(W):
+            assert oracle.wta_at(cost, msgs, x, y) == full[y, x]
