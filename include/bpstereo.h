@@ -166,6 +166,26 @@ int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32_t widt
                               void* stream);
 
 /*
+ * Allocation-free variant of bp_hierarchical_solve, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, semantics and results as bp_hierarchical_solve, except that
+ * the workspace is the library's own static device scratch of bp_noalloc_scratch_bytes()
+ * bytes (32 MiB; each GPU the library runs on holds one until the process ends).  The call
+ * allocates no device memory and creates no runtime object: the context's graph and timing
+ * modes are ignored (a caller may capture the call itself).  Shapes whose workspace
+ * (bp_workspace_bytes) exceeds the scratch return BP_E_WORKSPACE; the 384x288, D = 16,
+ * 4-scale solve needs about 22 MiB.  Every call on one GPU uses that GPU's one scratch, so
+ * calls that overlap on one GPU (other streams, other threads) race and must be serialised
+ * by the caller; the scratch keeps the last call's contents, which the next call does not
+ * depend on.
+ */
+int32_t bp_hierarchical_solve_noalloc(bp_context* ctx, const int16_t* cost, int32_t width, int32_t height,
+                                      const bp_params* params, int16_t* disparity, int16_t* final_msgs_or_null,
+                                      bp_stats* stats_or_null, void* stream);
+/* Bytes of the static device scratch bp_hierarchical_solve_noalloc uses. */
+size_t bp_noalloc_scratch_bytes(void);
+
+/*
  * Left-right consistency of two disparity maps (occlusion and mismatch detection): the
  * left pixel (x, y) with disparity d matches the right pixel (x - d, y), and keeps d when
  * the right map's disparity there (the right view as reference, matching right column u

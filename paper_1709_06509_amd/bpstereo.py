@@ -79,6 +79,10 @@ def _load():
         lib.bp_workspace_bytes.restype = ctypes.c_size_t
         lib.bp_hierarchical_solve.argtypes = [_vp, _vp, _i32, _i32, ctypes.POINTER(BPParams), _vp, ctypes.c_size_t,
                                               _vp, _vp, ctypes.POINTER(BPStats), _vp]
+        lib.bp_hierarchical_solve_noalloc.argtypes = [_vp, _vp, _i32, _i32, ctypes.POINTER(BPParams), _vp, _vp,
+                                                      ctypes.POINTER(BPStats), _vp]
+        lib.bp_noalloc_scratch_bytes.argtypes = []
+        lib.bp_noalloc_scratch_bytes.restype = ctypes.c_size_t
         lib.bp_energy_workspace_bytes.argtypes = [_i32, _i32]
         lib.bp_energy_workspace_bytes.restype = ctypes.c_size_t
         lib.bp_energy.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, ctypes.c_size_t, _vp]
@@ -89,7 +93,8 @@ def _load():
                                              _vp]
         for name in ("bp_context_create", "bp_context_destroy", "bp_context_set_timing", "bp_context_take_timing",
                      "bp_context_set_graphs", "bp_context_set_fused", "bp_context_graph_counts",
-                     "stereo_luma", "stereo_cost_volume", "bp_hierarchical_solve", "bp_energy",
+                     "stereo_luma", "stereo_cost_volume", "bp_hierarchical_solve", "bp_hierarchical_solve_noalloc",
+                     "bp_energy",
                      "bp_jacobi_iterations", "bp_lr_check"):
             getattr(lib, name).restype = ctypes.c_int32
         _lib = lib
@@ -242,6 +247,36 @@ def bp_hierarchical_solve(cost, num_scales, iters, lam, trunc, skip_mode=0, conv
                  "n_halfsteps": list(st.n_halfsteps),
                  "active": [[st.active[l][t] for t in range(64)] for l in range(8)]}
     return disp, msgs, stats
+
+
+def bp_noalloc_scratch_bytes():
+    """Bytes of the library's static per-device scratch (the largest solve workspace the
+    allocation-free solve accepts)."""
+    return int(_load().bp_noalloc_scratch_bytes())
+
+
+def bp_hierarchical_solve_noalloc(cost, num_scales, iters, lam, trunc, skip_mode=0, converge_iters=2, warm_msgs=None,
+                                  want_msgs=False, want_stats=False, ctx=None, disparity=None, msgs=None, stream=None):
+    """As bp_hierarchical_solve, with the library's static device scratch as its workspace
+    (the C call allocates no device memory).  Pass `disparity` (and `msgs`) to have this
+    wrapper allocate nothing either.  Returns (disparity, messages or None, stats or None)."""
+    H, W, D = cost.shape
+    cp = _dev(cost, torch.int16, 3, "cost")
+    p = make_params(D, num_scales, iters, lam, trunc, skip_mode, converge_iters, warm_msgs)
+    disp = torch.empty((H, W), dtype=torch.int16, device=cost.device) if disparity is None else disparity
+    if want_msgs and msgs is None:
+        msgs = torch.empty((4, H, W, D), dtype=torch.int16, device=cost.device)
+    st = BPStats() if want_stats else None
+    _check(_load().bp_hierarchical_solve_noalloc(ctx.handle if ctx is not None else None, cp, W, H, ctypes.byref(p),
+                                                 _dev(disp, torch.int16, 2, "disparity"),
+                                                 _dev(msgs, torch.int16, 4, "msgs") if want_msgs else None,
+                                                 ctypes.byref(st) if want_stats else None, _stream(stream)))
+    stats = None
+    if want_stats:
+        stats = {"msg_updates": st.msg_updates, "pixel_updates": st.pixel_updates,
+                 "n_halfsteps": list(st.n_halfsteps),
+                 "active": [[st.active[l][t] for t in range(64)] for l in range(8)]}
+    return disp, (msgs if want_msgs else None), stats
 
 
 def bp_energy_workspace_bytes(width, height):

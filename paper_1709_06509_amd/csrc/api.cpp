@@ -321,7 +321,7 @@ BP_API size_t bp_workspace_bytes(int32_t width, int32_t height, const bp_params*
 // Enqueue every launch of one solve on `st` (no synchronisation, no allocation).
 static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cost, const bp_params* params,
                              void* workspace, int16_t* disparity, int16_t* final_msgs_or_null, bool count,
-                             hipStream_t st)
+                             hipStream_t st, bool timing_allowed = true)
 {
     char* ws = static_cast<char*>(workspace);
     auto* stats = reinterpret_cast<bpst::DevStats*>(ws + pl.off_stats);
@@ -411,7 +411,8 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
             int t0, t1, steps, tw, th;
             long long rmax;
         };
-        std::vector<Seg> segs;
+        Seg segs[2];  // a fixed array: planning a solve allocates nothing
+        int nsegs = 0;
         const char* tail = getenv("BPSTEREO_FUSED_TAIL");
         if (tail && atoi(tail) >= 2 && atoi(tail) < iters && fsteps == 0 && fmode != 0 && mode == 1 && !count &&
             pl.G <= 8) {
@@ -421,11 +422,11 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
             const int steps = (iters - k + chunks - 1) / chunks;
             Seg b{k, iters, steps, 0, 0, 0};
             if (bpst::fused_geometry_max(pl.lv[l], pl.G, steps, &b.tw, &b.th, &b.rmax)) {
-                segs.push_back({0, k, 0, 0, 0, 0});
-                segs.push_back(b);
+                segs[nsegs++] = {0, k, 0, 0, 0, 0};
+                segs[nsegs++] = b;
             }
         }
-        if (segs.empty()) segs.push_back({0, iters, fsteps, ftw, fth, frmax});
+        if (nsegs == 0) segs[nsegs++] = {0, iters, fsteps, ftw, fth, frmax};
         int source = bpst::kSrcOwn;
         if (fuse) {
             source = (l == start) ? bpst::kSrcZero : bpst::kSrcParent;
@@ -459,7 +460,8 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         a.count = count ? 1 : 0;
         a.stats = stats;
         a.level = l;
-        for (const Seg& sg : segs) {
+        for (int si = 0; si < nsegs; ++si) {
+            const Seg& sg = segs[si];
             for (int t = sg.t0; sg.steps == 0 && t < sg.t1; ++t) {
                 a.t = t;
                 a.colour = t & 1;
@@ -478,7 +480,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                     wta_colour = 1 - (t & 1);
                 }
                 hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (ctx && ctx->timing) {
+                if (ctx && ctx->timing && timing_allowed) {
                     if (ctx->used == ctx->events.size()) {
                         hipEvent_t x, y;
                         HIP_TRY(hipEventCreate(&x));
@@ -525,7 +527,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                     f.keep_state = t0 + f.nsteps < iters ? 1 : 0;
                     f.narrow = narrow_ok(l, t0) && bpst::fused_narrow_pays(pl.G, sg.rmax) ? 1 : 0;
                     hipEvent_t e0 = nullptr, e1 = nullptr;
-                    if (ctx && ctx->timing) {
+                    if (ctx && ctx->timing && timing_allowed) {
                         if (ctx->used == ctx->events.size()) {
                             hipEvent_t x, y;
                             HIP_TRY(hipEventCreate(&x));
@@ -550,22 +552,16 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
     return BP_OK;
 }
 
-BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32_t width, int32_t height,
-                                     const bp_params* params, void* workspace, size_t workspace_bytes,
-                                     int16_t* disparity, int16_t* final_msgs_or_null, bp_stats* stats_or_null,
-                                     void* stream)
+// The solve after argument checks: graph replay or capture when the context asks for it,
+// else eager launches; then the counters, if requested.  `noalloc`: eager launches only and
+// no timing events (the context's graph and timing modes are ignored), so the call creates
+// no runtime object.
+static int32_t run_solve(bp_context* ctx, const Plan& pl, const int16_t* cost, int32_t width, int32_t height,
+                         const bp_params* params, void* workspace, size_t workspace_bytes, int16_t* disparity,
+                         int16_t* final_msgs_or_null, bp_stats* stats_or_null, bool noalloc, hipStream_t st)
 {
-    std::string why;
-    if (!params_valid(width, height, params, &why)) return fail(BP_E_INVAL, "%s", why.c_str());
-    if (!cost || !disparity) return fail(BP_E_INVAL, "cost/disparity is NULL");
-    const Plan pl = make_plan(width, height, params);
-    if (!workspace || workspace_bytes < pl.total)
-        return fail(BP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, pl.total);
-    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
-        return fail(BP_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
-    hipStream_t st = (hipStream_t)stream;
     const bool count = stats_or_null != nullptr;
-    if (ctx && ctx->graphs && !count && !ctx->timing && st != nullptr) {
+    if (!noalloc && ctx && ctx->graphs && !count && !ctx->timing && st != nullptr) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         HIP_TRY(hipStreamIsCapturing(st, &cs));
         if (cs == hipStreamCaptureStatusNone) {
@@ -604,7 +600,8 @@ BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32
         }
     }
     {
-        const int32_t rc = enqueue_solve(ctx, pl, cost, params, workspace, disparity, final_msgs_or_null, count, st);
+        const int32_t rc =
+            enqueue_solve(ctx, pl, cost, params, workspace, disparity, final_msgs_or_null, count, st, !noalloc);
         if (rc != BP_OK) return rc;
     }
     auto* stats = reinterpret_cast<bpst::DevStats*>(static_cast<char*>(workspace) + pl.off_stats);
@@ -621,6 +618,44 @@ BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32
         }
     }
     return ok();
+}
+
+BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32_t width, int32_t height,
+                                     const bp_params* params, void* workspace, size_t workspace_bytes,
+                                     int16_t* disparity, int16_t* final_msgs_or_null, bp_stats* stats_or_null,
+                                     void* stream)
+{
+    std::string why;
+    if (!params_valid(width, height, params, &why)) return fail(BP_E_INVAL, "%s", why.c_str());
+    if (!cost || !disparity) return fail(BP_E_INVAL, "cost/disparity is NULL");
+    const Plan pl = make_plan(width, height, params);
+    if (!workspace || workspace_bytes < pl.total)
+        return fail(BP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, pl.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(BP_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    return run_solve(ctx, pl, cost, width, height, params, workspace, workspace_bytes, disparity,
+                     final_msgs_or_null, stats_or_null, false, (hipStream_t)stream);
+}
+
+BP_API size_t bp_noalloc_scratch_bytes(void) { return bpst::kNoallocScratchBytes; }
+
+BP_API int32_t bp_hierarchical_solve_noalloc(bp_context* ctx, const int16_t* cost, int32_t width, int32_t height,
+                                             const bp_params* params, int16_t* disparity,
+                                             int16_t* final_msgs_or_null, bp_stats* stats_or_null, void* stream)
+{
+    std::string why;
+    if (!params_valid(width, height, params, &why)) return fail(BP_E_INVAL, "%s", why.c_str());
+    if (!cost || !disparity) return fail(BP_E_INVAL, "cost/disparity is NULL");
+    const Plan pl = make_plan(width, height, params);
+    if (pl.total > bpst::kNoallocScratchBytes)
+        return fail(BP_E_WORKSPACE,
+                    "this shape needs %zu bytes of scratch; the static scratch of the allocation-free solve holds "
+                    "%zu (use bp_hierarchical_solve with a workspace)",
+                    pl.total, bpst::kNoallocScratchBytes);
+    void* scratch = nullptr;
+    HIP_TRY(bpst::noalloc_scratch(&scratch));
+    return run_solve(ctx, pl, cost, width, height, params, scratch, bpst::kNoallocScratchBytes, disparity,
+                     final_msgs_or_null, stats_or_null, true, (hipStream_t)stream);
 }
 
 BP_API size_t bp_energy_workspace_bytes(int32_t width, int32_t height)

@@ -246,6 +246,11 @@ hipError_t launch_export(const int16_t* msgs, long long vol, Level lv, int D, in
 hipError_t launch_energy(const int16_t* cost, const int16_t* disp, int W, int H, int D, int lambda,
                          int trunc, int64_t* out, void* ws, hipStream_t st);
 size_t energy_ws_bytes();
+
+// Static device scratch of the solve that allocates nothing (noalloc.hip): its size, and its
+// device address on the current device (looked up once per device).
+constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;
+hipError_t noalloc_scratch(void** ptr);
 hipError_t launch_lr_check(const int16_t* dl, const int16_t* dr, int W, int H, int D, int tol, int16_t* out,
                            hipStream_t st);
 hipError_t launch_luma(const uint8_t* rgb, int W, int H, uint8_t* y, hipStream_t st);

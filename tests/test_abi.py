@@ -93,3 +93,25 @@ def test_jacobi_host_validation(lib):
     assert rc == B.BP_E_WORKSPACE
     rc = L.bp_jacobi_iterations(p(16), 64, 48, 16, 64, 4, 2, None, p(16), p(255), need, None)
     assert rc == B.BP_E_WORKSPACE
+
+
+def test_noalloc_host_validation(lib):
+    """The allocation-free solve checks its arguments and the scratch size on the host: a
+    shape whose workspace exceeds the static scratch is refused before any GPU call."""
+    from paper_1709_06509_amd import bpstereo as B
+
+    L = B.library()
+    cap = L.bp_noalloc_scratch_bytes()
+    assert cap == 32 << 20
+    prod = B.make_params(16, 4, 10, 64, 4, skip_mode=1)
+    assert L.bp_workspace_bytes(384, 288, ctypes.byref(prod)) <= cap
+    big = B.make_params(64, 4, 10, 64, 4)
+    assert L.bp_workspace_bytes(640, 480, ctypes.byref(big)) > cap
+    p = ctypes.c_void_p
+    rc = L.bp_hierarchical_solve_noalloc(None, p(16), 640, 480, ctypes.byref(big), p(16), None, None, None)
+    assert rc == B.BP_E_WORKSPACE and b"static scratch" in L.bp_last_error()
+    rc = L.bp_hierarchical_solve_noalloc(None, p(16), 640, 480, ctypes.byref(B.make_params(0, 4, 10, 64, 4)), p(16),
+                                         None, None, None)
+    assert rc == B.BP_E_INVAL
+    rc = L.bp_hierarchical_solve_noalloc(None, None, 64, 48, ctypes.byref(prod), p(16), None, None, None)
+    assert rc == B.BP_E_INVAL
