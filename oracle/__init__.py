@@ -63,6 +63,11 @@ def _load():
         lib.oracle_cost_at.argtypes = [_u8p, _u8p] + [_i32] * 8
         lib.oracle_cost_at.restype = ctypes.c_int16
         lib.oracle_cost_volume.argtypes = [_u8p, _u8p] + [_i32] * 6 + [_i16p, _f64p]
+        lib.oracle_ncc_rgb_at.argtypes = [_u8p, _u8p, _i32, _i32, _i32, _i32, _i32, _i32]
+        lib.oracle_ncc_rgb_at.restype = ctypes.c_double
+        lib.oracle_cost_rgb_at.argtypes = [_u8p, _u8p] + [_i32] * 8
+        lib.oracle_cost_rgb_at.restype = ctypes.c_int16
+        lib.oracle_cost_volume_rgb.argtypes = [_u8p, _u8p] + [_i32] * 6 + [_i16p, _f64p]
         lib.oracle_pyramid_level.argtypes = [_i16p, _i32, _i32, _i32, _i16p]
         lib.oracle_message.argtypes = [_i32p, _i32, _i32, _i32, _i16p]
         lib.oracle_bp_solve.argtypes = [_i16p, _i32, _i32, ctypes.POINTER(OracleParams), _i16p, _i16p,
@@ -146,6 +151,33 @@ def cost_volume(left, right, num_disp, window, cost_scale=256, cost_trunc=1024, 
     ncc = np.empty((H, W, num_disp), np.float64) if want_ncc else None
     _load().oracle_cost_volume(_p(left, _u8p), _p(right, _u8p), W, H, num_disp, window, cost_scale,
                                cost_trunc, _p(cost, _i16p), _p(ncc, _f64p) if want_ncc else None)
+    return (cost, ncc) if want_ncc else cost
+
+
+def ncc_rgb_at(left, right, window, x, y, d):
+    """Colour correlation of interleaved RGB views [H, W, 3] (channels pooled)."""
+    left, right = _c(left, np.uint8), _c(right, np.uint8)
+    H, W, _ = left.shape
+    return _load().oracle_ncc_rgb_at(_p(left, _u8p), _p(right, _u8p), W, H, window, x, y, d)
+
+
+def cost_rgb_at(left, right, window, x, y, d, cost_scale=256, cost_trunc=1024):
+    left, right = _c(left, np.uint8), _c(right, np.uint8)
+    H, W, _ = left.shape
+    return int(_load().oracle_cost_rgb_at(_p(left, _u8p), _p(right, _u8p), W, H, window, x, y, d,
+                                          cost_scale, cost_trunc))
+
+
+def cost_volume_rgb(left, right, num_disp, window, cost_scale=256, cost_trunc=1024, want_ncc=False):
+    """Colour cost volume int16 [H, W, D] from interleaved RGB views [H, W, 3]."""
+    left, right = _c(left, np.uint8), _c(right, np.uint8)
+    H, W, C = left.shape
+    if C != 3 or right.shape != left.shape:
+        raise ValueError("views must be interleaved RGB [H, W, 3] of one shape")
+    cost = np.empty((H, W, num_disp), np.int16)
+    ncc = np.empty((H, W, num_disp), np.float64) if want_ncc else None
+    _load().oracle_cost_volume_rgb(_p(left, _u8p), _p(right, _u8p), W, H, num_disp, window, cost_scale,
+                                   cost_trunc, _p(cost, _i16p), _p(ncc, _f64p) if want_ncc else None)
     return (cost, ncc) if want_ncc else cost
 
 

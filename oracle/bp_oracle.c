@@ -140,6 +140,98 @@ void oracle_cost_volume(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H
             }
 }
 
+/*
+ * ---- O2 for colour views: the same correlation over the window's three channels ----
+ * The views come from a regular RGB camera (paper, Abstract).  Reading: each channel is
+ * taken about its own window mean and the three channels are pooled into one correlation,
+ *   ncc = sum_c <I_c - mean I_c, J_c - mean J_c> / sqrt(sum_c |I_c - mean I_c|^2 * sum_c |J_c - mean J_c|^2),
+ * 0 if either pooled variance is 0.  Images are interleaved RGB [H][W][3]; windows are
+ * clamped to the image edge as for one channel.
+ */
+double oracle_ncc_rgb_at(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t win,
+                         int32_t x, int32_t y, int32_t d)
+{
+    if (x - d < 0) return -2.0;
+    const int r = win / 2, n = win * win;
+    double sij = 0.0, sii = 0.0, sjj = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double mi = 0.0, mj = 0.0;
+        for (int j = -r; j <= r; ++j) {
+            int yy = clampi(y + j, 0, H - 1);
+            for (int i = -r; i <= r; ++i) {
+                mi += L[((size_t)yy * W + clampi(x + i, 0, W - 1)) * 3 + c];
+                mj += R[((size_t)yy * W + clampi(x - d + i, 0, W - 1)) * 3 + c];
+            }
+        }
+        mi /= n;
+        mj /= n;
+        for (int j = -r; j <= r; ++j) {
+            int yy = clampi(y + j, 0, H - 1);
+            for (int i = -r; i <= r; ++i) {
+                double a = L[((size_t)yy * W + clampi(x + i, 0, W - 1)) * 3 + c] - mi;
+                double b = R[((size_t)yy * W + clampi(x - d + i, 0, W - 1)) * 3 + c] - mj;
+                sij += a * b;
+                sii += a * a;
+                sjj += b * b;
+            }
+        }
+    }
+    if (sii == 0.0 || sjj == 0.0) return 0.0;
+    return sij / sqrt(sii * sjj);
+}
+
+/* Quantised colour data cost, decided exactly as for one channel: with
+   num = sum_c (n S_IJc - S_Ic S_Jc) and P = sum_c (n S_IIc - S_Ic^2) * sum_c (n S_JJc - S_Jc^2). */
+int16_t oracle_cost_rgb_at(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t win,
+                           int32_t x, int32_t y, int32_t d, int32_t scale, int32_t trunc)
+{
+    if (x - d < 0) return (int16_t)trunc;
+    const int r = win / 2;
+    const int64_t n = (int64_t)win * win;
+    int64_t num = 0, vi = 0, vj = 0;
+    for (int c = 0; c < 3; ++c) {
+        int64_t si = 0, sj = 0, sii = 0, sjj = 0, sij = 0;
+        for (int j = -r; j <= r; ++j) {
+            int yy = clampi(y + j, 0, H - 1);
+            for (int i = -r; i <= r; ++i) {
+                int64_t a = L[((size_t)yy * W + clampi(x + i, 0, W - 1)) * 3 + c];
+                int64_t b = R[((size_t)yy * W + clampi(x - d + i, 0, W - 1)) * 3 + c];
+                si += a; sj += b; sii += a * a; sjj += b * b; sij += a * b;
+            }
+        }
+        num += n * sij - si * sj;
+        vi += n * sii - si * si;
+        vj += n * sjj - sj * sj;
+    }
+    int64_t k;
+    if (vi == 0 || vj == 0) {
+        k = scale;
+    } else {
+        uint64_t P = (uint64_t)vi * (uint64_t)vj;
+        double ncc = oracle_ncc_rgb_at(L, R, W, H, win, x, y, d);
+        k = (int64_t)floor((double)scale * (1.0 - ncc) + 0.5);
+        int64_t B = 2 * (int64_t)scale * num;
+        while (!le_times_sqrt(B, 2 * (int64_t)scale - 2 * k + 1, P)) --k;
+        while (le_times_sqrt(B, 2 * (int64_t)scale - 2 * (k + 1) + 1, P)) ++k;
+    }
+    if (k < 0) k = 0;
+    if (k > trunc) k = trunc;
+    return (int16_t)k;
+}
+
+void oracle_cost_volume_rgb(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t D,
+                            int32_t win, int32_t scale, int32_t trunc, int16_t* cost, double* ncc)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int d = 0; d < D; ++d) {
+                size_t o = ((size_t)y * W + x) * D + d;
+                cost[o] = oracle_cost_rgb_at(L, R, W, H, win, x, y, d, scale, trunc);
+                if (ncc) ncc[o] = oracle_ncc_rgb_at(L, R, W, H, win, x, y, d);
+            }
+}
+
 /* ---- O3: next coarser scale: sum the (up to 4) children, subtract the minimum, saturate ---- */
 void oracle_pyramid_level(const int16_t* c, int32_t W, int32_t H, int32_t D, int16_t* out)
 {

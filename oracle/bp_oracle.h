@@ -53,6 +53,17 @@ void oracle_cost_volume(const uint8_t* left, const uint8_t* right, int32_t width
                         int32_t num_disp, int32_t window, int32_t cost_scale, int32_t cost_trunc,
                         int16_t* cost, double* ncc_or_null);
 
+/* Colour views (interleaved RGB [H][W][3]): each channel about its own window mean, the
+   three channels pooled into one correlation; cost quantised as for one channel. */
+double oracle_ncc_rgb_at(const uint8_t* left, const uint8_t* right, int32_t width, int32_t height,
+                         int32_t window, int32_t x, int32_t y, int32_t d);
+int16_t oracle_cost_rgb_at(const uint8_t* left, const uint8_t* right, int32_t width, int32_t height,
+                           int32_t window, int32_t x, int32_t y, int32_t d, int32_t cost_scale,
+                           int32_t cost_trunc);
+void oracle_cost_volume_rgb(const uint8_t* left, const uint8_t* right, int32_t width, int32_t height,
+                            int32_t num_disp, int32_t window, int32_t cost_scale, int32_t cost_trunc,
+                            int16_t* cost, double* ncc_or_null);
+
 void oracle_pyramid_level(const int16_t* cost, int32_t width, int32_t height, int32_t num_disp,
                           int16_t* out);
 
