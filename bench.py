@@ -1,13 +1,16 @@
-"""Benchmark: stereo pairs/s of the whole GPU path on the production-shape workload.
+"""Benchmark: stereo pairs/s of the whole GPU path on the largest single-pair workload.
 
-One step = one synthetic 384x288 pair (D = 16, 7x7 NCC window) through the correlation
-volume, the 4-scale x 10-half-step hierarchical solve with the converged-pixel freeze
-(K = 2), winner-take-all and the energy.  Inputs are resident in HBM before timing.
+One step = one synthetic 1920x1080 RGB pair (luma of both views, D = 128, 9x9 NCC window)
+through the correlation volume, the 5-scale x 12-half-step hierarchical solve (plain BP),
+winner-take-all and the energy.  Inputs are resident in HBM before timing.  Other
+workloads (--workload production | tiny | batched | jacobi | live) are the smaller and
+batched configurations.
 
 Prints one JSON line.  Besides the headline pairs/s it reports message updates/s, the
 energy against plain BP on the same pair, the roofline of the dominant kernel (the
-half-step message update, timed with HIP events on its own stream) and the CPU
-checker's throughput on a bounded sample of the same workload.
+half-step message update, timed with HIP events on its launch stream inside the timed
+region), the run time against the number of half-steps, and the CPU oracle's throughput
+on a bounded sample of the same workload, single-threaded and on every host core.
 """
 import argparse
 import json
@@ -55,10 +58,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="production", choices=["production", "tiny", "large", "batched", "jacobi", "live"])
+    ap.add_argument("--workload", default="large", choices=["large", "production", "tiny", "batched", "jacobi", "live"])
     ap.add_argument("--batch-pairs", type=int, default=256, help="pairs of the batched workload")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-checker sample")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-checker leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample (small workloads)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle leg")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the step only: no event-free rerun, graph replay or half-step sweep (for profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB device-to-device 3 times (a kernel of "
                          "known traffic, for scaling profiler byte counters)")
@@ -81,28 +86,84 @@ def halfstep_bytes(stats, D, levels, skip):
     return total
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_pair_time(left, right, w, threads):
+    """Seconds the CPU oracle takes for one pair on `threads` host threads: luma (RGB),
+    cost volume, hierarchical solve, energy."""
+    import oracle
+
+    oracle.set_threads(threads)
+    t0 = time.perf_counter()
+    if w["rgb"]:
+        left, right = oracle.luma(left), oracle.luma(right)
+    cost = oracle.cost_volume(left, right, w["num_disp"], w["window"], w["cost_scale"], w["cost_trunc"])
+    d, _, _ = oracle.bp_solve(cost, w["num_scales"], [w["iters"]] * w["num_scales"], w["lam"], w["trunc"], w["skip"], 2,
+                              want_msgs=False)
+    oracle.energy(cost, d, w["lam"], w["trunc"])
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(w, seconds):
-    import numpy as np  # noqa: F401
+    """The CPU oracle (test infrastructure, never on the GPU path) timed on this host.
+
+    Small workloads: whole pairs, repeated for about `seconds`.  The large pair: a bounded
+    sample of it, full-width strips of its top rows (same D, window and schedule, the same
+    share of columns with x - d < 0), whose time scales with the pixel count; pairs/s is
+    extrapolated from the strip's pixels to the whole pair's.  Both single-threaded and on
+    every host thread the oracle's OpenMP loops use."""
+    import numpy as np
 
     import oracle
     from paper_1709_06509_amd import synth
 
     p = synth.workload_pair(w["name"])
-    if w["rgb"]:
-        return None
-    iters = [w["iters"]] * w["num_scales"]
-    n, t0 = 0, time.perf_counter()
-    while True:
-        cost = oracle.cost_volume(p["left"], p["right"], w["num_disp"], w["window"], w["cost_scale"], w["cost_trunc"])
-        d, _, _ = oracle.bp_solve(cost, w["num_scales"], iters, w["lam"], w["trunc"], w["skip"], 2, want_msgs=False)
-        oracle.energy(cost, d, w["lam"], w["trunc"])
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or n >= 1000:
-            break
-    return {"value": n / el, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+    H, W = w["height"], w["width"]
+    threads = oracle.threads()
+    if w["name"] == "large":
+        runs = {}
+        for nthr, rows in ((1, 8), (threads, min(H, 8 * threads))):
+            lc = np.ascontiguousarray(p["left"][:rows])
+            rc = np.ascontiguousarray(p["right"][:rows])
+            el = oracle_pair_time(lc, rc, w, nthr)
+            runs[nthr] = (rows, el, (rows * W) / (H * W) / el)
+        oracle.set_threads(threads)
+        rows, el, v = runs[threads]
+        rows1, el1, v1 = runs[1]
+        return {"value": v, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+                "sample": f"the top {rows} rows (full width {W}) of the {W}x{H} RGB pair: luma, cost volume, "
+                          f"{w['num_scales']}x{w['iters']} solve, energy; {el:.1f} s on {threads} threads, "
+                          f"extrapolated by pixel count to the whole pair",
+                "single_core_value": v1,
+                "single_core_sample": f"the top {rows1} rows, {el1:.1f} s on 1 thread",
+                "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+    res = {}
+    for nthr in (1, threads):
+        n, t0 = 0, time.perf_counter()
+        while True:
+            oracle_pair_time(p["left"], p["right"], w, nthr)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= seconds or n >= 1000:
+                break
+        res[nthr] = (n, el)
+    oracle.set_threads(threads)
+    n, el = res[threads]
+    n1, el1 = res[1]
+    return {"value": n / el, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} full {w['width']}x{w['height']} pairs (cost volume + {w['num_scales']}x{w['iters']} "
-                      f"solve, skip={w['skip']} + energy), single-threaded, {el:.1f} s"}
+                      f"solve, skip={w['skip']} + energy) on {threads} threads, {el:.1f} s",
+            "single_core_value": n1 / el1, "single_core_sample": f"{n1} pairs on 1 thread, {el1:.1f} s",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def plain_counts(W, H, levels, iters):
@@ -338,6 +399,44 @@ def run_live(args, frames=16, live_halfsteps=4):
     }
 
 
+def time_vs_halfsteps(B, cost, ws, w, stream, counts=(2, 4, 6, 8, 10, 12), reps=5):
+    """Run time of the solve against the number of half-steps per scale (the paper's claim:
+    plain BP's time is linear in its iterations), for plain BP and the freeze rule: the
+    median device time of `reps` solves at each count, and a least-squares line for plain
+    BP with its R^2.  Every scale runs the same count.  (Below two half-steps a scale's
+    initial messages are written by a separate pass, a different launch sequence, so the
+    line starts at two.)"""
+    import numpy as np
+    import torch
+
+    D, L, lam, T = w["num_disp"], w["num_scales"], w["lam"], w["trunc"]
+    H, W = cost.shape[0], cost.shape[1]
+    disp = torch.empty((H, W), dtype=torch.int16, device=cost.device)
+    res = {"halfsteps_per_scale": list(counts)}
+    for name, skip in (("plain", 0), ("freeze", 1)):
+        ms = []
+        for n in counts:
+            its = [n] * L
+            B.bp_hierarchical_solve(cost, L, its, lam, T, skip, 2, workspace=ws, disparity=disp, stream=stream)
+            times = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                B.bp_hierarchical_solve(cost, L, its, lam, T, skip, 2, workspace=ws, disparity=disp, stream=stream)
+                e1.record(stream)
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms.append(float(np.median(times)))
+        res[f"{name}_ms"] = ms
+    x = np.array(counts, np.float64)
+    y = np.array(res["plain_ms"])
+    slope, icpt = np.polyfit(x, y, 1)
+    pred = slope * x + icpt
+    res["plain_fit"] = {"slope_ms_per_halfstep": float(slope), "intercept_ms": float(icpt),
+                        "r2": float(1.0 - np.sum((y - pred) ** 2) / np.sum((y - y.mean()) ** 2))}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -402,49 +501,65 @@ def main():
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        # the timed region launches every kernel of each step eagerly on one stream (the host
-        # stays ahead of the GPU; on this stack that is about 3 % faster than replaying a
-        # HIP graph of the step, which is timed after it for the record)
+        # The timed region launches every kernel of each step eagerly on one stream (the host
+        # stays ahead of the GPU), with the context's timing mode on: a HIP event pair on the
+        # launch stream around each scale's run of message-update launches, so the roofline
+        # below comes from the very launches the headline times.  (An event pair around every
+        # launch costs about 5 % of the step on this stack; five pairs a step cost about 0.5 %.)
+        ctx.set_timing(2)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=stream):
-            step()
-        for _ in range(3):
-            graph.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            graph.replay()
-        torch.cuda.synchronize()
-        graph_elapsed = time.perf_counter() - t0
-        # kernel timing: the same step launched eagerly, each half-step bracketed by HIP
-        # events on the stream it runs on
-        ctx.set_timing(True)
-        n_timed = min(args.steps, 50)
-        for _ in range(n_timed):
-            step()
-        torch.cuda.synchronize()
         timing = ctx.take_timing()
         ctx.set_timing(False)
+        n_timed = args.steps
+        # for the record: the same steps without events, and replayed as one HIP graph
+        reps = 0 if args.no_extras else max(1, min(args.steps, 50))
+        no_event_elapsed = graph_elapsed = scaling = None
+        if reps:
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                step()
+            torch.cuda.synchronize()
+            no_event_elapsed = (time.perf_counter() - t0) / reps
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=stream):
+                step()
+            for _ in range(3):
+                graph.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                graph.replay()
+            torch.cuda.synchronize()
+            graph_elapsed = (time.perf_counter() - t0) / reps
+            del graph
+            scaling = time_vs_halfsteps(B, cost, ws, w, stream)
 
     # counters and energies (outside the timed region; the solve is deterministic)
     _, _, st = B.bp_hierarchical_solve(cost, L, iters, w["lam"], w["trunc"], w["skip"], 2, want_stats=True)
     e_run = int(B.bp_energy(cost, disp, w["lam"], w["trunc"]).cpu()[0])
     d_plain, _, st_plain = B.bp_hierarchical_solve(cost, L, iters, w["lam"], w["trunc"], 0, 2, want_stats=True)
     e_plain = int(B.bp_energy(cost, d_plain, w["lam"], w["trunc"]).cpu()[0])
+    d_frz, _, st_frz = B.bp_hierarchical_solve(cost, L, iters, w["lam"], w["trunc"], 1, 2, want_stats=True)
+    e_frz = int(B.bp_energy(cost, d_frz, w["lam"], w["trunc"]).cpu()[0])
 
     ms_per_step = 1000.0 * elapsed / args.steps
     pairs_per_s = args.steps / elapsed
     hs_bytes = halfstep_bytes(st, D, L, w["skip"])
     n_launch = timing["halfstep_launches"] // n_timed if n_timed else 0
     avg_launch_s = timing["halfstep_ms"] / 1000.0 / max(1, timing["halfstep_launches"])
+    halfstep_ms_per_step = timing["halfstep_ms"] / max(1, n_timed)
+    if halfstep_ms_per_step > ms_per_step:
+        raise RuntimeError(f"half-step time {halfstep_ms_per_step:.3f} ms exceeds the step {ms_per_step:.3f} ms")
     bytes_per_launch = hs_bytes / max(1, n_launch)
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     traffic = measured_traffic(args.workload)  # profiler-measured HBM bytes per launch, or None
+    # pixels of each colour at the finest scale: the freeze rule's active fraction per half-step
+    n0 = (W * H + 1) // 2
+    frz_active = [st_frz["active"][0][t] / (n0 if t % 2 == 0 else W * H - n0) for t in range(min(iters[0], 64))]
     out = {
         "metric": METRIC,
         "value": pairs_per_s,
@@ -458,9 +573,9 @@ def main():
         "vs_baseline": None,
         "dtype": "int16",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload} {W}x{H} D={D}, {w['window']}x{w['window']} NCC, "
-                               f"{L} scales x {w['iters']} half-steps, lambda={w['lam']} T={w['trunc']}, "
-                               f"skip={w['skip']} (K=2), seed={w['seed']}",
+        "config": {"workload": f"{args.workload} {W}x{H}{' RGB->luma' if rgb else ''} D={D}, "
+                               f"{w['window']}x{w['window']} NCC, {L} scales x {w['iters']} half-steps, "
+                               f"lambda={w['lam']} T={w['trunc']}, skip={w['skip']} (K=2), seed={w['seed']}",
                    "pairs_per_step": 1},
         "gmsg_updates_per_s": st["msg_updates"] * pairs_per_s / 1e9,
         "effective_gmsg_updates_per_s": st_plain["msg_updates"] * pairs_per_s / 1e9,
@@ -483,9 +598,18 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "launches_per_step": n_launch,
         },
-        "halfstep_ms_per_step_eager": timing["halfstep_ms"] / max(1, n_timed),
-        "graph_replay_pairs_per_s": args.steps / graph_elapsed,
-        "timing_note": "value: the whole step launched eagerly, steps back to back; graph_replay_pairs_per_s: the same step captured in one HIP graph and replayed; roofline: the step launched eagerly with HIP events around each message-update launch",
+        "halfstep_ms_per_step": halfstep_ms_per_step,
+        "halfstep_ms_per_scale": [timing["scale_ms"][l] / max(1, n_timed) for l in range(L)],
+        "halfstep_launches_per_scale": [timing["scale_launches"][l] // max(1, n_timed) for l in range(L)],
+        "pairs_per_s_without_events": 1.0 / no_event_elapsed if no_event_elapsed else None,
+        "graph_replay_pairs_per_s": 1.0 / graph_elapsed if graph_elapsed else None,
+        "time_vs_halfsteps": scaling,
+        "freeze_rule": {"energy_ratio_vs_plain": e_frz / e_plain if e_plain else None,
+                        "msg_updates_per_pair": st_frz["msg_updates"],
+                        "active_fraction_finest": frz_active},
+        "timing_note": "value: the whole step launched eagerly, steps back to back, with a HIP event pair around "
+                       "each message-update launch (the roofline's launch times); pairs_per_s_without_events and "
+                       "graph_replay_pairs_per_s: the same steps without the events and as one replayed HIP graph",
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -73,16 +73,22 @@ typedef struct {
 /* Device time of the message-update launches since the last bp_context_take_timing. */
 typedef struct {
     double halfstep_ms;         /* summed device time of the half-step kernels          */
-    int64_t halfstep_launches;  /* number of half-step launches measured                */
+    int64_t halfstep_launches;  /* number of half-step launches the events bracket       */
     int64_t halfstep_pixel_updates_max; /* pixels those launches could update (all active) */
+    double scale_ms[8];         /* the same time split by scale (0 = finest)              */
+    int64_t scale_launches[8];  /* and the launches of each scale                          */
 } bp_timing;
 
 int32_t bp_context_create(bp_context** out);
 int32_t bp_context_destroy(bp_context* ctx);
 
 /*
- * When `on` is non-zero, every later bp_hierarchical_solve on this context records a HIP
- * event pair around each half-step launch, on the stream the launch goes to.
+ * Timing of the message-update launches, with HIP events on the stream the launches go to.
+ * on = 1: every later bp_hierarchical_solve on this context records an event pair around
+ * each half-step launch (and the batched solve around each half-step phase); on = 2: one
+ * event pair around each scale's run of consecutive half-step launches (the average launch
+ * time then includes the short gaps between them, and the events perturb the run far less);
+ * on = 0: off.
  */
 int32_t bp_context_set_timing(bp_context* ctx, int32_t on);
 /* Synchronises on the recorded events, returns their sums in *out [host] and clears them. */
@@ -133,6 +139,21 @@ int32_t stereo_luma(const uint8_t* rgb, int32_t width, int32_t height, uint8_t* 
 int32_t stereo_cost_volume(const uint8_t* left, const uint8_t* right, int32_t width, int32_t height,
                            int32_t num_disp, int32_t window, int32_t cost_scale, int32_t cost_trunc,
                            int16_t* cost, float* ncc_or_null, void* stream);
+
+/*
+ * Correlation volume of colour views (Abstract: views from a regular RGB camera).  As
+ * stereo_cost_volume, with each channel taken about its own window mean and the three
+ * channels pooled into one correlation:
+ *   ncc = sum_c <I_c - mean I_c, J_c - mean J_c> / sqrt(sum_c |I_c - mean I_c|^2 sum_c |J_c - mean J_c|^2),
+ * 0 when either pooled variance is 0.  Grey views (R = G = B) give exactly the costs of
+ * stereo_cost_volume on one channel; a common gain with per-channel offsets leaves it unchanged.
+ *   left_rgb, right_rgb [device] uint8 [H][W][3], interleaved
+ *   window odd, 1..9 (the pooled integer sums then fit 32 bits); other arguments as
+ *   stereo_cost_volume
+ */
+int32_t stereo_cost_volume_rgb(const uint8_t* left_rgb, const uint8_t* right_rgb, int32_t width, int32_t height,
+                               int32_t num_disp, int32_t window, int32_t cost_scale, int32_t cost_trunc,
+                               int16_t* cost, float* ncc_or_null, void* stream);
 
 /* Bytes of device workspace bp_hierarchical_solve needs for this shape; 0 if invalid. */
 size_t bp_workspace_bytes(int32_t width, int32_t height, const bp_params* params);

@@ -51,6 +51,8 @@ class BPTiming(ctypes.Structure):
         ("halfstep_ms", ctypes.c_double),
         ("halfstep_launches", ctypes.c_int64),
         ("halfstep_pixel_updates_max", ctypes.c_int64),
+        ("scale_ms", ctypes.c_double * 8),
+        ("scale_launches", ctypes.c_int64 * 8),
     ]
 
 
@@ -75,6 +77,7 @@ def _load():
         lib.bp_context_take_timing.argtypes = [_vp, ctypes.POINTER(BPTiming)]
         lib.stereo_luma.argtypes = [_vp, _i32, _i32, _vp, _vp]
         lib.stereo_cost_volume.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp]
+        lib.stereo_cost_volume_rgb.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp]
         lib.bp_workspace_bytes.argtypes = [_i32, _i32, ctypes.POINTER(BPParams)]
         lib.bp_workspace_bytes.restype = ctypes.c_size_t
         lib.bp_hierarchical_solve.argtypes = [_vp, _vp, _i32, _i32, ctypes.POINTER(BPParams), _vp, ctypes.c_size_t,
@@ -93,7 +96,7 @@ def _load():
                                              _vp]
         for name in ("bp_context_create", "bp_context_destroy", "bp_context_set_timing", "bp_context_take_timing",
                      "bp_context_set_graphs", "bp_context_set_fused", "bp_context_graph_counts",
-                     "stereo_luma", "stereo_cost_volume", "bp_hierarchical_solve", "bp_hierarchical_solve_noalloc",
+                     "stereo_luma", "stereo_cost_volume", "stereo_cost_volume_rgb", "bp_hierarchical_solve", "bp_hierarchical_solve_noalloc",
                      "bp_energy",
                      "bp_jacobi_iterations", "bp_lr_check"):
             getattr(lib, name).restype = ctypes.c_int32
@@ -137,7 +140,9 @@ class Context:
         self.handle = h
 
     def set_timing(self, on=True):
-        _check(_load().bp_context_set_timing(self.handle, 1 if on else 0))
+        """Event timing of the message-update launches: True or 1 per launch, 2 per scale's
+        run of launches, False or 0 off."""
+        _check(_load().bp_context_set_timing(self.handle, int(on)))
 
     def set_graphs(self, on=True):
         _check(_load().bp_context_set_graphs(self.handle, 1 if on else 0))
@@ -155,7 +160,8 @@ class Context:
         t = BPTiming()
         _check(_load().bp_context_take_timing(self.handle, ctypes.byref(t)))
         return {"halfstep_ms": t.halfstep_ms, "halfstep_launches": t.halfstep_launches,
-                "halfstep_pixel_updates_max": t.halfstep_pixel_updates_max}
+                "halfstep_pixel_updates_max": t.halfstep_pixel_updates_max,
+                "scale_ms": list(t.scale_ms), "scale_launches": list(t.scale_launches)}
 
     def close(self):
         if self.handle:
@@ -193,6 +199,23 @@ def stereo_cost_volume(left, right, num_disp, window, cost_scale=256, cost_trunc
     _check(_load().stereo_cost_volume(lp, rp, W, H, num_disp, window, cost_scale, cost_trunc,
                                       _dev(cost, torch.int16, 3, "cost"),
                                       _dev(ncc, torch.float32, 3, "ncc") if want_ncc else None, _stream(stream)))
+    return (cost, ncc) if want_ncc else cost
+
+
+def stereo_cost_volume_rgb(left, right, num_disp, window, cost_scale=256, cost_trunc=1024, want_ncc=False, out=None,
+                           stream=None):
+    """Quantised colour NCC cost volume int16 [H, W, D] of interleaved RGB views [H, W, 3]."""
+    H, W, C = left.shape
+    if C != 3 or tuple(right.shape) != (H, W, 3):
+        raise ValueError("left and right must be [H, W, 3] of one shape")
+    lp, rp = _dev(left, torch.uint8, 3, "left"), _dev(right, torch.uint8, 3, "right")
+    cost = torch.empty((H, W, num_disp), dtype=torch.int16, device=left.device) if out is None else out
+    if tuple(cost.shape) != (H, W, num_disp):
+        raise ValueError("out has the wrong shape")
+    ncc = torch.empty((H, W, num_disp), dtype=torch.float32, device=left.device) if want_ncc else None
+    _check(_load().stereo_cost_volume_rgb(lp, rp, W, H, num_disp, window, cost_scale, cost_trunc,
+                                          _dev(cost, torch.int16, 3, "cost"),
+                                          _dev(ncc, torch.float32, 3, "ncc") if want_ncc else None, _stream(stream)))
     return (cost, ncc) if want_ncc else cost
 
 

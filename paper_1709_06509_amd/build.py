@@ -22,6 +22,10 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibilit
              "-I" + os.path.join(ROOT, "include")]
 
 
+# Extra flags of single source files (none at present).
+FILE_FLAGS = {}
+
+
 def _run_all(cmds):
     procs = [(c, subprocess.Popen(c, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)) for c in cmds]
     errs = []
@@ -54,7 +58,7 @@ def build_hip():
         o = os.path.join(BUILD_DIR, os.path.basename(s) + ".o")
         objs.append(o)
         lang = ["-x", "hip"] if s.endswith(".hip") else []
-        cmds.append([HIPCC] + HIP_FLAGS + lang + ["-c", s, "-o", o])
+        cmds.append([HIPCC] + HIP_FLAGS + FILE_FLAGS.get(os.path.basename(s), []) + lang + ["-c", s, "-o", o])
     _run_all(cmds)
     tmp = LIB + ".tmp"
     _run_all([[HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs])

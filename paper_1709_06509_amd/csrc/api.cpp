@@ -132,8 +132,10 @@ struct SolveKey {
 };
 
 struct bp_context {
-    bool timing = false;
+    int timing = 0;  // 0 off; 1 an event pair per message-update launch; 2 one per scale's launches
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    std::vector<int> event_scale;     // scale of the launches each event pair brackets
+    std::vector<int> event_launches;  // and how many launches it brackets
     size_t used = 0;
     long long pixels_max = 0;
     bool graphs = false;
@@ -154,6 +156,30 @@ struct bp_context {
     int forced_sched = -1, forced_bpc = 1, forced_order = 0;
     std::vector<std::pair<std::vector<char>, hipGraphExec_t>> batch_graphs;
 };
+
+namespace {
+// Event pair for timed launches on ctx (timing mode): `launches` consecutive launches of
+// one scale.  Returns the pair's index in *slot.
+int32_t timing_events(bp_context* ctx, int scale, int launches, hipEvent_t* e0, hipEvent_t* e1,
+                      size_t* slot = nullptr)
+{
+    if (ctx->used == ctx->events.size()) {
+        hipEvent_t x, y;
+        HIP_TRY(hipEventCreate(&x));
+        HIP_TRY(hipEventCreate(&y));
+        ctx->events.emplace_back(x, y);
+        ctx->event_scale.push_back(0);
+        ctx->event_launches.push_back(0);
+    }
+    *e0 = ctx->events[ctx->used].first;
+    *e1 = ctx->events[ctx->used].second;
+    ctx->event_scale[ctx->used] = scale;
+    ctx->event_launches[ctx->used] = launches;
+    if (slot) *slot = ctx->used;
+    ctx->used++;
+    return BP_OK;
+}
+}  // namespace
 
 BP_API int32_t bp_context_set_batch_schedule(bp_context* ctx, int32_t schedule, int32_t blocks_per_cu, int32_t order)
 {
@@ -255,7 +281,8 @@ BP_API int32_t bp_context_graph_counts(bp_context* ctx, int64_t* counts)
 BP_API int32_t bp_context_set_timing(bp_context* ctx, int32_t on)
 {
     if (!ctx) return fail(BP_E_INVAL, "ctx is NULL");
-    ctx->timing = on != 0;
+    if (on < 0 || on > 2) return fail(BP_E_INVAL, "timing mode must be 0, 1 or 2");
+    ctx->timing = on;
     return ok();
 }
 
@@ -263,14 +290,22 @@ BP_API int32_t bp_context_take_timing(bp_context* ctx, bp_timing* out)
 {
     if (!ctx || !out) return fail(BP_E_INVAL, "ctx/out is NULL");
     double ms = 0.0;
+    int64_t launches = 0;
+    std::memset(out, 0, sizeof *out);
     for (size_t i = 0; i < ctx->used; ++i) {
         HIP_TRY(hipEventSynchronize(ctx->events[i].second));
         float t = 0.f;
         HIP_TRY(hipEventElapsedTime(&t, ctx->events[i].first, ctx->events[i].second));
         ms += t;
+        launches += ctx->event_launches[i];
+        const int l = ctx->event_scale[i];
+        if (l >= 0 && l < bpst::kMaxScales) {
+            out->scale_ms[l] += t;
+            out->scale_launches[l] += ctx->event_launches[i];
+        }
     }
     out->halfstep_ms = ms;
-    out->halfstep_launches = (int64_t)ctx->used;
+    out->halfstep_launches = launches;
     out->halfstep_pixel_updates_max = ctx->pixels_max;
     ctx->used = 0;
     ctx->pixels_max = 0;
@@ -307,8 +342,24 @@ BP_API int32_t stereo_cost_volume(const uint8_t* left, const uint8_t* right, int
     if (window < 1 || window > 13 || (window & 1) == 0) return fail(BP_E_INVAL, "window must be odd, 1..13");
     if (cost_scale < 1 || cost_scale > 4096) return fail(BP_E_INVAL, "cost_scale must be in 1..4096");
     if (cost_trunc < 0 || cost_trunc > 32767) return fail(BP_E_INVAL, "cost_trunc must be in 0..32767");
-    HIP_TRY(bpst::launch_ncc(left, right, width, height, num_disp, window, cost_scale, cost_trunc, cost, ncc_or_null,
-                             (hipStream_t)stream));
+    HIP_TRY(bpst::launch_ncc_mfma(left, right, width, height, num_disp, window, 1, cost_scale, cost_trunc, cost,
+                                  ncc_or_null, (hipStream_t)stream));
+    return ok();
+}
+
+BP_API int32_t stereo_cost_volume_rgb(const uint8_t* left_rgb, const uint8_t* right_rgb, int32_t width, int32_t height,
+                                      int32_t num_disp, int32_t window, int32_t cost_scale, int32_t cost_trunc,
+                                      int16_t* cost, float* ncc_or_null, void* stream)
+{
+    if (!left_rgb || !right_rgb || !cost) return fail(BP_E_INVAL, "left_rgb/right_rgb/cost is NULL");
+    if (width < 1 || height < 1 || width > 16384 || height > 16384)
+        return fail(BP_E_INVAL, "width/height must be in 1..16384");
+    if (num_disp < 1 || num_disp > 256) return fail(BP_E_INVAL, "num_disp must be in 1..256");
+    if (window < 1 || window > 9 || (window & 1) == 0) return fail(BP_E_INVAL, "window must be odd, 1..9");
+    if (cost_scale < 1 || cost_scale > 4096) return fail(BP_E_INVAL, "cost_scale must be in 1..4096");
+    if (cost_trunc < 0 || cost_trunc > 32767) return fail(BP_E_INVAL, "cost_trunc must be in 0..32767");
+    HIP_TRY(bpst::launch_ncc_mfma(left_rgb, right_rgb, width, height, num_disp, window, 3, cost_scale, cost_trunc, cost,
+                                  ncc_or_null, (hipStream_t)stream));
     return ok();
 }
 
@@ -460,6 +511,16 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         a.count = count ? 1 : 0;
         a.stats = stats;
         a.level = l;
+        // timing mode 2: one event pair around all of this scale's message-update launches
+        const bool time_each = ctx && ctx->timing == 1 && timing_allowed;
+        hipEvent_t s0 = nullptr, s1 = nullptr;
+        size_t sslot = 0;
+        int scale_launches = 0;
+        if (ctx && ctx->timing == 2 && timing_allowed && iters > 0) {
+            const int32_t rc = timing_events(ctx, l, 0, &s0, &s1, &sslot);
+            if (rc != BP_OK) return rc;
+            HIP_TRY(hipEventRecord(s0, st));
+        }
         for (int si = 0; si < nsegs; ++si) {
             const Seg& sg = segs[si];
             for (int t = sg.t0; sg.steps == 0 && t < sg.t1; ++t) {
@@ -480,20 +541,14 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                     wta_colour = 1 - (t & 1);
                 }
                 hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (ctx && ctx->timing && timing_allowed) {
-                    if (ctx->used == ctx->events.size()) {
-                        hipEvent_t x, y;
-                        HIP_TRY(hipEventCreate(&x));
-                        HIP_TRY(hipEventCreate(&y));
-                        ctx->events.emplace_back(x, y);
-                    }
-                    e0 = ctx->events[ctx->used].first;
-                    e1 = ctx->events[ctx->used].second;
-                    ctx->used++;
-                    ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh;
+                if (time_each) {
+                    const int32_t rc = timing_events(ctx, l, 1, &e0, &e1);
+                    if (rc != BP_OK) return rc;
                     HIP_TRY(hipEventRecord(e0, st));
                 }
+                if (ctx && ctx->timing && timing_allowed) ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh;
                 HIP_TRY(bpst::launch_halfstep(a, st));
+                ++scale_launches;
                 if (e1) HIP_TRY(hipEventRecord(e1, st));
             }
             if (sg.steps > 0) {
@@ -527,23 +582,22 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                     f.keep_state = t0 + f.nsteps < iters ? 1 : 0;
                     f.narrow = narrow_ok(l, t0) && bpst::fused_narrow_pays(pl.G, sg.rmax) ? 1 : 0;
                     hipEvent_t e0 = nullptr, e1 = nullptr;
-                    if (ctx && ctx->timing && timing_allowed) {
-                        if (ctx->used == ctx->events.size()) {
-                            hipEvent_t x, y;
-                            HIP_TRY(hipEventCreate(&x));
-                            HIP_TRY(hipEventCreate(&y));
-                            ctx->events.emplace_back(x, y);
-                        }
-                        e0 = ctx->events[ctx->used].first;
-                        e1 = ctx->events[ctx->used].second;
-                        ctx->used++;
-                        ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh * f.nsteps;
+                    if (time_each) {
+                        const int32_t rc = timing_events(ctx, l, 1, &e0, &e1);
+                        if (rc != BP_OK) return rc;
                         HIP_TRY(hipEventRecord(e0, st));
                     }
+                    if (ctx && ctx->timing && timing_allowed)
+                        ctx->pixels_max += (long long)pl.lv[l].H * pl.lv[l].Wh * f.nsteps;
                     HIP_TRY(bpst::launch_fused(f, st));
+                    ++scale_launches;
                     if (e1) HIP_TRY(hipEventRecord(e1, st));
                 }
             }
+        }
+        if (s1) {
+            HIP_TRY(hipEventRecord(s1, st));
+            ctx->event_launches[sslot] = scale_launches;
         }
     }
     HIP_TRY(bpst::launch_wta(C[0], M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, wta_colour, disparity, st));
@@ -804,7 +858,7 @@ int32_t plan_batch(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* 
     long long acc = 0;
     for (int i = 0; i < n; ++i) {
         b.ncc_tiles[i] = (int)acc;
-        acc += bpst::ncc_tiles(pairs[i].width, pairs[i].height, pairs[i].num_disp);
+        acc += bpst::ncc_mfma_tiles(pairs[i].width, pairs[i].height);
     }
     b.ncc_tiles[n] = (int)acc;
     b.ncc_total = (int)acc;
@@ -939,20 +993,6 @@ bpst::BatchArgs batch_args(const BatchPlan& b, const bp_batch_params* p, char* w
 
 // The solve part of a batch: schedule 0 is one persistent launch of bpc workgroups per
 // compute unit; schedule 1 is one launch per phase.
-// Event pair for one timed launch on ctx (timing mode).
-int32_t timing_events(bp_context* ctx, hipEvent_t* e0, hipEvent_t* e1)
-{
-    if (ctx->used == ctx->events.size()) {
-        hipEvent_t x, y;
-        HIP_TRY(hipEventCreate(&x));
-        HIP_TRY(hipEventCreate(&y));
-        ctx->events.emplace_back(x, y);
-    }
-    *e0 = ctx->events[ctx->used].first;
-    *e1 = ctx->events[ctx->used].second;
-    ctx->used++;
-    return BP_OK;
-}
 
 int32_t enqueue_batch_solve(bp_context* ctx, const BatchPlan& b, const bp_batch_params* p, char* ws, int sched, int bpc,
                             int order, int cus, long long ticks, hipStream_t st)
@@ -966,7 +1006,7 @@ int32_t enqueue_batch_solve(bp_context* ctx, const BatchPlan& b, const bp_batch_
             // timing mode: an event pair around every half-step phase
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (ctx && ctx->timing && d.type == bpst::kPhHalfstep) {
-                const int32_t rc = timing_events(ctx, &e0, &e1);
+                const int32_t rc = timing_events(ctx, d.level, 1, &e0, &e1);
                 if (rc != BP_OK) return rc;
                 HIP_TRY(hipEventRecord(e0, st));
             }
@@ -987,9 +1027,9 @@ int32_t enqueue_batch_solve(bp_context* ctx, const BatchPlan& b, const bp_batch_
 int32_t enqueue_batch(bp_context* ctx, const BatchPlan& b, const bp_batch_params* p, char* ws, int sched, int bpc,
                       int order, int cus, long long ticks, hipStream_t st)
 {
-    HIP_TRY(bpst::launch_ncc_batched(reinterpret_cast<const bpst::NccPair*>(ws + b.off_ncc),
-                                     reinterpret_cast<const int*>(ws + b.off_ncc_tiles), b.n, b.ncc_total, b.max_d,
-                                     p->window, p->cost_scale, p->cost_trunc, st));
+    HIP_TRY(bpst::launch_ncc_mfma_batched(reinterpret_cast<const bpst::NccPair*>(ws + b.off_ncc),
+                                          reinterpret_cast<const int*>(ws + b.off_ncc_tiles), b.n, b.ncc_total,
+                                          b.max_d, p->window, p->cost_scale, p->cost_trunc, st));
     return enqueue_batch_solve(ctx, b, p, ws, sched, bpc, order, cus, ticks, st);
 }
 

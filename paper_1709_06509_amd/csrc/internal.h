@@ -211,9 +211,11 @@ hipError_t launch_warm_input(const uint8_t* L, const uint8_t* R, int W, int H, i
 hipError_t launch_warm_messages(const float* y, int Ws, int Hs, int D, int ystride, int lam_t, int16_t* out,
                                 hipStream_t st);
 
-int ncc_tiles(int W, int H, int D);
-hipError_t launch_ncc_batched(const NccPair* pairs, const int* tile_start, int n, int total_tiles, int max_d, int win,
-                              int scale, int trunc, hipStream_t st);
+// The batch's correlation volumes in one launch (ncc_mfma.hip): tiles of one row and 64
+// columns, listed by per-pair prefix sums of ncc_mfma_tiles.
+int ncc_mfma_tiles(int W, int H);
+hipError_t launch_ncc_mfma_batched(const NccPair* pairs, const int* tile_start, int n, int total_tiles, int max_d,
+                                   int win, int scale, int trunc, hipStream_t st);
 hipError_t launch_batch_reset(unsigned* barrier, int* error, hipStream_t st);
 // Largest co-resident grid of the persistent kernel for `lds` bytes of LDS per workgroup.
 hipError_t batch_max_blocks_per_cu(int mode, int gmax, size_t lds, int* blocks);
@@ -254,7 +256,9 @@ hipError_t noalloc_scratch(void** ptr);
 hipError_t launch_lr_check(const int16_t* dl, const int16_t* dr, int W, int H, int D, int tol, int16_t* out,
                            hipStream_t st);
 hipError_t launch_luma(const uint8_t* rgb, int W, int H, uint8_t* y, hipStream_t st);
-hipError_t launch_ncc(const uint8_t* L, const uint8_t* R, int W, int H, int D, int win, int scale,
-                      int trunc, int16_t* cost, float* ncc, hipStream_t st);
+// The correlation volume with the window sums on the matrix cores (ncc_mfma.hip): views of
+// `channels` (1, or 3 interleaved) bytes a pixel; channels 3 needs win <= 9.
+hipError_t launch_ncc_mfma(const uint8_t* L, const uint8_t* R, int W, int H, int D, int win, int channels, int scale,
+                           int trunc, int16_t* cost, float* ncc, hipStream_t st);
 
 }  // namespace bpst

@@ -4,6 +4,7 @@ Calls only the CPU oracle (``oracle/``) and the seeded input generator; nothing 
 touches the GPU library.  Run once on the CPU (OpenMP uses every host core):
 
     python tests/golden/make_golden.py large      # -> tests/golden/large_1920x1080_d128.json
+    python tests/golden/make_golden.py large_rgb  # adds the colour cost volume's digest to it
     python tests/golden/make_golden.py batch      # -> tests/golden/batch_256.json
 
 Digests are of the arrays' raw little-endian bytes in the library's layouts: images uint8
@@ -90,6 +91,22 @@ def make_large(out):
     log(f"wrote {out}")
 
 
+def add_large_rgb(out):
+    """The colour correlation volume of the same pair (9x9 window, channels pooled)."""
+    w = synth.WORKLOADS["large"]
+    p = synth.workload_pair("large")
+    with open(out) as f:
+        rec = json.load(f)
+    assert rec["left_rgb"] == digest(p["left"]) and rec["right_rgb"] == digest(p["right"])
+    t = time.time()
+    cost = oracle.cost_volume_rgb(p["left"], p["right"], w["num_disp"], w["window"], w["cost_scale"], w["cost_trunc"])
+    log(f"  colour cost volume: {time.time() - t:.1f} s")
+    rec["cost_rgb"] = digest(cost)
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    log(f"updated {out}")
+
+
 def make_batch(out, n):
     b = synth.BATCH
     L, iters = b["num_scales"], [b["iters"]] * b["num_scales"]
@@ -118,11 +135,13 @@ def make_batch(out, n):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["large", "batch"])
+    ap.add_argument("what", choices=["large", "large_rgb", "batch"])
     ap.add_argument("--pairs", type=int, default=synth.BATCH["count"])
     a = ap.parse_args()
     if a.what == "large":
         make_large(os.path.join(HERE, "large_1920x1080_d128.json"))
+    elif a.what == "large_rgb":
+        add_large_rgb(os.path.join(HERE, "large_1920x1080_d128.json"))
     else:
         make_batch(os.path.join(HERE, "batch_256.json"), a.pairs)
 

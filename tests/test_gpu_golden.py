@@ -65,6 +65,16 @@ def test_large_luma_cost_and_pyramid(large):
         assert digest(WS.pyramid_level(cost, L, l)) == g["pyramid"][l], f"pyramid scale {l}"
 
 
+def test_large_colour_cost_volume(large):
+    """The colour correlation volume of the same RGB pair (channels pooled), every element."""
+    g, w, _, _, _ = large
+    p = synth.workload_pair("large")
+    say("large pair: colour cost volume on the GPU")
+    c = B.stereo_cost_volume_rgb(torch.from_numpy(p["left"]).cuda(), torch.from_numpy(p["right"]).cuda(),
+                                 w["num_disp"], w["window"], w["cost_scale"], w["cost_trunc"])
+    assert digest(c) == g["cost_rgb"], "colour cost volume differs from the oracle's"
+
+
 def test_large_plain_solve_every_element(large):
     """The finest messages and disparities of the whole 5 x 12 solve, the messages each
     coarser scale ends with, and the energy."""

@@ -72,6 +72,42 @@ def test_cost_volume_other_scale_and_trunc():
         assert np.array_equal(got, oracle.cost_volume(L, R, 12, 5, scale, trunc))
 
 
+# ------------------------------------------------------------------ colour NCC
+@pytest.mark.parametrize("H,W,D,win", [(9, 77, 5, 3), (12, 40, 16, 5), (7, 33, 33, 7), (5, 70, 64, 9),
+                                       (6, 20, 1, 1), (3, 130, 128, 9), (2, 300, 256, 5), (17, 65, 16, 9)])
+def test_cost_volume_rgb_random(H, W, D, win):
+    rng = np.random.default_rng(H * 1000 + W + D + 7)
+    L = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+    R = np.clip(np.roll(L, -min(D - 1, 3), axis=1).astype(int) + rng.integers(-20, 21, (H, W, 3)), 0,
+                255).astype(np.uint8)
+    R[:, : W // 4] = (77, 12, 200)  # a flat band: zero-variance windows in every channel
+    L[:, W // 2: W // 2 + 3, 1] = 40  # one flat channel stretch
+    say(f"colour cost volume random H={H} W={W} D={D} win={win}")
+    cost, ncc = B.stereo_cost_volume_rgb(gpu(L), gpu(R), D, win, want_ncc=True)
+    ref_cost, ref_ncc = oracle.cost_volume_rgb(L, R, D, win, want_ncc=True)
+    assert np.array_equal(host(cost), ref_cost)
+    assert np.max(np.abs(host(ncc).astype(np.float64) - ref_ncc)) <= 1e-5
+
+
+def test_cost_volume_rgb_grey_views_equal_luma_volume():
+    """Grey views given as RGB (R = G = B) give exactly the one-channel volume."""
+    p = synth.workload_pair("tiny")
+    L3 = np.repeat(p["left"][..., None], 3, 2)
+    R3 = np.repeat(p["right"][..., None], 3, 2)
+    say("colour cost volume of grey views")
+    c3 = host(B.stereo_cost_volume_rgb(gpu(L3), gpu(R3), 16, 5))
+    c1 = host(B.stereo_cost_volume(gpu(p["left"]), gpu(p["right"]), 16, 5))
+    assert np.array_equal(c3, c1)
+    assert np.array_equal(c1, oracle.cost_volume(p["left"], p["right"], 16, 5))
+
+
+def test_cost_volume_rgb_rejects_wide_windows():
+    L = torch.zeros((8, 8, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.BPError) as e:
+        B.stereo_cost_volume_rgb(L, L, 4, 11)
+    assert e.value.code == B.BP_E_INVAL
+
+
 # ------------------------------------------------------------------ hierarchical solve
 def run_both(cost, L, iters, lam, T, skip=0, K=2, warm=None):
     say(f"solve shape={cost.shape} L={L} iters={iters} lam={lam} T={T} skip={skip} K={K} warm={warm is not None}")
