@@ -607,9 +607,10 @@ def main():
         "freeze_rule": {"energy_ratio_vs_plain": e_frz / e_plain if e_plain else None,
                         "msg_updates_per_pair": st_frz["msg_updates"],
                         "active_fraction_finest": frz_active},
-        "timing_note": "value: the whole step launched eagerly, steps back to back, with a HIP event pair around "
-                       "each message-update launch (the roofline's launch times); pairs_per_s_without_events and "
-                       "graph_replay_pairs_per_s: the same steps without the events and as one replayed HIP graph",
+        "timing_note": "value: the whole step launched eagerly, steps back to back, with a HIP event pair on the "
+                       "launch stream around each scale's run of message-update launches (the roofline's average "
+                       "launch duration is their summed time over the launch count); pairs_per_s_without_events "
+                       "and graph_replay_pairs_per_s: the same steps without the events and as one replayed HIP graph",
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -265,12 +265,13 @@ int32_t bp_energy(const int16_t* cost, const int16_t* disparity, int32_t width, 
 /* ---------------------------------------------------------------------------------------
  * Batched solve: the whole method (correlation volume, hierarchy, half-steps, winner-take-
  * all) for many independent pairs of different sizes and disparity ranges.  It enqueues
- * one launch for every pair's correlation volume and ONE persistent launch that solves
- * every pair.  That launch walks the same phase sequence as bp_hierarchical_solve (pyramid;
- * per scale, coarsest first, its start and its half-steps; winner-take-all) for all pairs
- * together, with a grid-wide barrier between phases.  Each pair's cost volume and
- * disparity are bit-identical to stereo_cost_volume + bp_hierarchical_solve on that pair
- * alone.
+ * one launch for every pair's correlation volume, then walks the same phase sequence as
+ * bp_hierarchical_solve (pyramid; per scale, coarsest first, its start and its half-steps;
+ * winner-take-all) for all pairs together: by default one launch per phase, each covering
+ * that phase of every pair; optionally (bp_autotune_batched, bp_context_set_batch_schedule)
+ * one persistent launch with a grid-wide barrier between phases.  Each pair's cost volume
+ * and disparity are bit-identical to stereo_cost_volume + bp_hierarchical_solve on that
+ * pair alone, whatever the schedule.
  * ------------------------------------------------------------------------------------- */
 typedef struct {
     const uint8_t* left;   /* [device] uint8 [H][W] */
@@ -328,7 +329,8 @@ typedef struct {
  * workgroups per compute unit and tile order), keeps the fastest in ctx for later
  * bp_solve_batched calls with the same pair shapes and parameters, and reports the table in
  * *out [host].  Synchronises the stream.  Results do not depend on the schedule.
- * Without tuning (or a forced shape) a batch runs as one persistent launch.
+ * Without tuning (or a forced shape) a batch runs one launch per phase (schedule 2, which
+ * runs as schedule 1 when lambda * trunc > 16383).
  */
 int32_t bp_autotune_batched(bp_context* ctx, const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params,
                             void* workspace, size_t workspace_bytes, void* stream, bp_batch_tuning* out);

@@ -369,11 +369,37 @@ BP_API size_t bp_workspace_bytes(int32_t width, int32_t height, const bp_params*
     return make_plan(width, height, params).total;
 }
 
+// Test and tuning hooks (environment variables), read once per solve: none changes a result,
+// only how the same arithmetic is cut into launches.
+struct Hooks {
+    int fused_steps = 0;        // BPSTEREO_FUSED_STEPS=n: fused launches of n half-steps
+    int tile_w = 0, tile_h = 0; // BPSTEREO_FUSED_TILE=WxH: smaller interior tiles of fused launches
+    int fused_tail = 0;         // BPSTEREO_FUSED_TAIL=k: freeze rule, one launch a half-step up to t = k
+    int compact = -1;           // BPSTEREO_FUSED_COMPACT=0/1: force the active-pixel listing off/on
+    bool graph_fail = false;    // BPSTEREO_GRAPH_FORCE_FAIL=1: make graph capture fail
+};
+
+static Hooks read_hooks()
+{
+    Hooks h;
+    if (const char* v = getenv("BPSTEREO_FUSED_STEPS")) h.fused_steps = atoi(v);
+    if (const char* v = getenv("BPSTEREO_FUSED_TILE")) {
+        if (sscanf(v, "%dx%d", &h.tile_w, &h.tile_h) != 2) h.tile_w = h.tile_h = 0;
+    }
+    if (const char* v = getenv("BPSTEREO_FUSED_TAIL")) h.fused_tail = atoi(v);
+    if (const char* v = getenv("BPSTEREO_FUSED_COMPACT")) {
+        if ((v[0] == '0' || v[0] == '1') && v[1] == 0) h.compact = v[0] - '0';
+    }
+    if (const char* v = getenv("BPSTEREO_GRAPH_FORCE_FAIL")) h.graph_fail = v[0] == '1';
+    return h;
+}
+
 // Enqueue every launch of one solve on `st` (no synchronisation, no allocation).
 static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cost, const bp_params* params,
                              void* workspace, int16_t* disparity, int16_t* final_msgs_or_null, bool count,
                              hipStream_t st, bool timing_allowed = true)
 {
+    const Hooks hk = read_hooks();
     char* ws = static_cast<char*>(workspace);
     auto* stats = reinterpret_cast<bpst::DevStats*>(ws + pl.off_stats);
     int16_t* C[bpst::kMaxScales];
@@ -432,8 +458,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         const int fmode = ctx ? ctx->fused : 2;
         if (fmode != 0 && !count && mode != 2 && iters >= 1 && pl.G <= 8) {
             // test and tuning hook: a fixed number of half-steps per fused launch
-            const char* fs = getenv("BPSTEREO_FUSED_STEPS");
-            const int forced_steps = fs ? atoi(fs) : 0;
+            const int forced_steps = hk.fused_steps;
             if (forced_steps > 0) {
                 fsteps = forced_steps < iters ? forced_steps : iters;
                 if (!bpst::fused_geometry_max(pl.lv[l], pl.G, fsteps, &ftw, &fth, &frmax)) fsteps = 0;
@@ -446,10 +471,8 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
             }
             {
                 // test hook: smaller interior tiles, so that small images are cut into many
-                const char* forced = getenv("BPSTEREO_FUSED_TILE");
-                int fw = 0, fh = 0;
-                if (fsteps > 0 && forced && sscanf(forced, "%dx%d", &fw, &fh) == 2 && fw >= 1 && fh >= 1 &&
-                    fw <= ftw && fh <= fth) {
+                const int fw = hk.tile_w, fh = hk.tile_h;
+                if (fsteps > 0 && fw >= 1 && fh >= 1 && fw <= ftw && fh <= fth) {
                     ftw = fw;
                     fth = fh;
                     frmax = (long long)(fw + 2 * fsteps) * (fh + 2 * fsteps);
@@ -464,11 +487,10 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         };
         Seg segs[2];  // a fixed array: planning a solve allocates nothing
         int nsegs = 0;
-        const char* tail = getenv("BPSTEREO_FUSED_TAIL");
-        if (tail && atoi(tail) >= 2 && atoi(tail) < iters && fsteps == 0 && fmode != 0 && mode == 1 && !count &&
+        if (hk.fused_tail >= 2 && hk.fused_tail < iters && fsteps == 0 && fmode != 0 && mode == 1 && !count &&
             pl.G <= 8) {
             // tuning hook: one launch per half-step up to t = k, then fused launches
-            const int k = atoi(tail);
+            const int k = hk.fused_tail;
             const int chunks = (iters - k + kFusedMaxSteps * 2 - 1) / (kFusedMaxSteps * 2);
             const int steps = (iters - k + chunks - 1) / chunks;
             Seg b{k, iters, steps, 0, 0, 0};
@@ -581,6 +603,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                     f.source = t0 == 0 ? source : bpst::kSrcOwn;
                     f.keep_state = t0 + f.nsteps < iters ? 1 : 0;
                     f.narrow = narrow_ok(l, t0) && bpst::fused_narrow_pays(pl.G, sg.rmax) ? 1 : 0;
+                    f.compact = hk.compact;
                     hipEvent_t e0 = nullptr, e1 = nullptr;
                     if (time_each) {
                         const int32_t rc = timing_events(ctx, l, 1, &e0, &e1);
@@ -627,8 +650,7 @@ static int32_t run_solve(bp_context* ctx, const Plan& pl, const int16_t* cost, i
                     ctx->graph_hits++;
                     return ok();
                 }
-            const char* force = getenv("BPSTEREO_GRAPH_FORCE_FAIL");
-            if (!(force && force[0] == '1') &&
+            if (!read_hooks().graph_fail &&
                 hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
                 const int32_t rc = enqueue_solve(ctx, pl, cost, params, workspace, disparity, final_msgs_or_null,
                                                  false, st);
@@ -992,7 +1014,8 @@ bpst::BatchArgs batch_args(const BatchPlan& b, const bp_batch_params* p, char* w
 }
 
 // The solve part of a batch: schedule 0 is one persistent launch of bpc workgroups per
-// compute unit; schedule 1 is one launch per phase.
+// compute unit; schedule 1 is one launch per phase; schedule 2 is schedule 1 with packed
+// 16-bit message sums where lambda * trunc allows them.
 
 int32_t enqueue_batch_solve(bp_context* ctx, const BatchPlan& b, const bp_batch_params* p, char* ws, int sched, int bpc,
                             int order, int cus, long long ticks, hipStream_t st)
@@ -1059,7 +1082,9 @@ BP_API int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int3
     long long ticks = 0;
     rc = device_limits(params->skip_mode, b.gmax, b.lds, &cus, &max_bpc, &ticks);
     if (rc != BP_OK) return rc;
-    int bpc = std::min(2, max_bpc), order = 0, sched = 0;
+    // untuned: one launch per phase with packed sums where they apply (schedule 2, which runs
+    // as schedule 1 when lambda * trunc > 16383): measured faster than the persistent launch
+    int bpc = std::min(2, max_bpc), order = 0, sched = 2;
     const std::vector<int32_t> sig = batch_signature(pairs, n, params);
     for (const auto& t : ctx->tuned)
         if (t.sig == sig) {

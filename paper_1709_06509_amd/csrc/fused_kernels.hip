@@ -568,8 +568,7 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t st)
     // workgroup per compute unit while the tiles fit the 256 units)
     FusedArgs b = a;
     b.compact = (long long)((tiles + 255) / 256) * ((block.x + 63) / 64) > 4 ? 1 : 0;
-    const char* fc = getenv("BPSTEREO_FUSED_COMPACT");  // test hook: force the listing on (1) or off (0)
-    if (fc && (fc[0] == '0' || fc[0] == '1') && fc[1] == 0) b.compact = fc[0] - '0';
+    if (a.compact == 0 || a.compact == 1) b.compact = a.compact;  // test hook: listing forced off / on
 #define BPST_FUSED_G(GG)                                                                        \
     case GG:                                                                                    \
         if (a.narrow) {                                                                         \

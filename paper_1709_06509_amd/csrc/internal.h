@@ -154,7 +154,8 @@ struct FusedArgs {
     long long rmax;          // region pixels the LDS holds: (TW + 2 halo) (TH + 2 halo)
     int keep_state;          // write the freeze state back (later half-steps of the scale follow)
     int narrow;              // packed 16-bit sums: incoming messages in [0, capv], capv <= kNarrowCap
-    int compact;             // list the active pixels of each freeze-rule half-step (set by launch_fused)
+    int compact;             // list the active pixels of each freeze-rule half-step: -1 launch_fused
+                             // decides (the default), 0 / 1 forced off / on (a test hook)
 };
 constexpr int kFusedLdsBytes = 160 * 1024;
 // Largest capv for which the packed 16-bit message sums are exact: with every cost

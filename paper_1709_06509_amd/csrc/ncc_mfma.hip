@@ -6,7 +6,7 @@
 //   S_IJ(x, k) = sum_m I(x + i - r, y + j - r)_c * J(k + i - r, y + j - r)_c.
 // Over a 16 x 16 block of (k, x) that is one small matrix product, A[k][m] B[m][x], with the
 // right view's window samples as the rows of A and the left view's as the columns of B.  The
-// bytes enter as signed values v - 128 (v_mfma_i32_16x16x32_i8, int32 accumulation, exact);
+// bytes enter as signed values v - 128 (v_mfma_i32_16x16x64_i8, int32 accumulation, exact);
 // the offsets are put back with the window sums S_I, S_J:
 //   sum I J = sum I'J' + 128 (S_I + S_J) - 128^2 N,      N = samples in the window.
 // With n = window^2, a channel's zero-mean numerator is n S_IJc - S_Ic S_Jc, and pooled over

@@ -42,7 +42,7 @@ from . import warmstart as WS
 
 DEFAULT = dict(num_disp=64, num_scales=4, iters=10, lam=64, trunc=4, window=7, long_factor=4,
                train_size=(384, 288), eval_size=(640, 480), train_seed0=100000, eval_seed0=200000,
-               planes=(8, 12), lr=1e-3, bound=1.005)
+               planes=(8, 12), lr=1e-3, bound=1.005, skip=0)
 
 # candidate half-steps per scale of the warm solve, finest first (scale L-1 is skipped)
 MENU = [(10, 10, 10), (10, 6, 6), (10, 4, 4), (9, 9, 9), (9, 6, 6), (8, 12, 12), (8, 8, 8), (8, 6, 6), (8, 4, 4),
@@ -140,14 +140,14 @@ class Trainer:
 
 def solve_plain(sample, cfg):
     L = cfg["num_scales"]
-    d, _, _ = B.bp_hierarchical_solve(sample.cost, L, [cfg["iters"]] * L, cfg["lam"], cfg["trunc"])
+    d, _, _ = B.bp_hierarchical_solve(sample.cost, L, [cfg["iters"]] * L, cfg["lam"], cfg["trunc"], cfg["skip"])
     return d
 
 
 def solve_warm_cost(cost, cfg, msgs, schedule):
     L = cfg["num_scales"]
     its = list(schedule) + [0] * (L - len(schedule))
-    d, _, _ = B.bp_hierarchical_solve(cost, L, its, cfg["lam"], cfg["trunc"], warm_msgs=msgs)
+    d, _, _ = B.bp_hierarchical_solve(cost, L, its, cfg["lam"], cfg["trunc"], cfg["skip"], warm_msgs=msgs)
     return d
 
 
@@ -175,7 +175,7 @@ class Pipelines:
         self.cost_w = torch.empty_like(self.cost_p)
         self.disp_p = torch.empty((H, W), dtype=torch.int16, device=dev)
         self.disp_w = torch.empty_like(self.disp_p)
-        p = B.make_params(D, L, cfg["iters"], cfg["lam"], cfg["trunc"])
+        p = B.make_params(D, L, cfg["iters"], cfg["lam"], cfg["trunc"], cfg["skip"])
         nws = B.bp_workspace_bytes(W, H, p)
         self.ws_p = torch.empty(nws, dtype=torch.uint8, device=dev)
         self.ws_w = torch.empty(nws, dtype=torch.uint8, device=dev)
@@ -208,8 +208,8 @@ class Pipelines:
     def plain(self):
         c, L = self.cfg, self.cfg["num_scales"]
         B.stereo_cost_volume(self.left, self.right, c["num_disp"], c["window"], out=self.cost_p)
-        B.bp_hierarchical_solve(self.cost_p, L, [c["iters"]] * L, c["lam"], c["trunc"], workspace=self.ws_p,
-                                disparity=self.disp_p)
+        B.bp_hierarchical_solve(self.cost_p, L, [c["iters"]] * L, c["lam"], c["trunc"], c["skip"],
+                                workspace=self.ws_p, disparity=self.disp_p)
 
     def warm(self, schedule):
         c, t, L = self.cfg, self.trainer, self.cfg["num_scales"]
@@ -219,8 +219,8 @@ class Pipelines:
         WS.forward(self.x, t.layout, t.params, t.w16, self.cnn_ws, y=self.y)
         WS.warmstart_messages(self.y, c["num_disp"], c["lam"], c["trunc"], out=self.msgs)
         its = list(schedule) + [0] * (L - len(schedule))
-        B.bp_hierarchical_solve(self.cost_w, L, its, c["lam"], c["trunc"], warm_msgs=self.msgs, workspace=self.ws_w,
-                                disparity=self.disp_w)
+        B.bp_hierarchical_solve(self.cost_w, L, its, c["lam"], c["trunc"], c["skip"], warm_msgs=self.msgs,
+                                workspace=self.ws_w, disparity=self.disp_w)
 
     def load(self, pair):
         with torch.cuda.stream(self.stream):
@@ -353,9 +353,13 @@ def main():
     ap.add_argument("--long-factor", type=int, default=DEFAULT["long_factor"],
                     help="labels: plain BP's scale-(L-2) messages after this many times the half-steps per scale "
                          "(1: exactly plain BP's own messages there)")
+    ap.add_argument("--skip", type=int, default=0, choices=[0, 1],
+                    help="skip mode of every solve judged and timed (0 plain BP, 1 the converged-pixel freeze); "
+                         "labels always come from plain BP")
     args = ap.parse_args()
     cfg = dict(DEFAULT)
     cfg["long_factor"] = args.long_factor
+    cfg["skip"] = args.skip
     os.makedirs(args.out, exist_ok=True)
 
     def log(msg):
@@ -398,7 +402,7 @@ def main():
     res["deployed"] = "warm" if warm_pays else "plain"
     res["speedup_deployed"] = res["speedup_charged"] if warm_pays else 1.0
     res.update({"train_pairs": args.train_pairs, "steps": trainer.step, "train_seconds": t_train,
-                "label_long_factor": cfg["long_factor"],
+                "label_long_factor": cfg["long_factor"], "skip_mode": cfg["skip"],
                 "heldout_l1_network": l_net, "heldout_l1_zero": l_zero, "loss_curve": losses,
                 "schedule_table": table})
     with open(os.path.join(args.out, "result.json"), "w") as f:

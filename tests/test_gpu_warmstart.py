@@ -304,10 +304,33 @@ def test_warm_solve_matches_oracle_end_to_end():
     assert np.array_equal(host(d), ref)
 
 
+@pytest.mark.parametrize("D,L,size", [(16, 3, (96, 72)), (64, 4, (160, 120))])
+@pytest.mark.parametrize("skip", [0, 1])
+def test_warm_solve_parity_learned_shapes(D, L, size, skip):
+    """The warm solve in the learned configuration's shape (D = 64, 4 scales: network messages
+    at scale 2, scale 3 skipped) and a smaller one, plain BP and the freeze rule: disparities,
+    messages and counters equal the oracle's solve from the same messages."""
+    from paper_1709_06509_amd import warmstart_train as T
+    cfg = dict(T.DEFAULT, num_disp=D, num_scales=L, iters=6)
+    say(f"warm solve parity D={D} L={L} size={size} skip={skip}")
+    pair = synth.make_pair(size[0], size[1], D, (3, 5), True, 0, False, seed=79 + D)
+    sample = T.Sample(pair, cfg, with_label=False)
+    msgs = T.Trainer(cfg, seed=6).predict(sample)
+    iters = [5, 4, 4, 0][:L]
+    d, m, st = B.bp_hierarchical_solve(sample.cost, L, iters, 64, 4, skip, 2, warm_msgs=msgs, want_msgs=True,
+                                       want_stats=True)
+    rd, rm, rs = oracle.bp_solve(host(sample.cost), L, iters, 64, 4, skip, 2, warm_msgs=host(msgs))
+    assert np.array_equal(host(d), rd) and np.array_equal(host(m), rm)
+    assert st["pixel_updates"] == rs["pixel_updates"] and st["msg_updates"] == rs["msg_updates"]
+
+
 def test_trained_network_gain_over_no_network():
-    """What training buys, on held-out pairs: the network's messages are far closer to plain
-    BP's converged scale-(L-2) messages than the zero start the hierarchy would otherwise
-    give there, and a solve started from them passes the 0.5 % energy judge."""
+    """What the trained network gains over the method without it, at equal schedule (the same
+    reduced half-steps from the warm scale down, the network's messages against the zero
+    start the hierarchy would otherwise have there), on held-out pairs.  With few half-steps
+    the start decides much of the result and the network must win on energy; with the
+    deployable schedule (8 half-steps a scale) the finest scale decides the energy and the two
+    starts come out within the 0.5 % judge of plain BP, which is all asserted there."""
     from paper_1709_06509_amd import warmstart_train as T
     cfg = dict(T.DEFAULT, num_disp=16, num_scales=3, iters=8, train_size=(128, 96), eval_size=(128, 96))
     say("training gain")
@@ -316,13 +339,20 @@ def test_trained_network_gain_over_no_network():
     held = [T.Sample(T.gen_pair(cfg["train_size"], 300000 + i, cfg), cfg) for i in range(8)]
     losses = [tr.heldout_loss(s) for s in held]
     net, zero = float(np.mean([l[0] for l in losses])), float(np.mean([l[1] for l in losses]))
-    ratios = []
-    for s in held:
-        ep = T.energy(s.cost, T.solve_plain(s, cfg), cfg)
-        ew = T.energy(s.cost, T.solve_warm(s, cfg, tr.predict(s), (8, 8)), cfg)
-        ez = T.energy(s.cost, T.solve_warm(s, cfg, torch.zeros_like(s.label), (8, 8)), cfg)
-        ratios.append((ew / ep, ez / ep))
-    say(f"held-out L1: network {net:.2f}, zero start {zero:.2f}; energy / plain: warm "
-        f"{np.mean([r[0] for r in ratios]):.5f}, zero start {np.mean([r[1] for r in ratios]):.5f}")
+    res = {}
+    for sched in [(1, 1), (8, 8)]:
+        rows = []
+        for s in held:
+            ep = T.energy(s.cost, T.solve_plain(s, cfg), cfg)
+            ew = T.energy(s.cost, T.solve_warm(s, cfg, tr.predict(s), sched), cfg)
+            ez = T.energy(s.cost, T.solve_warm(s, cfg, torch.zeros_like(s.label), sched), cfg)
+            rows.append((ew / ep, ez / ep))
+        res[sched] = np.array(rows)
+        say(f"schedule {sched}: energy / plain, network start {res[sched][:, 0].mean():.5f}, zero start "
+            f"{res[sched][:, 1].mean():.5f}, network lower on {int((res[sched][:, 0] < res[sched][:, 1]).sum())} of 8")
+    say(f"held-out L1: network {net:.2f}, zero start {zero:.2f}")
     assert net < 0.5 * zero
-    assert all(r[0] <= 1.005 for r in ratios)
+    short = res[(1, 1)]
+    assert short[:, 0].mean() < short[:, 1].mean()
+    assert (short[:, 0] < short[:, 1]).sum() >= 6
+    assert all(r <= 1.005 for r in res[(8, 8)][:, 0])
