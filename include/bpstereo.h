@@ -438,6 +438,26 @@ int32_t bp_warmstart_input(const uint8_t* left, const uint8_t* right, const int1
 int32_t bp_warmstart_messages(const float* y, int32_t Ws, int32_t Hs, int32_t num_disp, int32_t lambda, int32_t trunc,
                               int16_t* msgs, void* stream);
 
+/*
+ * The warm-started solve in one call: bp_warmstart_input, bp_cnn_forward,
+ * bp_warmstart_messages and bp_hierarchical_solve with those messages, with bit-identical
+ * disparities, messages and counters.  The network runs as ONE launch between the cost pyramid
+ * and the first half-step (every layer's activations stay in LDS over a shrinking tile) and
+ * writes the start of scale L-2 straight into the solve's workspace.
+ *   left, right  [device] uint8 [H][W], the views the cost volume was built from
+ *   params       as for bp_hierarchical_solve, warm_msgs NULL; iters[L-1] is not used (scale
+ *                L-1 is skipped); num_scales >= 2; num_disp a multiple of 16 in 16..64
+ *                (BP_E_UNSUPPORTED otherwise: the layer-level calls above take any D)
+ *   cnn_params   [device] fp32 parameter vector (biases are read from it)
+ *   cnn_weights  [device] bf16 copy of it (bp_cnn_to_bf16)
+ *   workspace, disparity, final_msgs_or_null, stats_or_null as for bp_hierarchical_solve
+ * Asynchronous unless stats are requested; always eager (the context's graph mode is not used).
+ */
+int32_t bp_warmstart_solve(bp_context* ctx, const uint8_t* left, const uint8_t* right, const int16_t* cost,
+                           int32_t width, int32_t height, const bp_params* params, const float* cnn_params,
+                           const uint16_t* cnn_weights, void* workspace, size_t workspace_bytes, int16_t* disparity,
+                           int16_t* final_msgs_or_null, bp_stats* stats_or_null, void* stream);
+
 /* Scale `level` (0..num_scales-1) of the solve's cost pyramid, in the caller's layout
    out [device] int16 [H_level][W_level][D]; workspace: a solve workspace. */
 int32_t bp_pyramid_level(const int16_t* cost, int32_t width, int32_t height, const bp_params* params, int32_t level,

@@ -394,10 +394,21 @@ static Hooks read_hooks()
     return h;
 }
 
-// Enqueue every launch of one solve on `st` (no synchronisation, no allocation).
+// The learned warm start computed inside a solve (bp_warmstart_solve): the views the cost
+// volume was built from and the network's parameters.
+struct WarmNet {
+    const uint8_t* left;
+    const uint8_t* right;
+    int width, height;
+    const float* params;
+    const uint16_t* w16;
+};
+
+// Enqueue every launch of one solve on `st` (no synchronisation, no allocation).  With `net`,
+// the solve starts at scale L - 2 from the network's messages, as with params->warm_msgs.
 static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cost, const bp_params* params,
                              void* workspace, int16_t* disparity, int16_t* final_msgs_or_null, bool count,
-                             hipStream_t st, bool timing_allowed = true)
+                             hipStream_t st, bool timing_allowed = true, const WarmNet* net = nullptr)
 {
     const Hooks hk = read_hooks();
     char* ws = static_cast<char*>(workspace);
@@ -429,7 +440,8 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         }
     }
 
-    const int start = params->warm_msgs ? pl.L - 2 : pl.L - 1;
+    const bool warm = params->warm_msgs || net;
+    const int start = warm ? pl.L - 2 : pl.L - 1;
     // Half-step t of scale l may use packed 16-bit sums (bp_device.h, the narrow path) when
     // every incoming message it reads is a transform output, in [0, capv], and capv is small
     // enough.  Raw warm messages (any value up to 32767) are read by the warm scale's first
@@ -437,7 +449,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
     // (then some slots are never rewritten).
     auto narrow_ok = [&](int l, int t) {
         if (capv > bpst::kNarrowCap) return false;
-        if (!params->warm_msgs) return true;
+        if (!warm) return true;
         if (l == start) return t > 0;
         return params->iters[start] >= 2;
     };
@@ -449,7 +461,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         // scale needs its initial messages materialised: fewer than two half-steps (the
         // colour-0 slots would never be written), a warm start, or the exact dirty-skip,
         // whose change test compares against the initial messages.
-        const bool fuse = iters >= 2 && mode != 2 && !(l == start && params->warm_msgs);
+        const bool fuse = iters >= 2 && mode != 2 && !(l == start && warm);
         // Several half-steps per launch from LDS (fused_kernels.hip): no counters, freeze
         // rule or plain, and (by default) only where a half-step moves little enough memory
         // that one launch per half-step would be bound by launch latency.
@@ -503,6 +515,29 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         int source = bpst::kSrcOwn;
         if (fuse) {
             source = (l == start) ? bpst::kSrcZero : bpst::kSrcParent;
+        } else if (l == start && net) {
+            bpst::WarmCnnArgs w{};
+            w.left = net->left;
+            w.right = net->right;
+            w.W = net->width;
+            w.H = net->height;
+            w.s = l;
+            w.coarse = C[l + 1];
+            w.lc = pl.lv[l + 1];
+            w.D = pl.D;
+            w.Dp = pl.Dp;
+            w.G = pl.G;
+            w.w16 = net->w16;
+            w.params = net->params;
+            if (!bpst::cnn_offsets(pl.D, w.w_off, w.b_off)) return fail(BP_E_INVAL, "num_disp outside the network's range");
+            w.lam_t = capv;
+            w.msgs = msgs;
+            w.lv = pl.lv[l];
+            w.vol = pl.vol[l];
+            w.state_a = sa;
+            w.state_b = sb;
+            w.mode = mode;
+            HIP_TRY(bpst::launch_warm_cnn(w, st));
         } else if (l == start && params->warm_msgs) {
             HIP_TRY(bpst::launch_import(params->warm_msgs, msgs, pl.lv[l], pl.vol[l], pl.D, pl.G, sa, sb, mode, st));
         } else if (l == start) {
@@ -635,10 +670,12 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
 // no runtime object.
 static int32_t run_solve(bp_context* ctx, const Plan& pl, const int16_t* cost, int32_t width, int32_t height,
                          const bp_params* params, void* workspace, size_t workspace_bytes, int16_t* disparity,
-                         int16_t* final_msgs_or_null, bp_stats* stats_or_null, bool noalloc, hipStream_t st)
+                         int16_t* final_msgs_or_null, bp_stats* stats_or_null, bool noalloc, hipStream_t st,
+                         const WarmNet* net = nullptr)
 {
     const bool count = stats_or_null != nullptr;
-    if (!noalloc && ctx && ctx->graphs && !count && !ctx->timing && st != nullptr) {
+    // (the context's graphs are keyed by the solve's buffers; a network-warmed solve runs eagerly)
+    if (!noalloc && !net && ctx && ctx->graphs && !count && !ctx->timing && st != nullptr) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         HIP_TRY(hipStreamIsCapturing(st, &cs));
         if (cs == hipStreamCaptureStatusNone) {
@@ -676,8 +713,8 @@ static int32_t run_solve(bp_context* ctx, const Plan& pl, const int16_t* cost, i
         }
     }
     {
-        const int32_t rc =
-            enqueue_solve(ctx, pl, cost, params, workspace, disparity, final_msgs_or_null, count, st, !noalloc);
+        const int32_t rc = enqueue_solve(ctx, pl, cost, params, workspace, disparity, final_msgs_or_null, count, st,
+                                         !noalloc, net);
         if (rc != BP_OK) return rc;
     }
     auto* stats = reinterpret_cast<bpst::DevStats*>(static_cast<char*>(workspace) + pl.off_stats);
@@ -689,7 +726,7 @@ static int32_t run_solve(bp_context* ctx, const Plan& pl, const int16_t* cost, i
         stats_or_null->msg_updates = (int64_t)hs.msg_updates;
         stats_or_null->pixel_updates = (int64_t)hs.pixel_updates;
         for (int l = 0; l < pl.L; ++l) {
-            stats_or_null->n_halfsteps[l] = (params->warm_msgs && l == pl.L - 1) ? 0 : params->iters[l];
+            stats_or_null->n_halfsteps[l] = ((params->warm_msgs || net) && l == pl.L - 1) ? 0 : params->iters[l];
             for (int t = 0; t < bpst::kStatHalfsteps; ++t) stats_or_null->active[l][t] = hs.active[l][t];
         }
     }
@@ -711,6 +748,31 @@ BP_API int32_t bp_hierarchical_solve(bp_context* ctx, const int16_t* cost, int32
         return fail(BP_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
     return run_solve(ctx, pl, cost, width, height, params, workspace, workspace_bytes, disparity,
                      final_msgs_or_null, stats_or_null, false, (hipStream_t)stream);
+}
+
+BP_API int32_t bp_warmstart_solve(bp_context* ctx, const uint8_t* left, const uint8_t* right, const int16_t* cost,
+                                  int32_t width, int32_t height, const bp_params* params, const float* cnn_params,
+                                  const uint16_t* cnn_weights, void* workspace, size_t workspace_bytes,
+                                  int16_t* disparity, int16_t* final_msgs_or_null, bp_stats* stats_or_null,
+                                  void* stream)
+{
+    std::string why;
+    if (!params_valid(width, height, params, &why)) return fail(BP_E_INVAL, "%s", why.c_str());
+    if (!left || !right || !cost || !disparity || !cnn_params || !cnn_weights)
+        return fail(BP_E_INVAL, "a pointer is NULL");
+    if (params->warm_msgs) return fail(BP_E_INVAL, "warm_msgs must be NULL: the network provides the start");
+    if (params->num_scales < 2) return fail(BP_E_INVAL, "the warm start needs num_scales >= 2");
+    if (!bpst::warm_cnn_supported(params->num_disp))
+        return fail(BP_E_UNSUPPORTED, "the one-launch network needs num_disp a multiple of 16 in 16..64 (the "
+                                      "layer-level calls take any num_disp)");
+    const Plan pl = make_plan(width, height, params);
+    if (!workspace || workspace_bytes < pl.total)
+        return fail(BP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, pl.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(BP_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    const WarmNet net{left, right, width, height, cnn_params, cnn_weights};
+    return run_solve(ctx, pl, cost, width, height, params, workspace, workspace_bytes, disparity,
+                     final_msgs_or_null, stats_or_null, false, (hipStream_t)stream, &net);
 }
 
 BP_API size_t bp_noalloc_scratch_bytes(void) { return bpst::kNoallocScratchBytes; }

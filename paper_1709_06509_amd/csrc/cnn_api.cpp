@@ -45,6 +45,8 @@ bool geometry(int D, LayerGeo g[kLayers], long long* total)
 
 size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
+static_assert(kLayers == bpst::kCnnLayers, "one layer count");
+
 struct CnnWs {
     size_t act[kLayers];  // act[l], l >= 1: bf16 [P][32], the input of layer l
     size_t gy, gh[2], wflip, part_w, part_b, part_loss, total;
@@ -100,6 +102,18 @@ int32_t hip_fail(hipError_t e, const char* what)
 bool size_ok(int32_t Ws, int32_t Hs) { return Ws >= 1 && Hs >= 1 && Ws <= 4096 && Hs <= 4096; }
 
 }  // namespace
+
+bool bpst::cnn_offsets(int D, long long w_off[kCnnLayers], long long b_off[kCnnLayers])
+{
+    LayerGeo g[kLayers];
+    long long n = 0;
+    if (!geometry(D, g, &n)) return false;
+    for (int l = 0; l < kLayers; ++l) {
+        w_off[l] = g[l].w_off;
+        b_off[l] = g[l].b_off;
+    }
+    return true;
+}
 
 BP_API int64_t bp_cnn_param_count(int32_t num_disp)
 {

@@ -10,6 +10,9 @@
 //
 // Reductions over pixels (weight and bias gradients, the loss) are split into fixed pixel
 // chunks whose partial sums are added in chunk order, so results are deterministic.
+#include <mutex>
+#include <vector>
+
 #include "internal.h"
 
 namespace bpst {
@@ -379,6 +382,399 @@ __global__ __launch_bounds__(kCT) void k_warm_messages(const float* __restrict__
     }
 }
 
+// ---- the whole warm start of one scale in one launch ----
+//
+// A workgroup of 8 waves takes a tile of kWTW x kWTH pixels of scale s.  A 3x3 layer's output
+// over a region needs its input over the region grown by one pixel a side, so the six layers
+// run over regions that shrink from the tile plus a 5-pixel border (layer 1) to the tile
+// itself (layer 6), and the network input is needed over the tile plus 6.  Nothing but the
+// messages leaves the workgroup:
+//   - the input is formed in LDS: the views' box averages per pixel and the parent's coarse
+//     cost per parent (both bf16, rounded as the input kernel rounds them), then expanded to
+//     one [pixel][channel] row per pixel of the input region;
+//   - hidden activations (32 channels, bf16) ping-pong between two LDS buffers;
+//   - every region position outside the image holds 0 in every buffer, which is the zero
+//     padding the next layer reads there, so no operand needs a bounds test;
+//   - the last layer's outputs are quantised in registers, normalised per message with
+//     minima exchanged through LDS, staged in LDS and stored as 16-byte vectors into the
+//     scale's message volumes (colour-split slots, Dp labels), with the state bytes a
+//     warm-started scale begins with.
+// Every output is computed as the layer-by-layer path computes it: the same MFMA, the same
+// K order (tap, then 16 channels at a time), the same bias, ReLU and bf16 rounding, the
+// same quantisation, so the messages are bit-identical.  A wave keeps the weight fragments
+// it needs for a layer in registers (every workgroup reads the same weights: they stay in
+// the caches).
+constexpr int kWT = 512;             // threads per workgroup (8 waves)
+constexpr int kWWaves = kWT / 64;
+constexpr int kWTW = 12, kWTH = 8;   // tile of scale s
+constexpr int kWIW = kWTW + 12, kWIH = kWTH + 12;          // network input region
+constexpr int kWPW = kWTW / 2 + 7, kWPH = kWTH / 2 + 7;    // parents of the input region
+constexpr int kWAS = 36;             // bf16 per pixel of an activation buffer: 32 channels + 4 (banks)
+constexpr int kWN = kWTW * kWTH;     // pixels of the tile
+static_assert(kWTW % 2 == 0 && kWTH % 2 == 0, "even tiles: the parent region starts at an exact half");
+
+__host__ __device__ constexpr int warm_act_pixels(int halo) { return (kWTW + 2 * halo) * (kWTH + 2 * halo); }
+// Pitch (bf16) of a pixel's row of network input: 16 NC1 channels + 4 (2-dword reads of 16
+// consecutive pixels then fall in distinct banks).
+__host__ __device__ constexpr int warm_in_pitch(int cin0) { return cin0 + 4; }
+
+// LDS: region 1 holds the box averages and the parents' costs while the input is formed, then
+// the activations of layers 1, 3, 5; region 2 holds the network input, then the activations
+// of layers 2 and 4, then the last layer's minima and staged messages.
+__host__ __device__ inline size_t warm_r1(int cin0)
+{
+    const size_t stage = (size_t)2 * kWIW * kWIH + (size_t)kWPW * kWPH * cin0;
+    const size_t act = (size_t)warm_act_pixels(5) * kWAS;
+    return 2 * (stage > act ? stage : act);
+}
+__host__ __device__ inline size_t warm_r2(int cin0, int D)
+{
+    const size_t inp = (size_t)kWIW * kWIH * warm_in_pitch(cin0) * 2;
+    const size_t act = (size_t)warm_act_pixels(4) * kWAS * 2;
+    const size_t last = (size_t)kWN * 16 * 4 /* block minima */ + (size_t)kWN * 4 * 4 /* side minima */ +
+                        (size_t)kWN * 4 * D * 2 /* messages */;
+    size_t m = inp > act ? inp : act;
+    return m > last ? m : last;
+}
+__host__ __device__ inline size_t warm_cnn_lds(int cin0, int D) { return warm_r1(cin0) + warm_r2(cin0, D); }
+
+__device__ __forceinline__ v4s lds_v4s(const uint16_t* p) { return *reinterpret_cast<const v4s*>(p); }
+
+// Minimum over the 16 lanes of each row of the wave (lanes 16 r .. 16 r + 15), in every lane
+// of the row: rotations within a row through DPP.
+__device__ __forceinline__ int row_min16(int v)
+{
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false));  // row_ror:8
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xf, 0xf, false));  // row_ror:4
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x122, 0xf, 0xf, false));  // row_ror:2
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x121, 0xf, 0xf, false));  // row_ror:1
+    return v;
+}
+
+// The weight fragments (B operands) of one wave for a 3x3 layer of cin_p = 16 NC input
+// channels: output channel co, every (tap, 16-channel chunk), lane layout of the MFMA.
+template <int NC>
+__device__ __forceinline__ void warm_frags(const WarmCnnArgs& a, int layer, int co, v4s (&bf)[9][NC])
+{
+    const int g = (threadIdx.x & 63) >> 4;
+    const uint16_t* bw = a.w16 + a.w_off[layer] + (long long)co * 9 * (16 * NC) + 4 * g;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) bf[tap][cc] = *reinterpret_cast<const v4s*>(bw + tap * 16 * NC + 16 * cc);
+}
+
+// One 3x3 layer, 32 output channels, over the region of halo HO around the tile: output
+// pixel q of the region (row-major, width kWTW + 2 HO) from the input region of halo HO + 1
+// (rows of PITCH bf16 per pixel).  Waves 0-3 compute output channels 0-15, waves 4-7
+// channels 16-31 (the caller's fragments bf and bias are those of channel 16 t + i); a wave
+// runs two blocks of 16 region pixels at a time (blocks b and b + 4 of every eighth pair),
+// two independent accumulation chains sharing each weight fragment.
+template <int NC, int PITCH, int HO>
+__device__ __forceinline__ void warm_layer(const WarmCnnArgs& a, const v4s (&bf)[9][NC], float bias, int x0, int y0,
+                                           const uint16_t* __restrict__ in, uint16_t* __restrict__ out)
+{
+    constexpr int OW = kWTW + 2 * HO, OH = kWTH + 2 * HO, N = OW * OH, IWl = OW + 2, NBLK = (N + 15) / 16;
+    const int Ws = a.lv.W, Hs = a.lv.H;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    const int t = wave >> 2, wq = wave & 3;
+    for (int b0 = wq; b0 < NBLK; b0 += 8) {
+        // this lane's A row in blocks b0 and b0 + 4: its input row at tap (0, 0) (rows past
+        // the region read row 0: their results are never stored)
+        const uint16_t* arow[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int q = 16 * (b0 + 4 * p) + i;
+            const int ry = q < N ? q / OW : 0, rx = q < N ? q - (q / OW) * OW : 0;
+            arow[p] = in + (ry * IWl + rx) * PITCH + 4 * g;
+        }
+        v4f acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int off = ((tap / 3) * IWl + (tap % 3)) * PITCH;
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(lds_v4s(arow[p] + off + 16 * cc), bf[tap][cc],
+                                                                       acc[p], 0, 0, 0);
+        }
+        // results: rows 4 g + e of block p (region pixels), column i (channel 16 t + i);
+        // positions outside the image store 0
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int qo = 16 * (b0 + 4 * p) + 4 * g + e;
+                const int oy = qo / OW, ox = qo - oy * OW;
+                const int Yo = y0 - HO + oy, Xo = x0 - HO + ox;
+                const bool img = Yo >= 0 && Yo < Hs && Xo >= 0 && Xo < Ws;
+                const uint16_t v = to_bf16(fmaxf(acc[p][e] + bias, 0.f));
+                if (qo < N) out[qo * kWAS + 16 * t + i] = img ? v : (uint16_t)0;
+            }
+    }
+}
+
+template <int NC1, int T>
+__global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
+{
+    extern __shared__ __align__(16) uint16_t wsm[];
+    constexpr int cin0 = 16 * NC1, D = 16 * T, IP = warm_in_pitch(cin0);
+    uint16_t* r1 = wsm;
+    uint16_t* r2 = wsm + warm_r1(cin0) / 2;
+    uint16_t* box = r1;                              // [2][kWIH][kWIW]
+    uint16_t* par = r1 + 2 * kWIW * kWIH;            // [kWPH][kWPW][cin0]
+    uint16_t* inp = r2;                              // [kWIH][kWIW][IP]
+    uint16_t* actA = r1;                             // layers 1, 3, 5
+    uint16_t* actB = r2;                             // layers 2, 4
+    const int x0 = blockIdx.x * kWTW, y0 = blockIdx.y * kWTH;
+    const int px0 = (x0 - 6) / 2, py0 = (y0 - 6) / 2;  // exact: x0, y0 are even
+    const int Ws = a.lv.W, Hs = a.lv.H;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    const int co = 16 * (wave >> 2) + i;  // this lane's output channel in layers 1-5
+
+    v4s w1[9][NC1];
+    float b1;
+
+    // network input channels 0 and 1 over the input region: the views averaged over the
+    // 2^s x 2^s block of each pixel (clipped at the image), / 255, bf16.  Up to 4 x 4 blocks
+    // every byte of a thread's items is loaded (from a valid address, masked) before any is
+    // added.
+    const int Bs = 1 << a.s;
+    {
+        constexpr int NI = 2 * kWIW * kWIH, NIT = (NI + kWT - 1) / kWT;
+        int px[NIT][16], ny[NIT], nx[NIT];
+        bool in_img[NIT];
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int e = threadIdx.x + j * kWT;
+            const int v = e / (kWIW * kWIH), r = e - v * (kWIW * kWIH);
+            const int ry = r / kWIW, rx = r - ry * kWIW;
+            const int Y = y0 - 6 + ry, X = x0 - 6 + rx;
+            in_img[j] = e < NI && Y >= 0 && Y < Hs && X >= 0 && X < Ws;
+            ny[j] = in_img[j] ? min(Bs, a.H - Y * Bs) : 0;  // >= 1 in the image: (Y, X) is in scale s
+            nx[j] = in_img[j] ? min(Bs, a.W - X * Bs) : 0;
+            const uint8_t* base = (v == 0 ? a.left : a.right) + (in_img[j] ? (long long)(Y * Bs) * a.W + X * Bs : 0);
+            if (Bs <= 4) {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        px[j][4 * jj + k] = base[(jj < ny[j] && k < nx[j]) ? jj * a.W + k : 0];
+            } else {
+                int sum = 0;
+                for (int jj = 0; jj < ny[j]; ++jj)
+                    for (int k = 0; k < nx[j]; ++k) sum += base[(long long)jj * a.W + k];
+                px[j][0] = sum;
+            }
+        }
+        // the first layer's weights, in flight while the input is formed (issued after the
+        // views' bytes, so the sums below do not wait for them)
+        warm_frags<NC1>(a, 0, co, w1);
+        b1 = a.params[a.b_off[0] + co];
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int e = threadIdx.x + j * kWT;
+            if (e >= NI) break;
+            int sum = px[j][0];
+            if (Bs <= 4) {
+                sum = 0;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) sum += (jj < ny[j] && k < nx[j]) ? px[j][4 * jj + k] : 0;
+            }
+            box[e] = in_img[j] ? to_bf16((float)sum / ((float)(ny[j] * nx[j]) * 255.0f)) : (uint16_t)0;
+        }
+    }
+    // channels 2 .. D + 1: the parent's cost at scale s + 1, / 1024, bf16, per parent of the
+    // input region (channels 0, 1 and the padding hold 0 here); four channels an item, a
+    // thread's loads all issued first
+    {
+        constexpr int NI = kWPW * kWPH * (cin0 / 4), NIT = (NI + kWT - 1) / kWT;
+        unsigned lo[NIT], hi[NIT];
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int e = threadIdx.x + j * kWT;
+            const int c4 = e % (cin0 / 4), pp = e / (cin0 / 4);
+            const int pr = pp / kWPW, pc = pp - pr * kWPW;
+            const int cy = py0 + pr, cx = px0 + pc;
+            const bool inside = e < NI && cy >= 0 && cy < a.lc.H && cx >= 0 && cx < a.lc.W;
+            const int16_t* src =
+                a.coarse + (inside ? ((long long)(2 * cy + ((cx + cy) & 1)) * a.lc.Wh + (cx >> 1)) * a.Dp : 0);
+            // labels 4 c4 - 2, 4 c4 - 1 (channels 4 c4, 4 c4 + 1) and 4 c4, 4 c4 + 1: pairs of
+            // labels are wholly inside [0, D) or outside it (D is even)
+            const bool lo_ok = inside && c4 >= 1 && 4 * c4 <= D;
+            const bool hi_ok = inside && 4 * c4 < D;
+            lo[j] = lo_ok ? *reinterpret_cast<const unsigned*>(src + 4 * c4 - 2) : 0u;
+            hi[j] = hi_ok ? *reinterpret_cast<const unsigned*>(src + 4 * c4) : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int e = threadIdx.x + j * kWT;
+            if (e >= NI) break;
+            const int c4 = e % (cin0 / 4), pp = e / (cin0 / 4);
+            const bool lo_ok = c4 >= 1 && 4 * c4 <= D, hi_ok = 4 * c4 < D;
+            auto cv = [](unsigned w, int half) {
+                return to_bf16((float)(int16_t)(half ? (w >> 16) : (w & 0xffffu)) / 1024.0f);
+            };
+            const unsigned w01 = lo_ok ? ((unsigned)cv(lo[j], 0) | ((unsigned)cv(lo[j], 1) << 16)) : 0u;
+            const unsigned w23 = hi_ok ? ((unsigned)cv(hi[j], 0) | ((unsigned)cv(hi[j], 1) << 16)) : 0u;
+            *reinterpret_cast<uint2*>(par + pp * cin0 + 4 * c4) = make_uint2(w01, w23);
+        }
+    }
+    __syncthreads();
+    // the network input, one row per pixel of the input region: channels 0, 1 the box
+    // averages, then the parent's costs; 0 outside the image.  A thread reads all its items
+    // before writing any.
+    {
+        constexpr int NI = kWIW * kWIH * (cin0 / 4), NIT = (NI + kWT - 1) / kWT;
+        uint2 w[NIT];
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int e = threadIdx.x + j * kWT;
+            const int c4 = e % (cin0 / 4), r = e / (cin0 / 4);
+            const int ry = r / kWIW, rx = r - ry * kWIW;
+            const int Y = y0 - 6 + ry, X = x0 - 6 + rx;
+            const bool inside = e < NI && Y >= 0 && Y < Hs && X >= 0 && X < Ws;
+            const int pidx = inside ? ((Y >> 1) - py0) * kWPW + ((X >> 1) - px0) : 0;
+            const uint2 v = *reinterpret_cast<const uint2*>(par + pidx * cin0 + 4 * c4);
+            const int rr = e < NI ? r : 0;
+            const unsigned bx = (unsigned)box[rr] | ((unsigned)box[kWIW * kWIH + rr] << 16);
+            w[j] = make_uint2(inside ? (c4 == 0 ? bx : v.x) : 0u, inside ? v.y : 0u);
+        }
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int e = threadIdx.x + j * kWT;
+            if (e >= NI) break;
+            const int c4 = e % (cin0 / 4), r = e / (cin0 / 4);
+            *reinterpret_cast<uint2*>(inp + r * IP + 4 * c4) = w[j];
+        }
+    }
+    __syncthreads();
+    // each layer's weights are loaded while the layer before it runs
+    v4s w2[9][2], w3[9][2], w4[9][2], w5[9][2];
+    warm_frags<2>(a, 1, co, w2);
+    const float b2 = a.params[a.b_off[1] + co];
+    warm_layer<NC1, IP, 5>(a, w1, b1, x0, y0, inp, actA);
+    __syncthreads();
+    warm_frags<2>(a, 2, co, w3);
+    const float b3 = a.params[a.b_off[2] + co];
+    warm_layer<2, kWAS, 4>(a, w2, b2, x0, y0, actA, actB);
+    __syncthreads();
+    warm_frags<2>(a, 3, co, w4);
+    const float b4 = a.params[a.b_off[3] + co];
+    warm_layer<2, kWAS, 3>(a, w3, b3, x0, y0, actB, actA);
+    __syncthreads();
+    warm_frags<2>(a, 4, co, w5);
+    const float b5 = a.params[a.b_off[4] + co];
+    warm_layer<2, kWAS, 2>(a, w4, b4, x0, y0, actA, actB);
+    __syncthreads();
+
+    // last layer: 4D outputs over the tile in 4T blocks of 16 channels (T per side k).  Wave w
+    // takes channel blocks w and w + 8 and runs every 16-pixel block of the tile: each output
+    // is quantised in registers and each channel block's minimum over its 16 channels goes to
+    // LDS; then each message's minimum over d (the minimum of its side's T block minima), and
+    // the normalised messages are staged in LDS and stored as 16-byte vectors.
+    constexpr int NT = 4 * T, TPW = (NT + kWWaves - 1) / kWWaves, NB = (kWN + 15) / 16;
+    v4s w6[TPW][9][2];
+    float bc[TPW];
+#pragma unroll
+    for (int m = 0; m < TPW; ++m) {
+        const int t = wave + kWWaves * m;
+        const int c6 = 16 * (t < NT ? t : 0) + i;
+        warm_frags<2>(a, kCnnLayers - 1, c6, w6[m]);
+        bc[m] = a.params[a.b_off[kCnnLayers - 1] + c6];
+    }
+    warm_layer<2, kWAS, 1>(a, w5, b5, x0, y0, actB, actA);
+    __syncthreads();
+
+    int* bmin = reinterpret_cast<int*>(r2);      // [kWN][NT]
+    int* smin = bmin + kWN * NT;                  // [kWN][4]
+    int16_t* msg = reinterpret_cast<int16_t*>(smin + kWN * 4);  // [kWN][4][D]
+    const float lamf = (float)a.lam_t;
+    int qv[TPW][NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int q = 16 * b + i;
+        const int ry = q < kWN ? q / kWTW : 0, rx = q < kWN ? q - (q / kWTW) * kWTW : 0;
+        const uint16_t* arow = actA + (ry * (kWTW + 2) + rx) * kWAS + 4 * g;
+        v4f acc[TPW];
+#pragma unroll
+        for (int m = 0; m < TPW; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                const v4s av = lds_v4s(arow + ((tap / 3) * (kWTW + 2) + (tap % 3)) * kWAS + 16 * cc);
+#pragma unroll
+                for (int m = 0; m < TPW; ++m)
+                    if (wave + kWWaves * m < NT)  // uniform over the wave
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, w6[m][tap][cc], acc[m], 0, 0, 0);
+            }
+#pragma unroll
+        for (int m = 0; m < TPW; ++m) {
+            const int t = wave + kWWaves * m;
+            if (t >= NT) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float r = rintf((acc[m][e] + bc[m]) * lamf);
+                const int qq = r < 0.f ? 0 : (r > lamf ? a.lam_t : (int)r);
+                qv[m][b][e] = qq;
+                const int mn = row_min16(qq);
+                const int qo = 16 * b + 4 * g + e;
+                if (i == 0 && qo < kWN) bmin[qo * NT + t] = mn;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kWN * 4; e += kWT) {
+        const int qo = e >> 2, k = e & 3;
+        int mn = bmin[qo * NT + k * T];
+#pragma unroll
+        for (int v = 1; v < T; ++v) mn = min(mn, bmin[qo * NT + k * T + v]);
+        smin[e] = mn;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < TPW; ++m) {
+        const int t = wave + kWWaves * m;
+        if (t >= NT) continue;
+        const int k = t / T, u = t - k * T;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int qo = 16 * b + 4 * g + e;
+                if (qo < kWN) msg[(qo * 4 + k) * D + 16 * u + i] = (int16_t)(qv[m][b][e] - smin[qo * 4 + k]);
+            }
+    }
+    __syncthreads();
+    // copy-out: 16-byte pieces of 8 labels; labels D .. Dp - 1 and sides without a neighbour
+    // are 0
+    const int P8 = a.Dp / 8;
+    for (int e = threadIdx.x; e < kWN * 4 * P8; e += kWT) {
+        const int c = e % P8, qk = e / P8, k = qk & 3, qo = qk >> 2;
+        const int oy = qo / kWTW, ox = qo - oy * kWTW;
+        const int Yo = y0 + oy, Xo = x0 + ox;
+        if (Yo >= Hs || Xo >= Ws) continue;
+        const bool has = k == 0 ? Xo > 0 : k == 1 ? Xo < Ws - 1 : k == 2 ? Yo > 0 : Yo < Hs - 1;
+        int4 v = make_int4(0, 0, 0, 0);
+        if (has && 8 * c < D) v = *reinterpret_cast<const int4*>(msg + (qo * 4 + k) * D + 8 * c);
+        const long long gi = (long long)(2 * Yo + ((Xo + Yo) & 1)) * a.lv.Wh + (Xo >> 1);
+        *reinterpret_cast<int4*>(a.msgs + k * a.vol + gi * a.Dp + 8 * c) = v;
+        if (k == 0 && c == 0) {
+            if (a.mode == 1) {
+                a.state_a[gi] = 1;
+                a.state_b[gi] = 0;
+            }
+            if (a.mode == 2) a.state_a[gi] = 1;
+        }
+    }
+}
+
 inline unsigned blocks_for(long long n, int t = kCT, long long cap = 8192)
 {
     long long b = (n + t - 1) / t;
@@ -480,6 +876,52 @@ hipError_t launch_warm_messages(const float* y, int Ws, int Hs, int D, int ystri
     }
 #undef BPST_WARM
     return hipGetLastError();
+}
+
+bool warm_cnn_supported(int D) { return D >= 16 && D <= 64 && D % 16 == 0; }
+
+// The kernel's LDS limit raised above the 64 KB default, once per device (the attribute
+// belongs to the device's copy of the kernel).
+template <int NC1, int T>
+hipError_t warm_lds_limit()
+{
+    static std::mutex mu;
+    static std::vector<bool> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((size_t)dev < done.size() && done[dev]) return hipSuccess;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_warm_cnn<NC1, T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)warm_cnn_lds(16 * NC1, 16 * T));
+    if (e != hipSuccess) return e;
+    if ((size_t)dev >= done.size()) done.resize(dev + 1, false);
+    done[dev] = true;
+    return hipSuccess;
+}
+
+template <int NC1, int T>
+hipError_t launch_warm_cnn_t(const WarmCnnArgs& a, hipStream_t st)
+{
+    const size_t lds = warm_cnn_lds(16 * NC1, 16 * T);
+    if (lds > 64 * 1024) {
+        const hipError_t e = warm_lds_limit<NC1, T>();
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid((unsigned)((a.lv.W + kWTW - 1) / kWTW), (unsigned)((a.lv.H + kWTH - 1) / kWTH));
+    hipLaunchKernelGGL((k_warm_cnn<NC1, T>), grid, dim3(kWT), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_cnn(const WarmCnnArgs& a, hipStream_t st)
+{
+    if (!warm_cnn_supported(a.D) || a.lv.W < 1 || a.lv.H < 1) return hipErrorInvalidValue;
+    switch (a.D) {
+    case 16: return launch_warm_cnn_t<2, 1>(a, st);
+    case 32: return launch_warm_cnn_t<3, 2>(a, st);
+    case 48: return launch_warm_cnn_t<4, 3>(a, st);
+    default: return launch_warm_cnn_t<5, 4>(a, st);
+    }
 }
 
 }  // namespace bpst

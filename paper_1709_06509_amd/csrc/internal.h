@@ -212,6 +212,38 @@ hipError_t launch_warm_input(const uint8_t* L, const uint8_t* R, int W, int H, i
 hipError_t launch_warm_messages(const float* y, int Ws, int Hs, int D, int ystride, int lam_t, int16_t* out,
                                 hipStream_t st);
 
+// The network's layer count, and the offsets of each layer's weights and biases in the
+// parameter vector (bf16 weights use the same offsets); false if D is outside 1..256.
+constexpr int kCnnLayers = 6;
+bool cnn_offsets(int D, long long w_off[kCnnLayers], long long b_off[kCnnLayers]);
+
+// The whole warm start of one scale in one launch (cnn_kernels.hip): network input, the six
+// convolutions and the quantisation, written straight into the scale's message volumes and
+// state bytes in the solve's internal layout.  Bit-identical to launch_warm_input +
+// launch_conv_fwd x 6 + launch_warm_messages + launch_import.
+struct WarmCnnArgs {
+    const uint8_t* left;     // finest views, uint8 [H][W]
+    const uint8_t* right;
+    int W, H;
+    int s;                   // the warm scale (views averaged over 2^s x 2^s blocks)
+    const int16_t* coarse;   // internal cost of scale s + 1
+    Level lc;
+    int D, Dp, G;
+    const uint16_t* w16;     // bf16 weights; biases are read from params (fp32)
+    const float* params;
+    long long w_off[kCnnLayers], b_off[kCnnLayers];
+    int lam_t;               // quantisation range: min(lambda * min(trunc, D), 32767)
+    int16_t* msgs;           // scale s: four volumes of vol elements, colour-split slots of Dp labels
+    Level lv;
+    long long vol;
+    uint8_t* state_a;
+    uint8_t* state_b;
+    int mode;                // skip mode: the state bytes a scale starts with
+};
+// D must be a multiple of 16 and at most 64 (else hipErrorInvalidValue, nothing launched).
+bool warm_cnn_supported(int D);
+hipError_t launch_warm_cnn(const WarmCnnArgs& a, hipStream_t st);
+
 // The batch's correlation volumes in one launch (ncc_mfma.hip): tiles of one row and 64
 // columns, listed by per-pair prefix sums of ncc_mfma_tiles.
 int ncc_mfma_tiles(int W, int H);

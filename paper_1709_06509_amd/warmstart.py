@@ -42,9 +42,11 @@ def _lib():
         lib.bp_warmstart_messages.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp]
         lib.bp_pyramid_level.argtypes = [_vp, _i32, _i32, ctypes.POINTER(B.BPParams), _i32, _vp, ctypes.c_size_t,
                                          _vp, _vp]
+        lib.bp_warmstart_solve.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, ctypes.POINTER(B.BPParams), _vp, _vp, _vp,
+                                           ctypes.c_size_t, _vp, _vp, _vp, _vp]
         for n in ("bp_cnn_layer", "bp_conv3x3_forward", "bp_conv3x3_data_grad", "bp_conv3x3_weight_grad",
                   "bp_cnn_forward", "bp_cnn_backward", "bp_adam_step", "bp_cnn_to_bf16", "bp_warmstart_input",
-                  "bp_warmstart_messages", "bp_pyramid_level"):
+                  "bp_warmstart_messages", "bp_pyramid_level", "bp_warmstart_solve"):
             getattr(lib, n).restype = ctypes.c_int32
         _ready = True
     return lib
@@ -200,3 +202,34 @@ def pyramid_level(cost, num_scales, level, workspace=None, out=None, stream=None
     B._check(_lib().bp_pyramid_level(_p(cost), W, H, ctypes.byref(p), level, _p(workspace), workspace.numel(), _p(out),
                                      _s(stream)))
     return out
+
+
+def warmstart_solve(left, right, cost, num_scales, iters, lam, trunc, params, w16, skip_mode=0, converge_iters=2,
+                    want_msgs=False, want_stats=False, ctx=None, workspace=None, disparity=None, stream=None):
+    """The warm-started solve in one library call (the network as one launch inside the solve):
+    the same results as warmstart_input, forward, warmstart_messages and the solve with those
+    messages.  Returns (disparity, messages or None, stats or None) as bp_hierarchical_solve."""
+    H, W, D = cost.shape
+    for t, name in ((left, "left"), (right, "right")):
+        if tuple(t.shape) != (H, W):
+            raise ValueError(f"{name} must be [{H}, {W}]")
+    p = B.make_params(D, num_scales, iters, lam, trunc, skip_mode, converge_iters)
+    need = B.bp_workspace_bytes(W, H, p)
+    if need == 0:
+        raise B.BPError(B.BP_E_INVAL, "invalid solve parameters")
+    workspace = torch.empty(need, dtype=torch.uint8, device=cost.device) if workspace is None else workspace
+    disp = torch.empty((H, W), dtype=torch.int16, device=cost.device) if disparity is None else disparity
+    msgs = torch.empty((4, H, W, D), dtype=torch.int16, device=cost.device) if want_msgs else None
+    st = B.BPStats() if want_stats else None
+    B._check(_lib().bp_warmstart_solve(ctx.handle if ctx is not None else None, B._dev(left, torch.uint8, 2, "left"),
+                                       B._dev(right, torch.uint8, 2, "right"), B._dev(cost, torch.int16, 3, "cost"),
+                                       W, H, ctypes.byref(p), B._dev(params, torch.float32, 1, "params"),
+                                       B._dev(w16, torch.uint16, 1, "w16"), _p(workspace), workspace.numel(),
+                                       B._dev(disp, torch.int16, 2, "disparity"), _p(msgs),
+                                       ctypes.byref(st) if want_stats else None, _s(stream)))
+    stats = None
+    if want_stats:
+        stats = {"msg_updates": st.msg_updates, "pixel_updates": st.pixel_updates,
+                 "n_halfsteps": list(st.n_halfsteps),
+                 "active": [[st.active[l][t] for t in range(64)] for l in range(8)]}
+    return disp, msgs, stats

@@ -164,10 +164,11 @@ class Pipelines:
     static buffers at one image size, each captured once as a graph: timings compare GPU
     work, not host overhead."""
 
-    def __init__(self, trainer, cfg, schedules, size):
+    def __init__(self, trainer, cfg, schedules, size, one_call=True):
         W, H = size
         D, L = cfg["num_disp"], cfg["num_scales"]
         self.cfg, self.trainer = cfg, trainer
+        self.one_call = one_call and D % 16 == 0 and 16 <= D <= 64
         dev = "cuda"
         self.left = torch.zeros((H, W), dtype=torch.uint8, device=dev)
         self.right = torch.zeros((H, W), dtype=torch.uint8, device=dev)
@@ -212,13 +213,19 @@ class Pipelines:
                                 workspace=self.ws_p, disparity=self.disp_p)
 
     def warm(self, schedule):
+        """The warm-started step as deployed: the network runs as one launch inside the solve
+        (bp_warmstart_solve) where the library supports it, else layer by layer."""
         c, t, L = self.cfg, self.trainer, self.cfg["num_scales"]
         B.stereo_cost_volume(self.left, self.right, c["num_disp"], c["window"], out=self.cost_w)
+        its = list(schedule) + [0] * (L - len(schedule))
+        if self.one_call:
+            WS.warmstart_solve(self.left, self.right, self.cost_w, L, its, c["lam"], c["trunc"], t.params, t.w16,
+                               c["skip"], workspace=self.ws_w, disparity=self.disp_w)
+            return
         WS.warmstart_input(self.left, self.right, self.cost_w, L, c["iters"], c["lam"], c["trunc"],
                            workspace=self.ws_w, out=self.x)
         WS.forward(self.x, t.layout, t.params, t.w16, self.cnn_ws, y=self.y)
         WS.warmstart_messages(self.y, c["num_disp"], c["lam"], c["trunc"], out=self.msgs)
-        its = list(schedule) + [0] * (L - len(schedule))
         B.bp_hierarchical_solve(self.cost_w, L, its, c["lam"], c["trunc"], c["skip"], warm_msgs=self.msgs,
                                 workspace=self.ws_w, disparity=self.disp_w)
 
@@ -356,6 +363,8 @@ def main():
     ap.add_argument("--skip", type=int, default=0, choices=[0, 1],
                     help="skip mode of every solve judged and timed (0 plain BP, 1 the converged-pixel freeze); "
                          "labels always come from plain BP")
+    ap.add_argument("--layer-path", action="store_true",
+                    help="time the warm start through the layer-level calls instead of the one-call solve")
     args = ap.parse_args()
     cfg = dict(DEFAULT)
     cfg["long_factor"] = args.long_factor
@@ -390,7 +399,8 @@ def main():
     l_net, l_zero = float(np.mean([h[0] for h in held])), float(np.mean([h[1] for h in held]))
     log(f"held-out L1: network {l_net:.3f}, zero messages {l_zero:.3f}")
 
-    pipes = Pipelines(trainer, cfg, MENU, cfg["eval_size"])
+    pipes = Pipelines(trainer, cfg, MENU, cfg["eval_size"], one_call=not args.layer_path)
+    log(f"warm start timed through {'the one-call solve' if pipes.one_call else 'the layer-level calls'}")
     tune = [gen_pair(cfg["eval_size"], base + args.heldout_pairs + i, cfg) for i in range(args.tune_pairs)]
     schedule, table = choose_schedule(pipes, tune, cfg["bound"], log)
     best = min(table, key=lambda r: r["ms_charged"])
@@ -403,6 +413,7 @@ def main():
     res["speedup_deployed"] = res["speedup_charged"] if warm_pays else 1.0
     res.update({"train_pairs": args.train_pairs, "steps": trainer.step, "train_seconds": t_train,
                 "label_long_factor": cfg["long_factor"], "skip_mode": cfg["skip"],
+                "network_path": "one-call" if pipes.one_call else "layers",
                 "heldout_l1_network": l_net, "heldout_l1_zero": l_zero, "loss_curve": losses,
                 "schedule_table": table})
     with open(os.path.join(args.out, "result.json"), "w") as f:

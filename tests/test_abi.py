@@ -115,3 +115,34 @@ def test_noalloc_host_validation(lib):
     assert rc == B.BP_E_INVAL
     rc = L.bp_hierarchical_solve_noalloc(None, None, 64, 48, ctypes.byref(prod), p(16), None, None, None)
     assert rc == B.BP_E_INVAL
+
+
+def test_warmstart_solve_host_validation(lib):
+    """The one-call warm-started solve rejects bad arguments on the host: NULL pointers, caller
+    messages (the network provides the start), a single scale, a disparity count the one-launch
+    network does not take, and a short workspace."""
+    from paper_1709_06509_amd import bpstereo as B
+    from paper_1709_06509_amd import warmstart as WS
+
+    L = WS._lib()
+    p = ctypes.c_void_p
+    good = B.make_params(64, 4, [6, 4, 4, 0], 64, 4)
+    need = L.bp_workspace_bytes(160, 120, ctypes.byref(good))
+    args = lambda prm, ws=need, left=p(16), cw=p(16): (None, left, p(16), p(16), 160, 120, ctypes.byref(prm), p(16),
+                                                       cw, p(256), ws, p(16), None, None, None)
+    rc = L.bp_warmstart_solve(*args(good, left=None))
+    assert rc == B.BP_E_INVAL and b"NULL" in L.bp_last_error()
+    rc = L.bp_warmstart_solve(*args(good, cw=None))
+    assert rc == B.BP_E_INVAL
+    warm = B.make_params(64, 4, [6, 4, 4, 0], 64, 4)
+    warm.warm_msgs = 4096
+    rc = L.bp_warmstart_solve(*args(warm))
+    assert rc == B.BP_E_INVAL and b"warm_msgs" in L.bp_last_error()
+    rc = L.bp_warmstart_solve(*args(B.make_params(64, 1, [6], 64, 4)))
+    assert rc == B.BP_E_INVAL
+    for D in (8, 40, 80, 128):
+        prm = B.make_params(D, 4, [6, 4, 4, 0], 64, 4)
+        rc = L.bp_warmstart_solve(*args(prm, ws=L.bp_workspace_bytes(160, 120, ctypes.byref(prm))))
+        assert rc == B.BP_E_UNSUPPORTED and b"multiple of 16" in L.bp_last_error(), D
+    rc = L.bp_warmstart_solve(*args(good, ws=need - 1))
+    assert rc == B.BP_E_WORKSPACE

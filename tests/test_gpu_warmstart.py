@@ -356,3 +356,119 @@ def test_trained_network_gain_over_no_network():
     assert short[:, 0].mean() < short[:, 1].mean()
     assert (short[:, 0] < short[:, 1]).sum() >= 6
     assert all(r <= 1.005 for r in res[(8, 8)][:, 0])
+
+
+def spread_network(D, seed):
+    """Parameters whose messages spread over the whole quantisation range: the layout's
+    initial weights, the last layer 10x larger with biases uniform in [0, 1] (and every bias
+    of the hidden layers small but non-zero, so bias addition is exercised)."""
+    lay = WS.Layout(D)
+    params = lay.init_params(seed)
+    gen = torch.Generator().manual_seed(seed + 1)
+    for i, L in enumerate(lay.layers):
+        b = lay.bias(params, i)
+        if i == 5:
+            w = lay.weights(params, i)
+            w.mul_(10.0)
+            b[:L["cout"]] = torch.rand(L["cout"], generator=gen).cuda()
+        else:
+            b[:L["cout"]] = (torch.rand(L["cout"], generator=gen) * 0.1 - 0.05).cuda()
+    return lay, params, WS.to_bf16(params)
+
+
+def layer_path(left, right, cost, L, iters, lam, T, skip, lay, params, w16):
+    """The warm-started solve through the layer-level calls: network input, forward, messages,
+    then the solve with those messages."""
+    H, W, D = cost.shape
+    x = WS.warmstart_input(left, right, cost, L, iters, lam, T)
+    Hs, Ws, _ = x.shape
+    y = WS.forward(x, lay, params, w16, WS.workspace(Ws, Hs, D))
+    msgs = WS.warmstart_messages(y, D, lam, T)
+    d, m, st = B.bp_hierarchical_solve(cost, L, iters, lam, T, skip, 2, warm_msgs=msgs, want_msgs=True,
+                                       want_stats=True)
+    return msgs, d, m, st
+
+
+# (W, H, D, L): scale-(L-2) sizes with ragged 12 x 8 tiles, smaller than one tile, one pixel
+# wide or high, and the learned configuration (640 x 480, D = 64, 4 scales: 160 x 120)
+ONE_LAUNCH_CASES = [
+    (70, 45, 16, 3),
+    (33, 29, 32, 2),
+    (96, 72, 48, 3),
+    (5, 3, 16, 2),
+    (1, 9, 32, 2),
+    (130, 1, 16, 2),
+    (200, 150, 64, 4),
+    (640, 480, 64, 4),
+]
+
+
+@pytest.mark.parametrize("case", ONE_LAUNCH_CASES)
+@pytest.mark.parametrize("skip", [0, 1, 2])
+def test_warmstart_solve_equals_layer_path(case, skip):
+    """bp_warmstart_solve (the network as one launch inside the solve) against the layer-level
+    calls on the same pair and parameters: with no half-steps the scale-(L-2) start itself
+    (L = 2: the finest scale's exported messages are the network's messages), else the
+    disparities, finest messages and counters of the whole solve, bit for bit."""
+    W, H, D, L = case
+    say(f"one-launch warm solve W={W} H={H} D={D} L={L} skip={skip}")
+    pair = synth.make_pair(W, H, D, (3, 6), True, 0, False, seed=500 + W + D + skip)
+    left, right = gpu(pair["left"]), gpu(pair["right"])
+    cost = B.stereo_cost_volume(left, right, D, 5)
+    lay, params, w16 = spread_network(D, 40 + D)
+    lam, T = 64, 4
+    for iters in ([0] * L, [4, 3, 3, 0][:L] if L > 2 else [5, 0]):
+        msgs, d_ref, m_ref, st_ref = layer_path(left, right, cost, L, iters, lam, T, skip, lay, params, w16)
+        d, m, st = WS.warmstart_solve(left, right, cost, L, iters, lam, T, params, w16, skip, want_msgs=True,
+                                      want_stats=True)
+        if L == 2 and not any(iters):
+            assert torch.equal(m, msgs), "network messages differ from the layer path's"
+            q = host(msgs)
+            assert q.min() == 0 and q.max() > lam  # spread over the range (not all clamped or zero)
+        assert torch.equal(d, d_ref), f"disparities differ (iters {iters})"
+        assert torch.equal(m, m_ref), f"finest messages differ (iters {iters})"
+        assert st["msg_updates"] == st_ref["msg_updates"] and st["pixel_updates"] == st_ref["pixel_updates"]
+        assert st["active"] == st_ref["active"] and st["n_halfsteps"] == st_ref["n_halfsteps"]
+
+
+def test_warmstart_solve_trained_network_and_graph_replays():
+    """A trained network (a short run) through the one-call solve equals the layer path, also
+    when the call is captured in a HIP graph and replayed with new views in place."""
+    from paper_1709_06509_amd import warmstart_train as T
+    cfg = dict(T.DEFAULT, num_disp=32, num_scales=3, iters=6)
+    say("one-launch warm solve with a trained network")
+    tr = T.Trainer(cfg, seed=8)
+    for i in range(20):
+        tr.train_step(T.Sample(synth.make_pair(96, 72, 32, (3, 5), True, 0, False, seed=900 + i), cfg))
+    W, H, D, L = 150, 110, 32, 3
+    iters = [4, 4, 0]
+    pairs = [synth.make_pair(W, H, D, (3, 6), True, 0, False, seed=950 + i) for i in range(3)]
+    left = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    right = torch.empty_like(left)
+    cost = torch.empty((H, W, D), dtype=torch.int16, device="cuda")
+    disp = torch.empty((H, W), dtype=torch.int16, device="cuda")
+    ws = torch.empty(B.bp_workspace_bytes(W, H, B.make_params(D, L, iters, 64, 4)), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+
+    def step():
+        B.stereo_cost_volume(left, right, D, cfg["window"], out=cost)
+        WS.warmstart_solve(left, right, cost, L, iters, 64, 4, tr.params, tr.w16, 1, workspace=ws, disparity=disp)
+
+    left.copy_(gpu(pairs[0]["left"]))
+    right.copy_(gpu(pairs[0]["right"]))
+    with torch.cuda.stream(stream):
+        step()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            step()
+    torch.cuda.synchronize()
+    for p in pairs + pairs[:1]:
+        left.copy_(gpu(p["left"]))
+        right.copy_(gpu(p["right"]))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            g.replay()
+        torch.cuda.synchronize()
+        _, d_ref, _, _ = layer_path(left, right, cost, L, iters, 64, 4, 1, tr.layout, tr.params, tr.w16)
+        assert torch.equal(disp, d_ref)
