@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="large", choices=["large", "production", "tiny", "batched", "jacobi", "live"])
+    ap.add_argument("--workload", default="large", choices=["large", "production", "tiny", "batched", "jacobi", "live", "warm"])
     ap.add_argument("--batch-pairs", type=int, default=256, help="pairs of the batched workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample (small workloads)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle leg")
@@ -399,6 +399,75 @@ def run_live(args, frames=16, live_halfsteps=4):
     }
 
 
+def run_warm(args, schedule=(8, 6, 6)):
+    """The learned warm start's step at its evaluation size (640x480, D = 64, 4 scales): cost
+    volume plus the warm-started solve with the network as one launch inside it
+    (bp_warmstart_solve), against the same step through the layer-level calls and against
+    plain BP.  The network is freshly initialised: the kernels' time does not depend on the
+    weights (its accuracy is the warm-start experiment's subject, not this one's)."""
+    import torch
+
+    from paper_1709_06509_amd import bpstereo as B
+    from paper_1709_06509_amd import synth
+    from paper_1709_06509_amd import warmstart as WS
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    W, H, D, L, win, lam, T, its = 640, 480, 64, 4, 7, 64, 4, 10
+    p = synth.make_pair(W, H, D, (8, 12), True, 0, False, 200000)
+    left, right = torch.from_numpy(p["left"]).to(dev), torch.from_numpy(p["right"]).to(dev)
+    cost = torch.empty((H, W, D), dtype=torch.int16, device=dev)
+    disp = torch.empty((H, W), dtype=torch.int16, device=dev)
+    warm_iters = list(schedule) + [0]
+    ws = torch.empty(B.bp_workspace_bytes(W, H, B.make_params(D, L, its, lam, T)), dtype=torch.uint8, device=dev)
+    lay = WS.Layout(D)
+    params = lay.init_params(1)
+    w16 = WS.to_bf16(params)
+    x = WS.warmstart_input(left, right, B.stereo_cost_volume(left, right, D, win), L, warm_iters, lam, T)
+    Hs, Ws_, _ = x.shape
+    cnn_ws = WS.workspace(Ws_, Hs, D)
+    y = torch.empty((Hs, Ws_, lay.layers[-1]["cout_p"]), dtype=torch.float32, device=dev)
+    msgs = torch.empty((4, Hs, Ws_, D), dtype=torch.int16, device=dev)
+
+    def plain():
+        B.stereo_cost_volume(left, right, D, win, out=cost)
+        B.bp_hierarchical_solve(cost, L, [its] * L, lam, T, 0, 2, workspace=ws, disparity=disp)
+
+    def one_call():
+        B.stereo_cost_volume(left, right, D, win, out=cost)
+        WS.warmstart_solve(left, right, cost, L, warm_iters, lam, T, params, w16, 0, workspace=ws, disparity=disp)
+
+    def layers():
+        B.stereo_cost_volume(left, right, D, win, out=cost)
+        WS.warmstart_input(left, right, cost, L, warm_iters, lam, T, workspace=ws, out=x)
+        WS.forward(x, lay, params, w16, cnn_ws, y=y)
+        WS.warmstart_messages(y, D, lam, T, out=msgs)
+        B.bp_hierarchical_solve(cost, L, warm_iters, lam, T, 0, 2, warm_msgs=msgs, workspace=ws, disparity=disp)
+
+    def timed(f):
+        for _ in range(args.warmup):
+            f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    t_one, t_layers, t_plain = timed(one_call), timed(layers), timed(plain)
+    return {
+        "metric": METRIC, "value": 1.0 / t_one, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_one * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int16+bf16", "data": "synthetic",
+        "config": {"workload": f"warm: {W}x{H} grey pair, D={D}, {win}x{win} NCC, {L} scales; the network's "
+                               f"messages start scale {L - 2}, half-steps {list(schedule)} at scales 0..{L - 2}; "
+                               "network as one launch inside the solve; eager launches, cost volume + solve"},
+        "layer_path_pairs_per_s": 1.0 / t_layers, "plain_pairs_per_s": 1.0 / t_plain,
+        "plain_config": f"{L} scales x {its} half-steps, plain BP",
+        "network_note": "freshly initialised weights: timing only",
+    }
+
+
 def time_vs_halfsteps(B, cost, ws, w, stream, counts=(2, 4, 6, 8, 10, 12), reps=5):
     """Run time of the solve against the number of half-steps per scale (the paper's claim:
     plain BP's time is linear in its iterations), for plain BP and the freeze rule: the
@@ -440,7 +509,7 @@ def time_vs_halfsteps(B, cost, ws, w, stream, counts=(2, 4, 6, 8, 10, 12), reps=
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
         print(json.dumps(run_batched(args)))
@@ -450,6 +519,9 @@ def main():
         return
     if args.workload == "live":
         print(json.dumps(run_live(args)))
+        return
+    if args.workload == "warm":
+        print(json.dumps(run_warm(args)))
         return
     import numpy as np
     import torch

@@ -41,7 +41,7 @@ extern "C" {
 #define BP_E_INVAL (-1)       /* an argument is out of range or inconsistent     */
 #define BP_E_NOMEM (-2)       /* a host-side allocation failed                    */
 #define BP_E_HIP (-3)         /* a HIP runtime call failed                        */
-#define BP_E_UNSUPPORTED (-4) /* valid but not supported by this build            */
+#define BP_E_UNSUPPORTED (-4) /* valid but not supported by the library          */
 #define BP_E_WORKSPACE (-5)   /* the workspace is missing or too small            */
 
 /* Opaque per-caller state: kernel timing events.  Not thread-safe; use one per stream. */
