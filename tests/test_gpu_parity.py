@@ -52,6 +52,29 @@ def test_cost_volume_random(H, W, D, win):
     assert np.max(np.abs(host(ncc).astype(np.float64) - ref_ncc)) <= 1e-5
 
 
+# the largest extents the boundary takes: 16384 columns (256 column tiles, every disparity
+# of a pair spanning tile edges), 16384 rows, and D = 256 with the widest window
+@pytest.mark.parametrize("H,W,D,win", [(2, 16384, 24, 5), (16384, 2, 3, 3), (3, 700, 256, 13)])
+def test_cost_volume_maximum_extents(H, W, D, win):
+    rng = np.random.default_rng(H + W + D)
+    L = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    R = np.clip(np.roll(L, -2, axis=1).astype(int) + rng.integers(-30, 31, (H, W)), 0, 255).astype(np.uint8)
+    say(f"cost volume at maximum extents H={H} W={W} D={D} win={win}")
+    cost = B.stereo_cost_volume(gpu(L), gpu(R), D, win)
+    assert np.array_equal(host(cost), oracle.cost_volume(L, R, D, win))
+
+
+@pytest.mark.parametrize("H,W,D,L", [(2, 16384, 8, 3), (16384, 2, 8, 3)])
+def test_solve_maximum_extents(H, W, D, L):
+    """A solve on an image 16384 pixels wide (or high), both skip modes that skip."""
+    rng = np.random.default_rng(H * 3 + W)
+    cost = rng.integers(0, 700, (H, W, D)).astype(np.int16)
+    for skip in (0, 1):
+        say(f"solve at maximum extents H={H} W={W} D={D} L={L} skip={skip}")
+        got = run_both(cost, L, [6, 4, 4], 64, 4, skip)
+        assert_same(got[:3], got[3:], L)
+
+
 def test_cost_volume_tiny_workload():
     w = synth.WORKLOADS["tiny"]
     p = synth.workload_pair("tiny")
