@@ -70,20 +70,20 @@ def parse():
     return ap.parse_args()
 
 
-def halfstep_bytes(stats, D, levels, skip):
-    """Algorithmic bytes of the half-step launches of one solve: 18*D per pixel update
-    (data term + 4 incoming messages read, 4 outgoing written, int16), plus 8*D for the
-    comparison with the previous outgoing messages where the freeze rule checks it."""
+def halfstep_bytes(stats, D, levels, skip, msg_bits=16):
+    """Algorithmic bytes of the half-step launches of one solve per pixel update: the data
+    term (int16, 2*D) and 4 incoming messages read and 4 outgoing written, each D labels of
+    msg_bits / 8 bytes (18*D in all with 16-bit messages, 14*D with 12-bit ones), plus the 4
+    previous outgoing messages read where the freeze rule or the exact skip compares them."""
+    mb = msg_bits / 8.0
     total = 0
     for l in range(levels):
         for t in range(min(stats["n_halfsteps"][l], 64)):
             n = stats["active"][l][t]
-            total += 18 * D * n
-            if skip == 1 and t >= 2:
-                total += 8 * D * n
-            elif skip == 2:
-                total += 8 * D * n
-    return total
+            total += (2 + 8 * mb) * D * n
+            if (skip == 1 and t >= 2) or skip == 2:
+                total += 4 * mb * D * n
+    return int(total)
 
 
 def cpu_model():
@@ -620,7 +620,8 @@ def main():
 
     ms_per_step = 1000.0 * elapsed / args.steps
     pairs_per_s = args.steps / elapsed
-    hs_bytes = halfstep_bytes(st, D, L, w["skip"])
+    msg_bits = B.bp_message_bits(W, H, B.make_params(D, L, iters, w["lam"], w["trunc"], w["skip"]))
+    hs_bytes = halfstep_bytes(st, D, L, w["skip"], msg_bits)
     n_launch = timing["halfstep_launches"] // n_timed if n_timed else 0
     avg_launch_s = timing["halfstep_ms"] / 1000.0 / max(1, timing["halfstep_launches"])
     halfstep_ms_per_step = timing["halfstep_ms"] / max(1, n_timed)
@@ -668,6 +669,7 @@ def main():
             "traffic_gbs": traffic / avg_launch_s / 1e9 if traffic and avg_launch_s > 0 else None,
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            "message_bits": msg_bits,
             "launches_per_step": n_launch,
         },
         "halfstep_ms_per_step": halfstep_ms_per_step,

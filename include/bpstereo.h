@@ -159,6 +159,15 @@ int32_t stereo_cost_volume_rgb(const uint8_t* left_rgb, const uint8_t* right_rgb
 size_t bp_workspace_bytes(int32_t width, int32_t height, const bp_params* params);
 
 /*
+ * Bits per label in which the solve keeps its messages in the workspace: 12 where a pixel's
+ * labels span 16 or more lanes (num_disp > 64), every message lies in [0, 4095]
+ * (min(lambda * min(trunc, num_disp), 32767) <= 4095) and no warm_msgs are given; else 16;
+ * 0 if the arguments are invalid.  Results do not depend on it (the values are the same);
+ * the half-steps move 14 * D bytes per pixel update instead of 18 * D.
+ */
+int32_t bp_message_bits(int32_t width, int32_t height, const bp_params* params);
+
+/*
  * Hierarchical min-sum BP ("Fast Converging BP"; "GPU Implementation").
  *  - Scale l+1 data cost: sum of the (up to 4) children's costs minus its minimum over d,
  *    saturated to 32767.  Scale sizes: W_{l+1} = ceil(W_l / 2).

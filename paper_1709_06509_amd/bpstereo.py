@@ -80,6 +80,8 @@ def _load():
         lib.stereo_cost_volume_rgb.argtypes = [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp]
         lib.bp_workspace_bytes.argtypes = [_i32, _i32, ctypes.POINTER(BPParams)]
         lib.bp_workspace_bytes.restype = ctypes.c_size_t
+        lib.bp_message_bits.argtypes = [_i32, _i32, ctypes.POINTER(BPParams)]
+        lib.bp_message_bits.restype = ctypes.c_int32
         lib.bp_hierarchical_solve.argtypes = [_vp, _vp, _i32, _i32, ctypes.POINTER(BPParams), _vp, ctypes.c_size_t,
                                               _vp, _vp, ctypes.POINTER(BPStats), _vp]
         lib.bp_hierarchical_solve_noalloc.argtypes = [_vp, _vp, _i32, _i32, ctypes.POINTER(BPParams), _vp, _vp,
@@ -236,6 +238,11 @@ def make_params(num_disp, num_scales, iters, lam, trunc, skip_mode=0, converge_i
 
 def bp_workspace_bytes(width, height, params):
     return int(_load().bp_workspace_bytes(width, height, ctypes.byref(params)))
+
+
+def bp_message_bits(width, height, params):
+    """Bits per label of the solve's stored messages (12 or 16; 0 for invalid arguments)."""
+    return int(_load().bp_message_bits(width, height, ctypes.byref(params)))
 
 
 def bp_hierarchical_solve(cost, num_scales, iters, lam, trunc, skip_mode=0, converge_iters=2, warm_msgs=None,

@@ -62,6 +62,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Workspace layout of one solve; offsets in bytes from the workspace base.
 struct Plan {
     int L, D, G, Dp;
+    bool packed;  // the solve's messages are stored in 12 bits (see bp_device.h)
     bpst::Level lv[bpst::kMaxScales];
     long long vol[bpst::kMaxScales];  // elements of one message volume at scale l
     size_t off_stats, off_cost[bpst::kMaxScales], off_msgs[2], off_sa, off_sb, total;
@@ -97,6 +98,11 @@ Plan make_plan(int W, int H, const bp_params* p)
     pl.D = p->num_disp;
     pl.G = bpst::lanes_for(pl.D);
     pl.Dp = 8 * pl.G;
+    // 12-bit messages where every message fits (its clamp min(lambda min(T, D), 32767) is at
+    // most 4095; caller-given warm messages can be larger) and a pixel spans 16 or more lanes
+    // (D > 64: there the half-steps are bound by memory, not by their instruction count)
+    const long long capv = std::min((long long)p->lambda * std::min(p->trunc, p->num_disp), 32767LL);
+    pl.packed = pl.G >= 16 && capv <= 4095 && !p->warm_msgs;
     pl.lv[0] = bpst::make_level(W, H);
     for (int l = 1; l < pl.L; ++l) pl.lv[l] = bpst::make_level((pl.lv[l - 1].W + 1) / 2, (pl.lv[l - 1].H + 1) / 2);
     size_t o = 0;
@@ -541,10 +547,11 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         } else if (l == start && params->warm_msgs) {
             HIP_TRY(bpst::launch_import(params->warm_msgs, msgs, pl.lv[l], pl.vol[l], pl.D, pl.G, sa, sb, mode, st));
         } else if (l == start) {
-            HIP_TRY(bpst::launch_init(nullptr, pl.lv[l], 0, msgs, pl.lv[l], pl.vol[l], pl.G, sa, sb, mode, st));
+            HIP_TRY(bpst::launch_init(nullptr, pl.lv[l], 0, msgs, pl.lv[l], pl.vol[l], pl.G, sa, sb, mode, st,
+                                      pl.packed));
         } else {
             HIP_TRY(bpst::launch_init(M[(l + 1) & 1], pl.lv[l + 1], pl.vol[l + 1], msgs, pl.lv[l], pl.vol[l], pl.G, sa,
-                                      sb, mode, st));
+                                      sb, mode, st, pl.packed));
         }
         bpst::HalfstepArgs a{};
         a.cost = C[l];
@@ -568,6 +575,7 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         a.count = count ? 1 : 0;
         a.stats = stats;
         a.level = l;
+        a.packed = pl.packed ? 1 : 0;
         // timing mode 2: one event pair around all of this scale's message-update launches
         const bool time_each = ctx && ctx->timing == 1 && timing_allowed;
         hipEvent_t s0 = nullptr, s1 = nullptr;
@@ -658,9 +666,9 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
             ctx->event_launches[sslot] = scale_launches;
         }
     }
-    HIP_TRY(bpst::launch_wta(C[0], M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, wta_colour, disparity, st));
+    HIP_TRY(bpst::launch_wta(C[0], M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, wta_colour, disparity, st, pl.packed));
     if (final_msgs_or_null)
-        HIP_TRY(bpst::launch_export(M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, final_msgs_or_null, st));
+        HIP_TRY(bpst::launch_export(M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, final_msgs_or_null, st, pl.packed));
     return BP_OK;
 }
 
@@ -773,6 +781,13 @@ BP_API int32_t bp_warmstart_solve(bp_context* ctx, const uint8_t* left, const ui
     const WarmNet net{left, right, width, height, cnn_params, cnn_weights};
     return run_solve(ctx, pl, cost, width, height, params, workspace, workspace_bytes, disparity,
                      final_msgs_or_null, stats_or_null, false, (hipStream_t)stream, &net);
+}
+
+BP_API int32_t bp_message_bits(int32_t width, int32_t height, const bp_params* params)
+{
+    std::string why;
+    if (!params_valid(width, height, params, &why)) return 0;
+    return make_plan(width, height, params).packed ? 12 : 16;
 }
 
 BP_API size_t bp_noalloc_scratch_bytes(void) { return bpst::kNoallocScratchBytes; }

@@ -197,6 +197,77 @@ __device__ __forceinline__ void st16(int16_t* p, const int4 v)
     }
 }
 
+// ---- messages stored in 12 bits ----
+// Where every message lies in [0, 4095] (capv <= 4095) and a pixel spans 16 or more lanes, a
+// lane's 8 labels of a message are stored as 12-bit fields in 12 bytes (label j at bits
+// 12 j .. 12 j + 11 of three little-endian words) instead of 16 bytes: a quarter fewer
+// message bytes for the same values.  Element index e (a multiple of 8) of the 16-bit layout
+// maps to byte 12 (e / 8), so every index computation stays as it is; loads unpack to the
+// 16-bit register form the arithmetic uses, stores pack from it.
+struct M12 {
+    unsigned a, b, c;
+};
+
+__device__ __forceinline__ int4 unpack12(const M12 w)
+{
+    const unsigned l0 = w.a & 0xfffu, l1 = (w.a >> 12) & 0xfffu;
+    const unsigned l2 = __builtin_amdgcn_alignbit(w.b, w.a, 24) & 0xfffu;
+    const unsigned l3 = (w.b >> 4) & 0xfffu, l4 = (w.b >> 16) & 0xfffu;
+    const unsigned l5 = __builtin_amdgcn_alignbit(w.c, w.b, 28) & 0xfffu;
+    const unsigned l6 = (w.c >> 8) & 0xfffu, l7 = w.c >> 20;
+    return make_int4((int)(l0 | (l1 << 16)), (int)(l2 | (l3 << 16)), (int)(l4 | (l5 << 16)), (int)(l6 | (l7 << 16)));
+}
+
+// (every label of v in [0, 4095])
+__device__ __forceinline__ M12 pack12(const int4 v)
+{
+    const unsigned l0 = (unsigned)v.x & 0xffffu, l1 = (unsigned)v.x >> 16;
+    const unsigned l2 = (unsigned)v.y & 0xffffu, l3 = (unsigned)v.y >> 16;
+    const unsigned l4 = (unsigned)v.z & 0xffffu, l5 = (unsigned)v.z >> 16;
+    const unsigned l6 = (unsigned)v.w & 0xffffu, l7 = (unsigned)v.w >> 16;
+    M12 w;
+    w.a = l0 | (l1 << 12) | (l2 << 24);
+    w.b = (l2 >> 8) | (l3 << 4) | (l4 << 16) | (l5 << 28);
+    w.c = (l5 >> 4) | (l6 << 8) | (l7 << 20);
+    return w;
+}
+
+// A lane's 8 labels of a message volume at element index e (a multiple of 8), in either
+// storage, as 8 16-bit values.
+// (three words at a 4-byte-aligned address: one dwordx3 access)
+typedef unsigned v3u_a4 __attribute__((ext_vector_type(3), aligned(4)));
+template <bool STREAM, bool PACKED>
+__device__ __forceinline__ int4 ldm(const int16_t* base, long long e)
+{
+    if constexpr (PACKED) {
+        const v3u_a4* p = reinterpret_cast<const v3u_a4*>(reinterpret_cast<const char*>(base) + (e >> 3) * 12);
+        const v3u_a4 v = STREAM ? __builtin_nontemporal_load(p) : *p;
+        M12 w;
+        w.a = v.x;
+        w.b = v.y;
+        w.c = v.z;
+        return unpack12(w);
+    } else {
+        return ld16<STREAM>(base + e);
+    }
+}
+
+template <bool STREAM, bool PACKED>
+__device__ __forceinline__ void stm(int16_t* base, long long e, const int4 v)
+{
+    if constexpr (PACKED) {
+        v3u_a4* p = reinterpret_cast<v3u_a4*>(reinterpret_cast<char*>(base) + (e >> 3) * 12);
+        const M12 w = pack12(v);
+        const v3u_a4 x = {w.a, w.b, w.c};
+        if constexpr (STREAM)
+            __builtin_nontemporal_store(x, p);
+        else
+            *p = x;
+    } else {
+        st16<STREAM>(base + e, v);
+    }
+}
+
 // ---- two messages at once in packed 16-bit halves ----
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
@@ -469,7 +540,7 @@ __device__ __forceinline__ ColourPix any_pixel(long long gi, const Level lv)
 // Start a scale for the pixel with slot gi: copy its parent's messages (zero for a missing
 // neighbour, on either scale, or when parent is null: the coarsest scale) and reset the
 // skip state.
-template <int G>
+template <int G, bool PACKED = false>
 __device__ __forceinline__ void init_pixel(const int16_t* __restrict__ parent, Level lp, long long pvol,
                                            int16_t* __restrict__ msgs, Level lv, long long vol, uint8_t* sa,
                                            uint8_t* sb, int mode, long long gi, int lane)
@@ -486,8 +557,8 @@ __device__ __forceinline__ void init_pixel(const int16_t* __restrict__ parent, L
     for (int k = 0; k < 4; ++k) {
         int4 v = make_int4(0, 0, 0, 0);
         // a slot is only ever read where its neighbour exists, on both scales
-        if (parent && has[k] && phas[k]) v = *reinterpret_cast<const int4*>(parent + k * pvol + ps * (8 * G) + d0);
-        *reinterpret_cast<int4*>(msgs + k * vol + gi * (8 * G) + d0) = v;
+        if (parent && has[k] && phas[k]) v = ldm<false, PACKED>(parent, k * pvol + ps * (8 * G) + d0);
+        stm<false, PACKED>(msgs, k * vol + gi * (8 * G) + d0, v);
     }
     if (lane == 0) {
         if (mode == 1) { sa[gi] = 1; sb[gi] = 0; }
@@ -655,7 +726,7 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
 // STREAM: the scale's volumes are streamed (nontemporal loads and stores, see ld16).
 // listed: the caller has already read the pixel's freeze state and passes only active
 // pixels (or gi past the end), so the state is not read again.
-template <int G, int MODE, int SRC, bool NARROW = false, bool STREAM = false>
+template <int G, int MODE, int SRC, bool NARROW = false, bool STREAM = false, bool PACKED = false>
 __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, int lane, bool listed = false)
 {
     constexpr int Dp = 8 * G;
@@ -703,7 +774,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
         for (int v = 0; v < NV; ++v) {
             op[e][v] = make_int4(0, 0, 0, 0);
             if (check && act && hr[e])
-                op[e][v] = ld16<STREAM>(a.msgs + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0 + 8 * v);
+                op[e][v] = ldm<STREAM, PACKED>(a.msgs, (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0 + 8 * v);
         }
     // incoming messages stay packed (two int16 per register, values in [0, 32767])
     int4 c4[NV], mp[4][NV];
@@ -722,7 +793,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
                 if (hr[r])
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
-                        mp[r][v] = ld16<STREAM>(a.msgs + role_msg(hi, r) * a.vol + slot * Dp + d0 + 8 * v);
+                        mp[r][v] = ldm<STREAM, PACKED>(a.msgs, role_msg(hi, r) * a.vol + slot * Dp + d0 + 8 * v);
         } else if (SRC == kSrcParent) {
             const int px = x >> 1, py = y >> 1;
             const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
@@ -732,7 +803,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
                 if (hr[r] && (hi ? phas[(r + 2) & 3] : phas[r]))
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
-                        mp[r][v] = ld16<STREAM>(a.pmsgs + role_msg(hi, r) * a.pvol + ps * Dp + d0 + 8 * v);
+                        mp[r][v] = ldm<STREAM, PACKED>(a.pmsgs, role_msg(hi, r) * a.pvol + ps * Dp + d0 + 8 * v);
         }
     }
     int4 out[4][NV];
@@ -796,9 +867,10 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
 #pragma unroll
     for (int e = 0; e < NK; ++e)
         if (stf[e]) {
-            int16_t* dst = (a.out ? a.out : a.msgs) + (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0;
+            int16_t* dst = a.out ? a.out : a.msgs;
+            const long long e0 = (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) st16<STREAM>(dst + 8 * v, out[e][v]);
+            for (int v = 0; v < NV; ++v) stm<STREAM, PACKED>(dst, e0 + 8 * v, out[e][v]);
             if (MODE == 2 && glane == 0) a.state_a[nbr[e]] = 1;
         }
     if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;  // own colour: no neighbour marks it now
@@ -819,7 +891,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
 }
 
 // Winner-take-all of the pixel with slot gi (both colours), lane `lane` of its G lanes.
-template <int G>
+template <int G, bool PACKED = false>
 __device__ __forceinline__ void wta_pixel(const int16_t* __restrict__ c0, const int16_t* __restrict__ msgs,
                                           long long vol, Level lv, int D, int16_t* __restrict__ disp, long long gi,
                                           int lane)
@@ -837,7 +909,7 @@ __device__ __forceinline__ void wta_pixel(const int16_t* __restrict__ c0, const 
     const int4 cv = *reinterpret_cast<const int4*>(c0 + s * Dp + d0);
     int4 mv[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) mv[k] = *reinterpret_cast<const int4*>(msgs + k * vol + s * Dp + d0);
+    for (int k = 0; k < 4; ++k) mv[k] = ldm<false, PACKED>(msgs, k * vol + s * Dp + d0);
     int b[8];
     unpack8u(cv, b);
 #pragma unroll

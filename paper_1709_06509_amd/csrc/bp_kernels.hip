@@ -80,13 +80,13 @@ __global__ __launch_bounds__(kThreads) void k_pyramid_tree(const int16_t* __rest
 
 // Start a scale: copy each pixel's parent messages (zero for a missing neighbour or for
 // the coarsest scale) and reset the skip state.
-template <int G>
+template <int G, bool PACKED>
 __global__ __launch_bounds__(kThreads) void k_init(const int16_t* __restrict__ parent, Level lp,
                                                     long long pvol, int16_t* __restrict__ msgs, Level lv,
                                                     long long vol, uint8_t* sa, uint8_t* sb, int mode)
 {
     const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
-    init_pixel<G>(parent, lp, pvol, msgs, lv, vol, sa, sb, mode, t / G, (int)(t & (G - 1)));
+    init_pixel<G, PACKED>(parent, lp, pvol, msgs, lv, vol, sa, sb, mode, t / G, (int)(t & (G - 1)));
 }
 
 // Start scale s from caller-given messages [4][H][W][D].
@@ -127,12 +127,13 @@ __global__ __launch_bounds__(kThreads) void k_import(const int16_t* __restrict__
 // update only active pixels.  Updates of one colour are independent, so the order does not
 // change any result.
 // Variant flags of k_halfstep.
-constexpr int kHsCount = 1, kHsNarrow = 2, kHsStream = 4;
+constexpr int kHsCount = 1, kHsNarrow = 2, kHsStream = 4, kHsPacked = 8;
 
 template <int G, int MODE, int SRC, int FL>
 __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
 {
     constexpr bool COUNT = (FL & kHsCount) != 0, NARROW = (FL & kHsNarrow) != 0, STREAM = (FL & kHsStream) != 0;
+    constexpr bool PACKED = (FL & kHsPacked) != 0;
     constexpr int kPix = kThreads / G;  // pixels of one tile
     const int lane = threadIdx.x & (G - 1);
     int gi = blockIdx.x * kPix + threadIdx.x / G;
@@ -162,7 +163,8 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
         if (!COUNT && (threadIdx.x & ~63) >= total * G) return;  // the whole wave has no pixel
         gi = threadIdx.x < total * G ? blockIdx.x * kPix + list[threadIdx.x / G] : (int)npix;  // npix: no pixel
     }
-    const PixOut r = halfstep_pixel<G, MODE, SRC, NARROW, STREAM>(a, gi, lane, MODE == 2 || (MODE == 1 && a.t >= 2));
+    const PixOut r =
+        halfstep_pixel<G, MODE, SRC, NARROW, STREAM, PACKED>(a, gi, lane, MODE == 2 || (MODE == 1 && a.t >= 2));
     if (COUNT) {
         __shared__ int cnt[2];
         if (threadIdx.x == 0) { cnt[0] = 0; cnt[1] = 0; }
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
 }
 
 // colour < 0: every slot; otherwise the slots of one colour (index y * Wh + xi)
-template <int G>
+template <int G, bool PACKED>
 __global__ __launch_bounds__(kThreads) void k_wta(const int16_t* __restrict__ c0, const int16_t* __restrict__ msgs,
                                                    long long vol, Level lv, int D, int colour,
                                                    int16_t* __restrict__ disp)
@@ -197,10 +199,10 @@ __global__ __launch_bounds__(kThreads) void k_wta(const int16_t* __restrict__ c0
         const long long y = gi / lv.Wh, xi = gi - y * lv.Wh;
         gi = y < lv.H ? (2 * y + colour) * lv.Wh + xi : lv.slots();  // slots(): no pixel
     }
-    wta_pixel<G>(c0, msgs, vol, lv, D, disp, gi, (int)(t & (G - 1)));
+    wta_pixel<G, PACKED>(c0, msgs, vol, lv, D, disp, gi, (int)(t & (G - 1)));
 }
 
-template <int G>
+template <int G, bool PACKED>
 __global__ __launch_bounds__(kThreads) void k_export(const int16_t* __restrict__ msgs, long long vol, Level lv,
                                                       int D, int16_t* __restrict__ out)
 {
@@ -214,8 +216,7 @@ __global__ __launch_bounds__(kThreads) void k_export(const int16_t* __restrict__
     const bool has[4] = {p.x > 0, p.x < lv.W - 1, p.y > 0, p.y < lv.H - 1};
     for (int k = 0; k < 4; ++k) {
         int16_t* dst = out + (((long long)k * lv.H + p.y) * lv.W + p.x) * D + d0;
-        const int4 m = has[k] ? *reinterpret_cast<const int4*>(msgs + k * vol + gi * (8 * G) + d0)
-                              : make_int4(0, 0, 0, 0);
+        const int4 m = has[k] ? ldm<false, PACKED>(msgs, k * vol + gi * (8 * G) + d0) : make_int4(0, 0, 0, 0);
         if ((D & 7) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
             // whole 16-byte vectors (dst 16-byte aligned): a lane's 8 labels are all real or
             // all padding
@@ -436,11 +437,17 @@ hipError_t launch_pyramid_tree(const int16_t* user, const PyramidArgs& a, int G,
 }
 
 hipError_t launch_init(const int16_t* parent, Level lp, long long pvol, int16_t* msgs, Level lv, long long vol,
-                       int G, uint8_t* sa, uint8_t* sb, int mode, hipStream_t st)
+                       int G, uint8_t* sa, uint8_t* sb, int mode, hipStream_t st, bool packed)
 {
     const unsigned g = grid_for(lv.slots(), G);
-    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_init<GG>), dim3(g), dim3(kThreads), 0, st, parent, lp, pvol, msgs, lv,
-                                          vol, sa, sb, mode));
+    if (packed) {
+        BPST_DISPATCH_G(G, if constexpr (GG >= 16) hipLaunchKernelGGL((k_init<GG, true>), dim3(g), dim3(kThreads), 0,
+                                                                      st, parent, lp, pvol, msgs, lv, vol, sa, sb, mode);
+                           else return hipErrorInvalidValue);
+    } else {
+        BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_init<GG, false>), dim3(g), dim3(kThreads), 0, st, parent, lp, pvol,
+                                              msgs, lv, vol, sa, sb, mode));
+    }
     return hipGetLastError();
 }
 
@@ -456,8 +463,9 @@ hipError_t launch_import(const int16_t* warm, int16_t* msgs, Level lv, long long
 template <int MODE, int SRC, int FL>
 static hipError_t launch_halfstep_t(const HalfstepArgs& a, unsigned g, hipStream_t st)
 {
-    // the narrow variants exist for G <= kNarrowMaxG only
-    BPST_DISPATCH_G(a.G, if constexpr ((FL & kHsNarrow) == 0 || GG <= kNarrowMaxG) hipLaunchKernelGGL(
+    // the narrow variants exist for G <= kNarrowMaxG only, the 12-bit ones for G >= 16 only
+    BPST_DISPATCH_G(a.G, if constexpr (((FL & kHsNarrow) == 0 || GG <= kNarrowMaxG) &&
+                                       ((FL & kHsPacked) == 0 || GG >= 16)) hipLaunchKernelGGL(
                              (k_halfstep<GG, MODE, SRC, FL>), dim3(g), dim3(kThreads), 0, st, a);
                          else return hipErrorInvalidValue);
     return hipGetLastError();
@@ -466,6 +474,12 @@ static hipError_t launch_halfstep_t(const HalfstepArgs& a, unsigned g, hipStream
 template <int MODE, int SRC>
 static hipError_t launch_halfstep_c(const HalfstepArgs& a, unsigned g, hipStream_t st)
 {
+    if (a.packed) {
+        if (a.capv < 0 || a.capv > 4095 || a.narrow || a.out) return hipErrorInvalidValue;
+        if (a.count) return launch_halfstep_t<MODE, SRC, kHsCount | kHsPacked>(a, g, st);
+        if (a.stream) return launch_halfstep_t<MODE, SRC, kHsStream | kHsPacked>(a, g, st);
+        return launch_halfstep_t<MODE, SRC, kHsPacked>(a, g, st);
+    }
     if (a.count) return launch_halfstep_t<MODE, SRC, kHsCount>(a, g, st);  // no narrow counting variant
     if (a.narrow) {
         if (a.capv < 0 || a.capv > kNarrowCap) return hipErrorInvalidValue;
@@ -498,18 +512,32 @@ hipError_t launch_halfstep(const HalfstepArgs& a, hipStream_t st)
 }
 
 hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G, int colour,
-                      int16_t* disp, hipStream_t st)
+                      int16_t* disp, hipStream_t st, bool packed)
 {
     const unsigned g = grid_for(colour < 0 ? lv.slots() : (long long)lv.H * lv.Wh, G);
-    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_wta<GG>), dim3(g), dim3(kThreads), 0, st, c0, msgs, vol, lv, D, colour,
-                                          disp));
+    if (packed) {
+        BPST_DISPATCH_G(G, if constexpr (GG >= 16) hipLaunchKernelGGL((k_wta<GG, true>), dim3(g), dim3(kThreads), 0,
+                                                                      st, c0, msgs, vol, lv, D, colour, disp);
+                           else return hipErrorInvalidValue);
+    } else {
+        BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_wta<GG, false>), dim3(g), dim3(kThreads), 0, st, c0, msgs, vol, lv, D,
+                                              colour, disp));
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_export(const int16_t* msgs, long long vol, Level lv, int D, int G, int16_t* out, hipStream_t st)
+hipError_t launch_export(const int16_t* msgs, long long vol, Level lv, int D, int G, int16_t* out, hipStream_t st,
+                         bool packed)
 {
     const unsigned g = grid_for(lv.slots(), G);
-    BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_export<GG>), dim3(g), dim3(kThreads), 0, st, msgs, vol, lv, D, out));
+    if (packed) {
+        BPST_DISPATCH_G(G, if constexpr (GG >= 16) hipLaunchKernelGGL((k_export<GG, true>), dim3(g), dim3(kThreads),
+                                                                      0, st, msgs, vol, lv, D, out);
+                           else return hipErrorInvalidValue);
+    } else {
+        BPST_DISPATCH_G(G, hipLaunchKernelGGL((k_export<GG, false>), dim3(g), dim3(kThreads), 0, st, msgs, vol, lv, D,
+                                              out));
+    }
     return hipGetLastError();
 }
 

@@ -58,6 +58,7 @@ struct HalfstepArgs {
     int colour, t, K, mode, source, count;
     int narrow;              // packed 16-bit sums (no counters): see the narrow path in bp_device.h
     int stream;              // nontemporal loads and stores (the scale's volumes exceed the caches)
+    int packed;              // messages stored in 12 bits (G >= 16, capv <= 4095; see bp_device.h)
     DevStats* stats;
     int level;
     int16_t* disp;           // non-null (plain BP, int32 path, last half-step of the finest scale):
@@ -268,16 +269,18 @@ hipError_t launch_zero_stats(DevStats* s, hipStream_t st);
 hipError_t launch_prep_level0(const int16_t* user, int16_t* c0, Level lv, int D, int G, hipStream_t st);
 hipError_t launch_pyramid(const int16_t* fine, Level lf, int16_t* coarse, Level lc, int D, int G,
                           hipStream_t st);
+// packed: the scale's messages are stored in 12 bits (see bp_device.h; G >= 16 only)
 hipError_t launch_init(const int16_t* parent, Level lp, long long pvol, int16_t* msgs, Level lv,
-                       long long vol, int G, uint8_t* state_a, uint8_t* state_b, int mode, hipStream_t st);
+                       long long vol, int G, uint8_t* state_a, uint8_t* state_b, int mode, hipStream_t st,
+                       bool packed = false);
 hipError_t launch_import(const int16_t* warm, int16_t* msgs, Level lv, long long vol, int D, int G,
                          uint8_t* state_a, uint8_t* state_b, int mode, hipStream_t st);
 hipError_t launch_halfstep(const HalfstepArgs& a, hipStream_t st);
 // colour -1: every pixel; 0 or 1: only the pixels with (x + y) & 1 == colour
 hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G, int colour,
-                      int16_t* disparity, hipStream_t st);
+                      int16_t* disparity, hipStream_t st, bool packed = false);
 hipError_t launch_export(const int16_t* msgs, long long vol, Level lv, int D, int G, int16_t* out,
-                         hipStream_t st);
+                         hipStream_t st, bool packed = false);
 hipError_t launch_energy(const int16_t* cost, const int16_t* disp, int W, int H, int D, int lambda,
                          int trunc, int64_t* out, void* ws, hipStream_t st);
 size_t energy_ws_bytes();

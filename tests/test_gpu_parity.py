@@ -186,6 +186,14 @@ CASES = [
     (70, 90, 64, 6, [4, 3, 3, 3, 3, 3], 64, 4, 1),
     (37, 45, 256, 5, [3, 3, 3, 3, 3], 64, 4, 0),
     (33, 29, 5, 8, [3, 3, 3, 3, 3, 3, 3, 3], 64, 4, 0),
+    # messages stored in 12 bits (D > 64, lambda * min(T, D) <= 4095): every skip mode, the
+    # largest clamp that fits (4095, messages reach it) and the first that does not (4096)
+    (20, 26, 96, 3, [6, 5, 4], 64, 4, 1),
+    (20, 26, 96, 3, [6, 5, 4], 64, 4, 2),
+    (17, 23, 72, 3, [5, 4, 4], 4095, 1, 0),
+    (17, 23, 72, 3, [5, 4, 4], 4095, 1, 1),
+    (17, 23, 72, 3, [5, 4, 4], 1024, 4, 0),
+    (11, 13, 256, 2, [4, 3], 600, 6, 2),
 ]
 
 
