@@ -268,6 +268,61 @@ __device__ __forceinline__ void stm(int16_t* base, long long e, const int4 v)
     }
 }
 
+// The 12-bit words of a lane's 8 labels as stored, label j of them, and a store of them.
+template <bool STREAM>
+__device__ __forceinline__ M12 ldm12(const int16_t* base, long long e)
+{
+    const v3u_a4* p = reinterpret_cast<const v3u_a4*>(reinterpret_cast<const char*>(base) + (e >> 3) * 12);
+    const v3u_a4 v = STREAM ? __builtin_nontemporal_load(p) : *p;
+    M12 w;
+    w.a = v.x;
+    w.b = v.y;
+    w.c = v.z;
+    return w;
+}
+
+__device__ __forceinline__ int lab12(const M12& w, int j)
+{
+    switch (j) {
+    case 0: return (int)(w.a & 0xfffu);
+    case 1: return (int)((w.a >> 12) & 0xfffu);
+    case 2: return (int)(__builtin_amdgcn_alignbit(w.b, w.a, 24) & 0xfffu);
+    case 3: return (int)((w.b >> 4) & 0xfffu);
+    case 4: return (int)((w.b >> 16) & 0xfffu);
+    case 5: return (int)(__builtin_amdgcn_alignbit(w.c, w.b, 28) & 0xfffu);
+    case 6: return (int)((w.c >> 8) & 0xfffu);
+    default: return (int)(w.c >> 20);
+    }
+}
+
+template <bool STREAM>
+__device__ __forceinline__ void stm12(int16_t* base, long long e, const M12 w)
+{
+    v3u_a4* p = reinterpret_cast<v3u_a4*>(reinterpret_cast<char*>(base) + (e >> 3) * 12);
+    const v3u_a4 x = {w.a, w.b, w.c};
+    if constexpr (STREAM)
+        __builtin_nontemporal_store(x, p);
+    else
+        *p = x;
+}
+
+// Bits of the real labels (d0 + j < D) among a lane's 12-bit fields: a prefix of 12 n bits.
+__device__ __forceinline__ M12 label_mask12(int d0, int D)
+{
+    const int n = D - d0 < 0 ? 0 : (D - d0 > 8 ? 8 : D - d0);
+    auto ones = [](int bits) { return bits <= 0 ? 0u : (bits >= 32 ? 0xffffffffu : (1u << bits) - 1u); };
+    M12 m;
+    m.a = ones(12 * n);
+    m.b = ones(12 * n - 32);
+    m.c = ones(12 * n - 64);
+    return m;
+}
+
+__device__ __forceinline__ bool same12(const M12& a, const M12& b, const M12& m)
+{
+    return (((a.a ^ b.a) & m.a) | ((a.b ^ b.b) & m.b) | ((a.c ^ b.c) & m.c)) == 0u;
+}
+
 // ---- two messages at once in packed 16-bit halves ----
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
@@ -768,22 +823,33 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
     // once the incoming sums were formed, a second memory latency in the pixel's path.
     int sb = MODE == 1 && a.t >= 2 ? (int)a.state_b[act ? slot : 0] : 0;
     int4 op[NK][NV];
+    M12 op12[NK];  // PACKED: the previous outgoing messages as stored (compared packed)
 #pragma unroll
-    for (int e = 0; e < NK; ++e)
+    for (int e = 0; e < NK; ++e) {
+        op12[e] = M12{0u, 0u, 0u};
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             op[e][v] = make_int4(0, 0, 0, 0);
-            if (check && act && hr[e])
-                op[e][v] = ldm<STREAM, PACKED>(a.msgs, (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0 + 8 * v);
+            if (check && act && hr[e]) {
+                const long long eo = (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0 + 8 * v;
+                if constexpr (PACKED)
+                    op12[e] = ldm12<STREAM>(a.msgs, eo);
+                else
+                    op[e][v] = ld16<STREAM>(a.msgs + eo);
+            }
         }
+    }
     // incoming messages stay packed (two int16 per register, values in [0, 32767])
     int4 c4[NV], mp[4][NV];
+    M12 mp12[4];  // PACKED: the incoming messages as stored (labels taken straight from the fields)
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         c4[v] = make_int4(0, 0, 0, 0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) mp[k][v] = make_int4(0, 0, 0, 0);
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mp12[k] = M12{0u, 0u, 0u};
     if (act) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) c4[v] = ld16<STREAM>(a.cost + slot * Dp + d0 + 8 * v);
@@ -792,8 +858,13 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
             for (int r = 0; r < 4; ++r)
                 if (hr[r])
 #pragma unroll
-                    for (int v = 0; v < NV; ++v)
-                        mp[r][v] = ldm<STREAM, PACKED>(a.msgs, role_msg(hi, r) * a.vol + slot * Dp + d0 + 8 * v);
+                    for (int v = 0; v < NV; ++v) {
+                        const long long em = role_msg(hi, r) * a.vol + slot * Dp + d0 + 8 * v;
+                        if constexpr (PACKED)
+                            mp12[r] = ldm12<STREAM>(a.msgs, em);
+                        else
+                            mp[r][v] = ld16<STREAM>(a.msgs + em);
+                    }
         } else if (SRC == kSrcParent) {
             const int px = x >> 1, py = y >> 1;
             const bool phas[4] = {px > 0, px < a.plv.W - 1, py > 0, py < a.plv.H - 1};
@@ -802,10 +873,17 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
             for (int r = 0; r < 4; ++r)
                 if (hr[r] && (hi ? phas[(r + 2) & 3] : phas[r]))
 #pragma unroll
-                    for (int v = 0; v < NV; ++v)
-                        mp[r][v] = ldm<STREAM, PACKED>(a.pmsgs, role_msg(hi, r) * a.pvol + ps * Dp + d0 + 8 * v);
+                    for (int v = 0; v < NV; ++v) {
+                        const long long em = role_msg(hi, r) * a.pvol + ps * Dp + d0 + 8 * v;
+                        if constexpr (PACKED)
+                            mp12[r] = ldm12<STREAM>(a.pmsgs, em);
+                        else
+                            mp[r][v] = ld16<STREAM>(a.pmsgs + em);
+                    }
         }
     }
+    // label j of incoming message k, in either storage
+    auto inc = [&](int k, int j) { return PACKED ? lab12(mp12[k], j) : msg_at(mp[k][0], j); };
     int4 out[4][NV];
     if constexpr (NARROW) {
         narrow_update<G>(nl, c4, mp, a.D, a.D < Dp, (unsigned)a.lambda, (unsigned)a.capv, out);
@@ -814,16 +892,14 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
         unpack8u(c4[0], Hs);
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            Hs[j] = (d0 + j < a.D) ? Hs[j] + msg_at(mp[0][0], j) + msg_at(mp[1][0], j) + msg_at(mp[2][0], j) +
-                                         msg_at(mp[3][0], j)
-                                   : kBig;
+            Hs[j] = (d0 + j < a.D) ? Hs[j] + inc(0, j) + inc(1, j) + inc(2, j) + inc(3, j) : kBig;
 #pragma unroll
         for (int k = 0; k < 4; k += 2) {
             int ha[8], hb[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                ha[j] = Hs[j] - msg_at(mp[k][0], j);
-                hb[j] = Hs[j] - msg_at(mp[k + 1][0], j);
+                ha[j] = Hs[j] - inc(k, j);
+                hb[j] = Hs[j] - inc(k + 1, j);
             }
             transform2<G>(ha, hb, a.lambda, a.capv, lane, out[k][0], out[k + 1][0]);
         }
@@ -842,13 +918,21 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
     // compiler wait for the store to complete before it reused the store's registers.
     bool all_eq = true;
     bool stf[NK];
+    M12 out12[NK];  // PACKED: the new outgoing messages as they are stored
+#pragma unroll
+    for (int e = 0; e < NK; ++e) out12[e] = PACKED ? pack12(out[e][0]) : M12{0u, 0u, 0u};
 #pragma unroll
     for (int e = 0; e < NK; ++e) {
         bool store = act && hr[e];
         if (check) {
             bool same = true;
+            if constexpr (PACKED) {
+                same = same12(op12[e], out12[e], label_mask12(d0, a.D));
+            } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) same = same && same_labels(op[e][v], out[e][v], label_mask(d0 + 8 * v, a.D));
+                for (int v = 0; v < NV; ++v)
+                    same = same && same_labels(op[e][v], out[e][v], label_mask(d0 + 8 * v, a.D));
+            }
             const int eq = group_min<GL>(same ? 1 : 0);  // the GL lanes of the message
             if (store && !eq) all_eq = false;
             if (eq) store = false;
@@ -869,8 +953,12 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
         if (stf[e]) {
             int16_t* dst = a.out ? a.out : a.msgs;
             const long long e0 = (role_msg(hi, e) ^ 1) * a.vol + nbr[e] * Dp + d0;
+            if constexpr (PACKED) {
+                stm12<STREAM>(dst, e0, out12[e]);
+            } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) stm<STREAM, PACKED>(dst, e0 + 8 * v, out[e][v]);
+                for (int v = 0; v < NV; ++v) st16<STREAM>(dst + e0 + 8 * v, out[e][v]);
+            }
             if (MODE == 2 && glane == 0) a.state_a[nbr[e]] = 1;
         }
     if (MODE == 2 && act && lane == 0) a.state_a[slot] = 0;  // own colour: no neighbour marks it now
