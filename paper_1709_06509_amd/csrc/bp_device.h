@@ -363,9 +363,10 @@ __device__ __forceinline__ u16x2 pk_scan_down(u16x2 c, unsigned step, int lane)
 // envelope is a min-plus convolution, so shifting h by its minimum first, clipping it at C
 // and saturating every sum at 65535 (>= C) leave min(., C) unchanged; f <= C throughout.
 // Outputs come in memory order (labels 2w, 2w+1 of one message per 32-bit word).
-template <int G>
+// PACKED: the results go to oa12, ob12 as 12-bit fields (outa, outb are left as they are).
+template <int G, bool PACKED = false>
 __device__ __forceinline__ void transform2(const int ha[8], const int hb[8], int lam, int capv, int lane, int4& outa,
-                                           int4& outb)
+                                           int4& outb, M12& oa12, M12& ob12)
 {
     int ma = min(min(min(ha[0], ha[1]), min(ha[2], ha[3])), min(min(ha[4], ha[5]), min(ha[6], ha[7])));
     int mb = min(min(min(hb[0], hb[1]), min(hb[2], hb[3])), min(min(hb[4], hb[5]), min(hb[6], hb[7])));
@@ -404,15 +405,40 @@ __device__ __forceinline__ void transform2(const int ha[8], const int hb[8], int
     f[7] = pk_min(f[7], pk_adds(cb, L));
 #pragma unroll
     for (int j = 6; j >= 0; --j) f[j] = pk_min(f[j], pk_adds(f[j + 1], L));
-    // regroup: low halves of labels 2w, 2w+1 -> word w of a; high halves -> word w of b
-    unsigned wa[4], wb[4];
+    if constexpr (PACKED) {
+        // straight into the 12-bit fields of each message (every value <= capv <= 4095): a
+        // from the low halves, b from the high halves
+        unsigned fa[8], fb[8];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        wa[w] = __builtin_amdgcn_perm(pk_bits(f[2 * w + 1]), pk_bits(f[2 * w]), 0x05040100u);
-        wb[w] = __builtin_amdgcn_perm(pk_bits(f[2 * w + 1]), pk_bits(f[2 * w]), 0x07060302u);
+        for (int j = 0; j < 8; ++j) {
+            fa[j] = pk_bits(f[j]) & 0xffffu;
+            fb[j] = pk_bits(f[j]) >> 16;
+        }
+        oa12.a = fa[0] | (fa[1] << 12) | (fa[2] << 24);
+        oa12.b = (fa[2] >> 8) | (fa[3] << 4) | (fa[4] << 16) | (fa[5] << 28);
+        oa12.c = (fa[5] >> 4) | (fa[6] << 8) | (fa[7] << 20);
+        ob12.a = fb[0] | (fb[1] << 12) | (fb[2] << 24);
+        ob12.b = (fb[2] >> 8) | (fb[3] << 4) | (fb[4] << 16) | (fb[5] << 28);
+        ob12.c = (fb[5] >> 4) | (fb[6] << 8) | (fb[7] << 20);
+    } else {
+        // regroup: low halves of labels 2w, 2w+1 -> word w of a; high halves -> word w of b
+        unsigned wa[4], wb[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            wa[w] = __builtin_amdgcn_perm(pk_bits(f[2 * w + 1]), pk_bits(f[2 * w]), 0x05040100u);
+            wb[w] = __builtin_amdgcn_perm(pk_bits(f[2 * w + 1]), pk_bits(f[2 * w]), 0x07060302u);
+        }
+        outa = make_int4((int)wa[0], (int)wa[1], (int)wa[2], (int)wa[3]);
+        outb = make_int4((int)wb[0], (int)wb[1], (int)wb[2], (int)wb[3]);
     }
-    outa = make_int4((int)wa[0], (int)wa[1], (int)wa[2], (int)wa[3]);
-    outb = make_int4((int)wb[0], (int)wb[1], (int)wb[2], (int)wb[3]);
+}
+
+template <int G>
+__device__ __forceinline__ void transform2(const int ha[8], const int hb[8], int lam, int capv, int lane, int4& outa,
+                                           int4& outb)
+{
+    M12 unused_a, unused_b;
+    transform2<G, false>(ha, hb, lam, capv, lane, outa, outb, unused_a, unused_b);
 }
 
 // ---- the narrow path: whole message sums in packed 16-bit ----
@@ -885,6 +911,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
     // label j of incoming message k, in either storage
     auto inc = [&](int k, int j) { return PACKED ? lab12(mp12[k], j) : msg_at(mp[k][0], j); };
     int4 out[4][NV];
+    M12 out12[4];  // PACKED: the new outgoing messages as they are stored
     if constexpr (NARROW) {
         narrow_update<G>(nl, c4, mp, a.D, a.D < Dp, (unsigned)a.lambda, (unsigned)a.capv, out);
     } else {
@@ -901,7 +928,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
                 ha[j] = Hs[j] - inc(k, j);
                 hb[j] = Hs[j] - inc(k + 1, j);
             }
-            transform2<G>(ha, hb, a.lambda, a.capv, lane, out[k][0], out[k + 1][0]);
+            transform2<G, PACKED>(ha, hb, a.lambda, a.capv, lane, out[k][0], out[k + 1][0], out12[k], out12[k + 1]);
         }
         if (a.disp) {
             // the winner from the same sums: after plain BP's last half-step at the finest
@@ -918,9 +945,6 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
     // compiler wait for the store to complete before it reused the store's registers.
     bool all_eq = true;
     bool stf[NK];
-    M12 out12[NK];  // PACKED: the new outgoing messages as they are stored
-#pragma unroll
-    for (int e = 0; e < NK; ++e) out12[e] = PACKED ? pack12(out[e][0]) : M12{0u, 0u, 0u};
 #pragma unroll
     for (int e = 0; e < NK; ++e) {
         bool store = act && hr[e];
