@@ -61,15 +61,25 @@ __device__ __forceinline__ long long slot_of(int x, int y, int Wh)
     return (long long)(2 * y + ((x + y) & 1)) * Wh + (x >> 1);
 }
 
-// Lane exchanges inside an aligned group of G lanes.  Groups of 2 or 4 lie inside one quad,
-// where a DPP quad permutation (a VALU operand modifier, no LDS round trip) moves the
-// value; wider groups use the LDS permute behind __shfl_*.  Quad permutation codes:
-// lane i of a quad reads lane sel_i, code = sel0 | sel1 << 2 | sel2 << 4 | sel3 << 6.
+// Lane exchanges inside an aligned group of G lanes, through DPP (a VALU operand modifier,
+// no LDS round trip) for groups of up to 8 lanes: quad permutations for exchanges inside a
+// quad, row shifts for the scans' "lane - O" and "lane + O", and mirrors for exchanges
+// between the quads of a half row.  Groups of 16 and 32 lanes use the LDS permute behind
+// __shfl_*: their half-steps (D > 64) stream the largest volumes and are close to the
+// vector issue rate, where the permute runs beside the vector unit (DPP there made the
+// 1920x1080 D = 128 pair about 1 % slower overall).  Quad permutation codes: lane i of a
+// quad reads lane sel_i, code = sel0 | sel1 << 2 | sel2 << 4 | sel3 << 6; row_shl:n = 0x100 + n, row_shr:n =
+// 0x110 + n (within a 16-lane row: an 8-lane group's lanes that use the result read inside
+// the group), row_half_mirror 0x141 (lane i reads 7 - i within each 8 lanes).
+#define BPST_DPP(v, ctrl) __builtin_amdgcn_update_dpp((v), (v), (ctrl), 0xF, 0xF, false)
+
+// value of lane ^ O of the group
 template <int G, int O>
 __device__ __forceinline__ int lanes_xor(int v)
 {
-    if constexpr (G == 2 || (G == 4 && O == 1)) return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);
-    else if constexpr (G == 4 && O == 2) return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);
+    if constexpr (O == 1 && G <= 8) return BPST_DPP(v, 0xB1);             // 1,0,3,2
+    else if constexpr (O == 2 && G <= 8) return BPST_DPP(v, 0x4E);        // 2,3,0,1
+    else if constexpr (O == 4 && G <= 8) return BPST_DPP(BPST_DPP(v, 0x141), 0x1B);   // half mirror, quad reverse
     else return __shfl_xor(v, O, G);
 }
 
@@ -77,9 +87,10 @@ __device__ __forceinline__ int lanes_xor(int v)
 template <int G, int O>
 __device__ __forceinline__ int lanes_up(int v)
 {
-    if constexpr (G == 2) return __builtin_amdgcn_update_dpp(v, v, 0xA0, 0xF, 0xF, false);          // 0,0,2,2
-    else if constexpr (G == 4 && O == 1) return __builtin_amdgcn_update_dpp(v, v, 0x90, 0xF, 0xF, false);  // 0,0,1,2
-    else if constexpr (G == 4 && O == 2) return __builtin_amdgcn_update_dpp(v, v, 0x44, 0xF, 0xF, false);  // 0,1,0,1
+    if constexpr (G == 2) return BPST_DPP(v, 0xA0);                       // 0,0,2,2
+    else if constexpr (G == 4 && O == 1) return BPST_DPP(v, 0x90);        // 0,0,1,2
+    else if constexpr (G == 4 && O == 2) return BPST_DPP(v, 0x44);        // 0,1,0,1
+    else if constexpr (G == 8) return BPST_DPP(v, 0x110 + O);             // row_shr:O
     else return __shfl_up(v, O, G);
 }
 
@@ -87,11 +98,13 @@ __device__ __forceinline__ int lanes_up(int v)
 template <int G, int O>
 __device__ __forceinline__ int lanes_down(int v)
 {
-    if constexpr (G == 2) return __builtin_amdgcn_update_dpp(v, v, 0xF5, 0xF, 0xF, false);          // 1,1,3,3
-    else if constexpr (G == 4 && O == 1) return __builtin_amdgcn_update_dpp(v, v, 0xF9, 0xF, 0xF, false);  // 1,2,3,3
-    else if constexpr (G == 4 && O == 2) return __builtin_amdgcn_update_dpp(v, v, 0xEE, 0xF, 0xF, false);  // 2,3,2,3
+    if constexpr (G == 2) return BPST_DPP(v, 0xF5);                       // 1,1,3,3
+    else if constexpr (G == 4 && O == 1) return BPST_DPP(v, 0xF9);        // 1,2,3,3
+    else if constexpr (G == 4 && O == 2) return BPST_DPP(v, 0xEE);        // 2,3,2,3
+    else if constexpr (G == 8) return BPST_DPP(v, 0x100 + O);             // row_shl:O
     else return __shfl_down(v, O, G);
 }
+#undef BPST_DPP
 
 template <int G, int O = 1>
 __device__ __forceinline__ int group_min(int v)
