@@ -380,7 +380,8 @@ size_t bp_cnn_workspace_bytes(int32_t Ws, int32_t Hs, int32_t num_disp);
  * non-NULL; written as bf16 (out_bf16) and/or fp32 before rounding (out_f32), both [P][cout_p]
  * with 0 in channels >= cout.  in [device] bf16 [H][W][cin_p] (cin_p % 16 == 0); w [device] bf16
  * [cout_p][9][cin_p] (cout_p % 32 == 0); bias [device] fp32 [cout_p] or NULL; mask [device] bf16
- * [P][cout_p] or NULL.
+ * [P][cout_p] or NULL.  in and w are read 16 bytes at a time: both 16-byte aligned
+ * (BP_E_INVAL otherwise).
  */
 int32_t bp_conv3x3_forward(const uint16_t* in, int32_t H, int32_t W, int32_t cin_p, const uint16_t* weights,
                            const float* bias, int32_t cout, int32_t cout_p, int32_t relu, const uint16_t* mask,
@@ -390,7 +391,8 @@ int32_t bp_conv3x3_forward(const uint16_t* in, int32_t H, int32_t W, int32_t cin
  * bf16 [P][cout_p] and the layer's weights [cout_p][9][cin_p], computes
  * d[p][ci] = sum_{tap, co} g[p - tap offset][co] * w[co][tap][ci], multiplied by (mask[p][ci] > 0)
  * when mask (the layer input after its ReLU) is non-NULL.  flip_scratch [device] bf16,
- * cin_p * 9 * cout_p elements.  cin_p and cout_p multiples of 32.
+ * cin_p * 9 * cout_p elements.  cin_p and cout_p multiples of 32; g and flip_scratch
+ * 16-byte aligned.
  */
 int32_t bp_conv3x3_data_grad(const uint16_t* g, int32_t H, int32_t W, int32_t cout_p, const uint16_t* weights,
                              int32_t cin, int32_t cin_p, const uint16_t* mask, uint16_t* flip_scratch,
@@ -409,6 +411,7 @@ int32_t bp_conv3x3_weight_grad(const uint16_t* in, const uint16_t* g, int32_t H,
  * Forward pass: input [device] bf16 [Hs][Ws][cin_p of layer 0]; params [device] fp32 (biases
  * are read from it); weights_bf16 [device]; y [device] fp32 [Hs][Ws][cout_p of layer 5], the
  * last layer's output.  The workspace keeps every layer's activation for bp_cnn_backward.
+ * input, weights_bf16 and workspace 16-byte aligned (BP_E_INVAL otherwise).
  */
 int32_t bp_cnn_forward(const uint16_t* input, int32_t Ws, int32_t Hs, int32_t num_disp, const float* params,
                        const uint16_t* weights_bf16, void* workspace, size_t workspace_bytes, float* y, void* stream);
@@ -417,6 +420,7 @@ int32_t bp_cnn_forward(const uint16_t* input, int32_t Ws, int32_t Hs, int32_t nu
  * slots that have a neighbour of |y * lam_t - label| (label [device] int16 [4][Hs][Ws][D],
  * the target messages); its gradient flows back through the network in bf16 with fp32
  * accumulation.  grads [device] fp32, the parameter layout (overwritten); loss [device] fp32.
+ * workspace 16-byte aligned.
  */
 int32_t bp_cnn_backward(const uint16_t* input, int32_t Ws, int32_t Hs, int32_t num_disp, const uint16_t* weights_bf16,
                         void* workspace, size_t workspace_bytes, const float* y, const int16_t* label, int32_t lam_t,
@@ -458,7 +462,7 @@ int32_t bp_warmstart_messages(const float* y, int32_t Ws, int32_t Hs, int32_t nu
  *                L-1 is skipped); num_scales >= 2; num_disp a multiple of 16 in 16..64
  *                (BP_E_UNSUPPORTED otherwise: the layer-level calls above take any D)
  *   cnn_params   [device] fp32 parameter vector (biases are read from it)
- *   cnn_weights  [device] bf16 copy of it (bp_cnn_to_bf16)
+ *   cnn_weights  [device] bf16 copy of it (bp_cnn_to_bf16), 16-byte aligned
  *   workspace, disparity, final_msgs_or_null, stats_or_null as for bp_hierarchical_solve
  * Asynchronous unless stats are requested; always eager (the context's graph mode is not used).
  */

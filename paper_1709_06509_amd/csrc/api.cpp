@@ -768,6 +768,7 @@ BP_API int32_t bp_warmstart_solve(bp_context* ctx, const uint8_t* left, const ui
     if (!params_valid(width, height, params, &why)) return fail(BP_E_INVAL, "%s", why.c_str());
     if (!left || !right || !cost || !disparity || !cnn_params || !cnn_weights)
         return fail(BP_E_INVAL, "a pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(cnn_weights) % 16 != 0) return fail(BP_E_INVAL, "cnn_weights must be 16-byte aligned");
     if (params->warm_msgs) return fail(BP_E_INVAL, "warm_msgs must be NULL: the network provides the start");
     if (params->num_scales < 2) return fail(BP_E_INVAL, "the warm start needs num_scales >= 2");
     if (!bpst::warm_cnn_supported(params->num_disp))

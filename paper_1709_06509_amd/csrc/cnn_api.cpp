@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 
@@ -101,6 +102,9 @@ int32_t hip_fail(hipError_t e, const char* what)
 
 bool size_ok(int32_t Ws, int32_t Hs) { return Ws >= 1 && Hs >= 1 && Ws <= 4096 && Hs <= 4096; }
 
+// The convolutions read activations and weights 16 bytes (8 bf16) at a time.
+bool a16(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; }
+
 }  // namespace
 
 bool bpst::cnn_offsets(int D, long long w_off[kCnnLayers], long long b_off[kCnnLayers])
@@ -153,6 +157,7 @@ BP_API int32_t bp_conv3x3_forward(const uint16_t* in, int32_t H, int32_t W, int3
                                   uint16_t* out_bf16, float* out_f32, void* stream)
 {
     if (!in || !weights || (!out_bf16 && !out_f32)) return fail(BP_E_INVAL, "in/weights/outputs are NULL");
+    if (!a16(in) || !a16(weights)) return fail(BP_E_INVAL, "in and weights must be 16-byte aligned");
     if (!size_ok(W, H) || cin_p < 16 || cin_p % 16 || cout < 1 || cout_p < cout || cout_p % 32)
         return fail(BP_E_INVAL, "bad sizes: cin_p must be a multiple of 16, cout_p a multiple of 32 >= cout");
     CNN_TRY(bpst::launch_conv_fwd(in, H, W, cin_p, weights, bias, cout, cout_p, relu, mask, out_bf16, out_f32,
@@ -165,6 +170,7 @@ BP_API int32_t bp_conv3x3_data_grad(const uint16_t* g, int32_t H, int32_t W, int
                                     uint16_t* out_bf16, float* out_f32, void* stream)
 {
     if (!g || !weights || !flip_scratch || (!out_bf16 && !out_f32)) return fail(BP_E_INVAL, "a pointer is NULL");
+    if (!a16(g) || !a16(flip_scratch)) return fail(BP_E_INVAL, "g and flip_scratch must be 16-byte aligned");
     if (!size_ok(W, H) || cout_p < 32 || cout_p % 32 || cin < 1 || cin_p < cin || cin_p % 32)
         return fail(BP_E_INVAL, "bad sizes: cout_p and cin_p must be multiples of 32");
     hipStream_t st = (hipStream_t)stream;
@@ -205,6 +211,8 @@ BP_API int32_t bp_cnn_forward(const uint16_t* input, int32_t Ws, int32_t Hs, int
     long long n = 0;
     if (!size_ok(Ws, Hs) || !geometry(num_disp, g, &n)) return fail(BP_E_INVAL, "bad size or num_disp");
     if (!input || !params || !weights_bf16 || !y || !workspace) return fail(BP_E_INVAL, "a pointer is NULL");
+    if (!a16(input) || !a16(weights_bf16) || !a16(workspace))
+        return fail(BP_E_INVAL, "input, weights_bf16 and workspace must be 16-byte aligned");
     const long long P = (long long)Ws * Hs;
     const CnnWs wl = ws_layout(P, g);
     if (workspace_bytes < wl.total) return fail(BP_E_WORKSPACE, "CNN workspace too small");
@@ -232,6 +240,7 @@ BP_API int32_t bp_cnn_backward(const uint16_t* input, int32_t Ws, int32_t Hs, in
     if (!input || !weights_bf16 || !y || !label || !grads || !loss || !workspace)
         return fail(BP_E_INVAL, "a pointer is NULL");
     if (lam_t < 1) return fail(BP_E_INVAL, "lam_t must be >= 1");
+    if (!a16(workspace)) return fail(BP_E_INVAL, "workspace must be 16-byte aligned");
     const long long P = (long long)Ws * Hs;
     const CnnWs wl = ws_layout(P, g);
     if (workspace_bytes < wl.total) return fail(BP_E_WORKSPACE, "CNN workspace too small");

@@ -4,9 +4,11 @@
 // Activations are NHWC bf16 [H][W][C_p] with C_p a multiple of 16 (padded channels hold 0);
 // weights are bf16 [Cout_p][9][Cin_p] (tap t = 3*dy + dx).  A convolution is an implicit
 // GEMM: D[pixel][co] = sum over (tap, ci) of A[pixel][(tap, ci)] * B[(tap, ci)][co], run on
-// v_mfma_f32_16x16x16_bf16 with the K dimension walked 16 channels of one tap at a time.
-// Operand layout of that instruction (64 lanes): A[i][k] sits in lane i + 16*(k/4), element
-// k%4; B[k][j] in lane j + 16*(k/4), element k%4; D[i][j] in lane j + 16*(i/4), element i%4.
+// v_mfma_f32_16x16x32_bf16 with K = (tap, ci) flattened (k = tap * cin_p + ci) and walked 32
+// at a time, zero past 9 cin_p.  Operand layout of that instruction (64 lanes, checked on the
+// GPU): A[i][k] sits in lane i + 16*(k/8), element k%8; B[k][j] in lane j + 16*(k/8), element
+// k%8; D[i][j] in lane j + 16*(i/4), element i%4.  cin_p is a multiple of 16, so a lane's 8
+// consecutive k never straddle two taps.
 //
 // Reductions over pixels (weight and bias gradients, the loss) are split into fixed pixel
 // chunks whose partial sums are added in chunk order, so results are deterministic.
@@ -32,90 +34,79 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
 
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ __forceinline__ v4s load4(const uint16_t* p)
-{
-    const uint2 u = *reinterpret_cast<const uint2*>(p);
-    v4s r;
-    r[0] = (short)(u.x & 0xffff);
-    r[1] = (short)(u.x >> 16);
-    r[2] = (short)(u.y & 0xffff);
-    r[3] = (short)(u.y >> 16);
-    return r;
-}
+typedef short v8s __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ v4s lds_load4(const uint16_t* p)
-{
-    const uint2 u = *reinterpret_cast<const uint2*>(p);
-    v4s r;
-    r[0] = (short)(u.x & 0xffff);
-    r[1] = (short)(u.x >> 16);
-    r[2] = (short)(u.y & 0xffff);
-    r[3] = (short)(u.y >> 16);
-    return r;
-}
+// 8 bf16 at a 16-byte-aligned address (global or LDS)
+__device__ __forceinline__ v8s load8(const uint16_t* p) { return *reinterpret_cast<const v8s*>(p); }
 
-// Weights of one workgroup's 32 output channels in LDS: row co holds [9][cin_p] plus 4
-// elements of padding, so the 16 rows one MFMA operand reads fall in different banks.
+// K-steps of 32 over a 3x3 layer's flattened (tap, channel) dimension of 9 cin_p
+__host__ __device__ constexpr int ksteps(int cin_p) { return (9 * cin_p + 31) / 32; }
+
+// Weights of one workgroup's 32 output channels in LDS: row co holds [9][cin_p] plus 8
+// elements of padding (rows stay 16-byte aligned, and the 16 rows one operand reads move
+// across the banks).
 constexpr int kLdsMaxCin = 112;
-__host__ __device__ constexpr int wrow(int cin_p) { return 9 * cin_p + 4; }
+__host__ __device__ constexpr int wrow(int cin_p) { return 9 * cin_p + 8; }
 
 // Forward convolution (also the data gradient, with flipped weights and a ReLU mask).
 // One workgroup: 64 pixels x 32 output channels; wave w owns pixels 16w..16w+15.
 //   out_bf16 [P][Cout_p] = bf16( act(acc + bias) ) where act = ReLU if relu, or
 //                         acc * (mask[p][co] > 0) if mask (the ReLU derivative)
 //   out_f32  [P][Cout_p] = the same value before bf16 rounding (nullable)
-// CS = cin_p / 16 when it is at most kLdsMaxCin / 16: the loops are unrolled (every load of a
-// tap is in flight together) and the weights come from LDS; CS = 0: any cin_p, weights read
-// from global memory.
+// K-step s covers k = 32 s .. 32 s + 31 of the flattened (tap, channel) dimension; lane group
+// g = lane / 16 supplies k0 = 32 s + 8 g .. + 7: channels c .. c + 7 of tap k0 / cin_p.
+// CS = cin_p / 16 when it is at most kLdsMaxCin / 16: the K loop is unrolled (its loads are
+// in flight together) and the weights come from LDS; CS = 0: any cin_p, weights read from
+// global memory.
 template <int CS>
 __global__ __launch_bounds__(kCT) void k_conv_fwd(const uint16_t* __restrict__ in, int H, int W, int cin_p,
                                                   const uint16_t* __restrict__ w, const float* __restrict__ bias,
                                                   int cout, int cout_p, int relu, const uint16_t* __restrict__ mask,
                                                   uint16_t* __restrict__ out_bf16, float* __restrict__ out_f32)
 {
-    extern __shared__ uint16_t wl[];
+    extern __shared__ __align__(16) uint16_t wl[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int P = H * W;
     const int p = blockIdx.x * 64 + wave * 16 + (lane & 15);  // this lane's A row (pixel)
     const int py = p / W, px = p - py * W;
-    const int kq = (lane >> 4) * 4;
+    const int g = lane >> 4;
     const int co0 = blockIdx.y * 32;
-    const int nc = CS ? CS : cin_p / 16;
-    const int rs = CS ? wrow(16 * CS) : 9 * cin_p;  // element stride between output channels
+    const int cp = CS ? 16 * CS : cin_p;
+    const int K = 9 * cp, NS = (K + 31) / 32;
+    const int rs = CS ? wrow(16 * CS) : K;  // element stride between output channels
     const uint16_t* wb;
     if (CS) {
         // stage [32][9][cin_p] (contiguous in global memory) into padded LDS rows, 8 B at a time
-        const uint16_t* src = w + (long long)co0 * 9 * cin_p;
-        const int per = 9 * cin_p / 4;  // 8-byte pieces per row
+        const uint16_t* src = w + (long long)co0 * K;
+        const int per = K / 4;  // 8-byte pieces per row
         for (int e = threadIdx.x; e < 32 * per; e += kCT) {
             const int r = e / per, q = e - r * per;
-            *reinterpret_cast<uint2*>(wl + r * rs + 4 * q) = *reinterpret_cast<const uint2*>(src + (long long)r * 9 * cin_p + 4 * q);
+            *reinterpret_cast<uint2*>(wl + r * rs + 4 * q) = *reinterpret_cast<const uint2*>(src + (long long)r * K + 4 * q);
         }
         __syncthreads();
         wb = wl;
     } else {
-        wb = w + (long long)co0 * 9 * cin_p;
+        wb = w + (long long)co0 * K;
     }
-    const uint16_t* b0 = wb + (long long)(lane & 15) * rs + kq;
-    const uint16_t* b1 = wb + (long long)(16 + (lane & 15)) * rs + kq;
+    const uint16_t* b0 = wb + (long long)(lane & 15) * rs;
+    const uint16_t* b1 = wb + (long long)(16 + (lane & 15)) * rs;
+    const v8s zero = {0, 0, 0, 0, 0, 0, 0, 0};
     v4f acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int ys = py + tap / 3 - 1, xs = px + tap % 3 - 1;
-        const bool ok = p < P && ys >= 0 && ys < H && xs >= 0 && xs < W;
-        // out-of-image taps read pixel 0 (always valid) and use zero
-        const uint16_t* arow = in + (ok ? ((long long)ys * W + xs) * cin_p : 0LL) + kq;
-        const int tb = tap * cin_p;
-#pragma unroll
-        for (int c = 0; c < (CS ? CS : 1); ++c) {
-            for (int cc = c; cc < nc; cc += (CS ? nc : 1)) {  // CS: one pass; otherwise the runtime loop
-                v4s a = load4(arow + 16 * cc);
-                if (!ok) a = v4s{0, 0, 0, 0};
-                const v4s bb0 = CS ? lds_load4(b0 + tb + 16 * cc) : load4(b0 + tb + 16 * cc);
-                const v4s bb1 = CS ? lds_load4(b1 + tb + 16 * cc) : load4(b1 + tb + 16 * cc);
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb0, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb1, acc[1], 0, 0, 0);
-            }
+    for (int s = 0; s < (CS ? ksteps(16 * CS) : 1); ++s) {
+        for (int ss = s; ss < NS; ss += (CS ? NS : 1)) {  // CS: one pass; otherwise the runtime loop
+            const int k0 = 32 * ss + 8 * g;
+            const bool kv = k0 < K;
+            const int tap = kv ? k0 / cp : 0, c = kv ? k0 - tap * cp : 0;
+            const int ys = py + tap / 3 - 1, xs = px + tap % 3 - 1;
+            const bool ok = kv && p < P && ys >= 0 && ys < H && xs >= 0 && xs < W;
+            // out-of-image taps and k past the end read valid addresses and use zero
+            const v8s av = load8(in + (ok ? ((long long)ys * W + xs) * cin_p + c : 0LL));
+            const v8s bv0 = load8(b0 + (kv ? k0 : 0));
+            const v8s bv1 = load8(b1 + (kv ? k0 : 0));
+            const v8s a = ok ? av : zero;
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, kv ? bv0 : zero, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, kv ? bv1 : zero, acc[1], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -400,7 +391,7 @@ __global__ __launch_bounds__(kCT) void k_warm_messages(const float* __restrict__
 //     scale's message volumes (colour-split slots, Dp labels), with the state bytes a
 //     warm-started scale begins with.
 // Every output is computed as the layer-by-layer path computes it: the same MFMA, the same
-// K order (tap, then 16 channels at a time), the same bias, ReLU and bf16 rounding, the
+// K order (32-wide steps of the flattened (tap, channel) dimension), the same bias, ReLU and bf16 rounding, the
 // same quantisation, so the messages are bit-identical.  A wave keeps the weight fragments
 // it needs for a layer in registers (every workgroup reads the same weights: they stay in
 // the caches).
@@ -409,14 +400,14 @@ constexpr int kWWaves = kWT / 64;
 constexpr int kWTW = 12, kWTH = 8;   // tile of scale s
 constexpr int kWIW = kWTW + 12, kWIH = kWTH + 12;          // network input region
 constexpr int kWPW = kWTW / 2 + 7, kWPH = kWTH / 2 + 7;    // parents of the input region
-constexpr int kWAS = 36;             // bf16 per pixel of an activation buffer: 32 channels + 4 (banks)
+constexpr int kWAS = 40;             // bf16 per pixel of an activation buffer: 32 channels + 8 (16-byte rows, banks)
 constexpr int kWN = kWTW * kWTH;     // pixels of the tile
 static_assert(kWTW % 2 == 0 && kWTH % 2 == 0, "even tiles: the parent region starts at an exact half");
 
 __host__ __device__ constexpr int warm_act_pixels(int halo) { return (kWTW + 2 * halo) * (kWTH + 2 * halo); }
-// Pitch (bf16) of a pixel's row of network input: 16 NC1 channels + 4 (2-dword reads of 16
-// consecutive pixels then fall in distinct banks).
-__host__ __device__ constexpr int warm_in_pitch(int cin0) { return cin0 + 4; }
+// Pitch (bf16) of a pixel's row of network input: 16 NC1 channels + 8 (16-byte rows; the
+// 16 pixels one operand reads spread over the banks).
+__host__ __device__ constexpr int warm_in_pitch(int cin0) { return cin0 + 8; }
 
 // LDS: region 1 holds the box averages and the parents' costs while the input is formed, then
 // the activations of layers 1, 3, 5; region 2 holds the network input, then the activations
@@ -438,7 +429,6 @@ __host__ __device__ inline size_t warm_r2(int cin0, int D)
 }
 __host__ __device__ inline size_t warm_cnn_lds(int cin0, int D) { return warm_r1(cin0) + warm_r2(cin0, D); }
 
-__device__ __forceinline__ v4s lds_v4s(const uint16_t* p) { return *reinterpret_cast<const v4s*>(p); }
 
 // Minimum over the 16 lanes of each row of the wave (lanes 16 r .. 16 r + 15), in every lane
 // of the row: rotations within a row through DPP.
@@ -452,16 +442,31 @@ __device__ __forceinline__ int row_min16(int v)
 }
 
 // The weight fragments (B operands) of one wave for a 3x3 layer of cin_p = 16 NC input
-// channels: output channel co, every (tap, 16-channel chunk), lane layout of the MFMA.
+// channels: output channel co, every K-step (zero past 9 cin_p), lane layout of the MFMA.
 template <int NC>
-__device__ __forceinline__ void warm_frags(const WarmCnnArgs& a, int layer, int co, v4s (&bf)[9][NC])
+__device__ __forceinline__ void warm_frags(const WarmCnnArgs& a, int layer, int co, v8s (&bf)[ksteps(16 * NC)])
 {
+    constexpr int K = 9 * 16 * NC;
     const int g = (threadIdx.x & 63) >> 4;
-    const uint16_t* bw = a.w16 + a.w_off[layer] + (long long)co * 9 * (16 * NC) + 4 * g;
+    const uint16_t* bw = a.w16 + a.w_off[layer] + (long long)co * K;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap)
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) bf[tap][cc] = *reinterpret_cast<const v4s*>(bw + tap * 16 * NC + 16 * cc);
+    for (int s = 0; s < ksteps(16 * NC); ++s) {
+        const int k0 = 32 * s + 8 * g;
+        const v8s v = load8(bw + (k0 < K ? k0 : 0));
+        bf[s] = k0 < K ? v : v8s{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+}
+
+// Offset (bf16) of lane group g's operand at K-step s in a region whose pixel rows are PITCH
+// apart and IWl pixels wide, relative to the pixel's row at tap (0, 0); -1 past 9 cin_p.
+template <int NC, int PITCH>
+__device__ __forceinline__ int warm_koff(int s, int g, int IWl)
+{
+    constexpr int cp = 16 * NC;
+    const int k0 = 32 * s + 8 * g;
+    if (k0 >= 9 * cp) return -1;
+    const int tap = k0 / cp, c = k0 - tap * cp;
+    return ((tap / 3) * IWl + (tap % 3)) * PITCH + c;
 }
 
 // One 3x3 layer, 32 output channels, over the region of halo HO around the tile: output
@@ -471,14 +476,16 @@ __device__ __forceinline__ void warm_frags(const WarmCnnArgs& a, int layer, int 
 // runs two blocks of 16 region pixels at a time (blocks b and b + 4 of every eighth pair),
 // two independent accumulation chains sharing each weight fragment.
 template <int NC, int PITCH, int HO>
-__device__ __forceinline__ void warm_layer(const WarmCnnArgs& a, const v4s (&bf)[9][NC], float bias, int x0, int y0,
-                                           const uint16_t* __restrict__ in, uint16_t* __restrict__ out)
+__device__ __forceinline__ void warm_layer(const WarmCnnArgs& a, const v8s (&bf)[ksteps(16 * NC)], float bias, int x0,
+                                           int y0, const uint16_t* __restrict__ in, uint16_t* __restrict__ out)
 {
     constexpr int OW = kWTW + 2 * HO, OH = kWTH + 2 * HO, N = OW * OH, IWl = OW + 2, NBLK = (N + 15) / 16;
+    constexpr int NS = ksteps(16 * NC);
     const int Ws = a.lv.W, Hs = a.lv.H;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, g = lane >> 4;
     const int t = wave >> 2, wq = wave & 3;
+    const v8s zero = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int b0 = wq; b0 < NBLK; b0 += 8) {
         // this lane's A row in blocks b0 and b0 + 4: its input row at tap (0, 0) (rows past
         // the region read row 0: their results are never stored)
@@ -487,18 +494,17 @@ __device__ __forceinline__ void warm_layer(const WarmCnnArgs& a, const v4s (&bf)
         for (int p = 0; p < 2; ++p) {
             const int q = 16 * (b0 + 4 * p) + i;
             const int ry = q < N ? q / OW : 0, rx = q < N ? q - (q / OW) * OW : 0;
-            arow[p] = in + (ry * IWl + rx) * PITCH + 4 * g;
+            arow[p] = in + (ry * IWl + rx) * PITCH;
         }
         v4f acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int off = ((tap / 3) * IWl + (tap % 3)) * PITCH;
+        for (int s = 0; s < NS; ++s) {
+            const int off = warm_koff<NC, PITCH>(s, g, IWl);
 #pragma unroll
-            for (int cc = 0; cc < NC; ++cc)
-#pragma unroll
-                for (int p = 0; p < 2; ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(lds_v4s(arow[p] + off + 16 * cc), bf[tap][cc],
-                                                                       acc[p], 0, 0, 0);
+            for (int p = 0; p < 2; ++p) {
+                const v8s av = load8(arow[p] + (off < 0 ? 0 : off));
+                acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(off < 0 ? zero : av, bf[s], acc[p], 0, 0, 0);
+            }
         }
         // results: rows 4 g + e of block p (region pixels), column i (channel 16 t + i);
         // positions outside the image store 0
@@ -535,7 +541,7 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     const int i = lane & 15, g = lane >> 4;
     const int co = 16 * (wave >> 2) + i;  // this lane's output channel in layers 1-5
 
-    v4s w1[9][NC1];
+    v8s w1[ksteps(16 * NC1)];
     float b1;
 
     // network input channels 0 and 1 over the input region: the views averaged over the
@@ -655,7 +661,7 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     }
     __syncthreads();
     // each layer's weights are loaded while the layer before it runs
-    v4s w2[9][2], w3[9][2], w4[9][2], w5[9][2];
+    v8s w2[ksteps(32)], w3[ksteps(32)], w4[ksteps(32)], w5[ksteps(32)];
     warm_frags<2>(a, 1, co, w2);
     const float b2 = a.params[a.b_off[1] + co];
     warm_layer<NC1, IP, 5>(a, w1, b1, x0, y0, inp, actA);
@@ -679,7 +685,7 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     // LDS; then each message's minimum over d (the minimum of its side's T block minima), and
     // the normalised messages are staged in LDS and stored as 16-byte vectors.
     constexpr int NT = 4 * T, TPW = (NT + kWWaves - 1) / kWWaves, NB = (kWN + 15) / 16;
-    v4s w6[TPW][9][2];
+    v8s w6[TPW][ksteps(32)];
     float bc[TPW];
 #pragma unroll
     for (int m = 0; m < TPW; ++m) {
@@ -700,20 +706,19 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     for (int b = 0; b < NB; ++b) {
         const int q = 16 * b + i;
         const int ry = q < kWN ? q / kWTW : 0, rx = q < kWN ? q - (q / kWTW) * kWTW : 0;
-        const uint16_t* arow = actA + (ry * (kWTW + 2) + rx) * kWAS + 4 * g;
+        const uint16_t* arow = actA + (ry * (kWTW + 2) + rx) * kWAS;
         v4f acc[TPW];
 #pragma unroll
         for (int m = 0; m < TPW; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap)
+        for (int s = 0; s < ksteps(32); ++s) {
+            // 32 input channels: K-step s is tap s, channels 8 g .. 8 g + 7
+            const v8s av = load8(arow + ((s / 3) * (kWTW + 2) + (s % 3)) * kWAS + 8 * g);
 #pragma unroll
-            for (int cc = 0; cc < 2; ++cc) {
-                const v4s av = lds_v4s(arow + ((tap / 3) * (kWTW + 2) + (tap % 3)) * kWAS + 16 * cc);
-#pragma unroll
-                for (int m = 0; m < TPW; ++m)
-                    if (wave + kWWaves * m < NT)  // uniform over the wave
-                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, w6[m][tap][cc], acc[m], 0, 0, 0);
-            }
+            for (int m = 0; m < TPW; ++m)
+                if (wave + kWWaves * m < NT)  // uniform over the wave
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w6[m][s], acc[m], 0, 0, 0);
+        }
 #pragma unroll
         for (int m = 0; m < TPW; ++m) {
             const int t = wave + kWWaves * m;
