@@ -32,6 +32,10 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
     return (uint16_t)(u >> 16);
 }
 
+// The same rounding (to nearest even) by the hardware conversion: the layers' activations,
+// where it saves the integer sequence above on every output.
+__device__ __forceinline__ uint16_t to_bf16_hw(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 typedef short v8s __attribute__((ext_vector_type(8)));
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(kCT) void k_conv_fwd(const uint16_t* __restrict__ i
                 if (relu) v = fmaxf(v, 0.f);
                 if (mask && from_bf16(mask[(long long)q * cout_p + co]) <= 0.f) v = 0.f;
             }
-            if (out_bf16) out_bf16[(long long)q * cout_p + co] = to_bf16(v);
+            if (out_bf16) out_bf16[(long long)q * cout_p + co] = to_bf16_hw(v);
             if (out_f32) out_f32[(long long)q * cout_p + co] = v;
         }
     }
@@ -405,9 +409,16 @@ constexpr int kWN = kWTW * kWTH;     // pixels of the tile
 static_assert(kWTW % 2 == 0 && kWTH % 2 == 0, "even tiles: the parent region starts at an exact half");
 
 __host__ __device__ constexpr int warm_act_pixels(int halo) { return (kWTW + 2 * halo) * (kWTH + 2 * halo); }
+// Rows of an activation buffer: the region's pixels rounded up to whole 16-pixel blocks (the
+// rows past the region take a block's unused results, so stores need no bounds test).
+__host__ __device__ constexpr int warm_act_rows(int halo) { return (warm_act_pixels(halo) + 15) / 16 * 16; }
 // Pitch (bf16) of a pixel's row of network input: 16 NC1 channels + 8 (16-byte rows; the
 // 16 pixels one operand reads spread over the banks).
 __host__ __device__ constexpr int warm_in_pitch(int cin0) { return cin0 + 8; }
+
+// Staged messages of one tile pixel (int16 elements): 4 D, padded so that the rows four pixels
+// apart fall on different banks.
+__host__ __device__ constexpr int warm_msg_stride(int D) { return 4 * D + 8; }
 
 // LDS: region 1 holds the box averages and the parents' costs while the input is formed, then
 // the activations of layers 1, 3, 5; region 2 holds the network input, then the activations
@@ -415,15 +426,15 @@ __host__ __device__ constexpr int warm_in_pitch(int cin0) { return cin0 + 8; }
 __host__ __device__ inline size_t warm_r1(int cin0)
 {
     const size_t stage = (size_t)2 * kWIW * kWIH + (size_t)kWPW * kWPH * cin0;
-    const size_t act = (size_t)warm_act_pixels(5) * kWAS;
-    return 2 * (stage > act ? stage : act);
+    const size_t act = (size_t)warm_act_rows(5) * kWAS;
+    return (2 * (stage > act ? stage : act) + 15) / 16 * 16;  // region 2 starts 16-byte aligned
 }
 __host__ __device__ inline size_t warm_r2(int cin0, int D)
 {
     const size_t inp = (size_t)kWIW * kWIH * warm_in_pitch(cin0) * 2;
-    const size_t act = (size_t)warm_act_pixels(4) * kWAS * 2;
-    const size_t last = (size_t)kWN * 16 * 4 /* block minima */ + (size_t)kWN * 4 * 4 /* side minima */ +
-                        (size_t)kWN * 4 * D * 2 /* messages */;
+    const size_t act = (size_t)warm_act_rows(4) * kWAS * 2;
+    const size_t last = (size_t)kWN * (D / 4 + 1) * 4 /* block minima */ + (size_t)kWN * 4 * 4 /* side minima */ +
+                        (size_t)kWN * warm_msg_stride(D) * 2 /* messages */;
     size_t m = inp > act ? inp : act;
     return m > last ? m : last;
 }
@@ -434,10 +445,11 @@ __host__ __device__ inline size_t warm_cnn_lds(int cin0, int D) { return warm_r1
 // of the row: rotations within a row through DPP.
 __device__ __forceinline__ int row_min16(int v)
 {
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false));  // row_ror:8
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xf, 0xf, false));  // row_ror:4
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x122, 0xf, 0xf, false));  // row_ror:2
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x121, 0xf, 0xf, false));  // row_ror:1
+    // (the old value, never used by a rotation, is min's identity so the moves fold into the mins)
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x128, 0xf, 0xf, false));  // row_ror:8
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x124, 0xf, 0xf, false));  // row_ror:4
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x122, 0xf, 0xf, false));  // row_ror:2
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x121, 0xf, 0xf, false));  // row_ror:1
     return v;
 }
 
@@ -469,56 +481,99 @@ __device__ __forceinline__ int warm_koff(int s, int g, int IWl)
     return ((tap / 3) * IWl + (tap % 3)) * PITCH + c;
 }
 
-// One 3x3 layer, 32 output channels, over the region of halo HO around the tile: output
-// pixel q of the region (row-major, width kWTW + 2 HO) from the input region of halo HO + 1
-// (rows of PITCH bf16 per pixel).  Waves 0-3 compute output channels 0-15, waves 4-7
-// channels 16-31 (the caller's fragments bf and bias are those of channel 16 t + i); a wave
-// runs two blocks of 16 region pixels at a time (blocks b and b + 4 of every eighth pair),
-// two independent accumulation chains sharing each weight fragment.
+// NP blocks of 16 region pixels (b0, b0 + 4, ...) of one 3x3 layer, 32 output channels, over
+// the region of halo HO around the tile: output pixel q of the region (row-major, width
+// kWTW + 2 HO) from the input region of halo HO + 1 (rows of PITCH bf16 per pixel).  The
+// caller's fragments bf and bias are those of output channel 16 t + i (t = wave / 4); the NP
+// accumulation chains share each weight fragment.
+template <int NC, int PITCH, int HO, int NP>
+__device__ __forceinline__ void warm_blocks(const WarmCnnArgs& a, const v8s (&bf)[ksteps(16 * NC)], float bias, int x0,
+                                            int y0, const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int b0)
+{
+    constexpr int OW = kWTW + 2 * HO, N = OW * (kWTH + 2 * HO), IWl = OW + 2;
+    constexpr int NS = ksteps(16 * NC);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4, t = wave >> 2;
+    const v8s zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    // this lane's A row in each block: its input row at tap (0, 0) (rows past the region read
+    // row 0; their results go to the buffer's padding rows)
+    const uint16_t* arow[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int q = 16 * (b0 + 4 * p) + i;
+        const int ry = q < N ? q / OW : 0, rx = q < N ? q - (q / OW) * OW : 0;
+        arow[p] = in + (ry * IWl + rx) * PITCH;
+    }
+    v4f acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = v4f{0.f, 0.f, 0.f, 0.f};
+    // operands are read PD K-steps ahead of their use (a ring of PD + 1 slots)
+    constexpr int PD = 3;
+    v8s ring[PD + 1][NP];
+    auto fetch = [&](int s) {
+        const int off = warm_koff<NC, PITCH>(s, g, IWl);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const v8s av = load8(arow[p] + (off < 0 ? 0 : off));
+            ring[s % (PD + 1)][p] = off < 0 ? zero : av;
+        }
+    };
+#pragma unroll
+    for (int s = 0; s < PD && s < NS; ++s) fetch(s);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (s + PD < NS) fetch(s + PD);
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ring[s % (PD + 1)][p], bf[s], acc[p], 0, 0, 0);
+    }
+    // results: rows 4 g + e of block p (region pixels), column i (channel 16 t + i), stored as
+    // computed (rows past the region go to the buffer's padding rows; region positions outside
+    // the image are cleared afterwards, warm_clear_outside)
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            out[(16 * (b0 + 4 * p) + 4 * g + e) * kWAS + 16 * t + i] = to_bf16_hw(fmaxf(acc[p][e] + bias, 0.f));
+}
+
+// Whether the region of halo HO around the tile reaches outside the image (uniform over the
+// workgroup).
+template <int HO>
+__device__ __forceinline__ bool warm_edge(int x0, int y0, int Ws, int Hs)
+{
+    return x0 - HO < 0 || y0 - HO < 0 || x0 + kWTW + HO > Ws || y0 + kWTH + HO > Hs;
+}
+
+// Zero the positions of the region of halo HO that lie outside the image (the next layer's
+// zero padding there), 32 channels as four 16-byte pieces; after the layer's stores.
+template <int HO>
+__device__ __forceinline__ void warm_clear_outside(int x0, int y0, int Ws, int Hs, uint16_t* __restrict__ out)
+{
+    constexpr int OW = kWTW + 2 * HO, N = OW * (kWTH + 2 * HO);
+    for (int e = threadIdx.x; e < N * 4; e += kWT) {
+        const int q = e >> 2, c = e & 3;
+        const int oy = q / OW, ox = q - oy * OW;
+        const int Yo = y0 - HO + oy, Xo = x0 - HO + ox;
+        if (Yo < 0 || Yo >= Hs || Xo < 0 || Xo >= Ws)
+            *reinterpret_cast<uint4*>(out + q * kWAS + 8 * c) = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+// One 3x3 layer over the region of halo HO.  Waves 0-3 compute output channels 0-15, waves
+// 4-7 channels 16-31; wave w takes blocks w % 4, w % 4 + 4, ... in pairs (the last one alone
+// when the count is odd).
 template <int NC, int PITCH, int HO>
 __device__ __forceinline__ void warm_layer(const WarmCnnArgs& a, const v8s (&bf)[ksteps(16 * NC)], float bias, int x0,
                                            int y0, const uint16_t* __restrict__ in, uint16_t* __restrict__ out)
 {
-    constexpr int OW = kWTW + 2 * HO, OH = kWTH + 2 * HO, N = OW * OH, IWl = OW + 2, NBLK = (N + 15) / 16;
-    constexpr int NS = ksteps(16 * NC);
-    const int Ws = a.lv.W, Hs = a.lv.H;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = lane & 15, g = lane >> 4;
-    const int t = wave >> 2, wq = wave & 3;
-    const v8s zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    constexpr int NBLK = (warm_act_pixels(HO) + 15) / 16;
+    const int wq = (threadIdx.x >> 6) & 3;
     for (int b0 = wq; b0 < NBLK; b0 += 8) {
-        // this lane's A row in blocks b0 and b0 + 4: its input row at tap (0, 0) (rows past
-        // the region read row 0: their results are never stored)
-        const uint16_t* arow[2];
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int q = 16 * (b0 + 4 * p) + i;
-            const int ry = q < N ? q / OW : 0, rx = q < N ? q - (q / OW) * OW : 0;
-            arow[p] = in + (ry * IWl + rx) * PITCH;
-        }
-        v4f acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int off = warm_koff<NC, PITCH>(s, g, IWl);
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                const v8s av = load8(arow[p] + (off < 0 ? 0 : off));
-                acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(off < 0 ? zero : av, bf[s], acc[p], 0, 0, 0);
-            }
-        }
-        // results: rows 4 g + e of block p (region pixels), column i (channel 16 t + i);
-        // positions outside the image store 0
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int qo = 16 * (b0 + 4 * p) + 4 * g + e;
-                const int oy = qo / OW, ox = qo - oy * OW;
-                const int Yo = y0 - HO + oy, Xo = x0 - HO + ox;
-                const bool img = Yo >= 0 && Yo < Hs && Xo >= 0 && Xo < Ws;
-                const uint16_t v = to_bf16(fmaxf(acc[p][e] + bias, 0.f));
-                if (qo < N) out[qo * kWAS + 16 * t + i] = img ? v : (uint16_t)0;
-            }
+        if (b0 + 4 < NBLK)
+            warm_blocks<NC, PITCH, HO, 2>(a, bf, bias, x0, y0, in, out, b0);
+        else
+            warm_blocks<NC, PITCH, HO, 1>(a, bf, bias, x0, y0, in, out, b0);
     }
 }
 
@@ -545,13 +600,17 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     float b1;
 
     // network input channels 0 and 1 over the input region: the views averaged over the
-    // 2^s x 2^s block of each pixel (clipped at the image), / 255, bf16.  Up to 4 x 4 blocks
-    // every byte of a thread's items is loaded (from a valid address, masked) before any is
-    // added.
+    // 2^s x 2^s block of each pixel (clipped at the image), / 255, bf16; channels 2 .. D + 1:
+    // the parent's cost at scale s + 1, / 1024, bf16, per parent of the input region (channels
+    // 0, 1 and the padding hold 0 there).  Every global load of the phase is issued before any
+    // is used: the views' bytes (up to 4 x 4 blocks, each from a valid address, masked), the
+    // parents' costs (four channels an item), then the first layer's weights.
     const int Bs = 1 << a.s;
     {
         constexpr int NI = 2 * kWIW * kWIH, NIT = (NI + kWT - 1) / kWT;
-        int px[NIT][16], ny[NIT], nx[NIT];
+        constexpr int NP = kWPW * kWPH * (cin0 / 4), NPT = (NP + kWT - 1) / kWT;
+        unsigned d0[NIT][4], d1[NIT][4];  // up to 4 x 4 blocks: per row, the aligned words holding its bytes
+        int ny[NIT], nx[NIT], bsum[NIT];
         bool in_img[NIT];
 #pragma unroll
         for (int j = 0; j < NIT; ++j) {
@@ -563,64 +622,70 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
             ny[j] = in_img[j] ? min(Bs, a.H - Y * Bs) : 0;  // >= 1 in the image: (Y, X) is in scale s
             nx[j] = in_img[j] ? min(Bs, a.W - X * Bs) : 0;
             const uint8_t* base = (v == 0 ? a.left : a.right) + (in_img[j] ? (long long)(Y * Bs) * a.W + X * Bs : 0);
+            bsum[j] = 0;
             if (Bs <= 4) {
+                // a row's nx bytes from the one or two 4-byte-aligned words that hold them (each
+                // word holds a byte of the view, so it lies in the view's pages); rows past ny
+                // read row 0
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        px[j][4 * jj + k] = base[(jj < ny[j] && k < nx[j]) ? jj * a.W + k : 0];
+                for (int jj = 0; jj < 4; ++jj) {
+                    const uintptr_t ra = reinterpret_cast<uintptr_t>(base) + (jj < ny[j] ? (uintptr_t)jj * a.W : 0);
+                    const unsigned sh = (unsigned)(ra & 3u);
+                    const unsigned* wp = reinterpret_cast<const unsigned*>(ra - sh);
+                    d0[j][jj] = wp[0];
+                    d1[j][jj] = wp[sh + nx[j] > 4 ? 1 : 0];
+                }
             } else {
-                int sum = 0;
                 for (int jj = 0; jj < ny[j]; ++jj)
-                    for (int k = 0; k < nx[j]; ++k) sum += base[(long long)jj * a.W + k];
-                px[j][0] = sum;
+                    for (int k = 0; k < nx[j]; ++k) bsum[j] += base[(long long)jj * a.W + k];
             }
         }
-        // the first layer's weights, in flight while the input is formed (issued after the
-        // views' bytes, so the sums below do not wait for them)
-        warm_frags<NC1>(a, 0, co, w1);
-        b1 = a.params[a.b_off[0] + co];
+        unsigned lo[NPT], hi[NPT];
 #pragma unroll
-        for (int j = 0; j < NIT; ++j) {
-            const int e = threadIdx.x + j * kWT;
-            if (e >= NI) break;
-            int sum = px[j][0];
-            if (Bs <= 4) {
-                sum = 0;
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) sum += (jj < ny[j] && k < nx[j]) ? px[j][4 * jj + k] : 0;
-            }
-            box[e] = in_img[j] ? to_bf16((float)sum / ((float)(ny[j] * nx[j]) * 255.0f)) : (uint16_t)0;
-        }
-    }
-    // channels 2 .. D + 1: the parent's cost at scale s + 1, / 1024, bf16, per parent of the
-    // input region (channels 0, 1 and the padding hold 0 here); four channels an item, a
-    // thread's loads all issued first
-    {
-        constexpr int NI = kWPW * kWPH * (cin0 / 4), NIT = (NI + kWT - 1) / kWT;
-        unsigned lo[NIT], hi[NIT];
-#pragma unroll
-        for (int j = 0; j < NIT; ++j) {
+        for (int j = 0; j < NPT; ++j) {
             const int e = threadIdx.x + j * kWT;
             const int c4 = e % (cin0 / 4), pp = e / (cin0 / 4);
             const int pr = pp / kWPW, pc = pp - pr * kWPW;
             const int cy = py0 + pr, cx = px0 + pc;
-            const bool inside = e < NI && cy >= 0 && cy < a.lc.H && cx >= 0 && cx < a.lc.W;
+            const bool inside = e < NP && cy >= 0 && cy < a.lc.H && cx >= 0 && cx < a.lc.W;
             const int16_t* src =
                 a.coarse + (inside ? ((long long)(2 * cy + ((cx + cy) & 1)) * a.lc.Wh + (cx >> 1)) * a.Dp : 0);
             // labels 4 c4 - 2, 4 c4 - 1 (channels 4 c4, 4 c4 + 1) and 4 c4, 4 c4 + 1: pairs of
             // labels are wholly inside [0, D) or outside it (D is even)
             const bool lo_ok = inside && c4 >= 1 && 4 * c4 <= D;
             const bool hi_ok = inside && 4 * c4 < D;
-            lo[j] = lo_ok ? *reinterpret_cast<const unsigned*>(src + 4 * c4 - 2) : 0u;
-            hi[j] = hi_ok ? *reinterpret_cast<const unsigned*>(src + 4 * c4) : 0u;
+            const unsigned lv = *reinterpret_cast<const unsigned*>(src + (lo_ok ? 4 * c4 - 2 : 0));
+            const unsigned hv = *reinterpret_cast<const unsigned*>(src + (hi_ok ? 4 * c4 : 0));
+            lo[j] = lo_ok ? lv : 0u;
+            hi[j] = hi_ok ? hv : 0u;
         }
+        // the first layer's weights, in flight while the input is formed
+        warm_frags<NC1>(a, 0, co, w1);
+        b1 = a.params[a.b_off[0] + co];
 #pragma unroll
         for (int j = 0; j < NIT; ++j) {
             const int e = threadIdx.x + j * kWT;
             if (e >= NI) break;
+            unsigned sum = (unsigned)bsum[j];
+            if (Bs <= 4) {
+                const int v = e / (kWIW * kWIH), r = e - v * (kWIW * kWIH);
+                const int ry = r / kWIW, rx = r - ry * kWIW;
+                const uint8_t* base = (v == 0 ? a.left : a.right) +
+                                      (in_img[j] ? (long long)((y0 - 6 + ry) * Bs) * a.W + (x0 - 6 + rx) * Bs : 0);
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const uintptr_t ra = reinterpret_cast<uintptr_t>(base) + (jj < ny[j] ? (uintptr_t)jj * a.W : 0);
+                    const unsigned x = __builtin_amdgcn_alignbyte(d1[j][jj], d0[j][jj], (unsigned)(ra & 3u));
+                    const unsigned m = jj < ny[j] ? (nx[j] >= 4 ? ~0u : (1u << (8 * nx[j])) - 1u) : 0u;
+                    sum = __builtin_amdgcn_udot4(x & m, 0x01010101u, sum, false);
+                }
+            }
+            box[e] = in_img[j] ? to_bf16((float)sum / ((float)(ny[j] * nx[j]) * 255.0f)) : (uint16_t)0;
+        }
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int e = threadIdx.x + j * kWT;
+            if (e >= NP) break;
             const int c4 = e % (cin0 / 4), pp = e / (cin0 / 4);
             const bool lo_ok = c4 >= 1 && 4 * c4 <= D, hi_ok = 4 * c4 < D;
             auto cv = [](unsigned w, int half) {
@@ -633,30 +698,30 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     }
     __syncthreads();
     // the network input, one row per pixel of the input region: channels 0, 1 the box
-    // averages, then the parent's costs; 0 outside the image.  A thread reads all its items
-    // before writing any.
+    // averages, then the parent's costs; 0 outside the image.  Eight channels an item; a
+    // thread reads all its items before writing any.
     {
-        constexpr int NI = kWIW * kWIH * (cin0 / 4), NIT = (NI + kWT - 1) / kWT;
-        uint2 w[NIT];
+        constexpr int C8 = cin0 / 8, NI = kWIW * kWIH * C8, NIT = (NI + kWT - 1) / kWT;
+        uint4 w[NIT];
 #pragma unroll
         for (int j = 0; j < NIT; ++j) {
             const int e = threadIdx.x + j * kWT;
-            const int c4 = e % (cin0 / 4), r = e / (cin0 / 4);
+            const int c8 = e % C8, r = e / C8;
             const int ry = r / kWIW, rx = r - ry * kWIW;
             const int Y = y0 - 6 + ry, X = x0 - 6 + rx;
             const bool inside = e < NI && Y >= 0 && Y < Hs && X >= 0 && X < Ws;
             const int pidx = inside ? ((Y >> 1) - py0) * kWPW + ((X >> 1) - px0) : 0;
-            const uint2 v = *reinterpret_cast<const uint2*>(par + pidx * cin0 + 4 * c4);
+            const uint4 v = *reinterpret_cast<const uint4*>(par + pidx * cin0 + 8 * c8);
             const int rr = e < NI ? r : 0;
             const unsigned bx = (unsigned)box[rr] | ((unsigned)box[kWIW * kWIH + rr] << 16);
-            w[j] = make_uint2(inside ? (c4 == 0 ? bx : v.x) : 0u, inside ? v.y : 0u);
+            w[j] = inside ? make_uint4(c8 == 0 ? bx : v.x, v.y, v.z, v.w) : make_uint4(0u, 0u, 0u, 0u);
         }
 #pragma unroll
         for (int j = 0; j < NIT; ++j) {
             const int e = threadIdx.x + j * kWT;
             if (e >= NI) break;
-            const int c4 = e % (cin0 / 4), r = e / (cin0 / 4);
-            *reinterpret_cast<uint2*>(inp + r * IP + 4 * c4) = w[j];
+            const int c8 = e % C8, r = e / C8;
+            *reinterpret_cast<uint4*>(inp + r * IP + 8 * c8) = w[j];
         }
     }
     __syncthreads();
@@ -666,25 +731,43 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     const float b2 = a.params[a.b_off[1] + co];
     warm_layer<NC1, IP, 5>(a, w1, b1, x0, y0, inp, actA);
     __syncthreads();
+    if (warm_edge<5>(x0, y0, Ws, Hs)) {
+        warm_clear_outside<5>(x0, y0, Ws, Hs, actA);
+        __syncthreads();
+    }
     warm_frags<2>(a, 2, co, w3);
     const float b3 = a.params[a.b_off[2] + co];
     warm_layer<2, kWAS, 4>(a, w2, b2, x0, y0, actA, actB);
     __syncthreads();
+    if (warm_edge<4>(x0, y0, Ws, Hs)) {
+        warm_clear_outside<4>(x0, y0, Ws, Hs, actB);
+        __syncthreads();
+    }
     warm_frags<2>(a, 3, co, w4);
     const float b4 = a.params[a.b_off[3] + co];
     warm_layer<2, kWAS, 3>(a, w3, b3, x0, y0, actB, actA);
     __syncthreads();
+    if (warm_edge<3>(x0, y0, Ws, Hs)) {
+        warm_clear_outside<3>(x0, y0, Ws, Hs, actA);
+        __syncthreads();
+    }
     warm_frags<2>(a, 4, co, w5);
     const float b5 = a.params[a.b_off[4] + co];
     warm_layer<2, kWAS, 2>(a, w4, b4, x0, y0, actA, actB);
     __syncthreads();
+    if (warm_edge<2>(x0, y0, Ws, Hs)) {
+        warm_clear_outside<2>(x0, y0, Ws, Hs, actB);
+        __syncthreads();
+    }
 
     // last layer: 4D outputs over the tile in 4T blocks of 16 channels (T per side k).  Wave w
     // takes channel blocks w and w + 8 and runs every 16-pixel block of the tile: each output
     // is quantised in registers and each channel block's minimum over its 16 channels goes to
     // LDS; then each message's minimum over d (the minimum of its side's T block minima), and
-    // the normalised messages are staged in LDS and stored as 16-byte vectors.
-    constexpr int NT = 4 * T, TPW = (NT + kWWaves - 1) / kWWaves, NB = (kWN + 15) / 16;
+    // the normalised messages are staged in LDS and stored as 16-byte vectors.  The minima and
+    // the staged messages have padded pixel strides (the rows four pixels apart that one
+    // store writes fall on different banks).
+    constexpr int NT = 4 * T, TPW = (NT + kWWaves - 1) / kWWaves, NB = (kWN + 15) / 16, MS = warm_msg_stride(D);
     v8s w6[TPW][ksteps(32)];
     float bc[TPW];
 #pragma unroll
@@ -696,10 +779,14 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     }
     warm_layer<2, kWAS, 1>(a, w5, b5, x0, y0, actB, actA);
     __syncthreads();
+    if (warm_edge<1>(x0, y0, Ws, Hs)) {
+        warm_clear_outside<1>(x0, y0, Ws, Hs, actA);
+        __syncthreads();
+    }
 
-    int* bmin = reinterpret_cast<int*>(r2);      // [kWN][NT]
-    int* smin = bmin + kWN * NT;                  // [kWN][4]
-    int16_t* msg = reinterpret_cast<int16_t*>(smin + kWN * 4);  // [kWN][4][D]
+    int* bmin = reinterpret_cast<int*>(r2);      // [kWN][NT + 1]
+    int* smin = bmin + kWN * (NT + 1);            // [kWN][4]
+    int16_t* msg = reinterpret_cast<int16_t*>(smin + kWN * 4);  // [kWN][MS]
     const float lamf = (float)a.lam_t;
     int qv[TPW][NB][4];
 #pragma unroll
@@ -710,50 +797,51 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
         v4f acc[TPW];
 #pragma unroll
         for (int m = 0; m < TPW; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
+        // 32 input channels: K-step s is tap s, channels 8 g .. 8 g + 7; the block's nine
+        // operands are read before the first product
+        v8s av[ksteps(32)];
 #pragma unroll
-        for (int s = 0; s < ksteps(32); ++s) {
-            // 32 input channels: K-step s is tap s, channels 8 g .. 8 g + 7
-            const v8s av = load8(arow + ((s / 3) * (kWTW + 2) + (s % 3)) * kWAS + 8 * g);
+        for (int s = 0; s < ksteps(32); ++s) av[s] = load8(arow + ((s / 3) * (kWTW + 2) + (s % 3)) * kWAS + 8 * g);
+#pragma unroll
+        for (int s = 0; s < ksteps(32); ++s)
 #pragma unroll
             for (int m = 0; m < TPW; ++m)
-                if (wave + kWWaves * m < NT)  // uniform over the wave
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w6[m][s], acc[m], 0, 0, 0);
-        }
+                if (NT % kWWaves == 0 || wave + kWWaves * m < NT)  // uniform over the wave
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], w6[m][s], acc[m], 0, 0, 0);
 #pragma unroll
         for (int m = 0; m < TPW; ++m) {
             const int t = wave + kWWaves * m;
-            if (t >= NT) continue;
+            if (NT % kWWaves != 0 && t >= NT) continue;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float r = rintf((acc[m][e] + bc[m]) * lamf);
-                const int qq = r < 0.f ? 0 : (r > lamf ? a.lam_t : (int)r);
+                const int qq = (int)fminf(fmaxf(rintf((acc[m][e] + bc[m]) * lamf), 0.f), lamf);
                 qv[m][b][e] = qq;
                 const int mn = row_min16(qq);
                 const int qo = 16 * b + 4 * g + e;
-                if (i == 0 && qo < kWN) bmin[qo * NT + t] = mn;
+                if (i == 0 && qo < kWN) bmin[qo * (NT + 1) + t] = mn;
             }
         }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kWN * 4; e += kWT) {
         const int qo = e >> 2, k = e & 3;
-        int mn = bmin[qo * NT + k * T];
+        int mn = bmin[qo * (NT + 1) + k * T];
 #pragma unroll
-        for (int v = 1; v < T; ++v) mn = min(mn, bmin[qo * NT + k * T + v]);
+        for (int v = 1; v < T; ++v) mn = min(mn, bmin[qo * (NT + 1) + k * T + v]);
         smin[e] = mn;
     }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < TPW; ++m) {
         const int t = wave + kWWaves * m;
-        if (t >= NT) continue;
+        if (NT % kWWaves != 0 && t >= NT) continue;
         const int k = t / T, u = t - k * T;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int qo = 16 * b + 4 * g + e;
-                if (qo < kWN) msg[(qo * 4 + k) * D + 16 * u + i] = (int16_t)(qv[m][b][e] - smin[qo * 4 + k]);
+                if (qo < kWN) msg[qo * MS + k * D + 16 * u + i] = (int16_t)(qv[m][b][e] - smin[qo * 4 + k]);
             }
     }
     __syncthreads();
@@ -767,7 +855,7 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
         if (Yo >= Hs || Xo >= Ws) continue;
         const bool has = k == 0 ? Xo > 0 : k == 1 ? Xo < Ws - 1 : k == 2 ? Yo > 0 : Yo < Hs - 1;
         int4 v = make_int4(0, 0, 0, 0);
-        if (has && 8 * c < D) v = *reinterpret_cast<const int4*>(msg + (qo * 4 + k) * D + 8 * c);
+        if (has && 8 * c < D) v = *reinterpret_cast<const int4*>(msg + qo * MS + k * D + 8 * c);
         const long long gi = (long long)(2 * Yo + ((Xo + Yo) & 1)) * a.lv.Wh + (Xo >> 1);
         *reinterpret_cast<int4*>(a.msgs + k * a.vol + gi * a.Dp + 8 * c) = v;
         if (k == 0 && c == 0) {
