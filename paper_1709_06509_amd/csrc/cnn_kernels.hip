@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kCT) void k_warm_messages(const float* __restrict__
 // the caches).
 constexpr int kWT = 512;             // threads per workgroup (8 waves)
 constexpr int kWWaves = kWT / 64;
-constexpr int kWTW = 12, kWTH = 8;   // tile of scale s
+constexpr int kWTW = 10, kWTH = 8;   // tile of scale s (240 workgroups at 160 x 120)
 constexpr int kWIW = kWTW + 12, kWIH = kWTH + 12;          // network input region
 constexpr int kWPW = kWTW / 2 + 7, kWPH = kWTH / 2 + 7;    // parents of the input region
 constexpr int kWAS = 40;             // bf16 per pixel of an activation buffer: 32 channels + 8 (16-byte rows, banks)
