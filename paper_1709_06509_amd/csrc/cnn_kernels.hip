@@ -39,6 +39,8 @@ __device__ __forceinline__ uint16_t to_bf16_hw(float f) { return __builtin_bit_c
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 typedef short v8s __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_u16x2(unsigned v) { return __builtin_bit_cast(u16x2, v); }
 
 // 8 bf16 at a 16-byte-aligned address (global or LDS)
 __device__ __forceinline__ v8s load8(const uint16_t* p) { return *reinterpret_cast<const v8s*>(p); }
@@ -388,17 +390,18 @@ __global__ __launch_bounds__(kCT) void k_warm_messages(const float* __restrict__
 //     cost per parent (both bf16, rounded as the input kernel rounds them), then expanded to
 //     one [pixel][channel] row per pixel of the input region;
 //   - hidden activations (32 channels, bf16) ping-pong between two LDS buffers;
-//   - every region position outside the image holds 0 in every buffer, which is the zero
-//     padding the next layer reads there, so no operand needs a bounds test;
-//   - the last layer's outputs are quantised in registers, normalised per message with
-//     minima exchanged through LDS, staged in LDS and stored as 16-byte vectors into the
-//     scale's message volumes (colour-split slots, Dp labels), with the state bytes a
-//     warm-started scale begins with.
+//   - a layer stores its outputs as computed; where its region reaches outside the image,
+//     those positions are then cleared to 0, the zero padding the next layer reads there, so
+//     no operand needs a bounds test;
+//   - the last layer's outputs are quantised in registers and staged in LDS; each message's
+//     minimum over d is taken from there, and the copy-out subtracts it as it stores 16-byte
+//     vectors into the scale's message volumes (colour-split slots, Dp labels), with the
+//     state bytes a warm-started scale begins with.
 // Every output is computed as the layer-by-layer path computes it: the same MFMA, the same
-// K order (32-wide steps of the flattened (tap, channel) dimension), the same bias, ReLU and bf16 rounding, the
-// same quantisation, so the messages are bit-identical.  A wave keeps the weight fragments
-// it needs for a layer in registers (every workgroup reads the same weights: they stay in
-// the caches).
+// K order (32-wide steps of the flattened (tap, channel) dimension), the same bias, ReLU and
+// bf16 rounding, the same quantisation, so the messages are bit-identical.  A wave keeps the
+// weight fragments it needs for a layer in registers (every workgroup reads the same
+// weights: they stay in the caches).
 constexpr int kWT = 512;             // threads per workgroup (8 waves)
 constexpr int kWWaves = kWT / 64;
 constexpr int kWTW = 10, kWTH = 8;   // tile of scale s (240 workgroups at 160 x 120)
@@ -419,6 +422,9 @@ __host__ __device__ constexpr int warm_in_pitch(int cin0) { return cin0 + 8; }
 // Staged messages of one tile pixel (int16 elements): 4 D, padded so that the rows four pixels
 // apart fall on different banks.
 __host__ __device__ constexpr int warm_msg_stride(int D) { return 4 * D + 8; }
+// Labels per message slot in the solve's volumes for the D the network supports (8 times the
+// power of two of lanes per pixel: 16, 32, 64, 64 for D = 16, 32, 48, 64).
+__host__ __device__ constexpr int warm_dp(int D) { return D <= 16 ? 16 : (D <= 32 ? 32 : 64); }
 
 // LDS: region 1 holds the box averages and the parents' costs while the input is formed, then
 // the activations of layers 1, 3, 5; region 2 holds the network input, then the activations
@@ -433,25 +439,12 @@ __host__ __device__ inline size_t warm_r2(int cin0, int D)
 {
     const size_t inp = (size_t)kWIW * kWIH * warm_in_pitch(cin0) * 2;
     const size_t act = (size_t)warm_act_rows(4) * kWAS * 2;
-    const size_t last = (size_t)kWN * (D / 4 + 1) * 4 /* block minima */ + (size_t)kWN * 4 * 4 /* side minima */ +
-                        (size_t)kWN * warm_msg_stride(D) * 2 /* messages */;
+    const size_t last = (size_t)kWN * 4 * 4 /* message minima */ + (size_t)kWN * warm_msg_stride(D) * 2 /* messages */;
     size_t m = inp > act ? inp : act;
     return m > last ? m : last;
 }
 __host__ __device__ inline size_t warm_cnn_lds(int cin0, int D) { return warm_r1(cin0) + warm_r2(cin0, D); }
 
-
-// Minimum over the 16 lanes of each row of the wave (lanes 16 r .. 16 r + 15), in every lane
-// of the row: rotations within a row through DPP.
-__device__ __forceinline__ int row_min16(int v)
-{
-    // (the old value, never used by a rotation, is min's identity so the moves fold into the mins)
-    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x128, 0xf, 0xf, false));  // row_ror:8
-    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x124, 0xf, 0xf, false));  // row_ror:4
-    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x122, 0xf, 0xf, false));  // row_ror:2
-    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x121, 0xf, 0xf, false));  // row_ror:1
-    return v;
-}
 
 // The weight fragments (B operands) of one wave for a 3x3 layer of cin_p = 16 NC input
 // channels: output channel co, every K-step (zero past 9 cin_p), lane layout of the MFMA.
@@ -603,8 +596,8 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     // 2^s x 2^s block of each pixel (clipped at the image), / 255, bf16; channels 2 .. D + 1:
     // the parent's cost at scale s + 1, / 1024, bf16, per parent of the input region (channels
     // 0, 1 and the padding hold 0 there).  Every global load of the phase is issued before any
-    // is used: the views' bytes (up to 4 x 4 blocks, each from a valid address, masked), the
-    // parents' costs (four channels an item), then the first layer's weights.
+    // is used: the views' bytes (up to 4 x 4 blocks, each from a valid address, masked), then
+    // the parents' costs (four channels an item).
     const int Bs = 1 << a.s;
     {
         constexpr int NI = 2 * kWIW * kWIH, NIT = (NI + kWT - 1) / kWT;
@@ -659,9 +652,6 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
             lo[j] = lo_ok ? lv : 0u;
             hi[j] = hi_ok ? hv : 0u;
         }
-        // the first layer's weights, in flight while the input is formed
-        warm_frags<NC1>(a, 0, co, w1);
-        b1 = a.params[a.b_off[0] + co];
 #pragma unroll
         for (int j = 0; j < NIT; ++j) {
             const int e = threadIdx.x + j * kWT;
@@ -696,6 +686,10 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
             *reinterpret_cast<uint2*>(par + pp * cin0 + 4 * c4) = make_uint2(w01, w23);
         }
     }
+    // the first layer's weights, in flight while the input is expanded (issued after the
+    // views' and parents' loads have returned, which they would otherwise delay)
+    warm_frags<NC1>(a, 0, co, w1);
+    b1 = a.params[a.b_off[0] + co];
     __syncthreads();
     // the network input, one row per pixel of the input region: channels 0, 1 the box
     // averages, then the parent's costs; 0 outside the image.  Eight channels an item; a
@@ -761,13 +755,13 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     }
 
     // last layer: 4D outputs over the tile in 4T blocks of 16 channels (T per side k).  Wave w
-    // takes channel blocks w and w + 8 and runs every 16-pixel block of the tile: each output
-    // is quantised in registers and each channel block's minimum over its 16 channels goes to
-    // LDS; then each message's minimum over d (the minimum of its side's T block minima), and
-    // the normalised messages are staged in LDS and stored as 16-byte vectors.  The minima and
-    // the staged messages have padded pixel strides (the rows four pixels apart that one
-    // store writes fall on different banks).
+    // takes channel blocks w and w + 8 and runs every 16-pixel block of the tile; each output
+    // is quantised in registers and staged in LDS as it is (pixel rows padded so that the rows
+    // four pixels apart that one store writes fall on different banks).  Then each message's
+    // minimum over d, eight lanes per message, and the copy-out subtracts it as it stores the
+    // messages as 16-byte vectors.
     constexpr int NT = 4 * T, TPW = (NT + kWWaves - 1) / kWWaves, NB = (kWN + 15) / 16, MS = warm_msg_stride(D);
+    constexpr int DP = warm_dp(D), P8 = DP / 8;
     v8s w6[TPW][ksteps(32)];
     float bc[TPW];
 #pragma unroll
@@ -784,11 +778,9 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
         __syncthreads();
     }
 
-    int* bmin = reinterpret_cast<int*>(r2);      // [kWN][NT + 1]
-    int* smin = bmin + kWN * (NT + 1);            // [kWN][4]
+    int* smin = reinterpret_cast<int*>(r2);                      // [kWN][4]
     int16_t* msg = reinterpret_cast<int16_t*>(smin + kWN * 4);  // [kWN][MS]
     const float lamf = (float)a.lam_t;
-    int qv[TPW][NB][4];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int q = 16 * b + i;
@@ -812,52 +804,53 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
         for (int m = 0; m < TPW; ++m) {
             const int t = wave + kWWaves * m;
             if (NT % kWWaves != 0 && t >= NT) continue;
+            const int k = t / T, u = t - k * T;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int qq = (int)fminf(fmaxf(rintf((acc[m][e] + bc[m]) * lamf), 0.f), lamf);
-                qv[m][b][e] = qq;
-                const int mn = row_min16(qq);
                 const int qo = 16 * b + 4 * g + e;
-                if (i == 0 && qo < kWN) bmin[qo * (NT + 1) + t] = mn;
+                if (kWN % 16 == 0 || qo < kWN) msg[qo * MS + k * D + 16 * u + i] = (int16_t)qq;
             }
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kWN * 4; e += kWT) {
-        const int qo = e >> 2, k = e & 3;
-        int mn = bmin[qo * (NT + 1) + k * T];
+    // each message's minimum over its D labels: lanes 8 j .. 8 j + 7 take one (pixel, side),
+    // eight labels each (lanes past D take none), combined through DPP within the 8 lanes
+    {
+        constexpr int NI = kWN * 4 * 8, NIT = (NI + kWT - 1) / kWT;
 #pragma unroll
-        for (int v = 1; v < T; ++v) mn = min(mn, bmin[qo * (NT + 1) + k * T + v]);
-        smin[e] = mn;
+        for (int j = 0; j < NIT; ++j) {
+            const int e = threadIdx.x + j * kWT;
+            const int c = e & 7, qk = e < NI ? e >> 3 : 0;
+            const int qo = qk >> 2, k = qk & 3;
+            const uint4 v = *reinterpret_cast<const uint4*>(msg + qo * MS + k * D + 8 * (8 * c < D ? c : 0));
+            const u16x2 m2 = __builtin_elementwise_min(__builtin_elementwise_min(as_u16x2(v.x), as_u16x2(v.y)),
+                                                       __builtin_elementwise_min(as_u16x2(v.z), as_u16x2(v.w)));
+            int mn = 8 * c < D ? min((int)m2[0], (int)m2[1]) : INT_MAX;
+            mn = min(mn, __builtin_amdgcn_update_dpp(INT_MAX, mn, 0xB1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+            mn = min(mn, __builtin_amdgcn_update_dpp(INT_MAX, mn, 0x4E, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+            mn = min(mn, __builtin_amdgcn_update_dpp(INT_MAX, mn, 0x141, 0xf, 0xf, false));  // row_half_mirror
+            if (c == 0 && e < NI) smin[qk] = mn;
+        }
     }
     __syncthreads();
-#pragma unroll
-    for (int m = 0; m < TPW; ++m) {
-        const int t = wave + kWWaves * m;
-        if (NT % kWWaves != 0 && t >= NT) continue;
-        const int k = t / T, u = t - k * T;
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int qo = 16 * b + 4 * g + e;
-                if (qo < kWN) msg[qo * MS + k * D + 16 * u + i] = (int16_t)(qv[m][b][e] - smin[qo * 4 + k]);
-            }
-    }
-    __syncthreads();
-    // copy-out: 16-byte pieces of 8 labels; labels D .. Dp - 1 and sides without a neighbour
-    // are 0
-    const int P8 = a.Dp / 8;
+    // copy-out: 16-byte pieces of 8 labels, less the message's minimum (every label is at
+    // least the minimum, so one 32-bit subtraction takes it off both halves); labels D .. Dp - 1
+    // and sides without a neighbour are 0
     for (int e = threadIdx.x; e < kWN * 4 * P8; e += kWT) {
         const int c = e % P8, qk = e / P8, k = qk & 3, qo = qk >> 2;
         const int oy = qo / kWTW, ox = qo - oy * kWTW;
         const int Yo = y0 + oy, Xo = x0 + ox;
         if (Yo >= Hs || Xo >= Ws) continue;
         const bool has = k == 0 ? Xo > 0 : k == 1 ? Xo < Ws - 1 : k == 2 ? Yo > 0 : Yo < Hs - 1;
-        int4 v = make_int4(0, 0, 0, 0);
-        if (has && 8 * c < D) v = *reinterpret_cast<const int4*>(msg + qo * MS + k * D + 8 * c);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (has && 8 * c < D) {
+            const uint4 r = *reinterpret_cast<const uint4*>(msg + qo * MS + k * D + 8 * c);
+            const unsigned m2 = (unsigned)smin[qk] * 0x10001u;
+            v = make_uint4(r.x - m2, r.y - m2, r.z - m2, r.w - m2);
+        }
         const long long gi = (long long)(2 * Yo + ((Xo + Yo) & 1)) * a.lv.Wh + (Xo >> 1);
-        *reinterpret_cast<int4*>(a.msgs + k * a.vol + gi * a.Dp + 8 * c) = v;
+        *reinterpret_cast<uint4*>(a.msgs + k * a.vol + gi * DP + 8 * c) = v;
         if (k == 0 && c == 0) {
             if (a.mode == 1) {
                 a.state_a[gi] = 1;
@@ -1008,7 +1001,7 @@ hipError_t launch_warm_cnn_t(const WarmCnnArgs& a, hipStream_t st)
 
 hipError_t launch_warm_cnn(const WarmCnnArgs& a, hipStream_t st)
 {
-    if (!warm_cnn_supported(a.D) || a.lv.W < 1 || a.lv.H < 1) return hipErrorInvalidValue;
+    if (!warm_cnn_supported(a.D) || a.lv.W < 1 || a.lv.H < 1 || a.Dp != warm_dp(a.D)) return hipErrorInvalidValue;
     switch (a.D) {
     case 16: return launch_warm_cnn_t<2, 1>(a, st);
     case 32: return launch_warm_cnn_t<3, 2>(a, st);
