@@ -386,9 +386,9 @@ __global__ __launch_bounds__(kCT) void k_warm_messages(const float* __restrict__
 // run over regions that shrink from the tile plus a 5-pixel border (layer 1) to the tile
 // itself (layer 6), and the network input is needed over the tile plus 6.  Nothing but the
 // messages leaves the workgroup:
-//   - the input is formed in LDS: the views' box averages per pixel and the parent's coarse
-//     cost per parent (both bf16, rounded as the input kernel rounds them), then expanded to
-//     one [pixel][channel] row per pixel of the input region;
+//   - the input is formed in LDS, one [pixel][channel] row per pixel of the input region:
+//     the views' box averages per pixel and the parent's coarse cost (both bf16, rounded as
+//     the input kernel rounds them) written to each of the parent's pixels;
 //   - hidden activations (32 channels, bf16) ping-pong between two LDS buffers;
 //   - a layer stores its outputs as computed; where its region reaches outside the image,
 //     those positions are then cleared to 0, the zero padding the next layer reads there, so
@@ -406,7 +406,7 @@ constexpr int kWT = 512;             // threads per workgroup (8 waves)
 constexpr int kWWaves = kWT / 64;
 constexpr int kWTW = 10, kWTH = 8;   // tile of scale s (240 workgroups at 160 x 120)
 constexpr int kWIW = kWTW + 12, kWIH = kWTH + 12;          // network input region
-constexpr int kWPW = kWTW / 2 + 7, kWPH = kWTH / 2 + 7;    // parents of the input region
+constexpr int kWPW = kWIW / 2, kWPH = kWIH / 2;            // parents of the input region (2 x 2 pixels each)
 constexpr int kWAS = 40;             // bf16 per pixel of an activation buffer: 32 channels + 8 (16-byte rows, banks)
 constexpr int kWN = kWTW * kWTH;     // pixels of the tile
 static_assert(kWTW % 2 == 0 && kWTH % 2 == 0, "even tiles: the parent region starts at an exact half");
@@ -426,14 +426,12 @@ __host__ __device__ constexpr int warm_msg_stride(int D) { return 4 * D + 8; }
 // power of two of lanes per pixel: 16, 32, 64, 64 for D = 16, 32, 48, 64).
 __host__ __device__ constexpr int warm_dp(int D) { return D <= 16 ? 16 : (D <= 32 ? 32 : 64); }
 
-// LDS: region 1 holds the box averages and the parents' costs while the input is formed, then
-// the activations of layers 1, 3, 5; region 2 holds the network input, then the activations
-// of layers 2 and 4, then the last layer's minima and staged messages.
-__host__ __device__ inline size_t warm_r1(int cin0)
+// LDS: region 1 holds the activations of layers 1, 3, 5; region 2 holds the network input,
+// then the activations of layers 2 and 4, then the last layer's staged messages and their
+// minima.
+__host__ __device__ inline size_t warm_r1(int)
 {
-    const size_t stage = (size_t)2 * kWIW * kWIH + (size_t)kWPW * kWPH * cin0;
-    const size_t act = (size_t)warm_act_rows(5) * kWAS;
-    return (2 * (stage > act ? stage : act) + 15) / 16 * 16;  // region 2 starts 16-byte aligned
+    return ((size_t)warm_act_rows(5) * kWAS * 2 + 15) / 16 * 16;  // region 2 starts 16-byte aligned
 }
 __host__ __device__ inline size_t warm_r2(int cin0, int D)
 {
@@ -577,8 +575,6 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     constexpr int cin0 = 16 * NC1, D = 16 * T, IP = warm_in_pitch(cin0);
     uint16_t* r1 = wsm;
     uint16_t* r2 = wsm + warm_r1(cin0) / 2;
-    uint16_t* box = r1;                              // [2][kWIH][kWIW]
-    uint16_t* par = r1 + 2 * kWIW * kWIH;            // [kWPH][kWPW][cin0]
     uint16_t* inp = r2;                              // [kWIH][kWIW][IP]
     uint16_t* actA = r1;                             // layers 1, 3, 5
     uint16_t* actB = r2;                             // layers 2, 4
@@ -592,12 +588,13 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     v8s w1[ksteps(16 * NC1)];
     float b1;
 
-    // network input channels 0 and 1 over the input region: the views averaged over the
-    // 2^s x 2^s block of each pixel (clipped at the image), / 255, bf16; channels 2 .. D + 1:
-    // the parent's cost at scale s + 1, / 1024, bf16, per parent of the input region (channels
-    // 0, 1 and the padding hold 0 there).  Every global load of the phase is issued before any
+    // the network input, one row of cin0 channels per pixel of the input region, 0 at pixels
+    // outside the image: channels 0 and 1 the views averaged over the 2^s x 2^s block of each
+    // pixel (clipped at the image), / 255, bf16; channels 2 .. D + 1 the parent's cost at
+    // scale s + 1, / 1024, bf16 (four channels an item, written to each of the parent's
+    // pixels); the padding channels 0.  Every global load of the phase is issued before any
     // is used: the views' bytes (up to 4 x 4 blocks, each from a valid address, masked), then
-    // the parents' costs (four channels an item).
+    // the parents' costs.
     const int Bs = 1 << a.s;
     {
         constexpr int NI = 2 * kWIW * kWIH, NIT = (NI + kWT - 1) / kWT;
@@ -670,7 +667,8 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
                     sum = __builtin_amdgcn_udot4(x & m, 0x01010101u, sum, false);
                 }
             }
-            box[e] = in_img[j] ? to_bf16((float)sum / ((float)(ny[j] * nx[j]) * 255.0f)) : (uint16_t)0;
+            const int v = e / (kWIW * kWIH), r = e - v * (kWIW * kWIH);
+            inp[r * IP + v] = in_img[j] ? to_bf16((float)sum / ((float)(ny[j] * nx[j]) * 255.0f)) : (uint16_t)0;
         }
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
@@ -683,41 +681,28 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
             };
             const unsigned w01 = lo_ok ? ((unsigned)cv(lo[j], 0) | ((unsigned)cv(lo[j], 1) << 16)) : 0u;
             const unsigned w23 = hi_ok ? ((unsigned)cv(hi[j], 0) | ((unsigned)cv(hi[j], 1) << 16)) : 0u;
-            *reinterpret_cast<uint2*>(par + pp * cin0 + 4 * c4) = make_uint2(w01, w23);
+            // straight into the rows of the parent's four pixels of the input region;
+            // 0 at pixels outside the image; channels 0, 1 belong to the box averages above
+            const int pr = pp / kWPW, pc = pp - pr * kWPW;
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx) {
+                    const int ry = 2 * pr + dy, rx = 2 * pc + dx;
+                    const int Y = y0 - 6 + ry, X = x0 - 6 + rx;
+                    const bool img = Y >= 0 && Y < Hs && X >= 0 && X < Ws;
+                    uint16_t* row = inp + (ry * kWIW + rx) * IP + 4 * c4;
+                    if (c4 == 0)
+                        *reinterpret_cast<unsigned*>(row + 2) = img ? w23 : 0u;
+                    else
+                        *reinterpret_cast<uint2*>(row) = img ? make_uint2(w01, w23) : make_uint2(0u, 0u);
+                }
         }
     }
-    // the first layer's weights, in flight while the input is expanded (issued after the
-    // views' and parents' loads have returned, which they would otherwise delay)
+    // the first layer's weights (issued after the views' and parents' loads have returned,
+    // which they would otherwise delay)
     warm_frags<NC1>(a, 0, co, w1);
     b1 = a.params[a.b_off[0] + co];
-    __syncthreads();
-    // the network input, one row per pixel of the input region: channels 0, 1 the box
-    // averages, then the parent's costs; 0 outside the image.  Eight channels an item; a
-    // thread reads all its items before writing any.
-    {
-        constexpr int C8 = cin0 / 8, NI = kWIW * kWIH * C8, NIT = (NI + kWT - 1) / kWT;
-        uint4 w[NIT];
-#pragma unroll
-        for (int j = 0; j < NIT; ++j) {
-            const int e = threadIdx.x + j * kWT;
-            const int c8 = e % C8, r = e / C8;
-            const int ry = r / kWIW, rx = r - ry * kWIW;
-            const int Y = y0 - 6 + ry, X = x0 - 6 + rx;
-            const bool inside = e < NI && Y >= 0 && Y < Hs && X >= 0 && X < Ws;
-            const int pidx = inside ? ((Y >> 1) - py0) * kWPW + ((X >> 1) - px0) : 0;
-            const uint4 v = *reinterpret_cast<const uint4*>(par + pidx * cin0 + 8 * c8);
-            const int rr = e < NI ? r : 0;
-            const unsigned bx = (unsigned)box[rr] | ((unsigned)box[kWIW * kWIH + rr] << 16);
-            w[j] = inside ? make_uint4(c8 == 0 ? bx : v.x, v.y, v.z, v.w) : make_uint4(0u, 0u, 0u, 0u);
-        }
-#pragma unroll
-        for (int j = 0; j < NIT; ++j) {
-            const int e = threadIdx.x + j * kWT;
-            if (e >= NI) break;
-            const int c8 = e % C8, r = e / C8;
-            *reinterpret_cast<uint4*>(inp + r * IP + 8 * c8) = w[j];
-        }
-    }
     __syncthreads();
     // each layer's weights are loaded while the layer before it runs
     v8s w2[ksteps(32)], w3[ksteps(32)], w4[ksteps(32)], w5[ksteps(32)];
