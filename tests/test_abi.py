@@ -146,3 +146,28 @@ def test_warmstart_solve_host_validation(lib):
         assert rc == B.BP_E_UNSUPPORTED and b"multiple of 16" in L.bp_last_error(), D
     rc = L.bp_warmstart_solve(*args(good, ws=need - 1))
     assert rc == B.BP_E_WORKSPACE
+    rc = L.bp_warmstart_solve(*args(good, cw=p(24)))  # the network reads its weights 16 bytes at a time
+    assert rc == B.BP_E_INVAL and b"16-byte" in L.bp_last_error()
+
+
+def test_convolution_alignment_validation(lib):
+    """The convolution entry points read activations and weights 16 bytes at a time and reject
+    operands that are not 16-byte aligned before any device work (the pointers here are never
+    dereferenced)."""
+    from paper_1709_06509_amd import bpstereo as B
+    from paper_1709_06509_amd import warmstart as WS
+
+    L = WS._lib()
+    p = ctypes.c_void_p
+    rc = L.bp_conv3x3_forward(p(24), 8, 8, 16, p(256), None, 32, 32, 1, None, p(256), None, None)
+    assert rc == B.BP_E_INVAL and b"16-byte" in L.bp_last_error()
+    rc = L.bp_conv3x3_forward(p(256), 8, 8, 16, p(264), None, 32, 32, 1, None, p(256), None, None)
+    assert rc == B.BP_E_INVAL and b"16-byte" in L.bp_last_error()
+    rc = L.bp_conv3x3_data_grad(p(24), 8, 8, 32, p(256), 16, 32, None, p(256), p(256), None, None)
+    assert rc == B.BP_E_INVAL and b"16-byte" in L.bp_last_error()
+    ws = L.bp_cnn_workspace_bytes(8, 8, 16)
+    assert ws > 0
+    rc = L.bp_cnn_forward(p(24), 8, 8, 16, p(256), p(256), p(256), ws, p(256), None)
+    assert rc == B.BP_E_INVAL and b"16-byte" in L.bp_last_error()
+    rc = L.bp_cnn_forward(p(256), 8, 8, 16, p(256), p(264), p(256), ws, p(256), None)
+    assert rc == B.BP_E_INVAL and b"16-byte" in L.bp_last_error()
