@@ -393,10 +393,10 @@ __global__ __launch_bounds__(kCT) void k_warm_messages(const float* __restrict__
 //   - a layer stores its outputs as computed; where its region reaches outside the image,
 //     those positions are then cleared to 0, the zero padding the next layer reads there, so
 //     no operand needs a bounds test;
-//   - the last layer's outputs are quantised in registers and staged in LDS; each message's
-//     minimum over d is taken from there, and the copy-out subtracts it as it stores 16-byte
-//     vectors into the scale's message volumes (colour-split slots, Dp labels), with the
-//     state bytes a warm-started scale begins with.
+//   - the last layer's outputs are quantised in registers and staged in LDS; the copy-out
+//     takes each message's minimum over d (DPP across the lanes holding its pieces) and
+//     subtracts it as it stores 16-byte vectors into the scale's message volumes
+//     (colour-split slots, Dp labels), with the state bytes a warm-started scale begins with.
 // Every output is computed as the layer-by-layer path computes it: the same MFMA, the same
 // K order (32-wide steps of the flattened (tap, channel) dimension), the same bias, ReLU and
 // bf16 rounding, the same quantisation, so the messages are bit-identical.  A wave keeps the
@@ -427,8 +427,7 @@ __host__ __device__ constexpr int warm_msg_stride(int D) { return 4 * D + 8; }
 __host__ __device__ constexpr int warm_dp(int D) { return D <= 16 ? 16 : (D <= 32 ? 32 : 64); }
 
 // LDS: region 1 holds the activations of layers 1, 3, 5; region 2 holds the network input,
-// then the activations of layers 2 and 4, then the last layer's staged messages and their
-// minima.
+// then the activations of layers 2 and 4, then the last layer's staged messages.
 __host__ __device__ inline size_t warm_r1(int)
 {
     return ((size_t)warm_act_rows(5) * kWAS * 2 + 15) / 16 * 16;  // region 2 starts 16-byte aligned
@@ -437,7 +436,7 @@ __host__ __device__ inline size_t warm_r2(int cin0, int D)
 {
     const size_t inp = (size_t)kWIW * kWIH * warm_in_pitch(cin0) * 2;
     const size_t act = (size_t)warm_act_rows(4) * kWAS * 2;
-    const size_t last = (size_t)kWN * 4 * 4 /* message minima */ + (size_t)kWN * warm_msg_stride(D) * 2 /* messages */;
+    const size_t last = (size_t)kWN * warm_msg_stride(D) * 2;  // staged messages
     size_t m = inp > act ? inp : act;
     return m > last ? m : last;
 }
@@ -742,9 +741,9 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     // last layer: 4D outputs over the tile in 4T blocks of 16 channels (T per side k).  Wave w
     // takes channel blocks w and w + 8 and runs every 16-pixel block of the tile; each output
     // is quantised in registers and staged in LDS as it is (pixel rows padded so that the rows
-    // four pixels apart that one store writes fall on different banks).  Then each message's
-    // minimum over d, eight lanes per message, and the copy-out subtracts it as it stores the
-    // messages as 16-byte vectors.
+    // four pixels apart that one store writes fall on different banks); the copy-out takes
+    // each message's minimum over d and subtracts it as it stores the messages as 16-byte
+    // vectors.
     constexpr int NT = 4 * T, TPW = (NT + kWWaves - 1) / kWWaves, NB = (kWN + 15) / 16, MS = warm_msg_stride(D);
     constexpr int DP = warm_dp(D), P8 = DP / 8;
     v8s w6[TPW][ksteps(32)];
@@ -763,8 +762,7 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
         __syncthreads();
     }
 
-    int* smin = reinterpret_cast<int*>(r2);                      // [kWN][4]
-    int16_t* msg = reinterpret_cast<int16_t*>(smin + kWN * 4);  // [kWN][MS]
+    int16_t* msg = reinterpret_cast<int16_t*>(r2);  // [kWN][MS]
     const float lamf = (float)a.lam_t;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -799,49 +797,42 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
         }
     }
     __syncthreads();
-    // each message's minimum over its D labels: lanes 8 j .. 8 j + 7 take one (pixel, side),
-    // eight labels each (lanes past D take none), combined through DPP within the 8 lanes
+    // copy-out: 16-byte pieces of 8 labels, the P8 pieces of a message on consecutive lanes,
+    // which take the message's minimum over its D labels through DPP and subtract it (every
+    // label is at least the minimum, so one 32-bit subtraction takes it off both halves);
+    // labels D .. Dp - 1 and sides without a neighbour are 0.  Every lane of the workgroup
+    // runs every iteration (the exchanges need them); the stores are predicated.
     {
-        constexpr int NI = kWN * 4 * 8, NIT = (NI + kWT - 1) / kWT;
+        constexpr int NI = kWN * 4 * P8, NIT = (NI + kWT - 1) / kWT;
 #pragma unroll
         for (int j = 0; j < NIT; ++j) {
             const int e = threadIdx.x + j * kWT;
-            const int c = e & 7, qk = e < NI ? e >> 3 : 0;
-            const int qo = qk >> 2, k = qk & 3;
-            const uint4 v = *reinterpret_cast<const uint4*>(msg + qo * MS + k * D + 8 * (8 * c < D ? c : 0));
-            const u16x2 m2 = __builtin_elementwise_min(__builtin_elementwise_min(as_u16x2(v.x), as_u16x2(v.y)),
-                                                       __builtin_elementwise_min(as_u16x2(v.z), as_u16x2(v.w)));
-            int mn = 8 * c < D ? min((int)m2[0], (int)m2[1]) : INT_MAX;
-            mn = min(mn, __builtin_amdgcn_update_dpp(INT_MAX, mn, 0xB1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
-            mn = min(mn, __builtin_amdgcn_update_dpp(INT_MAX, mn, 0x4E, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
-            mn = min(mn, __builtin_amdgcn_update_dpp(INT_MAX, mn, 0x141, 0xf, 0xf, false));  // row_half_mirror
-            if (c == 0 && e < NI) smin[qk] = mn;
-        }
-    }
-    __syncthreads();
-    // copy-out: 16-byte pieces of 8 labels, less the message's minimum (every label is at
-    // least the minimum, so one 32-bit subtraction takes it off both halves); labels D .. Dp - 1
-    // and sides without a neighbour are 0
-    for (int e = threadIdx.x; e < kWN * 4 * P8; e += kWT) {
-        const int c = e % P8, qk = e / P8, k = qk & 3, qo = qk >> 2;
-        const int oy = qo / kWTW, ox = qo - oy * kWTW;
-        const int Yo = y0 + oy, Xo = x0 + ox;
-        if (Yo >= Hs || Xo >= Ws) continue;
-        const bool has = k == 0 ? Xo > 0 : k == 1 ? Xo < Ws - 1 : k == 2 ? Yo > 0 : Yo < Hs - 1;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (has && 8 * c < D) {
-            const uint4 r = *reinterpret_cast<const uint4*>(msg + qo * MS + k * D + 8 * c);
-            const unsigned m2 = (unsigned)smin[qk] * 0x10001u;
-            v = make_uint4(r.x - m2, r.y - m2, r.z - m2, r.w - m2);
-        }
-        const long long gi = (long long)(2 * Yo + ((Xo + Yo) & 1)) * a.lv.Wh + (Xo >> 1);
-        *reinterpret_cast<uint4*>(a.msgs + k * a.vol + gi * DP + 8 * c) = v;
-        if (k == 0 && c == 0) {
-            if (a.mode == 1) {
-                a.state_a[gi] = 1;
-                a.state_b[gi] = 0;
+            const int c = e % P8, qk = e < NI ? e / P8 : 0, k = qk & 3, qo = qk >> 2;
+            const bool lab = 8 * c < D;
+            const uint4 r = *reinterpret_cast<const uint4*>(msg + qo * MS + k * D + 8 * (lab ? c : 0));
+            const u16x2 m2 = __builtin_elementwise_min(__builtin_elementwise_min(as_u16x2(r.x), as_u16x2(r.y)),
+                                                       __builtin_elementwise_min(as_u16x2(r.z), as_u16x2(r.w)));
+            int mn = lab ? min((int)m2[0], (int)m2[1]) : INT_MAX;
+            mn = min(mn, __builtin_amdgcn_update_dpp(INT_MAX, mn, 0xB1, 0xf, 0xf, false));  // quad_perm [1,0,3,2]
+            if constexpr (P8 >= 4)
+                mn = min(mn, __builtin_amdgcn_update_dpp(INT_MAX, mn, 0x4E, 0xf, 0xf, false));  // quad_perm [2,3,0,1]
+            if constexpr (P8 >= 8)
+                mn = min(mn, __builtin_amdgcn_update_dpp(INT_MAX, mn, 0x141, 0xf, 0xf, false));  // row_half_mirror
+            const int oy = qo / kWTW, ox = qo - oy * kWTW;
+            const int Yo = y0 + oy, Xo = x0 + ox;
+            if (e >= NI || Yo >= Hs || Xo >= Ws) continue;
+            const bool has = k == 0 ? Xo > 0 : k == 1 ? Xo < Ws - 1 : k == 2 ? Yo > 0 : Yo < Hs - 1;
+            const unsigned mm = (unsigned)mn * 0x10001u;
+            const uint4 v = has && lab ? make_uint4(r.x - mm, r.y - mm, r.z - mm, r.w - mm) : make_uint4(0u, 0u, 0u, 0u);
+            const long long gi = (long long)(2 * Yo + ((Xo + Yo) & 1)) * a.lv.Wh + (Xo >> 1);
+            *reinterpret_cast<uint4*>(a.msgs + k * a.vol + gi * DP + 8 * c) = v;
+            if (k == 0 && c == 0) {
+                if (a.mode == 1) {
+                    a.state_a[gi] = 1;
+                    a.state_b[gi] = 0;
+                }
+                if (a.mode == 2) a.state_a[gi] = 1;
             }
-            if (a.mode == 2) a.state_a[gi] = 1;
         }
     }
 }
