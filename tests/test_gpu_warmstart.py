@@ -389,8 +389,9 @@ def layer_path(left, right, cost, L, iters, lam, T, skip, lay, params, w16):
     return msgs, d, m, st
 
 
-# (W, H, D, L): scale-(L-2) sizes with ragged 12 x 8 tiles, smaller than one tile, one pixel
-# wide or high, and the learned configuration (640 x 480, D = 64, 4 scales: 160 x 120)
+# (W, H, D, L): scale-(L-2) sizes with ragged and whole 10 x 8 tiles, smaller than one tile,
+# one pixel wide or high, the learned configuration (640 x 480, D = 64, 4 scales: 160 x 120),
+# and five scales (the network at scale 3, the views averaged over 8 x 8 blocks)
 ONE_LAUNCH_CASES = [
     (70, 45, 16, 3),
     (33, 29, 32, 2),
@@ -400,6 +401,8 @@ ONE_LAUNCH_CASES = [
     (130, 1, 16, 2),
     (200, 150, 64, 4),
     (640, 480, 64, 4),
+    (160, 96, 16, 5),  # scale 3: the views averaged over 8 x 8 blocks
+    (97, 53, 32, 5),
 ]
 
 
@@ -417,7 +420,7 @@ def test_warmstart_solve_equals_layer_path(case, skip):
     cost = B.stereo_cost_volume(left, right, D, 5)
     lay, params, w16 = spread_network(D, 40 + D)
     lam, T = 64, 4
-    for iters in ([0] * L, [4, 3, 3, 0][:L] if L > 2 else [5, 0]):
+    for iters in ([0] * L, ([4, 3, 3, 0][:L] if L <= 4 else [4, 3, 3, 3, 0]) if L > 2 else [5, 0]):
         msgs, d_ref, m_ref, st_ref = layer_path(left, right, cost, L, iters, lam, T, skip, lay, params, w16)
         d, m, st = WS.warmstart_solve(left, right, cost, L, iters, lam, T, params, w16, skip, want_msgs=True,
                                       want_stats=True)
