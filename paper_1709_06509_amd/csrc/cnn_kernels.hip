@@ -567,6 +567,92 @@ __device__ __forceinline__ void warm_layer(const WarmCnnArgs& a, const v8s (&bf)
     }
 }
 
+// Layer 1 (the region of halo 5, 16 NC input channels) with every wave computing all 32
+// output channels for its blocks (w, w + 8, w + 16), so each operand read from LDS feeds two
+// MFMAs (channels i and 16 + i) and the layer reads its operands once, not once per channel
+// half.  The weights of both halves stream through registers in chunks of kW1Chunk K-steps,
+// the next chunk's loads in flight while a chunk runs.  Every output still accumulates its
+// K-steps in order, as warm_blocks does.
+constexpr int kW1Chunk = 6;
+
+// The weight fragments of K-steps kW1Chunk c .. of output channels i and 16 + i (zero past the
+// last step and past 9 cin_p).
+template <int NC>
+__device__ __forceinline__ void warm_l1_chunk(const WarmCnnArgs& a, int c, v8s (&dst)[2][kW1Chunk])
+{
+    constexpr int K = 9 * 16 * NC;
+    const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+    const uint16_t* bw = a.w16 + a.w_off[0] + (long long)i * K;
+    const v8s zero = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kW1Chunk; ++j) {
+        const int k0 = 32 * (c * kW1Chunk + j) + 8 * g;
+        const bool ok = k0 < K;
+        const v8s v0 = load8(bw + (ok ? k0 : 0)), v1 = load8(bw + 16LL * K + (ok ? k0 : 0));
+        dst[0][j] = ok ? v0 : zero;
+        dst[1][j] = ok ? v1 : zero;
+    }
+}
+
+template <int NC, int PITCH>
+__device__ __forceinline__ void warm_layer1(const WarmCnnArgs& a, v8s (&wb)[2][2][kW1Chunk], int x0, int y0,
+                                            const uint16_t* __restrict__ in, uint16_t* __restrict__ out)
+{
+    constexpr int HO = 5, OW = kWTW + 2 * HO, N = OW * (kWTH + 2 * HO), IWl = OW + 2;
+    constexpr int NS = ksteps(16 * NC), NBLK = (N + 15) / 16, MB = (NBLK + kWWaves - 1) / kWWaves;
+    constexpr int NCH = (NS + kW1Chunk - 1) / kW1Chunk;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    const v8s zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    const float bias0 = a.params[a.b_off[0] + i], bias1 = a.params[a.b_off[0] + 16 + i];
+    // this lane's A row in each of its blocks (rows past the region read row 0; their results
+    // go to the buffer's padding rows)
+    const uint16_t* arow[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        const int q = 16 * (wave + kWWaves * m) + i;
+        const int ry = q < N ? q / OW : 0, rx = q < N ? q - (q / OW) * OW : 0;
+        arow[m] = in + (ry * IWl + rx) * PITCH;
+    }
+    v4f acc[MB][2];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) acc[m][0] = acc[m][1] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        if (c + 1 < NCH) warm_l1_chunk<NC>(a, c + 1, wb[(c + 1) & 1]);
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            if (wave + kWWaves * m >= NBLK) continue;  // uniform over the wave
+            // the chunk's operands of the block, all read before the first product
+            v8s av[kW1Chunk];
+#pragma unroll
+            for (int j = 0; j < kW1Chunk; ++j) {
+                const int off = warm_koff<NC, PITCH>(c * kW1Chunk + j, g, IWl);
+                const v8s v = load8(arow[m] + (off < 0 ? 0 : off));
+                av[j] = off < 0 ? zero : v;
+            }
+#pragma unroll
+            for (int j = 0; j < kW1Chunk; ++j) {
+                if (c * kW1Chunk + j >= NS) break;
+                acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[j], wb[c & 1][0][j], acc[m][0], 0, 0, 0);
+                acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[j], wb[c & 1][1][j], acc[m][1], 0, 0, 0);
+            }
+        }
+    }
+    // results: rows 4 g + e of each block, channels i and 16 + i, stored as computed (region
+    // positions outside the image are cleared afterwards, warm_clear_outside)
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        if (wave + kWWaves * m >= NBLK) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            uint16_t* o = out + (16 * (wave + kWWaves * m) + 4 * g + e) * kWAS;
+            o[i] = to_bf16_hw(fmaxf(acc[m][0][e] + bias0, 0.f));
+            o[16 + i] = to_bf16_hw(fmaxf(acc[m][1][e] + bias1, 0.f));
+        }
+    }
+}
+
 template <int NC1, int T>
 __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
 {
@@ -584,8 +670,7 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
     const int i = lane & 15, g = lane >> 4;
     const int co = 16 * (wave >> 2) + i;  // this lane's output channel in layers 1-5
 
-    v8s w1[ksteps(16 * NC1)];
-    float b1;
+    v8s w1[2][2][kW1Chunk];  // the first layer's weights, chunk by chunk (warm_layer1)
 
     // the network input, one row of cin0 channels per pixel of the input region, 0 at pixels
     // outside the image: channels 0 and 1 the views averaged over the 2^s x 2^s block of each
@@ -698,16 +783,15 @@ __global__ __launch_bounds__(kWT) void k_warm_cnn(WarmCnnArgs a)
                 }
         }
     }
-    // the first layer's weights (issued after the views' and parents' loads have returned,
-    // which they would otherwise delay)
-    warm_frags<NC1>(a, 0, co, w1);
-    b1 = a.params[a.b_off[0] + co];
+    // the first layer's first weight chunk (issued after the views' and parents' loads have
+    // returned, which they would otherwise delay)
+    warm_l1_chunk<NC1>(a, 0, w1[0]);
     __syncthreads();
     // each layer's weights are loaded while the layer before it runs
     v8s w2[ksteps(32)], w3[ksteps(32)], w4[ksteps(32)], w5[ksteps(32)];
     warm_frags<2>(a, 1, co, w2);
     const float b2 = a.params[a.b_off[1] + co];
-    warm_layer<NC1, IP, 5>(a, w1, b1, x0, y0, inp, actA);
+    warm_layer1<NC1, IP>(a, w1, x0, y0, inp, actA);
     __syncthreads();
     if (warm_edge<5>(x0, y0, Ws, Hs)) {
         warm_clear_outside<5>(x0, y0, Ws, Hs, actA);
