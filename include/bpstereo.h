@@ -305,6 +305,13 @@ typedef struct {
 size_t bp_batch_workspace_bytes(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params);
 
 /*
+ * Bits per label in which a batched solve keeps every pair's messages: 12 where every
+ * message lies in [0, 4095] (lambda * trunc <= 4095), whatever num_disp; else 16; 0 if the
+ * batch is invalid (as bp_batch_workspace_bytes).  Results do not depend on it.
+ */
+int32_t bp_batch_message_bits(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params);
+
+/*
  * Solve a batch.  ctx is required: it owns the pinned staging buffer the per-batch tables
  * are uploaded from (a stream-ordered copy into the workspace at every call), the tuned
  * launch shape (bp_autotune_batched) and, when graphs are enabled, the captured graph of
@@ -325,6 +332,7 @@ typedef struct {
     int32_t schedule[16];      /* 0: one persistent launch; 1: one launch per phase (no grid barrier);
                                   2: as 1, with packed 16-bit message sums in the half-steps of
                                   scales that fit the caches (offered when lambda * trunc <= 16383;
+                                  the same as 1 where messages are kept in 12 bits;
                                   results are identical) */
     int32_t blocks_per_cu[16]; /* persistent launch: resident workgroups per compute unit */
     int32_t order[16];         /* 0: tiles dealt round-robin; 1: one contiguous eighth per XCD */

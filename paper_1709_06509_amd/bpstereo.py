@@ -383,6 +383,8 @@ def _batch_sigs(lib):
         return
     lib.bp_batch_workspace_bytes.argtypes = [ctypes.POINTER(PairDesc), _i32, ctypes.POINTER(BatchParams)]
     lib.bp_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.bp_batch_message_bits.argtypes = [ctypes.POINTER(PairDesc), _i32, ctypes.POINTER(BatchParams)]
+    lib.bp_batch_message_bits.restype = ctypes.c_int32
     lib.bp_solve_batched.argtypes = [_vp, ctypes.POINTER(PairDesc), _i32, ctypes.POINTER(BatchParams), _vp,
                                      ctypes.c_size_t, _vp]
     lib.bp_solve_batched.restype = ctypes.c_int32
@@ -435,6 +437,10 @@ class Batch:
         if need == 0:
             raise BPError(BP_E_INVAL, "invalid or unsupported batch")
         self.workspace = torch.empty(need, dtype=torch.uint8, device=lefts[0].device)
+
+    def message_bits(self):
+        """Bits per label of the batch's stored messages (12 or 16)."""
+        return int(_load().bp_batch_message_bits(self.descs, len(self.descs), ctypes.byref(self.params)))
 
     def solve(self, ctx, stream=None):
         _check(_load().bp_solve_batched(ctx.handle, self.descs, len(self.descs), ctypes.byref(self.params),

@@ -1065,6 +1065,11 @@ int32_t upload_tables(bp_context* ctx, const std::vector<char>& img, char* ws, h
     return BP_OK;
 }
 
+// A batch keeps its messages in 12 bits wherever every message fits (min(lambda * T, 32767)
+// <= 4095, as in the solo solve, whatever D): a quarter fewer message bytes on the streamed
+// half-step phases, which hold most of a batch's time.
+bool batch_packed(const bp_batch_params* p) { return (long long)p->lambda * p->trunc <= 4095; }
+
 bpst::BatchArgs batch_args(const BatchPlan& b, const bp_batch_params* p, char* ws, int order, long long ticks,
                            bool narrow)
 {
@@ -1080,7 +1085,8 @@ bpst::BatchArgs batch_args(const BatchPlan& b, const bp_batch_params* p, char* w
     // min(lambda * T, 32767) either way unless T >= D, where the clamp never binds
     const long long lt = (long long)p->lambda * p->trunc;
     a.capv = (int)(lt < 32767 ? lt : 32767);
-    a.narrow = narrow && a.capv <= bpst::kNarrowCap ? 1 : 0;
+    a.packed = batch_packed(p) ? 1 : 0;  // the narrow path does not take 12-bit messages
+    a.narrow = narrow && a.capv <= bpst::kNarrowCap && !a.packed ? 1 : 0;
     a.K = p->converge_iters;
     a.mode = p->skip_mode;
     a.order = order;
@@ -1112,7 +1118,7 @@ int32_t enqueue_batch_solve(bp_context* ctx, const BatchPlan& b, const bp_batch_
                 HIP_TRY(hipEventRecord(e0, st));
             }
             // streamed phases stay on the int32 path (the narrow path pays only off the memory bound)
-            const int hv = d.stream ? bpst::kHvStream : (a.narrow ? bpst::kHvNarrow : 0);
+            const int hv = (d.stream ? bpst::kHvStream : (a.narrow ? bpst::kHvNarrow : 0)) | (a.packed ? bpst::kHvPacked : 0);
             HIP_TRY(bpst::launch_batch_phase(a, ph, d.type, d.source, b.tiles[(size_t)ph * (b.n + 1) + b.n],
                                              b.lds, hv, st));
             if (e1) HIP_TRY(hipEventRecord(e1, st));
@@ -1141,6 +1147,13 @@ BP_API size_t bp_batch_workspace_bytes(const bp_pair_desc* pairs, int32_t n, con
     BatchPlan b;
     if (plan_batch(pairs, n, params, &b, false) != BP_OK) return 0;
     return b.total;
+}
+
+BP_API int32_t bp_batch_message_bits(const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params)
+{
+    BatchPlan b;
+    if (plan_batch(pairs, n, params, &b, false) != BP_OK) return 0;
+    return batch_packed(params) ? 12 : 16;
 }
 
 BP_API int32_t bp_solve_batched(bp_context* ctx, const bp_pair_desc* pairs, int32_t n, const bp_batch_params* params,

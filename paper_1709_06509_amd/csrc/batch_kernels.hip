@@ -78,14 +78,25 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs& a, int* s_ok)
 }
 
 // One tile of a phase whose type (and half-step message source) is known at compile time.
-// HV: the half-step variant, fixed at compile time for one-phase launches (bit 0 narrow
-// path, bit 1 streamed volumes) or -1 to read it from the arguments (persistent launch).
+// HV: the variant, fixed at compile time for one-phase launches (bit 0 narrow path, bit 1
+// streamed volumes, bit 2 messages in 12 bits) or -1 to read it from the arguments
+// (persistent launch).
 constexpr int kHvRuntime = -1;
 
 template <int G, int MODE, int TYPE, int SRC, int HV = kHvRuntime>
 __device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& ph, const PairDev& Q, int lt,
                                            int* lds)
 {
+    if constexpr (HV == kHvRuntime) {
+        // the persistent launch: the storage of the messages from the arguments
+        if (a.packed) {
+            run_tile_t<G, MODE, TYPE, SRC, kHvRuntime - 1>(a, ph, Q, lt, lds);
+            return;
+        }
+    }
+    // kHvRuntime - 1: the persistent launch's 12-bit variant
+    constexpr bool RT = HV == kHvRuntime || HV == kHvRuntime - 1;
+    constexpr bool PK = HV == kHvRuntime - 1 || (!RT && (HV & kHvPacked) != 0);
     constexpr int kPix = kThreads / G;  // pixels per tile
     const int lane = threadIdx.x & (G - 1);
     const long long gi = (long long)lt * kPix + threadIdx.x / G;
@@ -96,8 +107,8 @@ __device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& 
         else pyramid_tree_block<G, false>(Q.cost, Q.c, Q.lv, a.L, Q.D, c0, lds);
     } else if (TYPE == kPhInit) {
         const bool top = l == a.L - 1;
-        init_pixel<G>(top ? nullptr : Q.m[(l + 1) & 1], Q.lv[top ? l : l + 1], top ? 0 : Q.vol[l + 1], Q.m[l & 1],
-                      Q.lv[l], Q.vol[l], Q.sa, Q.sb, a.mode, gi, lane);
+        init_pixel<G, PK>(top ? nullptr : Q.m[(l + 1) & 1], Q.lv[top ? l : l + 1], top ? 0 : Q.vol[l + 1],
+                          Q.m[l & 1], Q.lv[l], Q.vol[l], Q.sa, Q.sb, a.mode, gi, lane);
     } else if (TYPE == kPhHalfstep) {
         HalfstepArgs h{};
         h.cost = Q.c[l];
@@ -121,29 +132,29 @@ __device__ __forceinline__ void run_tile_t(const BatchArgs& a, const PhaseDesc& 
         h.K = a.K;
         h.mode = MODE;
         if (MODE == 0 && ph.wta) h.disp = Q.disparity;  // written on the int32 path only
-        if constexpr (HV == kHvRuntime) {
-            if constexpr (G <= kNarrowMaxG) {
+        if constexpr (RT) {
+            if constexpr (G <= kNarrowMaxG && !PK) {
                 if (a.narrow && !ph.stream) {
                     halfstep_pixel<G, MODE, SRC, true>(h, (int)gi, lane);
                     return;
                 }
             }
-            if (ph.stream) halfstep_pixel<G, MODE, SRC, false, true>(h, (int)gi, lane);
-            else halfstep_pixel<G, MODE, SRC>(h, (int)gi, lane);
+            if (ph.stream) halfstep_pixel<G, MODE, SRC, false, true, PK>(h, (int)gi, lane);
+            else halfstep_pixel<G, MODE, SRC, false, false, PK>(h, (int)gi, lane);
         } else {
-            // pixels wider than kNarrowMaxG lanes stay on the int32 path
-            constexpr bool N = (HV & kHvNarrow) != 0 && G <= kNarrowMaxG;
-            halfstep_pixel<G, MODE, SRC, N, (HV & kHvStream) != 0>(h, (int)gi, lane);
+            // pixels wider than kNarrowMaxG lanes stay on the int32 path, as do 12-bit messages
+            constexpr bool N = (HV & kHvNarrow) != 0 && G <= kNarrowMaxG && !PK;
+            halfstep_pixel<G, MODE, SRC, N, (HV & kHvStream) != 0, PK>(h, (int)gi, lane);
         }
     } else {
         // the colour the last half-step already decided, where it ran on the int32 path (the
         // same rule as the half-step's own choice above)
-        const bool narrow = G <= kNarrowMaxG && a.narrow && !ph.stream;
+        const bool narrow = G <= kNarrowMaxG && a.narrow && !ph.stream && !PK;
         if (MODE == 0 && ph.wta >= 0 && !narrow && gi < Q.lv[0].slots()) {
             const long long row = gi / Q.lv[0].Wh;  // 2 y + colour
             if ((int)(row & 1) == ph.wta) return;
         }
-        wta_pixel<G>(Q.c[0], Q.m[0], Q.vol[0], Q.lv[0], Q.D, Q.disparity, gi, lane);
+        wta_pixel<G, PK>(Q.c[0], Q.m[0], Q.vol[0], Q.lv[0], Q.D, Q.disparity, gi, lane);
     }
 }
 
@@ -269,7 +280,9 @@ static void launch_phase_v(const BatchArgs& a, int phase, int type, int src, int
     case kPhPyramid:
         hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhPyramid, kSrcOwn, 0>), g, b, lds, st, a, phase);
         break;
-    case kPhInit: hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhInit, kSrcOwn, 0>), g, b, 0, st, a, phase); break;
+    case kPhInit:
+        hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhInit, kSrcOwn, HV & kHvPacked>), g, b, 0, st, a, phase);
+        break;
     case kPhHalfstep:
         if (src == kSrcParent)
             hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcParent, HV>), g, b, 0, st, a, phase);
@@ -278,11 +291,14 @@ static void launch_phase_v(const BatchArgs& a, int phase, int type, int src, int
         else
             hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhHalfstep, kSrcOwn, HV>), g, b, 0, st, a, phase);
         break;
-    default: hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhWta, kSrcOwn, 0>), g, b, 0, st, a, phase); break;
+    default:
+        hipLaunchKernelGGL((k_batch_phase<MODE, GMAX, kPhWta, kSrcOwn, HV & kHvPacked>), g, b, 0, st, a, phase);
+        break;
     }
 }
 
-// hv: the half-step variant (kHvNarrow | kHvStream bits), fixed per launch
+// hv: the variant (kHvNarrow | kHvStream | kHvPacked bits, never narrow with packed), fixed per
+// launch
 template <int MODE, int GMAX>
 static void launch_phase_m(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, int hv,
                            hipStream_t st)
@@ -290,6 +306,10 @@ static void launch_phase_m(const BatchArgs& a, int phase, int type, int src, int
     switch (hv) {
     case kHvNarrow: launch_phase_v<MODE, GMAX, kHvNarrow>(a, phase, type, src, tiles, lds, st); break;
     case kHvStream: launch_phase_v<MODE, GMAX, kHvStream>(a, phase, type, src, tiles, lds, st); break;
+    case kHvPacked: launch_phase_v<MODE, GMAX, kHvPacked>(a, phase, type, src, tiles, lds, st); break;
+    case kHvPacked | kHvStream:
+        launch_phase_v<MODE, GMAX, kHvPacked | kHvStream>(a, phase, type, src, tiles, lds, st);
+        break;
     default: launch_phase_v<MODE, GMAX, 0>(a, phase, type, src, tiles, lds, st); break;
     }
 }

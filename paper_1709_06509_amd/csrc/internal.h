@@ -131,6 +131,7 @@ struct BatchArgs {
     int lambda, capv, K, mode;
     int order;                // 0: chunk = workgroup index; 1: the workgroups of one XCD take adjacent chunks
     int narrow;               // half-steps on the narrow path (pairs with G <= kNarrowMaxG; capv <= kNarrowCap)
+    int packed;               // every message volume stored in 12 bits (capv <= 4095; never with narrow)
     int gmax;                 // largest lanes-per-pixel among the pairs (selects a leaner kernel when <= 8)
     unsigned* barrier;        // 10 words: per-XCD-group arrivals, group arrivals, generation
     int* error;               // set when a grid barrier times out
@@ -256,7 +257,7 @@ hipError_t batch_max_blocks_per_cu(int mode, int gmax, size_t lds, int* blocks);
 hipError_t launch_batch_solve(const BatchArgs& a, int blocks, size_t lds, hipStream_t st);
 // One phase of the batch as its own launch: `tiles` workgroups, one per tile.
 // Half-step variant bits of a one-phase launch: the narrow path, streamed volumes.
-constexpr int kHvNarrow = 1, kHvStream = 2;
+constexpr int kHvNarrow = 1, kHvStream = 2, kHvPacked = 4;  // kHvPacked: message volumes in 12 bits
 hipError_t launch_batch_phase(const BatchArgs& a, int phase, int type, int src, int tiles, size_t lds, int hv,
                               hipStream_t st);
 

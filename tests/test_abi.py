@@ -171,3 +171,21 @@ def test_convolution_alignment_validation(lib):
     assert rc == B.BP_E_INVAL and b"16-byte" in L.bp_last_error()
     rc = L.bp_cnn_forward(p(256), 8, 8, 16, p(256), p(264), p(256), ws, p(256), None)
     assert rc == B.BP_E_INVAL and b"16-byte" in L.bp_last_error()
+
+
+def test_batch_message_bits(lib):
+    """The batch's message storage: 12 bits wherever lambda T <= 4095 (any num_disp), else
+    16; 0 for a batch that bp_batch_workspace_bytes rejects."""
+    from paper_1709_06509_amd import bpstereo as B
+
+    L = B.library()
+    B._batch_sigs(L)
+    descs = (B.PairDesc * 3)()
+    for i, (W, H, D) in enumerate([(64, 48, 16), (33, 21, 64), (26, 18, 128)]):
+        descs[i] = B.PairDesc(0, 0, 0, 0, W, H, D, 0)
+    for lam, trunc, bits in [(64, 4, 12), (4095, 1, 12), (1, 4095, 12), (4096, 1, 16), (1500, 4, 16), (5000, 4, 16)]:
+        p = B.make_batch_params(5, 3, [6, 5, 4], lam, trunc)
+        assert L.bp_batch_message_bits(descs, 3, ctypes.byref(p)) == bits, (lam, trunc)
+    p = B.make_batch_params(5, 3, [6, 5, 4], 64, 4)
+    assert L.bp_batch_message_bits(descs, 0, ctypes.byref(p)) == 0
+    assert L.bp_batch_message_bits(descs, 3, ctypes.byref(B.make_batch_params(4, 3, [6, 5, 4], 64, 4))) == 0

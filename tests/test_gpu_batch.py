@@ -40,19 +40,26 @@ def small_pairs():
     return out
 
 
+# (lambda, T) with messages kept in 12 bits (lambda T <= 4095), in 16 bits with the packed
+# 16-bit sums available (<= 16383), and in 16 bits on the int32 path only
+STORAGES = [(64, 4, 12), (1500, 4, 16), (5000, 4, 16)]
+
+
+@pytest.mark.parametrize("lam,trunc,bits", STORAGES)
 @pytest.mark.parametrize("skip", [0, 1, 2])
-def test_batch_matches_oracle(skip):
+def test_batch_matches_oracle(skip, lam, trunc, bits):
     pairs = small_pairs()
-    params = B.make_batch_params(5, 3, [6, 5, 4], 64, 4, skip_mode=skip)
-    say(f"batch of {len(pairs)} small pairs, skip={skip}")
+    params = B.make_batch_params(5, 3, [6, 5, 4], lam, trunc, skip_mode=skip)
+    say(f"batch of {len(pairs)} small pairs, skip={skip}, lambda={lam}, T={trunc}")
     batch = B.Batch([gpu(l) for l, _, _ in pairs], [gpu(r) for _, r, _ in pairs], [D for _, _, D in pairs], params)
+    assert batch.message_bits() == bits
     ctx = B.Context()
     batch.solve(ctx)
     assert batch.status() == 0
     for i, (l, r, D) in enumerate(pairs):
         c = oracle.cost_volume(l, r, D, 5)
         assert np.array_equal(host(batch.costs[i]), c), f"pair {i} cost"
-        d, _, _ = oracle.bp_solve(c, 3, [6, 5, 4], 64, 4, skip, 2, want_msgs=False)
+        d, _, _ = oracle.bp_solve(c, 3, [6, 5, 4], lam, trunc, skip, 2, want_msgs=False)
         assert np.array_equal(host(batch.disps[i]), d), f"pair {i} disparity"
 
 
@@ -141,18 +148,21 @@ def test_every_schedule_gives_the_same_result(skip):
             assert all(torch.equal(a, b) for a, b in zip(got, ref))
 
 
+@pytest.mark.parametrize("lam,trunc", [(64, 4), (1500, 4)])
 @pytest.mark.parametrize("skip", [0, 1, 2])
-def test_batch_narrow_schedule_matches_oracle(skip):
+def test_batch_narrow_schedule_matches_oracle(skip, lam, trunc):
     """Schedule 2 (one launch per phase, packed 16-bit message sums where a pair's pixel
-    spans at most 8 lanes) against the oracle, with pairs of every lane width: D = 5 and 8
-    (one lane), 16 and 24 (two, four), 64 (eight) and 128 (sixteen lanes: the int32 path)."""
+    spans at most 8 lanes and messages are kept in 16 bits: lambda T = 6000) against the
+    oracle, with pairs of every lane width: D = 5 and 8 (one lane), 16 and 24 (two, four), 64
+    (eight) and 128 (sixteen lanes: the int32 path); with lambda T = 256 (12-bit messages)
+    schedule 2 runs as schedule 1."""
     shapes = [(40, 32, 16), (33, 21, 64), (48, 40, 8), (70, 22, 5), (24, 24, 24), (26, 18, 128)]
     pairs = []
     for i, (W, H, D) in enumerate(shapes):
         p = synth.make_pair(W, H, D, (3, 5), False, 0, False, seed=700 + i)
         pairs.append((p["left"], p["right"], D))
-    params = B.make_batch_params(5, 3, [6, 5, 4], 64, 4, skip_mode=skip)
-    say(f"narrow schedule, batch of {len(pairs)} small pairs, skip={skip}")
+    params = B.make_batch_params(5, 3, [6, 5, 4], lam, trunc, skip_mode=skip)
+    say(f"narrow schedule, batch of {len(pairs)} small pairs, skip={skip}, lambda={lam}, T={trunc}")
     batch = B.Batch([gpu(l) for l, _, _ in pairs], [gpu(r) for _, r, _ in pairs], [D for _, _, D in pairs], params)
     ctx = B.Context()
     B.set_batch_schedule(ctx, 2)
@@ -161,12 +171,13 @@ def test_batch_narrow_schedule_matches_oracle(skip):
     for i, (l, r, D) in enumerate(pairs):
         c = oracle.cost_volume(l, r, D, 5)
         assert np.array_equal(host(batch.costs[i]), c), f"pair {i} cost"
-        d, _, _ = oracle.bp_solve(c, 3, [6, 5, 4], 64, 4, skip, 2, want_msgs=False)
+        d, _, _ = oracle.bp_solve(c, 3, [6, 5, 4], lam, trunc, skip, 2, want_msgs=False)
         assert np.array_equal(host(batch.disps[i]), d), f"pair {i} disparity"
 
 
+@pytest.mark.parametrize("lam", [64, 1500])
 @pytest.mark.parametrize("sched", [0, 1, 2])
-def test_batch_plain_odd_finest_halfsteps(sched):
+def test_batch_plain_odd_finest_halfsteps(sched, lam):
     """Plain BP with an odd number of finest half-steps: the last one updates the other
     colour, whose winners it writes itself (int32 path), the WTA phase covering the rest."""
     shapes = [(40, 32, 16), (33, 21, 64), (70, 22, 5), (26, 18, 128), (31, 17, 100)]
@@ -174,8 +185,8 @@ def test_batch_plain_odd_finest_halfsteps(sched):
     for i, (W, H, D) in enumerate(shapes):
         p = synth.make_pair(W, H, D, (3, 5), False, 0, False, seed=900 + i)
         pairs.append((p["left"], p["right"], D))
-    params = B.make_batch_params(5, 3, [5, 4, 3], 64, 4, skip_mode=0)
-    say(f"plain batch, 5 finest half-steps, schedule {sched}")
+    params = B.make_batch_params(5, 3, [5, 4, 3], lam, 4, skip_mode=0)
+    say(f"plain batch, 5 finest half-steps, schedule {sched}, lambda={lam}")
     batch = B.Batch([gpu(l) for l, _, _ in pairs], [gpu(r) for _, r, _ in pairs], [D for _, _, D in pairs], params)
     ctx = B.Context()
     B.set_batch_schedule(ctx, sched, 1, 0)
@@ -183,7 +194,7 @@ def test_batch_plain_odd_finest_halfsteps(sched):
     assert batch.status() == 0
     for i, (l, r, D) in enumerate(pairs):
         c = oracle.cost_volume(l, r, D, 5)
-        d, _, _ = oracle.bp_solve(c, 3, [5, 4, 3], 64, 4, 0, 2, want_msgs=False)
+        d, _, _ = oracle.bp_solve(c, 3, [5, 4, 3], lam, 4, 0, 2, want_msgs=False)
         assert np.array_equal(host(batch.disps[i]), d), f"pair {i} disparity"
 
 
