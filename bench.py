@@ -560,7 +560,7 @@ def main():
     ews = torch.empty(B.bp_energy_workspace_bytes(W, H), dtype=torch.uint8, device=dev)
     ctx = B.Context()
 
-    def step():
+    def step(skip=w["skip"], wsp=ws):
         if rgb:
             B.stereo_luma(left, gl)
             B.stereo_luma(right, gr)
@@ -568,7 +568,7 @@ def main():
         else:
             a, b = left, right
         B.stereo_cost_volume(a, b, D, w["window"], w["cost_scale"], w["cost_trunc"], out=cost)
-        B.bp_hierarchical_solve(cost, L, iters, w["lam"], w["trunc"], w["skip"], 2, ctx=ctx, workspace=ws,
+        B.bp_hierarchical_solve(cost, L, iters, w["lam"], w["trunc"], skip, 2, ctx=ctx, workspace=wsp,
                                 disparity=disp)
         B.bp_energy(cost, disp, w["lam"], w["trunc"], workspace=ews, out=energy)
 
@@ -600,7 +600,7 @@ def main():
         n_timed = args.steps
         # for the record: the same steps without events, and replayed as one HIP graph
         reps = 0 if args.no_extras else max(1, min(args.steps, 50))
-        no_event_elapsed = graph_elapsed = scaling = None
+        no_event_elapsed = graph_elapsed = scaling = freeze_elapsed = None
         if reps:
             t0 = time.perf_counter()
             for _ in range(reps):
@@ -620,6 +620,19 @@ def main():
             graph_elapsed = (time.perf_counter() - t0) / reps
             del graph
             scaling = time_vs_halfsteps(B, cost, ws, w, stream)
+            # the same whole step under the paper's fast-converging rule (freeze rule, K = 2)
+            if w["skip"] != 1:
+                ws_frz = torch.empty(B.bp_workspace_bytes(W, H, B.make_params(D, L, iters, w["lam"], w["trunc"], 1, 2)),
+                                     dtype=torch.uint8, device=dev)
+                for _ in range(3):
+                    step(1, ws_frz)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    step(1, ws_frz)
+                torch.cuda.synchronize()
+                freeze_elapsed = (time.perf_counter() - t0) / reps
+                del ws_frz
 
     # counters and energies (outside the timed region; the solve is deterministic)
     _, _, st = B.bp_hierarchical_solve(cost, L, iters, w["lam"], w["trunc"], w["skip"], 2, want_stats=True)
@@ -691,7 +704,10 @@ def main():
         "time_vs_halfsteps": scaling,
         "freeze_rule": {"energy_ratio_vs_plain": e_frz / e_plain if e_plain else None,
                         "msg_updates_per_pair": st_frz["msg_updates"],
-                        "active_fraction_finest": frz_active},
+                        "active_fraction_finest": frz_active,
+                        "pairs_per_s": 1.0 / freeze_elapsed if freeze_elapsed else None,
+                        "speedup_vs_plain_without_events": (no_event_elapsed / freeze_elapsed
+                                                            if freeze_elapsed and no_event_elapsed else None)},
         "timing_note": "value: the whole step launched eagerly, steps back to back, with a HIP event pair on the "
                        "launch stream around each scale's run of message-update launches (the roofline's average "
                        "launch duration is their summed time over the launch count); pairs_per_s_without_events "

@@ -429,6 +429,12 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
     const int capv = params->lambda * tq < 32767 ? params->lambda * tq : 32767;
 
     if (count) HIP_TRY(bpst::launch_zero_stats(stats, st));
+    // With 12-bit messages (int32 sums, no narrow or fused launches) and a caller's volume laid
+    // out as the kernels read it (D == Dp, 16-byte aligned), the finest scale's half-steps and
+    // winner-take-all read the caller's cost directly: the pyramid then writes no internal copy
+    // of it, a full cost volume of writes saved.  Messages and winners are unchanged, since the
+    // internal copy differs only by a per-pixel shift.
+    bool user0 = pl.packed && pl.Dp == pl.D && (reinterpret_cast<uintptr_t>(cost) & 15) == 0;
     {
         bpst::PyramidArgs pa{};
         for (int l = 0; l < pl.L; ++l) {
@@ -437,9 +443,11 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
         }
         pa.L = pl.L;
         pa.D = pl.D;
+        pa.skip_finest = user0 ? 1 : 0;
         bool done = false;
         HIP_TRY(bpst::launch_pyramid_tree(cost, pa, pl.G, &done, st));
         if (!done) {
+            user0 = false;  // the per-scale pyramid builds the coarser scales from the internal copy
             HIP_TRY(bpst::launch_prep_level0(cost, C[0], pl.lv[0], pl.D, pl.G, st));
             for (int l = 0; l + 1 < pl.L; ++l)
                 HIP_TRY(bpst::launch_pyramid(C[l], pl.lv[l], C[l + 1], pl.lv[l + 1], pl.D, pl.G, st));
@@ -554,7 +562,8 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
                                       sb, mode, st, pl.packed));
         }
         bpst::HalfstepArgs a{};
-        a.cost = C[l];
+        a.cost = (l == 0 && user0) ? cost : C[l];
+        a.user_cost = (l == 0 && user0) ? 1 : 0;
         a.msgs = msgs;
         a.vol = pl.vol[l];
         if (l + 1 < pl.L) {
@@ -666,7 +675,8 @@ static int32_t enqueue_solve(bp_context* ctx, const Plan& pl, const int16_t* cos
             ctx->event_launches[sslot] = scale_launches;
         }
     }
-    HIP_TRY(bpst::launch_wta(C[0], M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, wta_colour, disparity, st, pl.packed));
+    HIP_TRY(bpst::launch_wta(user0 ? cost : C[0], M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, wta_colour, disparity, st,
+                             pl.packed, user0));
     if (final_msgs_or_null)
         HIP_TRY(bpst::launch_export(M[0], pl.vol[0], pl.lv[0], pl.D, pl.G, final_msgs_or_null, st, pl.packed));
     return BP_OK;

@@ -694,7 +694,8 @@ struct PixOut {
 // range on every scale and it only takes part in the barriers.
 template <int G, bool VEC>
 __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ user, int16_t* const* cs,
-                                                   const Level* lvs, int L, int D, int c0, int* lds)
+                                                   const Level* lvs, int L, int D, int c0, int* lds,
+                                                   bool write_finest = true)
 {
     constexpr int Dp = 8 * G;
     const int s1 = 1 << (L - 2), s2 = s1 / 2;
@@ -705,7 +706,8 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
     const int X = (c0 + sub) % Wc, Y = (c0 + sub) / Wc;
     int* cur = lds + sub * (s1 * s1 + s2 * s2) * Dp;  // scale l-1 of the block, [s_{l-1}^2][Dp]
     int* nxt = cur + s1 * s1 * Dp;                    // scale l
-    // scale 1 from the caller's finest costs; also writes the internal finest layout
+    // scale 1 from the caller's finest costs; also writes the internal finest layout, unless
+    // the solve reads the caller's volume at the finest scale itself (write_finest false)
     {
         const Level l0 = lvs[0], l1 = lvs[1];
         const int tasks = s1 * s1 * G;
@@ -741,14 +743,17 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
                 for (int k = 0; k < 4; ++k) {
                     const int x = 2 * px + (k & 1), y = 2 * py + (k >> 1);
                     const int keep = x < l0.W && y < l0.H ? -1 : 0;
-                    fin[k] = finest_internal<G>(v[k], d0, D);
+                    if (write_finest) fin[k] = finest_internal<G>(v[k], d0, D);
 #pragma unroll
                     for (int j = 0; j < 8; ++j) s[j] += v[k][j] & keep;
                 }
+                if (write_finest) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int x = 2 * px + (k & 1), y = 2 * py + (k >> 1);
-                    if (x < l0.W && y < l0.H) *reinterpret_cast<int4*>(cs[0] + slot_of(x, y, l0.Wh) * Dp + d0) = fin[k];
+                    for (int k = 0; k < 4; ++k) {
+                        const int x = 2 * px + (k & 1), y = 2 * py + (k >> 1);
+                        if (x < l0.W && y < l0.H)
+                            *reinterpret_cast<int4*>(cs[0] + slot_of(x, y, l0.Wh) * Dp + d0) = fin[k];
+                    }
                 }
             }
             int mn = kBig;
@@ -820,9 +825,13 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
 // STREAM: the scale's volumes are streamed (nontemporal loads and stores, see ld16).
 // listed: the caller has already read the pixel's freeze state and passes only active
 // pixels (or gi past the end), so the state is not read again.
-template <int G, int MODE, int SRC, bool NARROW = false, bool STREAM = false, bool PACKED = false>
+// USER: the cost is the caller's finest volume [H][W][Dp] (signed values, D == Dp), read at
+// (y W + x): messages and winners do not change under the per-pixel shift the internal finest
+// layout applies, and the sums stay in int32.
+template <int G, int MODE, int SRC, bool NARROW = false, bool STREAM = false, bool PACKED = false, bool USER = false>
 __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, int lane, bool listed = false)
 {
+    static_assert(!USER || (PACKED && !NARROW), "the caller's cost is read on the 12-bit path only");
     constexpr int Dp = 8 * G;
     constexpr int NV = NARROW ? NarrowLane<G>::NV : 1;  // label vectors a lane reads per volume
     constexpr int GL = NARROW ? NarrowLane<G>::GL : G;  // lanes that share one message
@@ -890,8 +899,9 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
 #pragma unroll
     for (int k = 0; k < 4; ++k) mp12[k] = M12{0u, 0u, 0u};
     if (act) {
+        const long long cslot = USER ? (long long)y * W + x : slot;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) c4[v] = ld16<STREAM>(a.cost + slot * Dp + d0 + 8 * v);
+        for (int v = 0; v < NV; ++v) c4[v] = ld16<STREAM>(a.cost + cslot * Dp + d0 + 8 * v);
         if (SRC == kSrcOwn) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -929,7 +939,10 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
         narrow_update<G>(nl, c4, mp, a.D, a.D < Dp, (unsigned)a.lambda, (unsigned)a.capv, out);
     } else {
         int Hs[8];
-        unpack8u(c4[0], Hs);
+        if constexpr (USER)
+            unpack8(c4[0], Hs);
+        else
+            unpack8u(c4[0], Hs);
 #pragma unroll
         for (int j = 0; j < 8; ++j)
             Hs[j] = (d0 + j < a.D) ? Hs[j] + inc(0, j) + inc(1, j) + inc(2, j) + inc(3, j) : kBig;
@@ -1016,7 +1029,8 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
 }
 
 // Winner-take-all of the pixel with slot gi (both colours), lane `lane` of its G lanes.
-template <int G, bool PACKED = false>
+// USER: c0 is the caller's finest volume [H][W][8 G] (signed values), read at (y W + x).
+template <int G, bool PACKED = false, bool USER = false>
 __device__ __forceinline__ void wta_pixel(const int16_t* __restrict__ c0, const int16_t* __restrict__ msgs,
                                           long long vol, Level lv, int D, int16_t* __restrict__ disp, long long gi,
                                           int lane)
@@ -1031,12 +1045,16 @@ __device__ __forceinline__ void wta_pixel(const int16_t* __restrict__ c0, const 
     // a lane without a pixel), and masked after: a load under a branch that also sums would
     // be waited for inside the branch, one memory latency per volume
     const long long s = valid ? gi : 0;
-    const int4 cv = *reinterpret_cast<const int4*>(c0 + s * Dp + d0);
+    const long long cs = USER ? (valid ? (long long)p.y * lv.W + p.x : 0) : s;
+    const int4 cv = *reinterpret_cast<const int4*>(c0 + cs * Dp + d0);
     int4 mv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) mv[k] = ldm<false, PACKED>(msgs, k * vol + s * Dp + d0);
     int b[8];
-    unpack8u(cv, b);
+    if constexpr (USER)
+        unpack8(cv, b);
+    else
+        unpack8u(cv, b);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int keep = valid && has[k] ? -1 : 0;  // a side with no neighbour holds no message

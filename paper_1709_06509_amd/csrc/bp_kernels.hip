@@ -75,7 +75,8 @@ template <int G, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_pyramid_tree(const int16_t* __restrict__ user, PyramidArgs a)
 {
     extern __shared__ int lds[];
-    pyramid_tree_block<G, VEC>(user, a.c, a.lv, a.L, a.D, (int)blockIdx.x * tree_blocks(a.L, G, blockDim.x), lds);
+    pyramid_tree_block<G, VEC>(user, a.c, a.lv, a.L, a.D, (int)blockIdx.x * tree_blocks(a.L, G, blockDim.x), lds,
+                               a.skip_finest == 0);
 }
 
 // Start a scale: copy each pixel's parent messages (zero for a missing neighbour or for
@@ -127,13 +128,14 @@ __global__ __launch_bounds__(kThreads) void k_import(const int16_t* __restrict__
 // update only active pixels.  Updates of one colour are independent, so the order does not
 // change any result.
 // Variant flags of k_halfstep.
-constexpr int kHsCount = 1, kHsNarrow = 2, kHsStream = 4, kHsPacked = 8;
+// kHsUser: the finest scale's cost read from the caller's volume (12-bit messages only).
+constexpr int kHsCount = 1, kHsNarrow = 2, kHsStream = 4, kHsPacked = 8, kHsUser = 16;
 
 template <int G, int MODE, int SRC, int FL>
 __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
 {
     constexpr bool COUNT = (FL & kHsCount) != 0, NARROW = (FL & kHsNarrow) != 0, STREAM = (FL & kHsStream) != 0;
-    constexpr bool PACKED = (FL & kHsPacked) != 0;
+    constexpr bool PACKED = (FL & kHsPacked) != 0, USER = (FL & kHsUser) != 0;
     constexpr int kPix = kThreads / G;  // pixels of one tile
     const int lane = threadIdx.x & (G - 1);
     int gi = blockIdx.x * kPix + threadIdx.x / G;
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
         gi = threadIdx.x < total * G ? blockIdx.x * kPix + list[threadIdx.x / G] : (int)npix;  // npix: no pixel
     }
     const PixOut r =
-        halfstep_pixel<G, MODE, SRC, NARROW, STREAM, PACKED>(a, gi, lane, MODE == 2 || (MODE == 1 && a.t >= 2));
+        halfstep_pixel<G, MODE, SRC, NARROW, STREAM, PACKED, USER>(a, gi, lane, MODE == 2 || (MODE == 1 && a.t >= 2));
     if (COUNT) {
         __shared__ int cnt[2];
         if (threadIdx.x == 0) { cnt[0] = 0; cnt[1] = 0; }
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
 }
 
 // colour < 0: every slot; otherwise the slots of one colour (index y * Wh + xi)
-template <int G, bool PACKED>
+template <int G, bool PACKED, bool USER = false>
 __global__ __launch_bounds__(kThreads) void k_wta(const int16_t* __restrict__ c0, const int16_t* __restrict__ msgs,
                                                    long long vol, Level lv, int D, int colour,
                                                    int16_t* __restrict__ disp)
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_wta(const int16_t* __restrict__ c0
         const long long y = gi / lv.Wh, xi = gi - y * lv.Wh;
         gi = y < lv.H ? (2 * y + colour) * lv.Wh + xi : lv.slots();  // slots(): no pixel
     }
-    wta_pixel<G, PACKED>(c0, msgs, vol, lv, D, disp, gi, (int)(t & (G - 1)));
+    wta_pixel<G, PACKED, USER>(c0, msgs, vol, lv, D, disp, gi, (int)(t & (G - 1)));
 }
 
 template <int G, bool PACKED>
@@ -476,6 +478,16 @@ static hipError_t launch_halfstep_c(const HalfstepArgs& a, unsigned g, hipStream
 {
     if (a.packed) {
         if (a.capv < 0 || a.capv > 4095 || a.narrow || a.out) return hipErrorInvalidValue;
+        if (a.user_cost) {
+            if (a.Dp != a.D || a.level != 0) return hipErrorInvalidValue;
+            if constexpr (SRC == kSrcZero) {
+                return hipErrorInvalidValue;  // the finest scale never starts from zero messages
+            } else {
+                if (a.count) return launch_halfstep_t<MODE, SRC, kHsCount | kHsPacked | kHsUser>(a, g, st);
+                if (a.stream) return launch_halfstep_t<MODE, SRC, kHsStream | kHsPacked | kHsUser>(a, g, st);
+                return launch_halfstep_t<MODE, SRC, kHsPacked | kHsUser>(a, g, st);
+            }
+        }
         if (a.count) return launch_halfstep_t<MODE, SRC, kHsCount | kHsPacked>(a, g, st);
         if (a.stream) return launch_halfstep_t<MODE, SRC, kHsStream | kHsPacked>(a, g, st);
         return launch_halfstep_t<MODE, SRC, kHsPacked>(a, g, st);
@@ -512,10 +524,15 @@ hipError_t launch_halfstep(const HalfstepArgs& a, hipStream_t st)
 }
 
 hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G, int colour,
-                      int16_t* disp, hipStream_t st, bool packed)
+                      int16_t* disp, hipStream_t st, bool packed, bool user)
 {
     const unsigned g = grid_for(colour < 0 ? lv.slots() : (long long)lv.H * lv.Wh, G);
-    if (packed) {
+    if (user) {
+        if (!packed || D != 8 * G || (reinterpret_cast<uintptr_t>(c0) & 15) != 0) return hipErrorInvalidValue;
+        BPST_DISPATCH_G(G, if constexpr (GG >= 16) hipLaunchKernelGGL((k_wta<GG, true, true>), dim3(g), dim3(kThreads),
+                                                                      0, st, c0, msgs, vol, lv, D, colour, disp);
+                           else return hipErrorInvalidValue);
+    } else if (packed) {
         BPST_DISPATCH_G(G, if constexpr (GG >= 16) hipLaunchKernelGGL((k_wta<GG, true>), dim3(g), dim3(kThreads), 0,
                                                                       st, c0, msgs, vol, lv, D, colour, disp);
                            else return hipErrorInvalidValue);

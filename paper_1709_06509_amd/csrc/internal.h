@@ -59,6 +59,8 @@ struct HalfstepArgs {
     int narrow;              // packed 16-bit sums (no counters): see the narrow path in bp_device.h
     int stream;              // nontemporal loads and stores (the scale's volumes exceed the caches)
     int packed;              // messages stored in 12 bits (G >= 16, capv <= 4095; see bp_device.h)
+    int user_cost;           // cost is the caller's finest volume [H][W][D] (D == Dp, 16-byte aligned,
+                             // 12-bit messages only), read at pixel (y W + x), not the colour-split slot
     DevStats* stats;
     int level;
     int16_t* disp;           // non-null (plain BP, int32 path, last half-step of the finest scale):
@@ -87,6 +89,7 @@ struct PyramidArgs {
     int16_t* c[kMaxScales];  // internal cost of every scale
     Level lv[kMaxScales];
     int L, D;
+    int skip_finest;         // the solve reads the caller's finest cost itself: c[0] is not written
 };
 
 // ---- batched solve ----
@@ -277,9 +280,10 @@ hipError_t launch_init(const int16_t* parent, Level lp, long long pvol, int16_t*
 hipError_t launch_import(const int16_t* warm, int16_t* msgs, Level lv, long long vol, int D, int G,
                          uint8_t* state_a, uint8_t* state_b, int mode, hipStream_t st);
 hipError_t launch_halfstep(const HalfstepArgs& a, hipStream_t st);
-// colour -1: every pixel; 0 or 1: only the pixels with (x + y) & 1 == colour
+// colour -1: every pixel; 0 or 1: only the pixels with (x + y) & 1 == colour.  user: c0 is the
+// caller's finest volume [H][W][D] (packed only, D == 8 G, 16-byte aligned), not the internal layout.
 hipError_t launch_wta(const int16_t* c0, const int16_t* msgs, long long vol, Level lv, int D, int G, int colour,
-                      int16_t* disparity, hipStream_t st, bool packed = false);
+                      int16_t* disparity, hipStream_t st, bool packed = false, bool user = false);
 hipError_t launch_export(const int16_t* msgs, long long vol, Level lv, int D, int G, int16_t* out,
                          hipStream_t st, bool packed = false);
 hipError_t launch_energy(const int16_t* cost, const int16_t* disp, int W, int H, int D, int lambda,

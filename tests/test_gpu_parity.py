@@ -216,6 +216,31 @@ def test_solve_negative_and_saturating_costs():
     assert_same(got[:3], got[3:], 4)
 
 
+@pytest.mark.parametrize("D", [128, 256])
+@pytest.mark.parametrize("skip", [0, 1, 2])
+def test_solve_caller_cost_read_directly(D, skip):
+    """With 12-bit messages and D a multiple of the lane width the finest scale reads the
+    caller's cost volume itself (signed values, no internal shifted copy): costs over the whole
+    int16 range, and the same volume at an address that is not 16-byte aligned (the internal
+    copy is used there), must both give the oracle's messages and winners."""
+    rng = np.random.default_rng(D + skip)
+    H, W = 19, 26
+    cost = rng.integers(-32768, 32768, (H, W, D)).astype(np.int16)
+    for aligned in (True, False):
+        say(f"caller cost D={D} skip={skip} aligned={aligned}")
+        if aligned:
+            c = gpu(cost)
+        else:
+            buf = torch.zeros(cost.size + 8, dtype=torch.int16, device="cuda")
+            c = buf[1:1 + cost.size].view(H, W, D)
+            c.copy_(gpu(cost))
+            assert c.data_ptr() % 16 != 0
+        assert B.bp_message_bits(W, H, B.make_params(D, 3, [6, 5, 4], 64, 4, skip)) == 12
+        d, m, st = B.bp_hierarchical_solve(c, 3, [6, 5, 4], 64, 4, skip, 2, want_msgs=True, want_stats=True)
+        rd, rm, rs = oracle.bp_solve(cost, 3, [6, 5, 4], 64, 4, skip, 2)
+        assert_same((host(d), host(m), st), (rd, rm, rs), 3)
+
+
 def test_solve_freeze_k4():
     rng = np.random.default_rng(12)
     cost = rng.integers(0, 300, (21, 26, 16)).astype(np.int16)
