@@ -384,6 +384,40 @@ def test_freeze_rule_timing_on_flat_cost():
     assert s["active"][1][:5].tolist() == [8, 8, 8, 8, 0] and s["active"][0][:5].tolist() == [32, 32, 32, 32, 0]
 
 
+def test_freeze_rule_timing_from_a_converged_chain():
+    """On a 1 x N chain min-sum BP reaches its fixed point (the exact dynamic-programming
+    messages) once every message has travelled the chain.  Started at that fixed point the
+    messages are non-zero, yet no update changes any of them, so the freeze rule must give
+    the flat-cost timetable: every pixel updated twice (its own state reset on the first),
+    found unchanged on the second, frozen from there with K = 2 (one more unchanged update
+    with K = 4).  Comparing a new message with any slot but the one it overwrites would keep
+    pixels active."""
+    rng = np.random.default_rng(21)
+    W, D = 9, 5
+    cost = rng.integers(0, 300, (1, W, D)).astype(np.int16)
+    _, m, _ = oracle.bp_solve(cost, 1, [60], 40, 3)
+    assert m[0].any() and m[1].any()  # messages that carry information both ways
+    # a fixed point: two more plain half-steps from it change nothing
+    _, m2, _ = oracle.bp_solve(cost, 2, [2, 0], 40, 3, warm_msgs=m)
+    assert np.array_equal(m2, m)
+    n0, n1 = (W + 1) // 2, W // 2  # pixels of colour 0 and 1
+    _, mf, s = oracle.bp_solve(cost, 2, [9, 0], 40, 3, skip_mode=1, converge_iters=2, warm_msgs=m)
+    assert s["active"][0][:9].tolist() == [n0, n1, n0, n1, 0, 0, 0, 0, 0]
+    assert np.array_equal(mf, m)
+    _, _, s = oracle.bp_solve(cost, 2, [9, 0], 40, 3, skip_mode=1, converge_iters=4, warm_msgs=m)
+    assert s["active"][0][:9].tolist() == [n0, n1, n0, n1, n0, n1, 0, 0, 0]
+
+
+def test_freeze_rule_with_unreachable_threshold_is_plain_bp():
+    """With K larger than twice the half-steps of any scale no pixel can freeze, so the
+    freeze rule performs exactly plain BP's updates."""
+    cost = _synthetic(D=8, seed=22)
+    d0, m0, s0 = oracle.bp_solve(cost, 3, [8, 8, 8], 64, 4, skip_mode=0)
+    d1, m1, s1 = oracle.bp_solve(cost, 3, [8, 8, 8], 64, 4, skip_mode=1, converge_iters=18)
+    assert np.array_equal(d0, d1) and np.array_equal(m0, m1)
+    assert s1["pixel_updates"] == s0["pixel_updates"] and s1["msg_updates"] == s0["msg_updates"]
+
+
 # ---------------------------------------------------------------- left-right consistency
 def test_lr_check_hand_cases():
     """Hand-worked cases of the left-right check: a left pixel at column x with disparity d
