@@ -828,10 +828,14 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
 // USER: the cost is the caller's finest volume [H][W][Dp] (signed values, D == Dp), read at
 // (y W + x): messages and winners do not change under the per-pixel shift the internal finest
 // layout applies, and the sums stay in int32.
-template <int G, int MODE, int SRC, bool NARROW = false, bool STREAM = false, bool PACKED = false, bool USER = false>
+// FULL_D: D == Dp, every label of every lane is a real one, so no label is masked (implied by
+// USER).
+template <int G, int MODE, int SRC, bool NARROW = false, bool STREAM = false, bool PACKED = false, bool USER = false,
+          bool FULL_D = false>
 __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, int lane, bool listed = false)
 {
     static_assert(!USER || (PACKED && !NARROW), "the caller's cost is read on the 12-bit path only");
+    constexpr bool FULL = USER || FULL_D;
     constexpr int Dp = 8 * G;
     constexpr int NV = NARROW ? NarrowLane<G>::NV : 1;  // label vectors a lane reads per volume
     constexpr int GL = NARROW ? NarrowLane<G>::GL : G;  // lanes that share one message
@@ -945,7 +949,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
             unpack8u(c4[0], Hs);
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            Hs[j] = (d0 + j < a.D) ? Hs[j] + inc(0, j) + inc(1, j) + inc(2, j) + inc(3, j) : kBig;
+            Hs[j] = (FULL || d0 + j < a.D) ? Hs[j] + inc(0, j) + inc(1, j) + inc(2, j) + inc(3, j) : kBig;
 #pragma unroll
         for (int k = 0; k < 4; k += 2) {
             int ha[8], hb[8];
@@ -962,7 +966,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
             // other colour, are not updated again), so Hs is their belief (as in wta_pixel)
             int key = 0x7fffffff;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) if (d0 + j < a.D) key = min(key, Hs[j] * 256 + d0 + j);
+            for (int j = 0; j < 8; ++j) if (FULL || d0 + j < a.D) key = min(key, Hs[j] * 256 + d0 + j);
             key = group_min<G>(key);
             if (act && lane == 0) a.disp[(long long)y * W + x] = (int16_t)(key & 255);
         }
@@ -977,7 +981,7 @@ __device__ __forceinline__ PixOut halfstep_pixel(const HalfstepArgs& a, int gi, 
         if (check) {
             bool same = true;
             if constexpr (PACKED) {
-                same = same12(op12[e], out12[e], label_mask12(d0, a.D));
+                same = same12(op12[e], out12[e], FULL ? M12{~0u, ~0u, ~0u} : label_mask12(d0, a.D));
             } else {
 #pragma unroll
                 for (int v = 0; v < NV; ++v)

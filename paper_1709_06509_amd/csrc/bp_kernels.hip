@@ -128,14 +128,15 @@ __global__ __launch_bounds__(kThreads) void k_import(const int16_t* __restrict__
 // update only active pixels.  Updates of one colour are independent, so the order does not
 // change any result.
 // Variant flags of k_halfstep.
-// kHsUser: the finest scale's cost read from the caller's volume (12-bit messages only).
-constexpr int kHsCount = 1, kHsNarrow = 2, kHsStream = 4, kHsPacked = 8, kHsUser = 16;
+// kHsUser: the finest scale's cost read from the caller's volume (12-bit messages only, D == Dp);
+// kHsFull: D == Dp on the 12-bit path, so no label is masked.
+constexpr int kHsCount = 1, kHsNarrow = 2, kHsStream = 4, kHsPacked = 8, kHsUser = 16, kHsFull = 32;
 
 template <int G, int MODE, int SRC, int FL>
 __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
 {
     constexpr bool COUNT = (FL & kHsCount) != 0, NARROW = (FL & kHsNarrow) != 0, STREAM = (FL & kHsStream) != 0;
-    constexpr bool PACKED = (FL & kHsPacked) != 0, USER = (FL & kHsUser) != 0;
+    constexpr bool PACKED = (FL & kHsPacked) != 0, USER = (FL & kHsUser) != 0, FULL_D = (FL & kHsFull) != 0;
     constexpr int kPix = kThreads / G;  // pixels of one tile
     const int lane = threadIdx.x & (G - 1);
     int gi = blockIdx.x * kPix + threadIdx.x / G;
@@ -166,7 +167,8 @@ __global__ __launch_bounds__(kThreads) void k_halfstep(HalfstepArgs a)
         gi = threadIdx.x < total * G ? blockIdx.x * kPix + list[threadIdx.x / G] : (int)npix;  // npix: no pixel
     }
     const PixOut r =
-        halfstep_pixel<G, MODE, SRC, NARROW, STREAM, PACKED, USER>(a, gi, lane, MODE == 2 || (MODE == 1 && a.t >= 2));
+        halfstep_pixel<G, MODE, SRC, NARROW, STREAM, PACKED, USER, FULL_D>(a, gi, lane,
+                                                                         MODE == 2 || (MODE == 1 && a.t >= 2));
     if (COUNT) {
         __shared__ int cnt[2];
         if (threadIdx.x == 0) { cnt[0] = 0; cnt[1] = 0; }
@@ -487,6 +489,11 @@ static hipError_t launch_halfstep_c(const HalfstepArgs& a, unsigned g, hipStream
                 if (a.stream) return launch_halfstep_t<MODE, SRC, kHsStream | kHsPacked | kHsUser>(a, g, st);
                 return launch_halfstep_t<MODE, SRC, kHsPacked | kHsUser>(a, g, st);
             }
+        }
+        if (a.Dp == a.D) {
+            if (a.count) return launch_halfstep_t<MODE, SRC, kHsCount | kHsPacked | kHsFull>(a, g, st);
+            if (a.stream) return launch_halfstep_t<MODE, SRC, kHsStream | kHsPacked | kHsFull>(a, g, st);
+            return launch_halfstep_t<MODE, SRC, kHsPacked | kHsFull>(a, g, st);
         }
         if (a.count) return launch_halfstep_t<MODE, SRC, kHsCount | kHsPacked>(a, g, st);
         if (a.stream) return launch_halfstep_t<MODE, SRC, kHsStream | kHsPacked>(a, g, st);
