@@ -47,10 +47,14 @@ def test_noalloc_matches_workspace_solve_on_consecutive_calls():
     cost_big = B.stereo_cost_volume(gpu(p["left"]), gpu(p["right"]), w["num_disp"], w["window"])
     rng = np.random.default_rng(3)
     cost_small = gpu(rng.integers(0, 800, (37, 51, 24)).astype(np.int16))
+    # D = 128: messages in 12 bits, the finest scale reading the caller's cost
+    cost_wide = gpu(rng.integers(-2000, 2000, (33, 40, 128)).astype(np.int16))
     L, iters = w["num_scales"], [w["iters"]] * w["num_scales"]
     for name, cost, LL, its, skip in [("production 384x288 D=16 freeze", cost_big, L, iters, 1),
                                       ("random 51x37 D=24 plain", cost_small, 3, [7, 6, 5], 0),
+                                      ("random 40x33 D=128 plain", cost_wide, 3, [6, 5, 4], 0),
                                       ("production 384x288 D=16 exact skip", cost_big, L, iters, 2),
+                                      ("random 40x33 D=128 freeze", cost_wide, 3, [7, 5, 4], 1),
                                       ("random 51x37 D=24 freeze", cost_small, 3, [9, 4, 4], 1)]:
         say(f"noalloc vs workspace solve: {name}")
         a, b = both(cost, LL, its, w["lam"], w["trunc"], skip)
