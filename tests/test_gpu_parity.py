@@ -241,6 +241,27 @@ def test_solve_caller_cost_read_directly(D, skip):
         assert_same((host(d), host(m), st), (rd, rm, rs), 3)
 
 
+@pytest.mark.parametrize("H,W,D,skip", [(384, 512, 256, 0), (384, 512, 256, 1), (600, 800, 128, 1)])
+def test_caller_cost_direct_read_equals_internal_copy_when_streamed(H, W, D, skip):
+    """At sizes whose finest volumes are streamed (nontemporal accesses, working set above
+    256 MB), the solve reading the caller's volume directly and the solve reading its internal
+    copy (the same volume at an address that is not 16-byte aligned) give the same messages,
+    winners and counters; both are checked against the oracle at smaller sizes."""
+    rng = np.random.default_rng(H + W + D + skip)
+    say(f"direct read vs internal copy, streamed: {W}x{H} D={D} skip={skip}")
+    cost = torch.from_numpy(rng.integers(0, 1025, (H, W, D)).astype(np.int16)).cuda()
+    buf = torch.zeros(cost.numel() + 8, dtype=torch.int16, device="cuda")
+    shifted = buf[1:1 + cost.numel()].view(H, W, D)
+    shifted.copy_(cost)
+    assert cost.data_ptr() % 16 == 0 and shifted.data_ptr() % 16 != 0
+    its = [6, 5, 4]
+    a = B.bp_hierarchical_solve(cost, 3, its, 64, 4, skip, 2, want_msgs=True, want_stats=True)
+    b = B.bp_hierarchical_solve(shifted, 3, its, 64, 4, skip, 2, want_msgs=True, want_stats=True)
+    assert torch.equal(a[0], b[0]), "disparities differ"
+    assert torch.equal(a[1], b[1]), "messages differ"
+    assert a[2]["msg_updates"] == b[2]["msg_updates"] and a[2]["active"] == b[2]["active"]
+
+
 def test_solve_freeze_k4():
     rng = np.random.default_rng(12)
     cost = rng.integers(0, 300, (21, 26, 16)).astype(np.int16)
