@@ -692,6 +692,15 @@ struct PixOut {
 // with its own lanes and LDS slice; all blocks meet the same barriers.  A coarsest index
 // past the last pixel has Y >= the coarsest height, so every pixel of its block is out of
 // range on every scale and it only takes part in the barriers.
+// Element of label j (0..7) of lane `lane` of block pixel p in the tree's LDS scale buffers.
+// A lane's 8 labels are two 16-byte chunks, and chunk k of a pixel's G lanes lie side by
+// side, so the lanes of a wave touch consecutive 16-byte chunks (no bank conflicts).
+template <int G>
+__device__ __forceinline__ int tree_at(int p, int lane, int j)
+{
+    return p * 8 * G + (j >> 2) * 4 * G + lane * 4 + (j & 3);
+}
+
 template <int G, bool VEC>
 __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ user, int16_t* const* cs,
                                                    const Level* lvs, int L, int D, int c0, int* lds,
@@ -766,7 +775,7 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
             if (valid) {
                 *reinterpret_cast<int4*>(cs[1] + slot_of(px, py, l1.Wh) * Dp + d0) = pack8(o);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) cur[p * Dp + d0 + j] = o[j];
+                for (int j = 0; j < 8; ++j) cur[tree_at<G>(p, lane, j)] = o[j];
             }
         }
     }
@@ -787,9 +796,9 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
                         if (2 * px + c >= lf.W || 2 * py + b >= lf.H) continue;
-                        const int* src = cur + ((2 * qy + b) * sf + (2 * qx + c)) * Dp + d0;
+                        const int child = (2 * qy + b) * sf + (2 * qx + c);
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) s[j] += src[j];
+                        for (int j = 0; j < 8; ++j) s[j] += cur[tree_at<G>(child, lane, j)];
                     }
             }
             int mn = kBig;
@@ -802,7 +811,7 @@ __device__ __forceinline__ void pyramid_tree_block(const int16_t* __restrict__ u
             if (valid) {
                 *reinterpret_cast<int4*>(cs[l] + slot_of(px, py, lc.Wh) * Dp + d0) = pack8(o);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) nxt[p * Dp + d0 + j] = o[j];
+                for (int j = 0; j < 8; ++j) nxt[tree_at<G>(p, lane, j)] = o[j];
             }
         }
         __syncthreads();
